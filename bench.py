@@ -1,0 +1,201 @@
+"""Benchmark: MG-MLMC++ trace estimates per second on one MI355X.
+
+One step = one full MG-MLMC++ estimate of tr(D^{-1}) to the workload's relative
+accuracy (Hutch++ low-rank parts on every level difference, then the adaptive
+stochastic part of Alg. 2 with optimal target variances), with the gauge
+field and the multigrid hierarchy already resident in HBM (the hierarchy
+setup is timed separately and reported as ``setup_s``).
+
+Prints one JSON line (see the fields below).  ``--gpus N`` with N > 1 is not
+supported: the build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def mg_setup_kwargs(cfg):
+    L = len(cfg["blocks"]) + 1
+    return dict(
+        nlevels=L, blocks=cfg["blocks"], ntv=cfg["ntv"],
+        sap_block=[cfg["blocks"][0]] + [(1, 1)] * L,
+        sap_cycles=[2] * 6, inner_iters=[8] * 6, inner_tol=0.1,
+        setup_iters=3, setup_tol=1e-10, setup_restart=32, setup_max_restarts=200,
+        seed=cfg["gauge_seed"] + 17,
+    )
+
+
+def trace_kwargs(cfg, step):
+    return dict(variant="mlmcpp", form="reduced", eps=cfg["eps"], d=cfg["d"], k_power=cfg["k_power"],
+                noise=cfg["noise"], targets="optimal", seed=cfg["trace_seed"] + step, batch=64)
+
+
+def time_apply(ctx, gid, level, nrhs, reps=20):
+    """Average duration (s) of one mgm_apply_D launch, HIP events on the
+    stream the library launches on (torch's current stream)."""
+    import torch
+    from lattice_inputs import rhs_vectors
+    n = ctx.level_info(gid, level)["n"]
+    x = torch.from_numpy(rhs_vectors(n, nrhs, 1)).to("cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        ctx.apply_D(gid, level, x, y)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.apply_D(gid, level, x, y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(cfg, gpu_samples, budget_s=25.0):
+    """Time the oracle (1 thread) on a bounded sample of the same workload and
+    scale to one estimate with the GPU run's per-level sample counts."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = (
+        "import json,sys; sys.path.insert(0, %r); import bench; "
+        "print(json.dumps(bench._oracle_sample(%r, %r, %r)))" % (ROOT, cfg["name"], gpu_samples, budget_s)
+    )
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=900)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _oracle_sample(name, gpu_samples, budget_s):
+    import numpy as np
+    from lattice_inputs import WORKLOADS, gauge_for
+    from oracle import mg as omg
+    from oracle import rng
+    from oracle import trace as otr
+    cfg = dict(WORKLOADS[name], name=name)
+    th = gauge_for(cfg)
+    hier = omg.setup_hierarchy(th, cfg["m0"], cfg["blocks"], cfg["ntv"], cfg["gauge_seed"] + 17)
+    ops, _ = otr.level_ops(hier, "mlmcpp", "reduced")
+    # warm the sparse LU factorisations (setup, excluded like the GPU setup)
+    for lev in hier.levels:
+        lev.solve(np.ones((lev.n, 1), dtype=complex))
+    noise = cfg["noise"]
+    total, parts = 0.0, []
+    t_start = time.perf_counter()
+    for l, (A, n) in enumerate(ops):
+        d = cfg["d"][l]
+        t0 = time.perf_counter()
+        Q, _ = otr.low_rank(A, n, d, cfg["k_power"], noise, cfg["trace_seed"], l)
+        t_lr = time.perf_counter() - t0
+        lv = otr.StochLevel(A, n, d, 1.0, Q=Q)
+        k = 0
+        t0 = time.perf_counter()
+        while k < 4 or (time.perf_counter() - t_start < budget_s and k < 64):
+            otr.sample(lv, noise, cfg["trace_seed"], l, k)
+            k += 1
+        t_s = (time.perf_counter() - t0) / k
+        total += t_lr + gpu_samples[l] * t_s
+        parts.append(dict(level=l, lowrank_s=t_lr, per_sample_s=t_s, timed_samples=k))
+    return dict(seconds_per_estimate=total, parts=parts)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="schwinger128")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from lattice_inputs import WORKLOADS, gauge_for, links_from_theta
+    from paper_2303_11512_amd import Context, mg_params, solve_params
+
+    cfg = dict(WORKLOADS[args.workload], name=args.workload)
+    th = gauge_for(cfg)
+    ctx = Context(0)
+    gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), cfg["m0"], True)
+    t0 = time.perf_counter()
+    ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg)))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"# setup done in {setup_s:.2f}s", file=sys.stderr, flush=True)
+
+    sp = solve_params(tol=1e-10, restart=16, max_restarts=50)
+    for w in range(args.warmup):
+        ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, 1000 + w))
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for k in range(args.steps):
+        outs.append(ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, k)))
+        print(f"# step {k}: tau={outs[-1]['tau']:.6f} samples={outs[-1]['level_samples']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = sum(sum(o["solves"]) for o in outs)
+
+    # roofline of the fine stencil at the step's RHS block (64)
+    nrhs = 64
+    t_k = time_apply(ctx, gid, 0, nrhs)
+    V = cfg["Lx"] * cfg["Lt"]
+    alg_bytes = V * (64 * nrhs + 32)
+    achieved = alg_bytes / t_k / 1e9
+
+    samples = [int(sum(o["level_samples"][l] for o in outs) / len(outs)) for l in range(len(outs[0]["level_samples"]))]
+    cpu = None
+    if not args.no_cpu:
+        cb = cpu_baseline(cfg, samples)
+        if "seconds_per_estimate" in cb:
+            cpu = {"value": 1.0 / cb["seconds_per_estimate"], "unit": "trace estimates/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": "oracle Hutch++ phase per level in full + >=4 stochastic samples per level "
+                             "(1 thread), scaled to the GPU run's mean per-level sample counts; setup "
+                             "and coarsest inverse excluded on both sides",
+                   "detail": cb["parts"]}
+        else:
+            cpu = {"error": cb.get("error")}
+    line = {
+        "metric": "trace estimates/s at 1e-3 rel. accuracy",
+        "value": args.steps / dt,
+        "unit": "trace estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {cfg['Lx']}x{cfg['Lt']} Schwinger, beta {cfg['beta']}, "
+                               f"m0 {cfg['m0']}, {len(cfg['blocks']) + 1}-level MG, Hutch++ d={cfg['d']}, "
+                               f"{cfg['noise']} noise, eps {cfg['eps']}, FGMRES tol 1e-10",
+                   "solves_per_s": solves / dt, "setup_s": setup_s,
+                   "level_samples": samples, "tau": [outs[-1]["tau"].real, outs[-1]["tau"].imag]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_wilson (fine stencil, 64 RHS)", "launch_us": t_k * 1e6},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

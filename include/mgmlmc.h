@@ -1,0 +1,237 @@
+/*
+ * mgmlmc.h -- C ABI of the MI355X (gfx950) MG-MLMC++ library.
+ *
+ * The library estimates tr(D^{-1}) for the 2D Schwinger (U(1) Wilson-Dirac)
+ * operator D with the multigrid multilevel Monte Carlo method combined with
+ * Hutch++ deflation (MG-MLMC++; Frommer & Nasr Khalil, Alg. 2).  The problem
+ * statement (Sec. 1) fixes the interface: D is large, sparse and non-singular,
+ * and D^{-1} is reached only through solves D x = zeta.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Vectors are complex128 (interleaved re, im doubles) in DEVICE memory,
+ *    caller-owned, in the natural layout [nrhs][n_level]: RHS r occupies
+ *    n_level consecutive complex numbers.
+ *  - Logical dof index on the fine level (level 0): (t * Lx + x) * 2 + s,
+ *    s the spin.  On a coarse level l >= 1 with site grid Nx_l x Nt_l and
+ *    ntv test vectors per chirality: ((A * 2 + c) * ntv + k), A = At*NAx+Ax
+ *    the aggregate (= coarse site), c the chirality, k the test vector.
+ *  - Every call is enqueued on the context's HIP stream (the stream given to
+ *    mgm_create).  mgm_apply_* and mgm_noise return without a host sync;
+ *    every other call synchronises the stream before returning.
+ *  - Calls return MGM_OK (0) or a negative status; they never abort.
+ *    mgm_last_error() gives the message of the last failing call.
+ *  - One context per host thread; no internal locking.  All internal state
+ *    (gauge copy, hierarchy, factorizations, workspaces) is owned by the
+ *    context and freed by mgm_destroy.
+ *  - FP64 results are bitwise reproducible for the same inputs, GPU and
+ *    build: reductions use fixed trees and no atomics.
+ */
+#ifndef MGMLMC_H
+#define MGMLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGM_OK 0
+#define MGM_EINVAL (-1)     /* bad argument: sizes, pointers, level range      */
+#define MGM_ENOMEM (-2)     /* device allocation failed                        */
+#define MGM_EHIP (-3)       /* a HIP runtime call failed                       */
+#define MGM_ESTATE (-4)     /* wrong order of calls (e.g. no setup_mg yet)     */
+#define MGM_ENOTCONV (-5)   /* a solve did not reach its tolerance             */
+#define MGM_ENONFINITE (-6) /* NaN or Inf in an input or a residual            */
+
+#define MGM_MAX_LEVELS 6
+
+/* noise kinds (isotropic vectors, Sec. 1 eq. random_props) */
+#define MGM_NOISE_RADEMACHER 0 /* z = +-1                                 */
+#define MGM_NOISE_Z2Z2 1       /* z = (+-1 +- i)/sqrt(2)                  */
+
+/* noise purposes: field of the counter key */
+#define MGM_PURPOSE_SETUP 1
+#define MGM_PURPOSE_SKETCH 2
+#define MGM_PURPOSE_SAMPLE 3
+
+/* precision of the multigrid preconditioner (the outer FGMRES is always FP64) */
+#define MGM_PREC_FP64 0
+#define MGM_PREC_FP32 1
+
+typedef struct mgm_ctx mgm_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the default stream). */
+int mgm_create(mgm_ctx **out, int device, void *stream);
+void mgm_destroy(mgm_ctx *ctx);
+const char *mgm_last_error(const mgm_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * set_gauge -- the fine operator (Sec. 4: Schwinger discretization shifted by
+ * a multiple of the identity):
+ *   D = (m0 + 2) I - 1/2 sum_mu [(1 - sigma_mu) U_mu(x) delta_{x+mu,y}
+ *                               + (1 + sigma_mu) U_mu(x-mu)^* delta_{x-mu,y}]
+ * sigma_0 = Pauli x, sigma_1 = Pauli y; periodic in x; antiperiodic in t when
+ * bc_t_anti != 0.
+ *   links: DEVICE complex128 [2][Lt][Lx]; links[mu][t][x] = U_mu(x, t), the
+ *          link from (x, t) to its neighbour in direction mu.  Copied in.
+ *   Lx, Lt even and >= 2.  Returns a gauge handle in *gauge_id.
+ * ------------------------------------------------------------------------- */
+int mgm_set_gauge(mgm_ctx *ctx, int Lx, int Lt, const void *links, double m0,
+                  int bc_t_anti, int *gauge_id);
+
+/* ---------------------------------------------------------------------------
+ * setup_mg -- aggregation multigrid hierarchy with R_l = P_l^H, P_l^H P_l = I
+ * and Galerkin coarse operators D_{l+1} = P_l^H D_l P_l (Sec. 3.1), built by
+ * the deterministic bootstrap documented with the oracle's setup:
+ *   V <- Z2xZ2 noise (purpose SETUP, level l, column k)
+ *   setup_iters times: V <- qr+(D_l^{-1} V)       (FGMRES solves to setup_tol)
+ *   P_l columns of aggregate A, chirality c <- qr+(rows of V in (A, c))
+ * then the coarsest operator is inverted densely (Gauss-Jordan with partial
+ * pivoting), which gives tr(D_{L-1}^{-1}) (Alg. 2, coarsest level).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int nlevels;                        /* L, 1 .. MGM_MAX_LEVELS              */
+  int block[MGM_MAX_LEVELS][2];       /* aggregate (bx, bt), step l -> l+1   */
+  int ntv[MGM_MAX_LEVELS];            /* test vectors per chirality, step l  */
+  int sap_block[MGM_MAX_LEVELS][2];   /* SAP block (sbx, sbt) on level l     */
+  int sap_cycles[MGM_MAX_LEVELS];     /* SAP post-smoothing cycles, level l  */
+  int inner_iters[MGM_MAX_LEVELS];    /* FGMRES steps of the coarse solve on
+                                         level l (1 <= l <= L-2)             */
+  double inner_tol;                   /* relative stop of those inner solves
+                                         (0: always inner_iters steps)       */
+  int setup_iters;                    /* inverse-iteration steps (3)          */
+  double setup_tol;                   /* relative residual of setup solves   */
+  int setup_restart;                  /* FGMRES restart length in the setup  */
+  int setup_max_restarts;
+  uint64_t seed;                      /* seed of the SETUP noise             */
+  int precision;                      /* MGM_PREC_FP64 | MGM_PREC_FP32       */
+} mgm_mg_params;
+
+int mgm_setup_mg(mgm_ctx *ctx, int gauge_id, const mgm_mg_params *prm);
+
+/* Level geometry: info[0..3] = Nx, Nt, dof per site M, n = Nx*Nt*M. */
+int mgm_level_info(mgm_ctx *ctx, int gauge_id, int level, int *info);
+
+/* ---------------------------------------------------------------------------
+ * apply_D -- y = D_level x for nrhs vectors (level 0 = the fine operator,
+ * level l >= 1 = the Galerkin operator; Sec. 3.1).  x, y: DEVICE
+ * [nrhs][n_level], must not overlap.
+ * apply_P -- y = P_level x: coarse (level+1) -> fine (level) vectors.
+ * apply_R -- y = P_level^H x: fine (level) -> coarse (level+1) vectors.
+ * ------------------------------------------------------------------------- */
+int mgm_apply_D(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *x, void *y);
+int mgm_apply_P(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *x, void *y);
+int mgm_apply_R(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *x, void *y);
+
+/* Apply the multigrid preconditioner M_level ~ D_level^{-1}: coarse
+ * correction by inner FGMRES (or the dense inverse on the coarsest level),
+ * then sap_cycles red/black SAP cycles with exact block solves.  r, x:
+ * DEVICE [nrhs][n_level]. */
+int mgm_precondition(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *r, void *x);
+
+/* Copy P_level's aggregate blocks to DEVICE `out`:
+ * complex128 [nagg][2][bx*bt*M_level/2][ntv]. */
+int mgm_get_prolongator(mgm_ctx *ctx, int gauge_id, int level, void *out);
+
+/* tr(D_{L-1}^{-1}) of the coarsest level, out[0] = re, out[1] = im (HOST). */
+int mgm_coarsest_trace(mgm_ctx *ctx, int gauge_id, double *out);
+
+/* ---------------------------------------------------------------------------
+ * solve_batch -- x = D_level^{-1} b for nrhs right-hand sides by right-
+ * preconditioned FGMRES(restart) in FP64 with the multigrid preconditioner
+ * (Alg. 2 "use mg to solve lin. sys.").  Every RHS stops on its true FP64
+ * residual ||b - D x|| <= tol ||b||.  x0 = 0.  On the coarsest level the
+ * dense inverse is applied.  b, x: DEVICE [nrhs][n_level].
+ * stats (optional, HOST arrays of nrhs entries, caller-owned): FGMRES
+ * iterations and final relative residual per RHS.  On MGM_ENOTCONV x holds
+ * the last iterate.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double tol;        /* relative residual, e.g. 1e-10 */
+  int restart;       /* FGMRES restart length m       */
+  int max_restarts;
+  int rhs_block;     /* RHS solved together (0 = all) */
+} mgm_solve_params;
+
+typedef struct {
+  int *iters;        /* HOST [nrhs] or NULL */
+  double *relres;    /* HOST [nrhs] or NULL */
+} mgm_solve_stats;
+
+int mgm_solve_batch(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *b, void *x,
+                    const mgm_solve_params *prm, mgm_solve_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * noise -- nrhs isotropic vectors of length n written to DEVICE out
+ * [nrhs][n] (complex128): vector r uses the counter key (seed, purpose,
+ * level, index0 + r), element i its SplitMix64 word i.
+ * ------------------------------------------------------------------------- */
+int mgm_noise(mgm_ctx *ctx, int kind, uint64_t seed, int purpose, int level, int64_t index0,
+              int64_t n, int nrhs, void *out);
+
+/* qr+ -- Q = thin QR factor of the d columns of Y (DEVICE [d][n]) with a
+ * real positive diagonal of R (CholQR2); Q written to DEVICE [d][n]. */
+int mgm_orthonormalize(mgm_ctx *ctx, int64_t n, int d, const void *Y, void *Q);
+
+/* ---------------------------------------------------------------------------
+ * trace_estimate -- tr(D^{-1}) by
+ *   MGM_VARIANT_HUTCH    Alg. 1 (plain Hutchinson) on D^{-1};
+ *   MGM_VARIANT_HUTCHPP  Hutch++ (Sec. 2.4) on D^{-1};
+ *   MGM_VARIANT_MLMC     MG-MLMC (Sec. 3.1), i.e. Alg. 2 with d_l = 0;
+ *   MGM_VARIANT_MLMCPP   MG-MLMC++ (Alg. 2).
+ * Level differences use the reduced form (eq. mlmc_dec_trace_reduced) or the
+ * full form with accumulated prolongations (eq. mlmc_decomp_trace).  Samples
+ * are drawn `batch` at a time per active level and Alg. 2's stopping rule is
+ * replayed sample by sample, so the result equals the sequential algorithm's
+ * on the same seeds.
+ * ------------------------------------------------------------------------- */
+#define MGM_VARIANT_HUTCH 0
+#define MGM_VARIANT_HUTCHPP 1
+#define MGM_VARIANT_MLMC 2
+#define MGM_VARIANT_MLMCPP 3
+#define MGM_FORM_REDUCED 0
+#define MGM_FORM_FULL 1
+#define MGM_TARGETS_OPTIMAL 0
+#define MGM_TARGETS_UNIFORM 1
+
+typedef struct {
+  int variant, form;
+  double eps;                        /* relative accuracy (1 sigma)          */
+  int d[MGM_MAX_LEVELS];             /* Hutch++ vectors per difference level */
+  int k_power;                       /* block power sweeps                   */
+  int noise;                         /* MGM_NOISE_*                          */
+  int targets;                       /* MGM_TARGETS_*                        */
+  int use_fixed_cost;                /* 1: cost per sample = fixed_cost[l]   */
+  double fixed_cost[MGM_MAX_LEVELS]; /* else nnz(D_l)+nnz(D_{l+1})+2 n_l d_l */
+  int min_samples;                   /* >= 2                                 */
+  int max_samples;
+  const int *fixed_samples;          /* HOST [levels] exact counts, or NULL  */
+  uint64_t seed;
+  int batch;                         /* samples per level per GPU batch      */
+  mgm_solve_params solve;
+} mgm_trace_params;
+
+typedef struct {
+  double tau[2];                       /* the estimate of tr(D^{-1})          */
+  double tau_exact[2];                 /* directly computed coarsest part     */
+  int nstoch;                          /* stochastic levels                   */
+  double lvl_mean[MGM_MAX_LEVELS][2];
+  double lvl_lr[MGM_MAX_LEVELS][2];    /* Hutch++ low-rank parts              */
+  double lvl_var[MGM_MAX_LEVELS];
+  double lvl_cost[MGM_MAX_LEVELS];
+  int lvl_samples[MGM_MAX_LEVELS];
+  int64_t lvl_solves[MGM_MAX_LEVELS];  /* solves on D_l issued (incl. discarded batch tail) */
+  int64_t lvl_iters[MGM_MAX_LEVELS];   /* FGMRES iterations on D_l            */
+  double *sample_dump;                 /* HOST [nstoch][max_dump][2] or NULL  */
+  int max_dump;
+} mgm_trace_result;
+
+int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
+                       mgm_trace_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGMLMC_H */

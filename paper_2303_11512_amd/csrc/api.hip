@@ -1,0 +1,253 @@
+// C ABI of the library (declared in include/mgmlmc.h).  Each entry point
+// validates its arguments, runs on the context's stream and converts internal
+// errors into status codes; nothing here aborts the process.
+#include <cstring>
+
+#include "internal.h"
+
+using namespace mgm;
+
+namespace mgm {
+
+// Solve in chunks of sp.rhs_block right-hand sides (all at once when 0).
+int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
+                  const mgm_solve_params& sp, int* iters, double* relres) {
+  const int blk = (sp.rhs_block > 0 && sp.rhs_block < nrhs) ? sp.rhs_block : nrhs;
+  const int64_t n = g.levels[l]->n;
+  int status = MGM_OK;
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    const int k = std::min(blk, nrhs - r0);
+    const int st = solve_level(c, g, l, k, b + (int64_t)r0 * n, x + (int64_t)r0 * n, sp,
+                               iters ? iters + r0 : nullptr, relres ? relres + r0 : nullptr);
+    if (st != MGM_OK) status = st;
+  }
+  return status;
+}
+
+}  // namespace mgm
+
+namespace {
+
+template <class F>
+int guarded(mgm_ctx* c, F&& f) {
+  if (!c) return MGM_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    const int st = f();
+    if (st == MGM_OK) c->err.clear();
+    return st;
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return MGM_EHIP;
+  }
+}
+
+Gauge& gauge_of(mgm_ctx* c, int id) {
+  require(id >= 0 && id < (int)c->gauges.size() && c->gauges[id], "unknown gauge id");
+  return *c->gauges[id];
+}
+
+Level& level_of(Gauge& g, int level) {
+  require(level >= 0 && level < (int)g.levels.size(),
+          "level out of range (call setup_mg for coarse levels)");
+  return *g.levels[level];
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgm_create(mgm_ctx** out, int device, void* stream) {
+  if (!out) return MGM_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MGM_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return MGM_EHIP;
+  mgm_ctx* c = new mgm_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  *out = c;
+  return MGM_OK;
+}
+
+void mgm_destroy(mgm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* mgm_last_error(const mgm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mgm_set_gauge(mgm_ctx* c, int Lx, int Lt, const void* links, double m0, int bc_t_anti,
+                  int* gauge_id) {
+  return guarded(c, [&] {
+    require(links && gauge_id, "null pointer");
+    require(Lx >= 2 && Lt >= 2 && Lx % 2 == 0 && Lt % 2 == 0, "Lx and Lt must be even and >= 2");
+    auto g = std::make_unique<Gauge>();
+    g->Lx = Lx;
+    g->Lt = Lt;
+    g->m0 = m0;
+    g->anti = bc_t_anti ? 1 : 0;
+    const int64_t cnt = 2 * (int64_t)Lx * Lt;
+    g->links.ensure(sizeof(cd) * cnt);
+    HIPCHK(hipMemcpyAsync(g->links.p, links, sizeof(cd) * cnt, hipMemcpyDeviceToDevice, c->stream));
+    if (g->anti) launch_fold_anti(c->stream, g->links.as<cd>(), Lx, Lt);
+    g->links32.ensure(sizeof(cf) * cnt);
+    launch_convert<float, double>(c->stream, g->links.as<cd>(), g->links32.as<cf>(), cnt);
+    // level 0 exists before any multigrid setup
+    auto L0 = std::make_unique<Level>();
+    L0->Nx = Lx;
+    L0->Nt = Lt;
+    L0->M = 2;
+    L0->sites = (int64_t)Lx * Lt;
+    L0->n = 2 * L0->sites;
+    g->levels.push_back(std::move(L0));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->gauges.push_back(std::move(g));
+    *gauge_id = (int)c->gauges.size() - 1;
+    return MGM_OK;
+  });
+}
+
+int mgm_setup_mg(mgm_ctx* c, int gauge_id, const mgm_mg_params* prm) {
+  return guarded(c, [&] {
+    require(prm != nullptr, "null params");
+    Gauge& g = gauge_of(c, gauge_id);
+    setup_hierarchy(c, g, *prm);
+    return MGM_OK;
+  });
+}
+
+int mgm_level_info(mgm_ctx* c, int gauge_id, int level, int* info) {
+  return guarded(c, [&] {
+    require(info != nullptr, "null pointer");
+    Gauge& g = gauge_of(c, gauge_id);
+    Level& L = level_of(g, level);
+    info[0] = L.Nx;
+    info[1] = L.Nt;
+    info[2] = L.M;
+    info[3] = (int)L.n;
+    return MGM_OK;
+  });
+}
+
+int mgm_apply_D(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, void* y) {
+  return guarded(c, [&] {
+    require(x && y && nrhs > 0 && x != y, "bad vectors");
+    Gauge& g = gauge_of(c, gauge_id);
+    level_of(g, level);
+    require(level == 0 || g.mg_ready, "coarse operators need setup_mg", MGM_ESTATE);
+    apply_level(c, g, level, nrhs, static_cast<const cd*>(x), static_cast<cd*>(y));
+    return MGM_OK;
+  });
+}
+
+int mgm_apply_P(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, void* y) {
+  return guarded(c, [&] {
+    require(x && y && nrhs > 0, "bad vectors");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    Level& L = level_of(g, level);
+    require(L.has_coarse, "level has no coarser level");
+    launch_prolong<double>(c->stream, L.d.P.as<cd>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs,
+                           static_cast<const cd*>(x), static_cast<cd*>(y), 0, nullptr);
+    return MGM_OK;
+  });
+}
+
+int mgm_apply_R(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, void* y) {
+  return guarded(c, [&] {
+    require(x && y && nrhs > 0, "bad vectors");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    Level& L = level_of(g, level);
+    require(L.has_coarse, "level has no coarser level");
+    launch_restrict<double>(c->stream, L.d.P.as<cd>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs,
+                            static_cast<const cd*>(x), static_cast<cd*>(y), nullptr);
+    return MGM_OK;
+  });
+}
+
+int mgm_precondition(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* r, void* x) {
+  return guarded(c, [&] {
+    require(r && x && nrhs > 0 && r != x, "bad vectors");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    level_of(g, level);
+    precondition_d(c, g, level, nrhs, static_cast<const cd*>(r), static_cast<cd*>(x), nullptr);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+int mgm_get_prolongator(mgm_ctx* c, int gauge_id, int level, void* out) {
+  return guarded(c, [&] {
+    require(out != nullptr, "null pointer");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    Level& L = level_of(g, level);
+    require(L.has_coarse, "level has no coarser level");
+    HIPCHK(hipMemcpyAsync(out, L.d.P.p, sizeof(cd) * (size_t)L.nagg() * 2 * L.nrow() * L.ntv,
+                          hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+int mgm_coarsest_trace(mgm_ctx* c, int gauge_id, double* out) {
+  return guarded(c, [&] {
+    require(out != nullptr, "null pointer");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    out[0] = g.trL[0];
+    out[1] = g.trL[1];
+    return MGM_OK;
+  });
+}
+
+int mgm_solve_batch(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* b, void* x,
+                    const mgm_solve_params* prm, mgm_solve_stats* stats) {
+  return guarded(c, [&] {
+    require(b && x && prm && nrhs > 0 && b != x, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    level_of(g, level);
+    return solve_chunked(c, g, level, nrhs, static_cast<const cd*>(b), static_cast<cd*>(x), *prm,
+                         stats ? stats->iters : nullptr, stats ? stats->relres : nullptr);
+  });
+}
+
+int mgm_noise(mgm_ctx* c, int kind, uint64_t seed, int purpose, int level, int64_t index0, int64_t n,
+              int nrhs, void* out) {
+  return guarded(c, [&] {
+    require(out && n > 0 && nrhs > 0, "bad arguments");
+    require(kind == MGM_NOISE_RADEMACHER || kind == MGM_NOISE_Z2Z2, "unknown noise kind");
+    require(purpose >= 0 && purpose < 256 && level >= 0 && level < 256, "key field out of range");
+    require(index0 >= 0 && index0 + nrhs <= (int64_t(1) << 48), "index out of range");
+    launch_noise<double>(c->stream, static_cast<cd*>(out), n, nrhs, kind, seed, purpose, level, index0);
+    return MGM_OK;
+  });
+}
+
+int mgm_orthonormalize(mgm_ctx* c, int64_t n, int d, const void* Y, void* Q) {
+  return guarded(c, [&] {
+    require(Y && Q && Y != Q, "bad arguments");
+    orthonormalize(c, n, d, static_cast<const cd*>(Y), static_cast<cd*>(Q));
+    return MGM_OK;
+  });
+}
+
+int mgm_trace_estimate(mgm_ctx* c, int gauge_id, const mgm_trace_params* prm,
+                       mgm_trace_result* res) {
+  return guarded(c, [&] {
+    require(prm && res, "null pointer");
+    Gauge& g = gauge_of(c, gauge_id);
+    return trace_estimate(c, g, *prm, *res);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,560 @@
+// Batched vector kernels for FGMRES (classical Gram-Schmidt applied twice,
+// Givens least squares) and for the CholQR2 orthonormalisation of tall-skinny
+// blocks.  Reductions are deterministic: every workgroup sums a fixed chunk in
+// a fixed order (wave64 butterfly, then the four waves), and a second kernel
+// adds the chunk partials in chunk order.  No atomics.
+#include "internal.h"
+
+namespace mgm {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int EPT = 8;              // elements per thread per chunk
+constexpr int CH = NT * EPT;        // chunk length
+
+inline unsigned nchunks(int64_t n) { return (unsigned)((n + CH - 1) / CH); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of v over the 256 threads, valid in thread 0.  `sh` holds 2*4 values.
+template <class T>
+__device__ __forceinline__ cx<T> block_sum(cx<T> v, T* sh) {
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[2 * w] = v.re;
+    sh[2 * w + 1] = v.im;
+  }
+  __syncthreads();
+  cx<T> r = mk<T>(0, 0);
+  if (threadIdx.x == 0) {
+    r.re = (sh[0] + sh[2]) + (sh[4] + sh[6]);
+    r.im = (sh[1] + sh[3]) + (sh[5] + sh[7]);
+  }
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum_real(T v, T* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+// partial[(r*nv + i)*nch + chunk] = sum_{k in chunk} conj(V_i[r][k]) w[r][k]
+template <class T>
+__global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
+                                                  int nv, const cx<T>* __restrict__ w, int64_t n,
+                                                  cx<T>* __restrict__ partial,
+                                                  const int* __restrict__ active) {
+  __shared__ T sh[8];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int nch = gridDim.x;
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  const cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  cx<T> wv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    wv[e] = (k < n) ? wr[k] : mk<T>(0, 0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cx<T>* __restrict__ vi = V + (int64_t)i * sI + (int64_t)r * sR;
+    cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t k = base + (int64_t)e * NT;
+      if (k < n) cjfma(acc, vi[k], wv[e]);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[((int64_t)r * nv + i) * nch + blockIdx.x] = acc;
+  }
+}
+
+// out[r*ldo + i] (=|+=) sum_chunks partial
+template <class T>
+__global__ void __launch_bounds__(NT) k_reduce_chunks(const cx<T>* __restrict__ partial, int nv, int nch,
+                                                      int nrhs, cx<T>* __restrict__ out, int ldo,
+                                                      int accumulate, const int* __restrict__ active) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)nv * nrhs) return;
+  const int r = (int)(t / nv), i = (int)(t % nv);
+  if (active && !active[r]) return;
+  const cx<T>* p = partial + ((int64_t)r * nv + i) * nch;
+  cx<T> acc = mk<T>(0, 0);
+  for (int c = 0; c < nch; ++c) acc = acc + p[c];
+  cx<T>* o = out + (int64_t)r * ldo + i;
+  *o = accumulate ? (*o + acc) : acc;
+}
+
+// w[r] += sign * sum_i V_i[r] coef[r*ldc + i]; optional partial |w|^2 per chunk
+template <class T>
+__global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
+                                                     int nv, const cx<T>* __restrict__ coef, int ldc,
+                                                     T sign, cx<T>* __restrict__ w, int64_t n,
+                                                     T* __restrict__ partial,
+                                                     const int* __restrict__ active,
+                                                     const int* __restrict__ nlim) {
+  __shared__ cx<T> cs[64];
+  __shared__ T sh[8];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  if (nlim) nv = min(nv, nlim[r]);
+  for (int i = threadIdx.x; i < nv; i += NT) cs[i] = sign * coef[(int64_t)r * ldc + i];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  cx<T> acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    acc[e] = (k < n) ? wr[k] : mk<T>(0, 0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cx<T>* __restrict__ vi = V + (int64_t)i * sI + (int64_t)r * sR;
+    const cx<T> c = cs[i];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t k = base + (int64_t)e * NT;
+      if (k < n) cfma(acc[e], vi[k], c);
+    }
+  }
+  T nrm = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    if (k < n) {
+      wr[k] = acc[e];
+      nrm += abs2(acc[e]);
+    }
+  }
+  if (partial) {
+    nrm = block_sum_real(nrm, sh);
+    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = nrm;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w, int64_t n,
+                                                     T* __restrict__ partial,
+                                                     const int* __restrict__ active) {
+  __shared__ T sh[8];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  const cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  T acc = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    if (k < n) acc += abs2(wr[k]);
+  }
+  acc = block_sum_real(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_norm_reduce(const T* __restrict__ partial, int nch, int nrhs,
+                                                    T* __restrict__ out, const int* __restrict__ active) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs) return;
+  if (active && !active[r]) return;
+  T acc = 0;
+  for (int c = 0; c < nch; ++c) acc += partial[(int64_t)r * nch + c];
+  out[r] = sqrt(acc);
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_scale(const cx<T>* __restrict__ w, const T* __restrict__ den,
+                                              int64_t n, cx<T>* __restrict__ v,
+                                              const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const T d = den[r];
+  const T s = (d > 0) ? (T)1 / d : (T)0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT)
+    v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_axpby(T a, const cx<T>* __restrict__ x, T b,
+                                              const cx<T>* __restrict__ y, cx<T>* __restrict__ z,
+                                              int64_t n, const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+    const int64_t o = (int64_t)r * n + k;
+    const cx<T> yv = y ? y[o] : mk<T>(0, 0);
+    z[o] = a * x[o] + b * yv;
+  }
+}
+
+template <class TO, class TI>
+__global__ void __launch_bounds__(NT) k_convert(const cx<TI>* __restrict__ in, cx<TO>* __restrict__ out,
+                                                int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < count; k += (int64_t)gridDim.x * NT)
+    out[k] = mk<TO>((TO)in[k].re, (TO)in[k].im);
+}
+
+// Arnoldi step j of RHS r: rotate column j of H (H[(r*m + j)*(m+1) + i]) by
+// the previous Givens rotations, form the new one, update g and the residual
+// estimate |g_{j+1}|; stop the RHS when it falls to thr[r], on breakdown, or
+// at the last step.
+template <class T>
+__global__ void __launch_bounds__(NT) k_givens(int j, int m, int nrhs, cx<T>* __restrict__ H,
+                                               T* __restrict__ cs, cx<T>* __restrict__ sn,
+                                               cx<T>* __restrict__ g, const T* __restrict__ thr,
+                                               int* __restrict__ active, int* __restrict__ nit) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
+  T* c = cs + (int64_t)r * m;
+  cx<T>* s = sn + (int64_t)r * m;
+  cx<T>* gr = g + (int64_t)r * (m + 1);
+  for (int i = 0; i < j; ++i) {
+    const cx<T> a = h[i], b = h[i + 1];
+    h[i] = c[i] * a + s[i] * b;
+    h[i + 1] = c[i] * b - conj(s[i]) * a;
+  }
+  const cx<T> a = h[j], b = h[j + 1];
+  const T na = sqrt(abs2(a)), nb = sqrt(abs2(b));
+  const T rho = sqrt(na * na + nb * nb);
+  T cj;
+  cx<T> sj;
+  if (na == (T)0) {
+    cj = 0;
+    sj = mk<T>(1, 0);
+    h[j] = b;
+  } else {
+    cj = na / rho;
+    const cx<T> ph = mk<T>(a.re / na, a.im / na);
+    sj = ph * conj(b);
+    sj = mk<T>(sj.re / rho, sj.im / rho);
+    h[j] = rho * ph;
+  }
+  h[j + 1] = mk<T>(0, 0);
+  c[j] = cj;
+  s[j] = sj;
+  const cx<T> gj = gr[j];
+  gr[j] = cj * gj;
+  gr[j + 1] = (T)-1 * (conj(sj) * gj);
+  nit[r] = j + 1;
+  const T res = sqrt(abs2(gr[j + 1]));
+  if (res <= thr[r] || nb == (T)0 || j + 1 == m) active[r] = 0;
+}
+
+// Hessenberg column j of RHS r: entries 0..j = c1 + c2 (the two Gram-Schmidt
+// passes), entry j+1 = ||w||.
+template <class T>
+__global__ void __launch_bounds__(NT) k_hcol(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
+                                             const cx<T>* __restrict__ c2, const T* __restrict__ hn,
+                                             cx<T>* __restrict__ H, const int* __restrict__ active) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs || (active && !active[r])) return;
+  cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
+  for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
+  h[j + 1] = mk<T>(hn[r], 0);
+}
+
+// y = R^{-1} g with R the rotated (upper triangular) H of nit[r] steps
+template <class T>
+__global__ void __launch_bounds__(NT) k_backsolve(int m, int nrhs, const cx<T>* __restrict__ H,
+                                                  const cx<T>* __restrict__ g,
+                                                  const int* __restrict__ nit, cx<T>* __restrict__ y) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs) return;
+  const int k = nit[r];
+  cx<T>* yr = y + (int64_t)r * m;
+  const cx<T>* Hr = H + (int64_t)r * m * (m + 1);
+  const cx<T>* gr = g + (int64_t)r * (m + 1);
+  for (int i = k; i < m; ++i) yr[i] = mk<T>(0, 0);
+  for (int i = k - 1; i >= 0; --i) {
+    cx<T> acc = gr[i];
+    for (int l = i + 1; l < k; ++l) acc = acc - Hr[(int64_t)l * (m + 1) + i] * yr[l];
+    yr[i] = cdiv(acc, Hr[(int64_t)i * (m + 1) + i]);
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_fgmres_init(int nrhs, const T* __restrict__ beta,
+                                                    const int* __restrict__ parent,
+                                                    const int* __restrict__ done, T tol,
+                                                    const T* __restrict__ bnorm, int m,
+                                                    int* __restrict__ active, int* __restrict__ nit,
+                                                    cx<T>* __restrict__ g, T* __restrict__ thr) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs) return;
+  const bool on = (!parent || parent[r]) && (!done || !done[r]) && beta[r] > (T)0;
+  active[r] = on ? 1 : 0;
+  nit[r] = 0;
+  g[(int64_t)r * (m + 1)] = mk<T>(on ? beta[r] : (T)0, 0);
+  thr[r] = tol * (bnorm ? bnorm[r] : beta[r]);
+}
+
+// ------------------------------------------------------------------ CholQR2 pieces
+// partial[chunk][i][j] = sum_{k in chunk} conj(Y_i[k]) Y_j[k], d <= 64
+constexpr int GS = 32;     // elements per LDS stage
+constexpr int GCH = 512;   // elements per chunk
+__global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, int64_t n, int d,
+                                                     cd* __restrict__ partial) {
+  __shared__ cd Ys[64][GS + 1];
+  const int tid = threadIdx.x;
+  const int npair = d * d;
+  cd acc[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) acc[p] = mk(0.0, 0.0);
+  const int64_t c0 = (int64_t)blockIdx.x * GCH;
+  for (int64_t s0 = c0; s0 < c0 + GCH && s0 < n; s0 += GS) {
+    for (int e = tid; e < d * GS; e += NT) {
+      const int i = e / GS, kk = e % GS;
+      const int64_t k = s0 + kk;
+      Ys[i][kk] = (k < n) ? Y[(int64_t)i * n + k] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int pr = tid + p * NT;
+      if (pr < npair) {
+        const int i = pr / d, j = pr % d;
+        for (int kk = 0; kk < GS; ++kk) cjfma(acc[p], Ys[i][kk], Ys[j][kk]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int pr = tid + p * NT;
+    if (pr < npair) partial[(int64_t)blockIdx.x * npair + pr] = acc[p];
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ partial, int nch, int d,
+                                                    cd* __restrict__ G) {
+  const int pr = blockIdx.x * NT + threadIdx.x;
+  if (pr >= d * d) return;
+  cd acc = mk(0.0, 0.0);
+  for (int c = 0; c < nch; ++c) acc = acc + partial[(int64_t)c * d * d + pr];
+  G[pr] = acc;
+}
+
+// G + shift * tr(G)/d * I = R^H R (R upper, positive real diagonal); on exit G
+// holds R^{-1} (upper).
+__global__ void k_cholesky_rinv(cd* __restrict__ G, cd* __restrict__ R, int d, double shift,
+                                int* __restrict__ fail) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (shift > 0.0) {
+    double tr = 0.0;
+    for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
+    for (int j = 0; j < d; ++j) G[j * d + j].re += shift * tr;
+  }
+  for (int j = 0; j < d; ++j)
+    for (int i = 0; i < d; ++i) R[j * d + i] = mk(0.0, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double s = G[j * d + j].re;
+    for (int k = 0; k < j; ++k) s -= abs2(R[k * d + j]);
+    if (!(s > 0.0)) {
+      *fail = 1;
+      return;
+    }
+    const double rjj = sqrt(s);
+    R[j * d + j] = mk(rjj, 0.0);
+    for (int i = j + 1; i < d; ++i) {
+      cd t = G[j * d + i];
+      for (int k = 0; k < j; ++k) t = t - cjmul(R[k * d + j], R[k * d + i]);
+      R[j * d + i] = mk(t.re / rjj, t.im / rjj);
+    }
+  }
+  // upper-triangular inverse, column by column
+  for (int j = 0; j < d; ++j)
+    for (int i = 0; i < d; ++i) G[i * d + j] = mk(0.0, 0.0);
+  for (int j = 0; j < d; ++j) {
+    const double rjj = R[j * d + j].re;
+    G[j * d + j] = mk(1.0 / rjj, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      cd t = mk(0.0, 0.0);
+      for (int k = i; k < j; ++k) cfma(t, G[i * d + k], R[k * d + j]);
+      G[i * d + j] = mk(-t.re / rjj, -t.im / rjj);
+    }
+  }
+}
+
+// Q_j[k] = sum_{i <= j} Y_i[k] Rinv[i][j]
+__global__ void __launch_bounds__(NT) k_right_tri(const cd* __restrict__ Y, const cd* __restrict__ Rinv,
+                                                  int64_t n, int d, cd* __restrict__ Q) {
+  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  for (int j = 0; j < d; ++j) {
+    cd acc = mk(0.0, 0.0);
+    for (int i = 0; i <= j; ++i) cfma(acc, Y[(int64_t)i * n + k], Rinv[i * d + j]);
+    Q[(int64_t)j * n + k] = acc;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+// out[r*ldo + i] (=|+=) V_i[r]^H w[r]
+template <class T>
+void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
+                         const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
+                         const int* active, cx<T>* partial) {
+  if (nv <= 0) return;
+  const unsigned nch = nchunks(n);
+  hipLaunchKernelGGL(k_dot_multi<T>, dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv, w, n, partial,
+                     active);
+  KCHK();
+  const int64_t tot = (int64_t)nv * nrhs;
+  hipLaunchKernelGGL(k_reduce_chunks<T>, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, s, partial,
+                     nv, (int)nch, nrhs, out, ldo, accumulate, active);
+  KCHK();
+}
+
+template <class T>
+void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
+                         const cx<T>* coef, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                         const int* active, T* norm_out, T* partial, const int* nlim) {
+  require(nv <= 64, "update_multi: at most 64 vectors");
+  if (nv <= 0) return;
+  const unsigned nch = nchunks(n);
+  hipLaunchKernelGGL(k_update_multi<T>, dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv, coef, ldc,
+                     sign, w, n, norm_out ? partial : (T*)nullptr, active, nlim);
+  KCHK();
+  if (norm_out) {
+    hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
+                       nrhs, norm_out, active);
+    KCHK();
+  }
+}
+
+template <class T>
+void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
+                 T* partial) {
+  const unsigned nch = nchunks(n);
+  hipLaunchKernelGGL(k_norm_partial<T>, dim3(nch, nrhs), dim3(NT), 0, s, w, n, partial, active);
+  KCHK();
+  hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
+                     nrhs, out, active);
+  KCHK();
+}
+
+template <class T>
+void launch_scale(hipStream_t s, const cx<T>* w, const T* den, int64_t n, int nrhs, cx<T>* v,
+                  const int* active) {
+  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_scale<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, den, n, v, active);
+  KCHK();
+}
+
+template <class T>
+void launch_axpby(hipStream_t s, T a, const cx<T>* x, T b, const cx<T>* y, cx<T>* z, int64_t n,
+                  int nrhs, const int* active) {
+  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_axpby<T>, dim3(gx, nrhs), dim3(NT), 0, s, a, x, b, y, z, n, active);
+  KCHK();
+}
+
+template <class TO, class TI>
+void launch_convert(hipStream_t s, const cx<TI>* in, cx<TO>* out, int64_t count) {
+  unsigned gx = (unsigned)std::min<int64_t>((count + NT - 1) / NT, 65535);
+  hipLaunchKernelGGL((k_convert<TO, TI>), dim3(gx), dim3(NT), 0, s, in, out, count);
+  KCHK();
+}
+
+template <class T>
+void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g,
+                   const T* thr, int* active, int* nit) {
+  hipLaunchKernelGGL(k_givens<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, j, m, nrhs, H, cs, sn, g,
+                     thr, active, nit);
+  KCHK();
+}
+
+template <class T>
+void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
+                 cx<T>* H, const int* active) {
+  hipLaunchKernelGGL(k_hcol<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, j, m, nrhs, c1, c2, hn, H,
+                     active);
+  KCHK();
+}
+
+template <class T>
+void launch_backsolve(hipStream_t s, int m, int nrhs, const cx<T>* H, const cx<T>* g, const int* nit,
+                      cx<T>* y) {
+  hipLaunchKernelGGL(k_backsolve<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, m, nrhs, H, g, nit, y);
+  KCHK();
+}
+
+template <class T>
+void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
+                        T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr) {
+  hipLaunchKernelGGL(k_fgmres_init<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, nrhs, beta, parent,
+                     done, tol, bnorm, m, active, nit, g, thr);
+  KCHK();
+}
+
+void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial) {
+  require(d >= 1 && d <= 64, "orthonormalize: 1 <= d <= 64");
+  const unsigned nch = (unsigned)((n + GCH - 1) / GCH);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nch), dim3(NT), 0, s, Y, n, d, partial);
+  KCHK();
+  hipLaunchKernelGGL(k_gram_reduce, dim3((d * d + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch, d, G);
+  KCHK();
+}
+
+int cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev) {
+  DevBuf R;
+  R.ensure(sizeof(cd) * d * d);
+  HIPCHK(hipMemsetAsync(fail_dev, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_cholesky_rinv, dim3(1), dim3(64), 0, s, G, R.as<cd>(), d, shift, fail_dev);
+  KCHK();
+  int fail = 0;
+  HIPCHK(hipMemcpyAsync(&fail, fail_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return fail;
+}
+
+void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int d, cd* Q) {
+  hipLaunchKernelGGL(k_right_tri, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, Y, Rinv, n, d, Q);
+  KCHK();
+}
+
+#define INST(T)                                                                                   \
+  template void launch_dot_multi_ld<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
+                                       const cx<T>*, int64_t, int, cx<T>*, int, int, const int*,  \
+                                       cx<T>*);                                                   \
+  template void launch_update_multi<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
+                                       const cx<T>*, int, T, cx<T>*, int64_t, int, const int*, T*, \
+                                       T*, const int*);                                           \
+  template void launch_hcol<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*, const T*,   \
+                               cx<T>*, const int*);                                               \
+  template void launch_norm<T>(hipStream_t, const cx<T>*, int64_t, int, T*, const int*, T*);       \
+  template void launch_scale<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,         \
+                                const int*);                                                      \
+  template void launch_axpby<T>(hipStream_t, T, const cx<T>*, T, const cx<T>*, cx<T>*, int64_t, int, \
+                                const int*);                                                      \
+  template void launch_givens<T>(hipStream_t, int, int, int, cx<T>*, T*, cx<T>*, cx<T>*, const T*, \
+                                 int*, int*);                                                     \
+  template void launch_backsolve<T>(hipStream_t, int, int, const cx<T>*, const cx<T>*, const int*, \
+                                    cx<T>*);                                                      \
+  template void launch_fgmres_init<T>(hipStream_t, int, const T*, const int*, const int*, T,       \
+                                      const T*, int, int*, int*, cx<T>*, T*);
+INST(double)
+INST(float)
+#undef INST
+template void launch_convert<float, double>(hipStream_t, const cd*, cf*, int64_t);
+template void launch_convert<double, float>(hipStream_t, const cf*, cd*, int64_t);
+
+}  // namespace mgm

@@ -1,0 +1,274 @@
+// Internal types and kernel launchers of the MG-MLMC++ library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mgmlmc.h"
+
+namespace mgm {
+
+// ---------------------------------------------------------------- complex
+template <class T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+using cd = cx<double>;
+using cf = cx<float>;
+
+template <class T>
+__host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
+  return cx<T>{a, b};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return {s * a.re, s * a.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> conj(cx<T> a) {
+  return {a.re, -a.im};
+}
+// conj(a) * b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// acc += a * b
+template <class T>
+__host__ __device__ __forceinline__ void cfma(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += conj(a) * b
+template <class T>
+__host__ __device__ __forceinline__ void cjfma(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+template <class T>
+__host__ __device__ __forceinline__ T abs2(cx<T> a) {
+  return a.re * a.re + a.im * a.im;
+}
+// a / b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
+  T d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw ::mgm::Error(e_ == hipErrorOutOfMemory ? MGM_ENOMEM : MGM_EHIP,          \
+                         std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define KCHK() HIPCHK(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg, int code = MGM_EINVAL) {
+  if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------- memory
+// Owning device buffer (freed with hipFree; never used for host memory).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    release();
+    HIPCHK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// ---------------------------------------------------------------- noise
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+template <class T>
+void launch_noise(hipStream_t s, cx<T>* out, int64_t n, int nrhs, int kind, uint64_t seed,
+                  int purpose, int level, int64_t index0);
+
+// ---------------------------------------------------------------- level operators
+// Direction order of the block stencil: 0 self, 1 +x, 2 -x, 3 +t, 4 -t.
+template <class T>
+void launch_wilson(hipStream_t s, const cx<T>* links, T diag, int Lx, int Lt, int nrhs,
+                   const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active);
+void launch_fine_blocks(hipStream_t s, const cd* links, double diag, int Lx, int Lt, cd* blocks);
+void launch_fold_anti(hipStream_t s, cd* links, int Lx, int Lt);
+template <class T>
+void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, int nrhs,
+                    const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active);
+template <class T>
+void launch_restrict(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
+                     int nrhs, const cx<T>* xf, cx<T>* xc, const int* active);
+template <class T>
+void launch_prolong(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
+                    int nrhs, const cx<T>* xc, cx<T>* yf, int accumulate, const int* active);
+void launch_galerkin(hipStream_t s, const cd* Bf, int Nx, int Nt, int Mf, const cd* P, int bx,
+                     int bt, int ntv, cd* Bc);
+void launch_sap_extract(hipStream_t s, const cd* B, int Nx, int Nt, int M, int sbx, int sbt,
+                        cd* blocks_out);
+void launch_small_inverse(hipStream_t s, cd* mats, int K, int count, int* fail);
+template <class T>
+void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, int Nt, int M,
+                      int sbx, int sbt, const int* blist, int nb, int nrhs, const cx<T>* r,
+                      cx<T>* x, const int* active);
+void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M, cd* A);
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A.
+int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* scratch_out);
+void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out);
+template <class T>
+void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, const cx<T>* x,
+                        cx<T>* y, const int* active);
+
+// ---------------------------------------------------------------- batched BLAS
+// V_i of RHS r sits at V + i*sI + r*sR (complex elements).
+template <class T>
+void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
+                         const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
+                         const int* active, cx<T>* partial);
+// number of chunk partials a reduction over n elements produces
+inline int64_t reduce_chunks(int64_t n) { return (n + 2047) / 2048; }
+// w[r] += sign * sum_{i < min(nv, nlim[r])} V_i[r] coef[r*ldc + i]; optional ||w||
+template <class T>
+void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
+                         const cx<T>* coef, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                         const int* active, T* norm_out, T* partial, const int* nlim = nullptr);
+template <class T>
+void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
+                 cx<T>* H, const int* active);
+template <class T>
+void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
+                 T* partial);
+template <class T>
+void launch_scale(hipStream_t s, const cx<T>* w, const T* den, int64_t n, int nrhs, cx<T>* v,
+                  const int* active);
+template <class T>
+void launch_axpby(hipStream_t s, T a, const cx<T>* x, T b, const cx<T>* y, cx<T>* z, int64_t n,
+                  int nrhs, const int* active);
+template <class TO, class TI>
+void launch_convert(hipStream_t s, const cx<TI>* in, cx<TO>* out, int64_t count);
+template <class T>
+void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g,
+                   const T* thr, int* active, int* nit);
+template <class T>
+void launch_backsolve(hipStream_t s, int m, int nrhs, const cx<T>* H, const cx<T>* g,
+                      const int* nit, cx<T>* y);
+template <class T>
+void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
+                        T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr);
+void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial);
+int cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev);
+void launch_local_qr(hipStream_t s, const cd* V, int64_t n, int Nx, int Nt, int M, int bx, int bt,
+                     int ntv, cd* P);
+void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int d, cd* Q);
+
+// ---------------------------------------------------------------- context
+template <class T>
+struct LevelData {
+  DevBuf blocks;   // [sites][5][M][M]
+  DevBuf P;        // [nagg][2][nrow][ntv]   (level -> level+1)
+  DevBuf sapinv;   // [nblk][K][K]
+  DevBuf dinv;     // coarsest: [n][n]
+  const cx<T>* B() const { return blocks.as<cx<T>>(); }
+};
+
+template <class T>
+struct Work {  // FGMRES + multigrid workspace of one level in one precision
+  int cap = 0, mcap = 0;
+  int64_t n = 0;
+  DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, coef, coef2;
+  DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
+};
+
+struct Level {
+  int Nx = 0, Nt = 0, M = 0;
+  int64_t sites = 0, n = 0;
+  int bx = 0, bt = 0, ntv = 0;  // aggregation to level+1 (0 on the coarsest)
+  int sbx = 0, sbt = 0, K = 0, nblk = 0, sap_cycles = 0, inner_iters = 0;
+  bool has_coarse = false, is_coarsest = false;
+  DevBuf color_list[2];
+  int ncolor[2] = {0, 0};
+  LevelData<double> d;
+  LevelData<float> f;
+  Work<double> wd;
+  Work<float> wf;
+  int64_t nrow() const { return (int64_t)bx * bt * (M / 2); }
+  int64_t nagg() const { return bx ? (int64_t)(Nx / bx) * (Nt / bt) : 0; }
+};
+
+struct Gauge {
+  int Lx = 0, Lt = 0, anti = 1;
+  double m0 = 0;
+  DevBuf links;    // complex128 [2][Lt][Lx], t-boundary sign folded in
+  DevBuf links32;  // complex64 copy
+  std::vector<std::unique_ptr<Level>> levels;
+  bool mg_ready = false;
+  mgm_mg_params prm{};
+  double trL[2] = {0, 0};
+};
+
+}  // namespace mgm
+
+struct mgm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<std::unique_ptr<mgm::Gauge>> gauges;
+  mgm::DevBuf scratch, scratch2, scratch3, ibuf;
+};
+
+namespace mgm {
+// host-side solver entry points (solver.hip)
+void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act);
+int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
+                const mgm_solve_params& sp, int* iters_out, double* relres_out);
+void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y);
+void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p);
+void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q);
+int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r);
+}  // namespace mgm

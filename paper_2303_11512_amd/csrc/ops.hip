@@ -1,0 +1,851 @@
+// Level operators of the multigrid hierarchy on gfx950: the fine Schwinger
+// (2D Wilson-Dirac, U(1)) stencil, the Galerkin block stencil of the coarse
+// levels, restriction/prolongation, the SAP smoother, the coarsest dense
+// inverse, and the counter-based noise.
+//
+// Vectors are complex [nrhs][n] with n = sites * M (M dofs per site, site
+// index t * Nx + x).  The block stencil stores, per site u, five M x M blocks
+// B[u][d] (d = 0 self, 1 +x, 2 -x, 3 +t, 4 -t) with
+//     (D x)_u = sum_d B[u][d] x_{nb(u, d)},   periodic neighbours.
+#include "internal.h"
+
+namespace mgm {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ int64_t nb_site(int64_t u, int d, int Nx, int Nt) {
+  int x = (int)(u % Nx), t = (int)(u / Nx);
+  switch (d) {
+    case 1: x = (x + 1 == Nx) ? 0 : x + 1; break;
+    case 2: x = (x == 0) ? Nx - 1 : x - 1; break;
+    case 3: t = (t + 1 == Nt) ? 0 : t + 1; break;
+    case 4: t = (t == 0) ? Nt - 1 : t - 1; break;
+    default: break;
+  }
+  return (int64_t)t * Nx + x;
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+// ------------------------------------------------------------------ noise
+// SplitMix64 counter stream: key = mix64(seed + golden) ^ purpose<<56 ^
+// level<<48 ^ index; word_i = mix64(mix64(key) + (i+1) golden).  Bit 63 is the
+// sign of the real part, bit 62 of the imaginary part.
+template <class T>
+__global__ void __launch_bounds__(NT) k_noise(cx<T>* out, int64_t n, int kind, uint64_t base,
+                                              int purpose, int level, int64_t index0) {
+  const int r = blockIdx.y;
+  const uint64_t key = base ^ ((uint64_t)purpose << 56) ^ ((uint64_t)level << 48) ^
+                       (uint64_t)(index0 + r);
+  const uint64_t s0 = mix64(key);
+  const T h = (T)0.70710678118654752440;  // sqrt(1/2)
+  cx<T>* o = out + (int64_t)r * n;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const uint64_t w = mix64(s0 + (uint64_t)(i + 1) * kGolden);
+    const bool re_neg = (w >> 63) & 1ull;
+    if (kind == MGM_NOISE_RADEMACHER) {
+      o[i] = mk<T>(re_neg ? (T)-1 : (T)1, (T)0);
+    } else {
+      const bool im_neg = (w >> 62) & 1ull;
+      o[i] = mk<T>(re_neg ? -h : h, im_neg ? -h : h);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fine Wilson
+// (D psi)(x) = (m0+2) psi(x) - 1/2 sum_mu [(1 - sigma_mu) U_mu(x) psi(x+mu)
+//              + (1 + sigma_mu) U_mu(x-mu)^* psi(x-mu)],
+// sigma_0 = Pauli x, sigma_1 = Pauli y.  Each (1 -+ sigma_mu) has rank one, so
+// every hop moves one complex number h (spin projection):
+//   +x: h = c0 - c1, contributes (-h/2, +h/2) * U
+//   -x: h = c0 + c1, contributes (-h/2, -h/2) * U^*
+//   +t: h = c0 + i c1, contributes (-h/2, +i h/2) * U
+//   -t: h = c0 - i c1, contributes (-h/2, -i h/2) * U^*
+// The antiperiodic t boundary is folded into the links.  y = D x, or
+// y = b - D x when b is given.
+template <class T>
+__global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T diag, int Lx, int Lt,
+                                               const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                               const cx<T>* __restrict__ b,
+                                               const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t V = (int64_t)Lx * Lt;
+  const int64_t site = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (site >= V) return;
+  const int xx = (int)(site % Lx), tt = (int)(site / Lx);
+  const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
+  const int64_t sxp = (int64_t)tt * Lx + (xx + 1 == Lx ? 0 : xx + 1);
+  const int64_t sxm = (int64_t)tt * Lx + (xx == 0 ? Lx - 1 : xx - 1);
+  const int64_t stp = (int64_t)(tt + 1 == Lt ? 0 : tt + 1) * Lx + xx;
+  const int64_t stm = (int64_t)(tt == 0 ? Lt - 1 : tt - 1) * Lx + xx;
+  const cx<T>* __restrict__ U0 = U;
+  const cx<T>* __restrict__ U1 = U + V;
+  const T half = (T)0.5;
+
+  cx<T> a0 = diag * xr[2 * site];
+  cx<T> a1 = diag * xr[2 * site + 1];
+  {
+    const cx<T> c0 = xr[2 * sxp], c1 = xr[2 * sxp + 1];
+    const cx<T> h = U0[site] * (c0 - c1);
+    a0 = a0 - half * h;
+    a1 = a1 + half * h;
+  }
+  {
+    const cx<T> c0 = xr[2 * sxm], c1 = xr[2 * sxm + 1];
+    const cx<T> h = cjmul(U0[sxm], c0 + c1);
+    a0 = a0 - half * h;
+    a1 = a1 - half * h;
+  }
+  {
+    const cx<T> c0 = xr[2 * stp], c1 = xr[2 * stp + 1];
+    const cx<T> h = U1[site] * mk<T>(c0.re - c1.im, c0.im + c1.re);
+    a0 = a0 - half * h;
+    a1 = a1 + half * mk<T>(-h.im, h.re);
+  }
+  {
+    const cx<T> c0 = xr[2 * stm], c1 = xr[2 * stm + 1];
+    const cx<T> h = cjmul(U1[stm], mk<T>(c0.re + c1.im, c0.im - c1.re));
+    a0 = a0 - half * h;
+    a1 = a1 - half * mk<T>(-h.im, h.re);
+  }
+  cx<T>* yr = y + (int64_t)r * 2 * V;
+  if (b) {
+    const cx<T>* br = b + (int64_t)r * 2 * V;
+    a0 = br[2 * site] - a0;
+    a1 = br[2 * site + 1] - a1;
+  }
+  yr[2 * site] = a0;
+  yr[2 * site + 1] = a1;
+}
+
+// The fine operator written as a block stencil (2x2 blocks), for the setup.
+__global__ void __launch_bounds__(NT) k_fine_blocks(const cd* __restrict__ U, double diag, int Lx,
+                                                    int Lt, cd* __restrict__ B) {
+  const int64_t V = (int64_t)Lx * Lt;
+  const int64_t u = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (u >= V) return;
+  const cd* U0 = U;
+  const cd* U1 = U + V;
+  cd* o = B + u * 20;  // [5][2][2]
+  const cd z = mk(0.0, 0.0);
+  // self
+  o[0] = mk(diag, 0.0); o[1] = z; o[2] = z; o[3] = mk(diag, 0.0);
+  // +x: -1/2 U [[1,-1],[-1,1]]
+  {
+    const cd h = -0.5 * U0[u];
+    o[4] = h; o[5] = -1.0 * h; o[6] = -1.0 * h; o[7] = h;
+  }
+  // -x: -1/2 U(u-x)^* [[1,1],[1,1]]
+  {
+    const cd h = -0.5 * conj(U0[nb_site(u, 2, Lx, Lt)]);
+    o[8] = h; o[9] = h; o[10] = h; o[11] = h;
+  }
+  // +t: -1/2 U [[1, i],[-i, 1]]
+  {
+    const cd h = -0.5 * U1[u];
+    o[12] = h; o[13] = mk(-h.im, h.re); o[14] = mk(h.im, -h.re); o[15] = h;
+  }
+  // -t: -1/2 U(u-t)^* [[1, -i],[i, 1]]
+  {
+    const cd h = -0.5 * conj(U1[nb_site(u, 4, Lx, Lt)]);
+    o[16] = h; o[17] = mk(h.im, -h.re); o[18] = mk(-h.im, h.re); o[19] = h;
+  }
+}
+
+// ------------------------------------------------------------------ block stencil
+// One thread per (site, row i); blockIdx.y = RHS.
+template <class T, int M>
+__global__ void __launch_bounds__(NT) k_stencil(const cx<T>* __restrict__ B, int Nx, int Nt,
+                                                const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                const cx<T>* __restrict__ b,
+                                                const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t sites = (int64_t)Nx * Nt;
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= sites * M) return;
+  const int64_t u = idx / M;
+  const int i = (int)(idx % M);
+  const int64_t n = sites * M;
+  const cx<T>* __restrict__ xr = x + (int64_t)r * n;
+  cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    const cx<T>* __restrict__ row = B + ((u * 5 + d) * M + i) * M;
+    const cx<T>* __restrict__ xv = xr + nb_site(u, d, Nx, Nt) * M;
+#pragma unroll
+    for (int j = 0; j < M; ++j) cfma(acc, row[j], xv[j]);
+  }
+  if (b) acc = b[(int64_t)r * n + idx] - acc;
+  y[(int64_t)r * n + idx] = acc;
+}
+
+// ------------------------------------------------------------------ restriction / prolongation
+// P[A][c][s][k]: row s of aggregate A, chirality c -- site sl = s / Mh of the
+// aggregate (t-major), dof c*Mh + s % Mh of that site; column k.
+__device__ __forceinline__ int64_t agg_row(int64_t A, int c, int s, int Nx, int M, int bx, int bt,
+                                           int NAx) {
+  const int Mh = M / 2;
+  const int sl = s / Mh, a = s % Mh;
+  const int dx = sl % bx, dt = sl / bx;
+  const int Ax = (int)(A % NAx), At = (int)(A / NAx);
+  const int64_t site = (int64_t)(At * bt + dt) * Nx + (Ax * bx + dx);
+  return site * M + c * Mh + a;
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_restrict(const cx<T>* __restrict__ P, int Nx, int Nt, int M,
+                                                 int bx, int bt, int ntv, const cx<T>* __restrict__ xf,
+                                                 cx<T>* __restrict__ xc,
+                                                 const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int NAx = Nx / bx;
+  const int64_t nagg = (int64_t)NAx * (Nt / bt);
+  const int64_t nc = nagg * 2 * ntv;
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nc) return;
+  const int64_t A = idx / (2 * ntv);
+  const int c = (int)((idx / ntv) % 2);
+  const int k = (int)(idx % ntv);
+  const int nrow = bx * bt * (M / 2);
+  const cx<T>* __restrict__ xr = xf + (int64_t)r * Nx * Nt * M;
+  const cx<T>* __restrict__ Pc = P + ((A * 2 + c) * nrow) * ntv + k;
+  cx<T> acc = mk<T>(0, 0);
+  for (int s = 0; s < nrow; ++s) cjfma(acc, Pc[(int64_t)s * ntv], xr[agg_row(A, c, s, Nx, M, bx, bt, NAx)]);
+  xc[(int64_t)r * nc + idx] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_prolong(const cx<T>* __restrict__ P, int Nx, int Nt, int M,
+                                                int bx, int bt, int ntv, const cx<T>* __restrict__ xc,
+                                                cx<T>* __restrict__ yf, int accumulate,
+                                                const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t n = (int64_t)Nx * Nt * M;
+  const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (row >= n) return;
+  const int NAx = Nx / bx;
+  const int64_t nc = (int64_t)NAx * (Nt / bt) * 2 * ntv;
+  const int Mh = M / 2;
+  const int64_t site = row / M;
+  const int alpha = (int)(row % M);
+  const int c = alpha / Mh, a = alpha % Mh;
+  const int sx = (int)(site % Nx), st = (int)(site / Nx);
+  const int64_t A = (int64_t)(st / bt) * NAx + sx / bx;
+  const int sl = (st % bt) * bx + (sx % bx);
+  const int s = sl * Mh + a;
+  const int nrow = bx * bt * Mh;
+  const cx<T>* __restrict__ Pr = P + ((A * 2 + c) * nrow + s) * ntv;
+  const cx<T>* __restrict__ xv = xc + (int64_t)r * nc + (A * 2 + c) * ntv;
+  cx<T> acc = mk<T>(0, 0);
+  for (int k = 0; k < ntv; ++k) cfma(acc, Pr[k], xv[k]);
+  cx<T>* o = yf + (int64_t)r * n + row;
+  *o = accumulate ? (*o + acc) : acc;
+}
+
+// ------------------------------------------------------------------ Galerkin
+// Bc[A][D][I][J] = sum over hops (u, d) of aggregate A that land in the
+// aggregate nbA(A, D) (D = 0: hops that stay inside A, including the self
+// block) of conj(P_A[u, I]) Bf[u][d] P_{nbA}[v, J],  v = nb(u, d).
+__global__ void __launch_bounds__(NT) k_galerkin(const cd* __restrict__ Bf, int Nx, int Nt, int Mf,
+                                                 const cd* __restrict__ P, int bx, int bt, int ntv,
+                                                 cd* __restrict__ Bc) {
+  const int Mc = 2 * ntv;
+  const int NAx = Nx / bx, NAt = Nt / bt;
+  const int64_t nagg = (int64_t)NAx * NAt;
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nagg * 5 * Mc * Mc) return;
+  const int J = (int)(idx % Mc);
+  const int I = (int)((idx / Mc) % Mc);
+  const int D = (int)((idx / (Mc * Mc)) % 5);
+  const int64_t A = idx / (5 * Mc * Mc);
+  const int c = I / ntv, k = I % ntv, c2 = J / ntv, k2 = J % ntv;
+  const int Ax = (int)(A % NAx), At = (int)(A / NAx);
+  int Bx = Ax, Bt = At;
+  if (D == 1) Bx = (Ax + 1 == NAx) ? 0 : Ax + 1;
+  if (D == 2) Bx = (Ax == 0) ? NAx - 1 : Ax - 1;
+  if (D == 3) Bt = (At + 1 == NAt) ? 0 : At + 1;
+  if (D == 4) Bt = (At == 0) ? NAt - 1 : At - 1;
+  const int64_t An = (int64_t)Bt * NAx + Bx;
+  const int Mh = Mf / 2;
+  const int nrow = bx * bt * Mh;
+  const cd* __restrict__ PA = P + (A * 2 + c) * nrow * ntv;
+  const cd* __restrict__ PB = P + (An * 2 + c2) * nrow * ntv;
+  cd acc = mk(0.0, 0.0);
+  for (int dt = 0; dt < bt; ++dt) {
+    for (int dx = 0; dx < bx; ++dx) {
+      const int64_t u = (int64_t)(At * bt + dt) * Nx + (Ax * bx + dx);
+      const int sl = dt * bx + dx;
+      for (int d = 0; d < 5; ++d) {
+        int route = 0;
+        if (d == 1 && dx == bx - 1) route = 1;
+        if (d == 2 && dx == 0) route = 2;
+        if (d == 3 && dt == bt - 1) route = 3;
+        if (d == 4 && dt == 0) route = 4;
+        if (route != D) continue;
+        const int64_t v = nb_site(u, d, Nx, Nt);
+        const int vsl = (int)((v / Nx) % bt) * bx + (int)((v % Nx) % bx);
+        const cd* __restrict__ Bud = Bf + (u * 5 + d) * Mf * Mf;
+        for (int a = 0; a < Mh; ++a) {
+          const cd pu = PA[(int64_t)(sl * Mh + a) * ntv + k];
+          cd t = mk(0.0, 0.0);
+          for (int bb = 0; bb < Mh; ++bb) {
+            const cd pv = PB[(int64_t)(vsl * Mh + bb) * ntv + k2];
+            cfma(t, Bud[(int64_t)(c * Mh + a) * Mf + c2 * Mh + bb], pv);
+          }
+          cjfma(acc, pu, t);
+        }
+      }
+    }
+  }
+  Bc[idx] = acc;
+}
+
+// ------------------------------------------------------------------ SAP blocks
+// D restricted to each sbx x sbt block of sites (local dof q = sl * M + alpha,
+// sl = dt * sbx + dx): out[blk][q][q'] = sum_{d : nb(u_q, d) = u_q'} B[u_q][d].
+__global__ void __launch_bounds__(NT) k_sap_extract(const cd* __restrict__ B, int Nx, int Nt, int M,
+                                                    int sbx, int sbt, cd* __restrict__ out) {
+  const int K = sbx * sbt * M;
+  const int NBx = Nx / sbx;
+  const int64_t nblk = (int64_t)NBx * (Nt / sbt);
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nblk * K * K) return;
+  const int q2 = (int)(idx % K);
+  const int q = (int)((idx / K) % K);
+  const int64_t blk = idx / ((int64_t)K * K);
+  const int ibx = (int)(blk % NBx), ibt = (int)(blk / NBx);
+  const int sl = q / M, al = q % M, sl2 = q2 / M, be = q2 % M;
+  const int64_t u = (int64_t)(ibt * sbt + sl / sbx) * Nx + ibx * sbx + sl % sbx;
+  const int64_t u2 = (int64_t)(ibt * sbt + sl2 / sbx) * Nx + ibx * sbx + sl2 % sbx;
+  cd acc = mk(0.0, 0.0);
+  for (int d = 0; d < 5; ++d)
+    if (nb_site(u, d, Nx, Nt) == u2) acc = acc + B[((u * 5 + d) * M + al) * M + be];
+  out[idx] = acc;
+}
+
+// Gauss-Jordan inverse with partial pivoting of `count` K x K matrices in LDS
+// (one workgroup per matrix, K <= 32).  Sets *fail on a zero pivot.
+__global__ void __launch_bounds__(NT) k_small_inverse(cd* __restrict__ mats, int K,
+                                                      int* __restrict__ fail) {
+  __shared__ cd A[32 * 32];
+  __shared__ cd fcol[32];
+  __shared__ int perm[32];
+  __shared__ cd pivinv;
+  __shared__ int prow;
+  const int tid = threadIdx.x;
+  cd* g = mats + (int64_t)blockIdx.x * K * K;
+  for (int e = tid; e < K * K; e += NT) A[e] = g[e];
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    if (tid == 0) {
+      int p = k;
+      double best = abs2(A[k * K + k]);
+      for (int i = k + 1; i < K; ++i) {
+        const double v = abs2(A[i * K + k]);
+        if (v > best) { best = v; p = i; }
+      }
+      perm[k] = p;
+      prow = p;
+      if (best == 0.0) {
+        *fail = 1;
+        pivinv = mk(0.0, 0.0);
+      } else {
+        pivinv = cdiv(mk(1.0, 0.0), A[p * K + k]);
+      }
+    }
+    __syncthreads();
+    const int p = prow;
+    for (int j = tid; j < K; j += NT) {
+      const cd vk = A[k * K + j], vp = A[p * K + j];
+      if (p != k) A[p * K + j] = vk;
+      A[k * K + j] = ((j == k) ? mk(1.0, 0.0) : vp) * pivinv;
+    }
+    __syncthreads();
+    for (int i = tid; i < K; i += NT) fcol[i] = (i == k) ? mk(0.0, 0.0) : A[i * K + k];
+    __syncthreads();
+    for (int e = tid; e < K * K; e += NT) {
+      const int i = e / K, j = e % K;
+      if (i == k) continue;
+      const cd base = (j == k) ? mk(0.0, 0.0) : A[e];
+      A[e] = base - fcol[i] * A[k * K + j];
+    }
+    __syncthreads();
+  }
+  for (int k = K - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k) {
+      for (int i = tid; i < K; i += NT) {
+        const cd t = A[i * K + k];
+        A[i * K + k] = A[i * K + p];
+        A[i * K + p] = t;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < K * K; e += NT) g[e] = A[e];
+}
+
+// One colour of the red/black Schwarz sweep with exact block solves:
+//   res_B = r_B - (D x)_B ;  x_B += inv_B res_B
+// for every listed block B.  K = sbx*sbt*M dofs per block, 256/K RHS per WG.
+template <class T>
+__global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
+                                                  const cx<T>* __restrict__ inv, int Nx, int Nt, int M,
+                                                  int sbx, int sbt, const int* __restrict__ blist,
+                                                  int nrhs, const cx<T>* __restrict__ rr,
+                                                  cx<T>* __restrict__ x,
+                                                  const int* __restrict__ active) {
+  __shared__ cx<T> res[NT];
+  const int K = sbx * sbt * M;
+  const int rpw = NT / K;
+  const int tid = threadIdx.x;
+  const int q = tid % K, rl = tid / K;
+  const int r = blockIdx.y * rpw + rl;
+  const bool valid = rl < rpw && r < nrhs && (!active || active[r]);
+  const int blk = blist[blockIdx.x];
+  const int NBx = Nx / sbx;
+  const int ibx = blk % NBx, ibt = blk / NBx;
+  const int sl = q / M, al = q % M;
+  const int64_t u = (int64_t)(ibt * sbt + sl / sbx) * Nx + ibx * sbx + sl % sbx;
+  const int64_t n = (int64_t)Nx * Nt * M;
+  if (valid) {
+    const cx<T>* __restrict__ xr = x + (int64_t)r * n;
+    cx<T> acc = rr[(int64_t)r * n + u * M + al];
+    for (int d = 0; d < 5; ++d) {
+      const cx<T>* __restrict__ row = B + ((u * 5 + d) * M + al) * M;
+      const cx<T>* __restrict__ xv = xr + nb_site(u, d, Nx, Nt) * M;
+      cx<T> t = mk<T>(0, 0);
+      for (int j = 0; j < M; ++j) cfma(t, row[j], xv[j]);
+      acc = acc - t;
+    }
+    res[tid] = acc;
+  }
+  __syncthreads();
+  if (valid) {
+    const cx<T>* __restrict__ irow = inv + ((int64_t)blk * K + q) * K;
+    const cx<T>* rs = res + rl * K;
+    cx<T> acc = mk<T>(0, 0);
+    for (int j = 0; j < K; ++j) cfma(acc, irow[j], rs[j]);
+    cx<T>* o = x + (int64_t)r * n + u * M + al;
+    *o = *o + acc;
+  }
+}
+
+// ------------------------------------------------------------------ dense coarsest level
+__global__ void __launch_bounds__(NT) k_dense_from_stencil(const cd* __restrict__ B, int Nx, int Nt,
+                                                           int M, cd* __restrict__ A) {
+  const int64_t sites = (int64_t)Nx * Nt;
+  const int64_t n = sites * M;
+  const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (row >= n) return;
+  const int64_t u = row / M;
+  const int al = (int)(row % M);
+  for (int d = 0; d < 5; ++d) {
+    const int64_t v = nb_site(u, d, Nx, Nt);
+    for (int be = 0; be < M; ++be) {
+      cd* o = A + row * n + v * M + be;
+      *o = *o + B[((u * 5 + d) * M + al) * M + be];
+    }
+  }
+}
+
+// pivot search in column k below the diagonal (largest |a|, first on ties)
+__global__ void __launch_bounds__(NT) k_gj_pivot(const cd* __restrict__ A, int64_t n, int64_t k,
+                                                 int* __restrict__ perm, cd* __restrict__ pivinv,
+                                                 int* __restrict__ fail) {
+  __shared__ double bv[NT];
+  __shared__ int64_t bi[NT];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int64_t bidx = k;
+  for (int64_t i = k + tid; i < n; i += NT) {
+    const double v = abs2(A[i * n + k]);
+    if (v > best) { best = v; bidx = i; }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double v2 = bv[tid + s];
+      const int64_t i2 = bi[tid + s];
+      if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) { bv[tid] = v2; bi[tid] = i2; }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    perm[k] = (int)bi[0];
+    if (bv[0] <= 0.0) {
+      *fail = 1;
+      *pivinv = mk(0.0, 0.0);
+    } else {
+      *pivinv = cdiv(mk(1.0, 0.0), A[bi[0] * n + k]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_gj_swap_scale(cd* __restrict__ A, int64_t n, int64_t k,
+                                                      const int* __restrict__ perm,
+                                                      const cd* __restrict__ pivinv) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  const int64_t p = perm[k];
+  const cd vk = A[k * n + j], vp = A[p * n + j];
+  if (p != k) A[p * n + j] = vk;
+  A[k * n + j] = ((j == k) ? mk(1.0, 0.0) : vp) * (*pivinv);
+}
+
+__global__ void __launch_bounds__(NT) k_gj_col(const cd* __restrict__ A, int64_t n, int64_t k,
+                                               cd* __restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  f[i] = (i == k) ? mk(0.0, 0.0) : A[i * n + k];
+}
+
+__global__ void __launch_bounds__(NT) k_gj_eliminate(cd* __restrict__ A, int64_t n, int64_t k,
+                                                     const cd* __restrict__ f) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i == k || j >= n) return;
+  const cd fi = f[i];
+  if (fi.re == 0.0 && fi.im == 0.0) return;
+  cd* o = A + i * n + j;
+  const cd base = (j == k) ? mk(0.0, 0.0) : *o;
+  *o = base - fi * A[k * n + j];
+}
+
+__global__ void __launch_bounds__(NT) k_gather_cols(const cd* __restrict__ W, int64_t n,
+                                                    const int* __restrict__ pi, cd* __restrict__ out) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  out[i * n + j] = W[i * n + pi[j]];
+}
+
+__global__ void __launch_bounds__(NT) k_diag_sum(const cd* __restrict__ A, int64_t n,
+                                                 cd* __restrict__ out) {
+  __shared__ cd part[NT];
+  const int tid = threadIdx.x;
+  cd acc = mk(0.0, 0.0);
+  for (int64_t i = tid; i < n; i += NT) acc = acc + A[i * n + i];
+  part[tid] = acc;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) part[tid] = part[tid] + part[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) *out = part[0];
+}
+
+// y[r][i] = sum_j A[i][j] x[r][j]: tiles of 64 rows x 16 RHS, 32-wide k steps.
+template <class T>
+__global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A, int64_t n, int nrhs,
+                                                    const cx<T>* __restrict__ x,
+                                                    cx<T>* __restrict__ y,
+                                                    const int* __restrict__ active) {
+  constexpr int TI = 64, TR = 16, TJ = 32;
+  __shared__ cx<T> As[TI][TJ + 1];
+  __shared__ cx<T> Xs[TR][TJ + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * TI;
+  const int r0 = blockIdx.y * TR;
+  const int il = tid % TI, rg = tid / TI;  // 4 groups of 4 RHS
+  cx<T> acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
+  for (int64_t j0 = 0; j0 < n; j0 += TJ) {
+    for (int e = tid; e < TI * TJ; e += NT) {
+      const int ii = e / TJ, jj = e % TJ;
+      const int64_t gi = i0 + ii, gj = j0 + jj;
+      As[ii][jj] = (gi < n && gj < n) ? A[gi * n + gj] : mk<T>(0, 0);
+    }
+    for (int e = tid; e < TR * TJ; e += NT) {
+      const int rr = e / TJ, jj = e % TJ;
+      const int gr = r0 + rr;
+      const int64_t gj = j0 + jj;
+      Xs[rr][jj] = (gr < nrhs && gj < n) ? x[(int64_t)gr * n + gj] : mk<T>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < TJ; ++jj) {
+      const cx<T> a = As[il][jj];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cfma(acc[q], a, Xs[rg * 4 + q][jj]);
+    }
+    __syncthreads();
+  }
+  const int64_t gi = i0 + il;
+  if (gi < n) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gr = r0 + rg * 4 + q;
+      if (gr < nrhs && (!active || active[gr])) y[(int64_t)gr * n + gi] = acc[q];
+    }
+  }
+}
+
+// qr+ of the rows of V (columns = test vectors, V[k][n]) belonging to each
+// aggregate A and chirality c: classical Gram-Schmidt applied twice per column,
+// positive real norms.  One workgroup per (A, c), one thread per row.
+constexpr int QR_MAXTV = 16;
+__global__ void __launch_bounds__(NT) k_local_qr(const cd* __restrict__ V, int64_t n, int Nx, int M,
+                                                 int bx, int bt, int ntv, cd* __restrict__ P) {
+  __shared__ cd red[4][QR_MAXTV];
+  const int64_t A = blockIdx.x / 2;
+  const int c = blockIdx.x % 2;
+  const int s = threadIdx.x;
+  const int nrow = bx * bt * (M / 2);
+  const int NAx = Nx / bx;
+  const int lane = s & 63, wv = s >> 6;
+  cd v[QR_MAXTV];
+  const bool has = s < nrow;
+  const int64_t row = has ? agg_row(A, c, s, Nx, M, bx, bt, NAx) : 0;
+#pragma unroll
+  for (int k = 0; k < QR_MAXTV; ++k) v[k] = (has && k < ntv) ? V[(int64_t)k * n + row] : mk(0.0, 0.0);
+  for (int k = 0; k < ntv; ++k) {
+    for (int pass = 0; pass < 2; ++pass) {
+      cd coef[QR_MAXTV];
+#pragma unroll
+      for (int i = 0; i < QR_MAXTV; ++i) {
+        coef[i] = mk(0.0, 0.0);
+        if (i < k) {
+          cd t = cjmul(v[i], v[k]);
+          for (int o = 32; o > 0; o >>= 1) {
+            t.re += __shfl_xor(t.re, o, 64);
+            t.im += __shfl_xor(t.im, o, 64);
+          }
+          if (lane == 0) red[wv][i] = t;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < QR_MAXTV; ++i)
+        if (i < k) coef[i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < QR_MAXTV; ++i)
+        if (i < k) v[k] = v[k] - v[i] * coef[i];
+    }
+    double t = abs2(v[k]);
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) red[wv][0] = mk(t, 0.0);
+    __syncthreads();
+    const double nrm = sqrt((red[0][0].re + red[1][0].re) + (red[2][0].re + red[3][0].re));
+    __syncthreads();
+    v[k] = (1.0 / nrm) * v[k];
+  }
+  if (has) {
+    cd* o = P + ((A * 2 + c) * nrow + s) * ntv;
+#pragma unroll
+    for (int k = 0; k < QR_MAXTV; ++k)
+      if (k < ntv) o[k] = v[k];
+  }
+}
+
+// antiperiodic t boundary: the t-links leaving the last time slice get -1
+__global__ void __launch_bounds__(NT) k_fold_anti(cd* __restrict__ links, int Lx, int Lt) {
+  const int x = blockIdx.x * NT + threadIdx.x;
+  if (x >= Lx) return;
+  cd* u = links + (int64_t)Lx * Lt + (int64_t)(Lt - 1) * Lx + x;
+  *u = -1.0 * (*u);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void launch_fold_anti(hipStream_t s, cd* links, int Lx, int Lt) {
+  hipLaunchKernelGGL(k_fold_anti, dim3(grid1(Lx)), dim3(NT), 0, s, links, Lx, Lt);
+  KCHK();
+}
+void launch_local_qr(hipStream_t s, const cd* V, int64_t n, int Nx, int Nt, int M, int bx, int bt,
+                     int ntv, cd* P) {
+  require(ntv >= 1 && ntv <= QR_MAXTV, "at most 16 test vectors per chirality");
+  require(bx * bt * (M / 2) <= NT, "aggregate has more than 256 rows per chirality");
+  require(bx * bt * (M / 2) >= ntv, "aggregate has fewer rows than test vectors");
+  const int64_t nagg = (int64_t)(Nx / bx) * (Nt / bt);
+  hipLaunchKernelGGL(k_local_qr, dim3((unsigned)(nagg * 2)), dim3(NT), 0, s, V, n, Nx, M, bx, bt, ntv, P);
+  KCHK();
+}
+template <class T>
+void launch_noise(hipStream_t s, cx<T>* out, int64_t n, int nrhs, int kind, uint64_t seed,
+                  int purpose, int level, int64_t index0) {
+  if (n <= 0 || nrhs <= 0) return;
+  const uint64_t base = mix64(seed + kGolden);
+  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 4096);
+  hipLaunchKernelGGL(k_noise<T>, dim3(gx, nrhs), dim3(NT), 0, s, out, n, kind, base, purpose, level,
+                     index0);
+  KCHK();
+}
+template void launch_noise<double>(hipStream_t, cd*, int64_t, int, int, uint64_t, int, int, int64_t);
+template void launch_noise<float>(hipStream_t, cf*, int64_t, int, int, uint64_t, int, int, int64_t);
+
+template <class T>
+void launch_wilson(hipStream_t s, const cx<T>* links, T diag, int Lx, int Lt, int nrhs,
+                   const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active) {
+  const int64_t V = (int64_t)Lx * Lt;
+  hipLaunchKernelGGL(k_wilson<T>, dim3(grid1(V), nrhs), dim3(NT), 0, s, links, diag, Lx, Lt, x, y, b,
+                     active);
+  KCHK();
+}
+template void launch_wilson<double>(hipStream_t, const cd*, double, int, int, int, const cd*, cd*,
+                                    const cd*, const int*);
+template void launch_wilson<float>(hipStream_t, const cf*, float, int, int, int, const cf*, cf*,
+                                   const cf*, const int*);
+
+void launch_fine_blocks(hipStream_t s, const cd* links, double diag, int Lx, int Lt, cd* blocks) {
+  hipLaunchKernelGGL(k_fine_blocks, dim3(grid1((int64_t)Lx * Lt)), dim3(NT), 0, s, links, diag, Lx,
+                     Lt, blocks);
+  KCHK();
+}
+
+template <class T>
+void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, int nrhs,
+                    const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active) {
+  const int64_t n = (int64_t)Nx * Nt * M;
+  dim3 g(grid1(n), nrhs);
+  switch (M) {
+    case 2: hipLaunchKernelGGL((k_stencil<T, 2>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    case 4: hipLaunchKernelGGL((k_stencil<T, 4>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    case 8: hipLaunchKernelGGL((k_stencil<T, 8>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    case 16: hipLaunchKernelGGL((k_stencil<T, 16>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    default: throw Error(MGM_EINVAL, "block stencil: dofs per site must be 2, 4, 8, 16 or 32");
+  }
+  KCHK();
+}
+template void launch_stencil<double>(hipStream_t, const cd*, int, int, int, int, const cd*, cd*,
+                                     const cd*, const int*);
+template void launch_stencil<float>(hipStream_t, const cf*, int, int, int, int, const cf*, cf*,
+                                    const cf*, const int*);
+
+template <class T>
+void launch_restrict(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
+                     int nrhs, const cx<T>* xf, cx<T>* xc, const int* active) {
+  const int64_t nc = (int64_t)(Nx / bx) * (Nt / bt) * 2 * ntv;
+  hipLaunchKernelGGL(k_restrict<T>, dim3(grid1(nc), nrhs), dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv,
+                     xf, xc, active);
+  KCHK();
+}
+template void launch_restrict<double>(hipStream_t, const cd*, int, int, int, int, int, int, int,
+                                      const cd*, cd*, const int*);
+template void launch_restrict<float>(hipStream_t, const cf*, int, int, int, int, int, int, int,
+                                     const cf*, cf*, const int*);
+
+template <class T>
+void launch_prolong(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
+                    int nrhs, const cx<T>* xc, cx<T>* yf, int accumulate, const int* active) {
+  const int64_t n = (int64_t)Nx * Nt * M;
+  hipLaunchKernelGGL(k_prolong<T>, dim3(grid1(n), nrhs), dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv, xc,
+                     yf, accumulate, active);
+  KCHK();
+}
+template void launch_prolong<double>(hipStream_t, const cd*, int, int, int, int, int, int, int,
+                                     const cd*, cd*, int, const int*);
+template void launch_prolong<float>(hipStream_t, const cf*, int, int, int, int, int, int, int,
+                                    const cf*, cf*, int, const int*);
+
+void launch_galerkin(hipStream_t s, const cd* Bf, int Nx, int Nt, int Mf, const cd* P, int bx,
+                     int bt, int ntv, cd* Bc) {
+  const int64_t tot = (int64_t)(Nx / bx) * (Nt / bt) * 5 * (2 * ntv) * (2 * ntv);
+  hipLaunchKernelGGL(k_galerkin, dim3(grid1(tot)), dim3(NT), 0, s, Bf, Nx, Nt, Mf, P, bx, bt, ntv, Bc);
+  KCHK();
+}
+
+void launch_sap_extract(hipStream_t s, const cd* B, int Nx, int Nt, int M, int sbx, int sbt,
+                        cd* out) {
+  const int64_t K = (int64_t)sbx * sbt * M;
+  const int64_t tot = (int64_t)(Nx / sbx) * (Nt / sbt) * K * K;
+  hipLaunchKernelGGL(k_sap_extract, dim3(grid1(tot)), dim3(NT), 0, s, B, Nx, Nt, M, sbx, sbt, out);
+  KCHK();
+}
+
+void launch_small_inverse(hipStream_t s, cd* mats, int K, int count, int* fail) {
+  require(K >= 1 && K <= 32, "SAP block too large: sbx*sbt*M must be <= 32");
+  hipLaunchKernelGGL(k_small_inverse, dim3(count), dim3(NT), 0, s, mats, K, fail);
+  KCHK();
+}
+
+template <class T>
+void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, int Nt, int M,
+                      int sbx, int sbt, const int* blist, int nb, int nrhs, const cx<T>* r,
+                      cx<T>* x, const int* active) {
+  if (nb <= 0) return;
+  const int K = sbx * sbt * M;
+  const int rpw = NT / K;
+  hipLaunchKernelGGL(k_sap_sweep<T>, dim3(nb, (nrhs + rpw - 1) / rpw), dim3(NT), 0, s, B, inv, Nx, Nt,
+                     M, sbx, sbt, blist, nrhs, r, x, active);
+  KCHK();
+}
+template void launch_sap_sweep<double>(hipStream_t, const cd*, const cd*, int, int, int, int, int,
+                                       const int*, int, int, const cd*, cd*, const int*);
+template void launch_sap_sweep<float>(hipStream_t, const cf*, const cf*, int, int, int, int, int,
+                                      const int*, int, int, const cf*, cf*, const int*);
+
+void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M, cd* A) {
+  const int64_t n = (int64_t)Nx * Nt * M;
+  HIPCHK(hipMemsetAsync(A, 0, sizeof(cd) * n * n, s));
+  hipLaunchKernelGGL(k_dense_from_stencil, dim3(grid1(n)), dim3(NT), 0, s, B, Nx, Nt, M, A);
+  KCHK();
+}
+
+// In-place Gauss-Jordan with partial pivoting; the column unscrambling is a
+// gather into `out`.  Returns 0, or 1 on a zero pivot.
+int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* out) {
+  DevBuf perm, piv, fcol, fail, pi;
+  perm.ensure(sizeof(int) * n);
+  piv.ensure(sizeof(cd));
+  fcol.ensure(sizeof(cd) * n);
+  fail.ensure(sizeof(int));
+  pi.ensure(sizeof(int) * n);
+  HIPCHK(hipMemsetAsync(fail.p, 0, sizeof(int), s));
+  for (int64_t k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, s, A, n, k, perm.as<int>(), piv.as<cd>(),
+                       fail.as<int>());
+    hipLaunchKernelGGL(k_gj_swap_scale, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, perm.as<int>(),
+                       piv.as<cd>());
+    hipLaunchKernelGGL(k_gj_col, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, fcol.as<cd>());
+    hipLaunchKernelGGL(k_gj_eliminate, dim3(grid1(n), (unsigned)n), dim3(NT), 0, s, A, n, k,
+                       fcol.as<cd>());
+    KCHK();
+  }
+  std::vector<int> hperm(n), hpi(n);
+  int hfail = 0;
+  HIPCHK(hipMemcpyAsync(hperm.data(), perm.p, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hfail, fail.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hfail) return 1;
+  for (int64_t j = 0; j < n; ++j) hpi[j] = (int)j;
+  for (int64_t k = n - 1; k >= 0; --k)
+    if (hperm[k] != k) std::swap(hpi[k], hpi[hperm[k]]);
+  HIPCHK(hipMemcpyAsync(pi.p, hpi.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid1(n), (unsigned)n), dim3(NT), 0, s, A, n, pi.as<int>(),
+                     out);
+  KCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return 0;
+}
+
+void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out) {
+  hipLaunchKernelGGL(k_diag_sum, dim3(1), dim3(NT), 0, s, A, n, out);
+  KCHK();
+}
+
+template <class T>
+void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, const cx<T>* x,
+                        cx<T>* y, const int* active) {
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((n + 63) / 64), (nrhs + 15) / 16), dim3(NT), 0, s,
+                     A, n, nrhs, x, y, active);
+  KCHK();
+}
+template void launch_dense_apply<double>(hipStream_t, const cd*, int64_t, int, const cd*, cd*,
+                                         const int*);
+template void launch_dense_apply<float>(hipStream_t, const cf*, int64_t, int, const cf*, cf*,
+                                        const int*);
+
+}  // namespace mgm

@@ -1,0 +1,447 @@
+// Solvers on top of the level kernels: the multigrid preconditioner (coarse
+// correction by a fixed-length inner FGMRES -- a K-cycle -- or the dense
+// coarsest inverse, then red/black SAP post-smoothing), the outer FP64
+// right-preconditioned FGMRES with per-RHS stopping on the true residual, the
+// CholQR orthonormalisation, and the deterministic bootstrap setup of the
+// aggregation hierarchy.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace mgm {
+
+namespace {
+
+template <class T>
+LevelData<T>& ldata(Level& L);
+template <>
+LevelData<double>& ldata<double>(Level& L) { return L.d; }
+template <>
+LevelData<float>& ldata<float>(Level& L) { return L.f; }
+
+template <class T>
+Work<T>& work(Level& L);
+template <>
+Work<double>& work<double>(Level& L) { return L.wd; }
+template <>
+Work<float>& work<float>(Level& L) { return L.wf; }
+
+template <class T>
+const cx<T>* links_of(Gauge& g);
+template <>
+const cd* links_of<double>(Gauge& g) { return g.links.as<cd>(); }
+template <>
+const cf* links_of<float>(Gauge& g) { return g.links32.as<cf>(); }
+
+template <class T>
+void ensure_work(Level& L, int nrhs, int m) {
+  Work<T>& W = work<T>(L);
+  const int64_t n = L.n;
+  const size_t c = sizeof(cx<T>);
+  W.V.ensure(c * (size_t)(m + 1) * nrhs * n);
+  W.Z.ensure(c * (size_t)m * nrhs * n);
+  W.w.ensure(c * (size_t)nrhs * n);
+  W.H.ensure(c * (size_t)nrhs * m * (m + 1));
+  W.cs.ensure(sizeof(T) * (size_t)nrhs * m);
+  W.sn.ensure(c * (size_t)nrhs * m);
+  W.g.ensure(c * (size_t)nrhs * (m + 1));
+  W.y.ensure(c * (size_t)nrhs * m);
+  W.beta.ensure(sizeof(T) * nrhs);
+  W.thr.ensure(sizeof(T) * nrhs);
+  W.bnorm.ensure(sizeof(T) * nrhs);
+  W.act.ensure(sizeof(int) * 2 * nrhs);  // active flags, then "done" flags
+  W.nit.ensure(sizeof(int) * nrhs);
+  W.part.ensure(c * (size_t)nrhs * (m + 1) * reduce_chunks(n));
+  W.coef.ensure(c * (size_t)nrhs * (m + 1));
+  W.coef2.ensure(c * (size_t)nrhs * (m + 1));
+}
+
+template <class T>
+void apply_op(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* x, cx<T>* y, const cx<T>* b,
+              const int* act) {
+  Level& L = *g.levels[l];
+  if (l == 0) {
+    launch_wilson<T>(c->stream, links_of<T>(g), (T)(g.m0 + 2.0), g.Lx, g.Lt, nrhs, x, y, b, act);
+  } else {
+    launch_stencil<T>(c->stream, ldata<T>(L).B(), L.Nx, L.Nt, L.M, nrhs, x, y, b, act);
+  }
+}
+
+template <class T>
+void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* x, int m, T tol,
+                  const int* parent);
+
+// M_l r -> x.  Coarsest: x = D^{-1} r.  Else x = P_l C_{l+1}(P_l^H r) (or 0
+// while the hierarchy below l is not built), then SAP cycles on D x = r.
+template <class T>
+void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, const int* act) {
+  hipStream_t s = c->stream;
+  Level& L = *g.levels[l];
+  LevelData<T>& D = ldata<T>(L);
+  if (L.is_coarsest) {
+    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act);
+    return;
+  }
+  if (L.has_coarse) {
+    Level& C = *g.levels[l + 1];
+    Work<T>& W = work<T>(L);
+    W.rc.ensure(sizeof(cx<T>) * (size_t)nrhs * C.n);
+    W.ec.ensure(sizeof(cx<T>) * (size_t)nrhs * C.n);
+    cx<T>* rc = W.rc.template as<cx<T>>();
+    cx<T>* ec = W.ec.template as<cx<T>>();
+    launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
+    if (C.is_coarsest) {
+      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act);
+    } else {
+      fgmres_inner<T>(c, g, l + 1, nrhs, rc, ec, C.inner_iters, (T)g.prm.inner_tol, act);
+    }
+    launch_prolong<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, ec, x, 0, act);
+  } else {
+    launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
+  }
+  for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
+    for (int col = 0; col < 2; ++col)
+      launch_sap_sweep<T>(s, D.B(), D.sapinv.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
+                          L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
+}
+
+// One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
+// Hessenberg column, v_{j+1} = w/||w||, Givens update.
+template <class T, class PrecFn>
+void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec) {
+  hipStream_t s = c->stream;
+  Level& L = *g.levels[l];
+  const int64_t n = L.n;
+  const int64_t vs = (int64_t)nrhs * n;
+  cx<T>* V = W.V.template as<cx<T>>();
+  cx<T>* Z = W.Z.template as<cx<T>>();
+  cx<T>* w = W.w.template as<cx<T>>();
+  int* act = W.act.template as<int>();
+  cx<T>* part = W.part.template as<cx<T>>();
+  cx<T>* c1 = W.coef.template as<cx<T>>();
+  cx<T>* c2 = W.coef2.template as<cx<T>>();
+  T* hn = W.beta.template as<T>() ;  // beta is free after the cycle start: reuse for ||w||
+  prec(V + j * vs, Z + j * vs, (const int*)act);
+  apply_op<T>(c, g, l, nrhs, Z + j * vs, w, nullptr, act);
+  launch_dot_multi_ld<T>(s, V, vs, n, j + 1, w, n, nrhs, c1, m + 1, 0, act, part);
+  launch_update_multi<T>(s, V, vs, n, j + 1, c1, m + 1, (T)-1, w, n, nrhs, act, nullptr, nullptr);
+  launch_dot_multi_ld<T>(s, V, vs, n, j + 1, w, n, nrhs, c2, m + 1, 0, act, part);
+  launch_update_multi<T>(s, V, vs, n, j + 1, c2, m + 1, (T)-1, w, n, nrhs, act, hn, (T*)part);
+  launch_hcol<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), act);
+  launch_scale<T>(s, w, hn, n, nrhs, V + (j + 1) * vs, act);
+  launch_givens<T>(s, j, m, nrhs, W.H.template as<cx<T>>(), W.cs.template as<T>(),
+                   W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
+                   W.nit.template as<int>());
+}
+
+// x = m steps of FGMRES from x0 = 0 on D_l x = b (no restart), a RHS stops
+// early when its residual estimate reaches tol * ||b||.  No host sync.
+template <class T>
+void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* x, int m, T tol,
+                  const int* parent) {
+  hipStream_t s = c->stream;
+  Level& L = *g.levels[l];
+  require(m >= 1 && m <= 63, "inner FGMRES length must be in [1, 63]");
+  ensure_work<T>(L, nrhs, m);
+  Work<T>& W = work<T>(L);
+  const int64_t n = L.n;
+  cx<T>* V = W.V.template as<cx<T>>();
+  cx<T>* Z = W.Z.template as<cx<T>>();
+  int* act = W.act.template as<int>();
+  T* beta = W.beta.template as<T>();
+  launch_norm<T>(s, b, n, nrhs, beta, parent, (T*)W.part.p);
+  launch_fgmres_init<T>(s, nrhs, beta, parent, nullptr, tol, nullptr, m, act, W.nit.template as<int>(),
+                        W.g.template as<cx<T>>(), W.thr.template as<T>());
+  launch_scale<T>(s, b, beta, n, nrhs, V, act);
+  for (int j = 0; j < m; ++j)
+    arnoldi_step<T>(c, g, l, nrhs, j, m, W, [&](const cx<T>* v, cx<T>* z, const int* a) {
+      precond<T>(c, g, l, nrhs, v, z, a);
+    });
+  launch_backsolve<T>(s, m, nrhs, W.H.template as<cx<T>>(), W.g.template as<cx<T>>(),
+                      W.nit.template as<int>(), W.y.template as<cx<T>>());
+  launch_axpby<T>(s, (T)0, b, (T)0, nullptr, x, n, nrhs, parent);
+  launch_update_multi<T>(s, Z, (int64_t)nrhs * n, n, m, W.y.template as<cx<T>>(), m, (T)1, x, n, nrhs,
+                         parent, nullptr, nullptr, W.nit.template as<int>());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ public solver pieces
+void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y) {
+  apply_op<double>(c, g, l, nrhs, x, y, nullptr, nullptr);
+}
+
+// FP64 preconditioner entry; in FP32 mode the residual is rounded to FP32, the
+// whole multigrid cycle runs in FP32, and the correction is widened again.
+void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
+  Level& L = *g.levels[l];
+  if (g.prm.precision == MGM_PREC_FP32 && g.mg_ready) {
+    Work<double>& W = L.wd;
+    const int64_t cnt = (int64_t)nrhs * L.n;
+    W.cvt_in.ensure(sizeof(cf) * cnt);
+    W.cvt_out.ensure(sizeof(cf) * cnt);
+    launch_convert<float, double>(c->stream, r, W.cvt_in.as<cf>(), cnt);
+    precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act);
+    launch_convert<double, float>(c->stream, W.cvt_out.as<cf>(), x, cnt);
+  } else {
+    precond<double>(c, g, l, nrhs, r, x, act);
+  }
+}
+
+// Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
+// residual, checked at the end of every cycle); the host polls the active
+// flags after each Arnoldi step to end a cycle once every RHS has converged.
+int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
+                const mgm_solve_params& sp, int* iters_out, double* relres_out) {
+  hipStream_t s = c->stream;
+  Level& L = *g.levels[l];
+  const int64_t n = L.n;
+  const int m = sp.restart;
+  require(m >= 1 && m <= 63, "restart length must be in [1, 63]");
+  require(sp.tol > 0, "tolerance must be positive");
+  ensure_work<double>(L, nrhs, m);
+  Work<double>& W = L.wd;
+  cd* V = W.V.as<cd>();
+  cd* Z = W.Z.as<cd>();
+  cd* w = W.w.as<cd>();
+  int* act = W.act.as<int>();
+  int* done = act + nrhs;
+  double* bnorm = W.bnorm.as<double>();
+  double* beta = W.beta.as<double>();
+  std::vector<int> hact(nrhs), hdone(nrhs, 0), hnit(nrhs), its(nrhs, 0);
+  std::vector<double> hb(nrhs), hr(nrhs);
+
+  launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p);
+  HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int r = 0; r < nrhs; ++r) {
+    if (!std::isfinite(hb[r])) throw Error(MGM_ENONFINITE, "non-finite right-hand side");
+    hdone[r] = hb[r] == 0.0;
+  }
+  HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+  launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
+
+  if (L.is_coarsest) {
+    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr);
+  } else {
+    for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
+      // r0 = b - D x ; v0 = r0 / ||r0||
+      apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
+      launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+      launch_fgmres_init<double>(s, nrhs, beta, nullptr, done, sp.tol, bnorm, m, act,
+                                 W.nit.as<int>(), W.g.as<cd>(), W.thr.as<double>());
+      launch_scale<double>(s, w, beta, n, nrhs, V, act);
+      for (int j = 0; j < m; ++j) {
+        arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
+          precondition_d(c, g, l, nrhs, v, z, a);
+        });
+        HIPCHK(hipMemcpyAsync(hact.data(), act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (std::all_of(hact.begin(), hact.end(), [](int a) { return a == 0; })) break;
+      }
+      launch_backsolve<double>(s, m, nrhs, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(), W.y.as<cd>());
+      launch_update_multi<double>(s, Z, (int64_t)nrhs * n, n, m, W.y.as<cd>(), m, 1.0, x, n, nrhs,
+                                  nullptr, nullptr, nullptr, W.nit.as<int>());
+      // true residual
+      apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
+      launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+      HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hnit.data(), W.nit.p, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool all = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (hdone[r]) continue;
+        its[r] += hnit[r];
+        if (!std::isfinite(hr[r])) throw Error(MGM_ENONFINITE, "non-finite residual in FGMRES");
+        if (hr[r] <= sp.tol * hb[r]) hdone[r] = 1;
+        else all = false;
+      }
+      if (all) break;
+      HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    }
+  }
+  // final relative residuals
+  apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
+  launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+  HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bool ok = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const double rel = hb[r] > 0 ? hr[r] / hb[r] : 0.0;
+    if (!std::isfinite(rel)) throw Error(MGM_ENONFINITE, "non-finite residual");
+    if (rel > sp.tol) ok = false;
+    if (iters_out) iters_out[r] = its[r];
+    if (relres_out) relres_out[r] = rel;
+  }
+  return ok ? MGM_OK : MGM_ENOTCONV;
+}
+
+// Q = qr+(Y): shifted CholQR followed by two plain CholQR passes.  The
+// product of the three triangular factors has a positive diagonal, so Q is
+// the unique thin-QR factor with positive real diag(R).
+void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
+  hipStream_t s = c->stream;
+  require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
+  DevBuf tmp, G, part, fail;
+  tmp.ensure(sizeof(cd) * (size_t)d * n);
+  G.ensure(sizeof(cd) * d * d);
+  part.ensure(sizeof(cd) * (size_t)d * d * ((n + 511) / 512));
+  fail.ensure(sizeof(int));
+  // pass 0: Y -> tmp (shifted Gram), pass 1: tmp -> Q, pass 2: copy of Q -> Q
+  const double shifts[3] = {1e-14, 0.0, 0.0};
+  for (int pass = 0; pass < 3; ++pass) {
+    const cd* src = Y;
+    cd* dst = tmp.as<cd>();
+    if (pass == 1) {
+      src = tmp.as<cd>();
+      dst = Q;
+    } else if (pass == 2) {
+      HIPCHK(hipMemcpyAsync(tmp.p, Q, sizeof(cd) * (size_t)d * n, hipMemcpyDeviceToDevice, s));
+      src = tmp.as<cd>();
+      dst = Q;
+    }
+    launch_gram(s, src, n, d, G.as<cd>(), part.as<cd>());
+    if (cholesky_rinv(s, G.as<cd>(), d, shifts[pass], fail.as<int>()))
+      throw Error(MGM_ENONFINITE, "CholQR: Gram matrix not positive definite (rank-deficient block)");
+    launch_right_tri(s, src, G.as<cd>(), n, d, dst);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ setup
+namespace {
+
+void build_sap(mgm_ctx* c, Level& L, int sbx, int sbt) {
+  hipStream_t s = c->stream;
+  require(sbx >= 1 && sbt >= 1 && L.Nx % sbx == 0 && L.Nt % sbt == 0,
+          "SAP block must divide the level's lattice");
+  const int NBx = L.Nx / sbx, NBt = L.Nt / sbt;
+  require((NBx == 1 || NBx % 2 == 0) && (NBt == 1 || NBt % 2 == 0),
+          "SAP needs an even number of blocks (or one) per direction");
+  L.sbx = sbx;
+  L.sbt = sbt;
+  L.K = sbx * sbt * L.M;
+  require(L.K <= 32, "SAP block too large: sbx*sbt*dofs must be <= 32");
+  L.nblk = NBx * NBt;
+  L.d.sapinv.ensure(sizeof(cd) * (size_t)L.nblk * L.K * L.K);
+  launch_sap_extract(s, L.d.B(), L.Nx, L.Nt, L.M, sbx, sbt, L.d.sapinv.as<cd>());
+  DevBuf fail;
+  fail.ensure(sizeof(int));
+  HIPCHK(hipMemsetAsync(fail.p, 0, sizeof(int), s));
+  launch_small_inverse(s, L.d.sapinv.as<cd>(), L.K, L.nblk, fail.as<int>());
+  int hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, fail.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<int> lists[2];
+  for (int b = 0; b < L.nblk; ++b) lists[((b % NBx) + (b / NBx)) % 2].push_back(b);
+  for (int col = 0; col < 2; ++col) {
+    L.ncolor[col] = (int)lists[col].size();
+    L.color_list[col].ensure(sizeof(int) * std::max<size_t>(1, lists[col].size()));
+    if (!lists[col].empty())
+      HIPCHK(hipMemcpyAsync(L.color_list[col].p, lists[col].data(), sizeof(int) * lists[col].size(),
+                            hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  require(!hf, "singular SAP block", MGM_ENONFINITE);
+}
+
+template <class TO>
+void copy_convert(mgm_ctx* c, const DevBuf& src, DevBuf& dst) {
+  if (!src.p) return;
+  const int64_t cnt = (int64_t)(src.bytes / sizeof(cd));
+  dst.ensure(sizeof(cx<TO>) * cnt);
+  launch_convert<TO, double>(c->stream, src.as<cd>(), dst.as<cx<TO>>(), cnt);
+}
+
+}  // namespace
+
+void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
+  hipStream_t s = c->stream;
+  const int Lv = p.nlevels;
+  require(Lv >= 1 && Lv <= MGM_MAX_LEVELS, "nlevels out of range");
+  g.prm = p;
+  g.mg_ready = false;
+  g.levels.clear();
+  auto L0 = std::make_unique<Level>();
+  L0->Nx = g.Lx;
+  L0->Nt = g.Lt;
+  L0->M = 2;
+  L0->sites = (int64_t)g.Lx * g.Lt;
+  L0->n = 2 * L0->sites;
+  L0->d.blocks.ensure(sizeof(cd) * (size_t)L0->sites * 20);
+  launch_fine_blocks(s, g.links.as<cd>(), g.m0 + 2.0, g.Lx, g.Lt, L0->d.blocks.as<cd>());
+  g.levels.push_back(std::move(L0));
+
+  for (int l = 0; l < Lv; ++l) {
+    Level& L = *g.levels[l];
+    L.is_coarsest = (l == Lv - 1);
+    if (L.is_coarsest) {
+      require(L.n <= 20000, "coarsest level too large for the dense inverse (n > 20000)");
+      DevBuf work;
+      work.ensure(sizeof(cd) * (size_t)L.n * L.n);
+      L.d.dinv.ensure(sizeof(cd) * (size_t)L.n * L.n);
+      launch_dense_from_stencil(s, L.d.B(), L.Nx, L.Nt, L.M, work.as<cd>());
+      if (dense_inverse(s, work.as<cd>(), L.n, L.d.dinv.as<cd>()))
+        throw Error(MGM_ENONFINITE, "coarsest operator is singular");
+      DevBuf tr;
+      tr.ensure(sizeof(cd));
+      launch_diag_sum(s, L.d.dinv.as<cd>(), L.n, tr.as<cd>());
+      cd h;
+      HIPCHK(hipMemcpyAsync(&h, tr.p, sizeof(cd), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      g.trL[0] = h.re;
+      g.trL[1] = h.im;
+      break;
+    }
+    const int bx = p.block[l][0], bt = p.block[l][1], ntv = p.ntv[l];
+    require(bx >= 1 && bt >= 1 && L.Nx % bx == 0 && L.Nt % bt == 0,
+            "aggregate block must divide the level's lattice");
+    require(ntv >= 1 && ntv <= 16, "ntv must be in [1, 16]");
+    const int Mc = 2 * ntv;
+    require(Mc == 2 || Mc == 4 || Mc == 8 || Mc == 16 || Mc == 32, "2*ntv must be 2, 4, 8, 16 or 32");
+    L.sap_cycles = std::max(1, p.sap_cycles[l]);
+    L.inner_iters = p.inner_iters[l];
+    build_sap(c, L, std::max(1, p.sap_block[l][0]), std::max(1, p.sap_block[l][1]));
+
+    // test vectors: block inverse iteration from Z2xZ2 noise
+    DevBuf Vb, Wb;
+    Vb.ensure(sizeof(cd) * (size_t)ntv * L.n);
+    Wb.ensure(sizeof(cd) * (size_t)ntv * L.n);
+    launch_noise<double>(s, Vb.as<cd>(), L.n, ntv, MGM_NOISE_Z2Z2, p.seed, MGM_PURPOSE_SETUP, l, 0);
+    mgm_solve_params sp{p.setup_tol, p.setup_restart, p.setup_max_restarts, 0};
+    for (int it = 0; it < p.setup_iters; ++it) {
+      const int st = solve_level(c, g, l, ntv, Vb.as<cd>(), Wb.as<cd>(), sp, nullptr, nullptr);
+      if (st != MGM_OK) throw Error(st, "setup solve did not converge on level " + std::to_string(l));
+      orthonormalize(c, L.n, ntv, Wb.as<cd>(), Vb.as<cd>());
+    }
+    L.bx = bx;
+    L.bt = bt;
+    L.ntv = ntv;
+    L.d.P.ensure(sizeof(cd) * (size_t)L.nagg() * 2 * L.nrow() * ntv);
+    launch_local_qr(s, Vb.as<cd>(), L.n, L.Nx, L.Nt, L.M, bx, bt, ntv, L.d.P.as<cd>());
+
+    auto C = std::make_unique<Level>();
+    C->Nx = L.Nx / bx;
+    C->Nt = L.Nt / bt;
+    C->M = Mc;
+    C->sites = (int64_t)C->Nx * C->Nt;
+    C->n = C->sites * Mc;
+    C->d.blocks.ensure(sizeof(cd) * (size_t)C->sites * 5 * Mc * Mc);
+    launch_galerkin(s, L.d.B(), L.Nx, L.Nt, L.M, L.d.P.as<cd>(), bx, bt, ntv, C->d.blocks.as<cd>());
+    HIPCHK(hipStreamSynchronize(s));
+    L.has_coarse = true;
+    g.levels.push_back(std::move(C));
+  }
+  // FP32 copies for the mixed-precision preconditioner
+  for (auto& Lp : g.levels) {
+    Level& L = *Lp;
+    copy_convert<float>(c, L.d.blocks, L.f.blocks);
+    copy_convert<float>(c, L.d.P, L.f.P);
+    copy_convert<float>(c, L.d.sapinv, L.f.sapinv);
+    copy_convert<float>(c, L.d.dinv, L.f.dinv);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  g.mg_ready = true;
+}
+
+}  // namespace mgm

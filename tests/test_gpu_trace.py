@@ -1,0 +1,119 @@
+"""GPU parity of the trace estimators (Alg. 1, Hutch++, MG-MLMC, MG-MLMC++
+Alg. 2) against the oracle on identical seeds: per-sample values, the
+low-rank parts, sample counts and the final estimate (1e-8 relative)."""
+import numpy as np
+import pytest
+
+from gpu_util import Recipe, log
+from lattice_inputs import WORKLOADS, gauge_for, metropolis_u1
+from oracle import trace as otr
+
+pytestmark = pytest.mark.gpu
+
+SOLVE_TOL = 1e-12  # tight solves so that solver error stays far below 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2303_11512_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def s16(ctx):
+    """The 16x16 plain-method workload: beta 3.0 Metropolis field, m0 = -0.05,
+    4x4 aggregates with 4 test vectors per chirality, Rademacher noise."""
+    cfg = WORKLOADS["schwinger16"]
+    th = gauge_for(cfg)
+    rec = Recipe(th, cfg["m0"], cfg["blocks"], cfg["ntv"], seed=3, sap_block=[(4, 4), (1, 1)])
+    log("setup schwinger16")
+    return cfg, rec, rec.gpu(ctx), rec.oracle()
+
+
+@pytest.fixture(scope="module")
+def s32(ctx):
+    th = metropolis_u1(32, 32, 3.0, 100, 932)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11,
+                 sap_block=[(4, 4), (1, 1), (1, 1)], inner_iters=[4, 4, 4])
+    log("setup s32")
+    return rec, rec.gpu(ctx), rec.oracle()
+
+
+def _gpu(ctx, gid, **kw):
+    from paper_2303_11512_amd import solve_params
+    return ctx.trace_estimate(gid, solve=solve_params(tol=SOLVE_TOL, restart=24), max_dump=4096,
+                              **kw)
+
+
+def _cmp(got, want, tol=1e-8):
+    scale = max(abs(want["tau"]), 1e-300)
+    assert abs(got["tau"] - want["tau"]) < tol * scale, (got["tau"], want["tau"])
+    for l in range(len(want["level_samples"])):
+        assert got["level_samples"][l] == want["level_samples"][l]
+        ws = np.array(want["samples"][l])
+        gs = got["samples"][l]
+        # samples are differences of two solves: compare on the scale of the level
+        sc = max(np.max(np.abs(ws)), 1e-300)
+        assert np.max(np.abs(gs - ws)) < tol * max(sc, scale / max(1, len(ws))), l
+        assert abs(got["level_lr"][l] - want["level_lr"][l]) < tol * scale
+
+
+@pytest.mark.parametrize("variant,form", [("hutchinson", "reduced"), ("hutchpp", "reduced"),
+                                          ("mlmc", "reduced"), ("mlmcpp", "reduced"),
+                                          ("mlmcpp", "full")])
+def test_replay_parity_s16(ctx, s16, variant, form):
+    cfg, rec, gid, hier = s16
+    log(f"trace replay {variant}/{form}")
+    fixed = [37]
+    kw = dict(variant=variant, form=form, eps=cfg["eps"], d=[cfg["d"][0]], k_power=2,
+              noise="rademacher", seed=cfg["trace_seed"], fixed_samples=fixed)
+    got = _gpu(ctx, gid, batch=16, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
+
+
+def test_adaptive_parity_s16(ctx, s16):
+    """The full plain-method workload: Hutch++ (8 vectors) + MG-MLMC,
+    Rademacher noise, rel. accuracy 1e-2, optimal targets."""
+    cfg, rec, gid, hier = s16
+    kw = dict(variant="mlmcpp", form="reduced", eps=cfg["eps"], d=[cfg["d"][0]], k_power=2,
+              noise="rademacher", seed=cfg["trace_seed"])
+    got = _gpu(ctx, gid, batch=8, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
+    # and the estimate is within 4 sigma (sigma = eps |tau|) of the exact trace
+    exact = np.trace(np.linalg.inv(hier.levels[0].D.toarray()))
+    assert abs(got["tau"] - exact) < 4 * cfg["eps"] * abs(exact)
+
+
+@pytest.mark.parametrize("batch", [3, 64])
+def test_batching_does_not_change_result(ctx, s16, batch):
+    cfg, rec, gid, hier = s16
+    kw = dict(variant="mlmcpp", eps=3e-2, d=[4], k_power=1, noise="z2z2", seed=5)
+    a = _gpu(ctx, gid, batch=batch, **kw)
+    b = _gpu(ctx, gid, batch=1, **kw)
+    assert a["level_samples"] == b["level_samples"]
+    assert abs(a["tau"] - b["tau"]) < 1e-12 * abs(b["tau"])
+
+
+def test_three_level_mlmcpp_parity(ctx, s32):
+    rec, gid, hier = s32
+    for targets in ("optimal", "uniform"):
+        kw = dict(variant="mlmcpp", eps=2e-2, d=[8, 8], k_power=2, noise="z2z2", seed=21,
+                  targets=targets)
+        log(f"trace s32 mlmcpp {targets}")
+        got = _gpu(ctx, gid, batch=32, **kw)
+        want = otr.estimate(hier, otr.TraceParams(**kw))
+        _cmp(got, want)
+    assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
+
+
+def test_fixed_cost_and_full_form_s32(ctx, s32):
+    rec, gid, hier = s32
+    kw = dict(variant="mlmcpp", form="full", eps=5e-2, d=[4, 4], k_power=1, noise="z2z2", seed=8,
+              fixed_cost=[3.0, 1.0], fixed_samples=[12, 20])
+    got = _gpu(ctx, gid, batch=8, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
