@@ -98,7 +98,8 @@ typedef struct {
   int sap_block[MGM_MAX_LEVELS][2];   /* SAP block (sbx, sbt) on level l     */
   int sap_cycles[MGM_MAX_LEVELS];     /* SAP post-smoothing cycles, level l  */
   int inner_iters[MGM_MAX_LEVELS];    /* FGMRES steps of the coarse solve on
-                                         level l (1 <= l <= L-2)             */
+                                         level l (1 <= l <= L-2); 0 = one
+                                         multigrid cycle on l, no Krylov    */
   double inner_tol;                   /* relative stop of those inner solves
                                          (0: always inner_iters steps)       */
   int setup_iters;                    /* inverse-iteration steps (3)          */
@@ -107,6 +108,12 @@ typedef struct {
   int setup_max_restarts;
   uint64_t seed;                      /* seed of the SETUP noise             */
   int precision;                      /* MGM_PREC_FP64 | MGM_PREC_FP32       */
+  int mlmc_levels;                    /* levels 0..mlmc_levels-1 form the
+                                         MLMC telescoping sum; level
+                                         mlmc_levels-1 is inverted densely
+                                         for its exact trace and exact
+                                         solves.  Coarser levels only serve
+                                         the preconditioner.  0 = nlevels.  */
 } mgm_mg_params;
 
 int mgm_setup_mg(mgm_ctx *ctx, int gauge_id, const mgm_mg_params *prm);
@@ -135,7 +142,8 @@ int mgm_precondition(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void
  * complex128 [nagg][2][bx*bt*M_level/2][ntv]. */
 int mgm_get_prolongator(mgm_ctx *ctx, int gauge_id, int level, void *out);
 
-/* tr(D_{L-1}^{-1}) of the coarsest level, out[0] = re, out[1] = im (HOST). */
+/* tr(D_T^{-1}) of the MLMC coarsest level T = mlmc_levels-1, out[0] = re,
+ * out[1] = im (HOST). */
 int mgm_coarsest_trace(mgm_ctx *ctx, int gauge_id, double *out);
 
 /* ---------------------------------------------------------------------------

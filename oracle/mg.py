@@ -249,7 +249,8 @@ class KCycle:
     M_l(r):  x  = P_l C_{l+1}(P_l^H r)
              x  = SAP_l(r, x)                      (sap_cycles[l] red/black cycles)
     C_{L-1}  = D_{L-1}^{-1} (dense, exact)
-    C_j      = inner_iters[j] steps of FGMRES on D_j preconditioned by M_j (0 < j < L-1)
+    C_j      = inner_iters[j] steps of FGMRES on D_j preconditioned by M_j (0 < j < L-1),
+               or, when inner_iters[j] == 0, one application of M_j (a V-cycle level)
     """
 
     def __init__(self, hier: Hierarchy, prm: CycleParams):
@@ -263,6 +264,8 @@ class KCycle:
         L = self.h.L
         if l == L - 1:
             return self.coarse_inv @ rc
+        if self.prm.inner_iters[l] == 0:
+            return self.apply(l, rc)
         return fgmres_fixed(self.h.levels[l].D, rc, self.prm.inner_iters[l],
                             lambda v: self.apply(l, v))
 

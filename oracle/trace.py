@@ -70,6 +70,7 @@ class TraceParams:
     max_samples: int = 1_000_000
     fixed_samples: Optional[list] = None   # replay mode: exact sample counts
     seed: int = 1
+    levels: int = 0                    # hierarchy levels used by the MLMC variants (0 = all)
 
 
 @dataclass
@@ -97,19 +98,22 @@ class StochLevel:
         return float(np.sum(np.abs(t - t.mean()) ** 2) / (len(t) - 1))
 
 
-def _cost_model(hier: Hierarchy, l: int, n: int, d: int) -> float:
+def _cost_model(hier: Hierarchy, l: int, n: int, d: int, L: int) -> float:
     def nnz(j):
         lev = hier.levels[j]
         return 9 * lev.n if j == 0 else 5 * lev.M * lev.n
     c = nnz(l) + 2 * n * d
-    if l + 1 < hier.L:
+    if l + 1 < L:
         c += nnz(l + 1)
     return float(c)
 
 
-def level_ops(hier: Hierarchy, variant: str, form: str):
-    """List of (apply_A, n) for the stochastic levels and the exact part."""
-    L = hier.L
+def level_ops(hier: Hierarchy, variant: str, form: str, levels: int = 0):
+    """List of (apply_A, n) for the stochastic levels and the exact part.
+
+    ``levels`` < hier.L closes the telescoping sum at level ``levels - 1``:
+    the coarser levels of the hierarchy then only serve the solver."""
+    L = levels if levels else hier.L
     if variant in ("hutchinson", "hutchpp"):
         lev0 = hier.levels[0]
         return [(lev0.solve, lev0.n)], 0.0
@@ -164,13 +168,14 @@ def sample(lvl: StochLevel, noise: str, seed: int, level: int, index: int) -> co
 
 
 def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
-    ops, tau_exact = level_ops(hier, prm.variant, prm.form)
+    ops, tau_exact = level_ops(hier, prm.variant, prm.form, prm.levels)
     nl = len(ops)
     use_lr = prm.variant in ("hutchpp", "mlmcpp")
     levels = []
     for l, (A, n) in enumerate(ops):
         d = prm.d[l] if use_lr else 0
-        cost = prm.fixed_cost[l] if prm.fixed_cost is not None else _cost_model(hier, l, n, d)
+        cost = (prm.fixed_cost[l] if prm.fixed_cost is not None
+                else _cost_model(hier, l, n, d, prm.levels or hier.L))
         levels.append(StochLevel(A, n, d, cost))
 
     # deflation vectors and low-rank parts (Alg. 2, first loop)

@@ -41,6 +41,7 @@ class MGParams(C.Structure):
         ("setup_max_restarts", C.c_int),
         ("seed", C.c_uint64),
         ("precision", C.c_int),
+        ("mlmc_levels", C.c_int),
     ]
 
 
@@ -156,9 +157,10 @@ def _check_vec(t, n: int | None = None):
 
 def mg_params(nlevels, blocks, ntv, sap_block=None, sap_cycles=None, inner_iters=None,
               inner_tol=0.0, setup_iters=3, setup_tol=1e-12, setup_restart=32,
-              setup_max_restarts=200, seed=1, precision="fp64") -> MGParams:
+              setup_max_restarts=200, seed=1, precision="fp64", mlmc_levels=0) -> MGParams:
     p = MGParams()
     p.nlevels = nlevels
+    p.mlmc_levels = mlmc_levels
     for l, (bx, bt) in enumerate(blocks):
         p.block[l][0], p.block[l][1] = bx, bt
     for l, v in enumerate(ntv):

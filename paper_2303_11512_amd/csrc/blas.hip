@@ -353,41 +353,53 @@ __global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ parti
 
 // G + shift * tr(G)/d * I = R^H R (R upper, positive real diagonal); on exit G
 // holds R^{-1} (upper).
-__global__ void k_cholesky_rinv(cd* __restrict__ G, cd* __restrict__ R, int d, double shift,
-                                int* __restrict__ fail) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (shift > 0.0) {
-    double tr = 0.0;
-    for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
-    for (int j = 0; j < d; ++j) G[j * d + j].re += shift * tr;
-  }
-  for (int j = 0; j < d; ++j)
-    for (int i = 0; i < d; ++i) R[j * d + i] = mk(0.0, 0.0);
-  for (int j = 0; j < d; ++j) {
-    double s = G[j * d + j].re;
-    for (int k = 0; k < j; ++k) s -= abs2(R[k * d + j]);
-    if (!(s > 0.0)) {
-      *fail = 1;
-      return;
-    }
-    const double rjj = sqrt(s);
-    R[j * d + j] = mk(rjj, 0.0);
-    for (int i = j + 1; i < d; ++i) {
-      cd t = G[j * d + i];
-      for (int k = 0; k < j; ++k) t = t - cjmul(R[k * d + j], R[k * d + i]);
-      R[j * d + i] = mk(t.re / rjj, t.im / rjj);
+// One wave (64 threads, d <= 64): right-looking Cholesky in R, then every
+// thread back-substitutes one column of R^{-1}.
+__global__ void __launch_bounds__(64) k_cholesky_rinv(cd* __restrict__ G, cd* __restrict__ R, int d,
+                                                      double shift, int* __restrict__ fail) {
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    bad = 0;
+    if (shift > 0.0) {
+      double tr = 0.0;
+      for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
+      for (int j = 0; j < d; ++j) G[j * d + j].re += shift * tr;
     }
   }
-  // upper-triangular inverse, column by column
-  for (int j = 0; j < d; ++j)
-    for (int i = 0; i < d; ++i) G[i * d + j] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int e = t; e < d * d; e += 64) R[e] = ((e % d) >= (e / d)) ? G[e] : mk(0.0, 0.0);
+  __syncthreads();
   for (int j = 0; j < d; ++j) {
+    if (t == 0) {
+      const double s = R[j * d + j].re;
+      if (!(s > 0.0)) bad = 1;
+      R[j * d + j] = mk(s > 0.0 ? sqrt(s) : 1.0, 0.0);
+    }
+    __syncthreads();
+    if (bad) break;
     const double rjj = R[j * d + j].re;
-    G[j * d + j] = mk(1.0 / rjj, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      cd t = mk(0.0, 0.0);
-      for (int k = i; k < j; ++k) cfma(t, G[i * d + k], R[k * d + j]);
-      G[i * d + j] = mk(-t.re / rjj, -t.im / rjj);
+    for (int i = j + 1 + t; i < d; i += 64) R[j * d + i] = (1.0 / rjj) * R[j * d + i];
+    __syncthreads();
+    const int m = d - j - 1;
+    for (int e = t; e < m * m; e += 64) {
+      const int k = j + 1 + e / m, i = j + 1 + e % m;
+      if (i >= k) R[k * d + i] = R[k * d + i] - cjmul(R[j * d + k], R[j * d + i]);
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) *fail = 1;
+    return;
+  }
+  // column t of R^{-1}: R x = e_t by back substitution, written to G
+  if (t < d) {
+    for (int i = d - 1; i > t; --i) G[i * d + t] = mk(0.0, 0.0);
+    G[t * d + t] = mk(1.0 / R[t * d + t].re, 0.0);
+    for (int i = t - 1; i >= 0; --i) {
+      cd acc = mk(0.0, 0.0);
+      for (int k = i + 1; k <= t; ++k) cfma(acc, R[i * d + k], G[k * d + t]);
+      G[i * d + t] = (-1.0 / R[i * d + i].re) * acc;
     }
   }
 }

@@ -231,6 +231,7 @@ struct Level {
   int bx = 0, bt = 0, ntv = 0;  // aggregation to level+1 (0 on the coarsest)
   int sbx = 0, sbt = 0, K = 0, nblk = 0, sap_cycles = 0, inner_iters = 0;
   bool has_coarse = false, is_coarsest = false;
+  bool has_dense = false;  // dense inverse available (coarsest or MLMC-closing level)
   DevBuf color_list[2];
   int ncolor[2] = {0, 0};
   LevelData<double> d;
@@ -249,7 +250,8 @@ struct Gauge {
   std::vector<std::unique_ptr<Level>> levels;
   bool mg_ready = false;
   mgm_mg_params prm{};
-  double trL[2] = {0, 0};
+  int mlmc_levels = 0;      // levels of the MLMC telescoping sum
+  double trL[2] = {0, 0};   // tr(D^{-1}) of level mlmc_levels-1
 };
 
 }  // namespace mgm

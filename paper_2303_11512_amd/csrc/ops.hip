@@ -183,6 +183,48 @@ __global__ void __launch_bounds__(NT) k_stencil(const cx<T>* __restrict__ B, int
   y[(int64_t)r * n + idx] = acc;
 }
 
+// Coarse levels: one workgroup per site and up to `rpc` RHS.  The site's five
+// M x M blocks are staged once in LDS, transposed ([d][j][i]) so that the M
+// lanes computing rows i of one RHS read consecutive words; x is read with a
+// broadcast across those lanes.  256/M RHS per round.
+template <class T, int M>
+__global__ void __launch_bounds__(NT) k_stencil_lds(const cx<T>* __restrict__ B, int Nx, int Nt,
+                                                    int nrhs, int rpc, const cx<T>* __restrict__ x,
+                                                    cx<T>* __restrict__ y, const cx<T>* __restrict__ b,
+                                                    const int* __restrict__ active) {
+  __shared__ cx<T> BT[5 * M * M];
+  constexpr int RPW = NT / M;
+  const int tid = threadIdx.x;
+  const int64_t u = blockIdx.x;
+  for (int e = tid; e < 5 * M * M; e += NT) {
+    const int j = e % M, i = (e / M) % M, d = e / (M * M);
+    BT[(d * M + j) * M + i] = B[u * 5 * M * M + e];
+  }
+  __syncthreads();
+  const int i = tid % M, rl = tid / M;
+  const int64_t n = (int64_t)Nx * Nt * M;
+  int64_t nbs[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) nbs[d] = nb_site(u, d, Nx, Nt) * M;
+  const int rbeg = blockIdx.y * rpc;
+  const int rend = min(nrhs, rbeg + rpc);
+  for (int r = rbeg + rl; r < rend; r += RPW) {
+    if (active && !active[r]) continue;
+    const cx<T>* __restrict__ xr = x + (int64_t)r * n;
+    cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      const cx<T>* __restrict__ xv = xr + nbs[d];
+      const cx<T>* bt = BT + d * M * M + i;
+#pragma unroll
+      for (int j = 0; j < M; ++j) cfma(acc, bt[j * M], xv[j]);
+    }
+    const int64_t o = (int64_t)r * n + u * M + i;
+    if (b) acc = b[o] - acc;
+    y[o] = acc;
+  }
+}
+
 // ------------------------------------------------------------------ restriction / prolongation
 // P[A][c][s][k]: row s of aggregate A, chirality c -- site sl = s / Mh of the
 // aggregate (t-major), dof c*Mh + s % Mh of that site; column k.
@@ -393,47 +435,82 @@ __global__ void __launch_bounds__(NT) k_small_inverse(cd* __restrict__ mats, int
 
 // One colour of the red/black Schwarz sweep with exact block solves:
 //   res_B = r_B - (D x)_B ;  x_B += inv_B res_B
-// for every listed block B.  K = sbx*sbt*M dofs per block, 256/K RHS per WG.
+// for every listed block B.  K = sbx*sbt*M dofs per block.  A workgroup owns
+// one block and `rpc` RHS: it stages the block inverse and the block's rows
+// of the stencil in LDS once (transposed, so that lanes of a wave read
+// consecutive words) and then sweeps its RHS 256/K at a time.
+constexpr int SAP_INV_MAX = 1024;   // K <= 32
+constexpr int SAP_B_MAX = 1280;     // sites_in_block * 5 * M * M staged in LDS
 template <class T>
 __global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
                                                   const cx<T>* __restrict__ inv, int Nx, int Nt, int M,
                                                   int sbx, int sbt, const int* __restrict__ blist,
-                                                  int nrhs, const cx<T>* __restrict__ rr,
+                                                  int nrhs, int rpc, const cx<T>* __restrict__ rr,
                                                   cx<T>* __restrict__ x,
                                                   const int* __restrict__ active) {
+  __shared__ cx<T> invT[SAP_INV_MAX];
+  __shared__ cx<T> BT[SAP_B_MAX];
   __shared__ cx<T> res[NT];
-  const int K = sbx * sbt * M;
+  const int nsb = sbx * sbt;
+  const int K = nsb * M;
   const int rpw = NT / K;
   const int tid = threadIdx.x;
   const int q = tid % K, rl = tid / K;
-  const int r = blockIdx.y * rpw + rl;
-  const bool valid = rl < rpw && r < nrhs && (!active || active[r]);
   const int blk = blist[blockIdx.x];
   const int NBx = Nx / sbx;
   const int ibx = blk % NBx, ibt = blk / NBx;
+  // stage inv^T and the block's stencil rows (B^T per direction)
+  for (int e = tid; e < K * K; e += NT) {
+    const int q1 = e / K, q2 = e % K;
+    invT[q2 * K + q1] = inv[((int64_t)blk * K + q1) * K + q2];
+  }
+  const int nbe = nsb * 5 * M * M;
+  const bool staged = nbe <= SAP_B_MAX;
+  if (staged) {
+    for (int e = tid; e < nbe; e += NT) {
+      const int b = e % M, a = (e / M) % M, d = (e / (M * M)) % 5, s = e / (5 * M * M);
+      const int64_t us = (int64_t)(ibt * sbt + s / sbx) * Nx + ibx * sbx + s % sbx;
+      BT[((s * 5 + d) * M + b) * M + a] = B[((us * 5 + d) * M + a) * M + b];
+    }
+  }
+  __syncthreads();
   const int sl = q / M, al = q % M;
   const int64_t u = (int64_t)(ibt * sbt + sl / sbx) * Nx + ibx * sbx + sl % sbx;
   const int64_t n = (int64_t)Nx * Nt * M;
-  if (valid) {
-    const cx<T>* __restrict__ xr = x + (int64_t)r * n;
-    cx<T> acc = rr[(int64_t)r * n + u * M + al];
-    for (int d = 0; d < 5; ++d) {
-      const cx<T>* __restrict__ row = B + ((u * 5 + d) * M + al) * M;
-      const cx<T>* __restrict__ xv = xr + nb_site(u, d, Nx, Nt) * M;
-      cx<T> t = mk<T>(0, 0);
-      for (int j = 0; j < M; ++j) cfma(t, row[j], xv[j]);
-      acc = acc - t;
+  int64_t nbs[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) nbs[d] = nb_site(u, d, Nx, Nt) * M;
+  const int rbeg = blockIdx.y * rpc;
+  const int rend = min(nrhs, rbeg + rpc);
+  for (int r0 = rbeg; r0 < rend; r0 += rpw) {
+    const int r = r0 + rl;
+    const bool valid = rl < rpw && r < rend && (!active || active[r]);
+    if (valid) {
+      const cx<T>* __restrict__ xr = x + (int64_t)r * n;
+      cx<T> acc = rr[(int64_t)r * n + u * M + al];
+      for (int d = 0; d < 5; ++d) {
+        const cx<T>* __restrict__ xv = xr + nbs[d];
+        cx<T> t = mk<T>(0, 0);
+        if (staged) {
+          const cx<T>* bt = BT + (sl * 5 + d) * M * M + al;
+          for (int j = 0; j < M; ++j) cfma(t, bt[j * M], xv[j]);
+        } else {
+          const cx<T>* __restrict__ row = B + ((u * 5 + d) * M + al) * M;
+          for (int j = 0; j < M; ++j) cfma(t, row[j], xv[j]);
+        }
+        acc = acc - t;
+      }
+      res[tid] = acc;
     }
-    res[tid] = acc;
-  }
-  __syncthreads();
-  if (valid) {
-    const cx<T>* __restrict__ irow = inv + ((int64_t)blk * K + q) * K;
-    const cx<T>* rs = res + rl * K;
-    cx<T> acc = mk<T>(0, 0);
-    for (int j = 0; j < K; ++j) cfma(acc, irow[j], rs[j]);
-    cx<T>* o = x + (int64_t)r * n + u * M + al;
-    *o = *o + acc;
+    __syncthreads();
+    if (valid) {
+      const cx<T>* rs = res + rl * K;
+      cx<T> acc = mk<T>(0, 0);
+      for (int j = 0; j < K; ++j) cfma(acc, invT[j * K + q], rs[j]);
+      cx<T>* o = x + (int64_t)r * n + u * M + al;
+      *o = *o + acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -556,6 +633,11 @@ __global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A,
   const int64_t i0 = (int64_t)blockIdx.x * TI;
   const int r0 = blockIdx.y * TR;
   const int il = tid % TI, rg = tid / TI;  // 4 groups of 4 RHS
+  if (active) {  // skip tiles whose RHS are all converged (uniform per workgroup)
+    bool any = false;
+    for (int q = 0; q < TR; ++q) any = any || (r0 + q < nrhs && active[r0 + q]);
+    if (!any) return;
+  }
   cx<T> acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
@@ -708,12 +790,19 @@ template <class T>
 void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, int nrhs,
                     const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active) {
   const int64_t n = (int64_t)Nx * Nt * M;
+  const int64_t sites = (int64_t)Nx * Nt;
   dim3 g(grid1(n), nrhs);
+  // LDS-staged variant: RHS per workgroup chosen to give ~1024 workgroups
+  int rpc = std::min(nrhs, 64);
+  if (sites < 1024) rpc = std::max(1, std::min(rpc, (int)(nrhs * sites / 1024 + 1)));
+  const int rpw = M > 0 ? NT / M : 1;
+  rpc = std::min(((rpc + rpw - 1) / rpw) * rpw, std::max(nrhs, 1));
+  dim3 gl((unsigned)sites, (nrhs + rpc - 1) / rpc);
   switch (M) {
     case 2: hipLaunchKernelGGL((k_stencil<T, 2>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
-    case 4: hipLaunchKernelGGL((k_stencil<T, 4>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
-    case 8: hipLaunchKernelGGL((k_stencil<T, 8>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
-    case 16: hipLaunchKernelGGL((k_stencil<T, 16>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
+    case 4: hipLaunchKernelGGL((k_stencil_lds<T, 4>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
+    case 8: hipLaunchKernelGGL((k_stencil_lds<T, 8>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
+    case 16: hipLaunchKernelGGL((k_stencil_lds<T, 16>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
     default: throw Error(MGM_EINVAL, "block stencil: dofs per site must be 2, 4, 8, 16 or 32");
   }
@@ -777,9 +866,15 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
                       cx<T>* x, const int* active) {
   if (nb <= 0) return;
   const int K = sbx * sbt * M;
+  require(K <= 32, "SAP block too large");
   const int rpw = NT / K;
-  hipLaunchKernelGGL(k_sap_sweep<T>, dim3(nb, (nrhs + rpw - 1) / rpw), dim3(NT), 0, s, B, inv, Nx, Nt,
-                     M, sbx, sbt, blist, nrhs, r, x, active);
+  // RHS per workgroup: all of them (up to 64) when there are enough blocks to
+  // fill the chip, fewer when the level is small
+  int rpc = std::min(nrhs, 64);
+  if (nb < 512) rpc = std::max(rpw, std::min(rpc, (int)((int64_t)nrhs * nb / 512 + 1)));
+  rpc = ((rpc + rpw - 1) / rpw) * rpw;
+  hipLaunchKernelGGL(k_sap_sweep<T>, dim3(nb, (nrhs + rpc - 1) / rpc), dim3(NT), 0, s, B, inv, Nx, Nt,
+                     M, sbx, sbt, blist, nrhs, rpc, r, x, active);
   KCHK();
 }
 template void launch_sap_sweep<double>(hipStream_t, const cd*, const cd*, int, int, int, int, int,

@@ -93,6 +93,8 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
     if (C.is_coarsest) {
       launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act);
+    } else if (C.inner_iters <= 0) {
+      precond<T>(c, g, l + 1, nrhs, rc, ec, act);  // plain V-cycle on the coarse level
     } else {
       fgmres_inner<T>(c, g, l + 1, nrhs, rc, ec, C.inner_iters, (T)g.prm.inner_tol, act);
     }
@@ -222,7 +224,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
   launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
-  if (L.is_coarsest) {
+  if (L.has_dense) {
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
@@ -372,17 +374,20 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
   launch_fine_blocks(s, g.links.as<cd>(), g.m0 + 2.0, g.Lx, g.Lt, L0->d.blocks.as<cd>());
   g.levels.push_back(std::move(L0));
 
-  for (int l = 0; l < Lv; ++l) {
-    Level& L = *g.levels[l];
-    L.is_coarsest = (l == Lv - 1);
-    if (L.is_coarsest) {
-      require(L.n <= 20000, "coarsest level too large for the dense inverse (n > 20000)");
-      DevBuf work;
-      work.ensure(sizeof(cd) * (size_t)L.n * L.n);
-      L.d.dinv.ensure(sizeof(cd) * (size_t)L.n * L.n);
-      launch_dense_from_stencil(s, L.d.B(), L.Nx, L.Nt, L.M, work.as<cd>());
-      if (dense_inverse(s, work.as<cd>(), L.n, L.d.dinv.as<cd>()))
-        throw Error(MGM_ENONFINITE, "coarsest operator is singular");
+  const int T = p.mlmc_levels > 0 ? p.mlmc_levels - 1 : Lv - 1;
+  require(T >= 0 && T < Lv, "mlmc_levels must be in [0, nlevels]");
+  g.mlmc_levels = T + 1;
+  // dense inverse of level l; its trace closes the MLMC sum when l == T
+  auto densify = [&](Level& L, int l) {
+    require(L.n <= 20000, "level too large for the dense inverse (n > 20000)");
+    DevBuf work;
+    work.ensure(sizeof(cd) * (size_t)L.n * L.n);
+    L.d.dinv.ensure(sizeof(cd) * (size_t)L.n * L.n);
+    launch_dense_from_stencil(s, L.d.B(), L.Nx, L.Nt, L.M, work.as<cd>());
+    if (dense_inverse(s, work.as<cd>(), L.n, L.d.dinv.as<cd>()))
+      throw Error(MGM_ENONFINITE, "operator of level " + std::to_string(l) + " is singular");
+    L.has_dense = true;
+    if (l == T) {
       DevBuf tr;
       tr.ensure(sizeof(cd));
       launch_diag_sum(s, L.d.dinv.as<cd>(), L.n, tr.as<cd>());
@@ -391,8 +396,17 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
       HIPCHK(hipStreamSynchronize(s));
       g.trL[0] = h.re;
       g.trL[1] = h.im;
+    }
+  };
+
+  for (int l = 0; l < Lv; ++l) {
+    Level& L = *g.levels[l];
+    L.is_coarsest = (l == Lv - 1);
+    if (L.is_coarsest) {
+      densify(L, l);
       break;
     }
+    if (l == T) densify(L, l);
     const int bx = p.block[l][0], bt = p.block[l][1], ntv = p.ntv[l];
     require(bx >= 1 && bt >= 1 && L.Nx % bx == 0 && L.Nt % bt == 0,
             "aggregate block must divide the level's lattice");

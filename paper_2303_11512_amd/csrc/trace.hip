@@ -62,7 +62,7 @@ struct Estimator {
 
   Estimator(mgm_ctx* c_, Gauge& g_, const mgm_trace_params& p_, mgm_trace_result& r_)
       : c(c_), g(g_), p(p_), res(r_) {
-    L = (int)g.levels.size();
+    L = g.mlmc_levels;
     full = p.form == MGM_FORM_FULL;
     hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
   }
@@ -255,28 +255,46 @@ struct Estimator {
       bool any = false;
       for (auto& sl : lv) any = any || sl.active;
       if (!any) break;
-      // speculative batch for every active level
+      // speculative batch for every active level.  The batch length only
+      // decides how much work may be discarded, never the result: in
+      // adaptive mode it is the number of samples the current variances and
+      // targets predict are still missing (all active levels advance
+      // together, as in Alg. 2), between 4 and p.batch.
+      int common = p.batch;
+      if (!p.fixed_samples) {
+        if (s < 2) {
+          common = std::max(minS, p.batch / 2);
+        } else {
+          const std::vector<double> w = weights(lv);
+          double need = 0;
+          for (int i = 0; i < nst; ++i) {
+            if (!lv[i].active) continue;
+            const double rho2 = w[i] * (p.eps * std::abs(tau)) * (p.eps * std::abs(tau));
+            const double want = rho2 > 0 ? lv[i].var() / rho2 : 1e30;
+            need = std::max(need, std::isfinite(want) ? want - lv[i].s() : 1e30);
+          }
+          common = (int)std::min<double>(p.batch, std::max(4.0, std::ceil(1.15 * need) + 2));
+        }
+      }
       std::vector<std::vector<zc>> vals(nst);
       for (int i = 0; i < nst; ++i) {
         if (!lv[i].active) continue;
-        int b = p.batch;
+        int b = common;
         if (p.fixed_samples) b = std::min(b, p.fixed_samples[i] - lv[i].s());
         b = std::min(b, maxS - lv[i].s());
         if (b > 0) sample_batch(i, lv[i], lv[i].s(), b, vals[i]);
       }
-      // replay Alg. 2 sample by sample
+      // replay Alg. 2 sample by sample; stop where an active level has no
+      // evaluated sample left (levels advance in lockstep)
       for (int t = 0; t < p.batch; ++t) {
-        bool any_active = false;
-        for (auto& sl : lv) any_active = any_active || sl.active;
-        if (!any_active) break;
-        bool consumed = false;
+        bool any_active = false, missing = false;
         for (int i = 0; i < nst; ++i) {
-          if (!lv[i].active) continue;
-          if (t >= (int)vals[i].size()) continue;
-          lv[i].samples.push_back(vals[i][t]);
-          consumed = true;
+          any_active = any_active || lv[i].active;
+          if (lv[i].active && t >= (int)vals[i].size()) missing = true;
         }
-        if (!consumed) break;
+        if (!any_active || missing) break;
+        for (int i = 0; i < nst; ++i)
+          if (lv[i].active) lv[i].samples.push_back(vals[i][t]);
         ++s;
         tau = tau_exact;
         for (auto& sl : lv) tau += sl.mean() + sl.tau_lr;

@@ -33,8 +33,9 @@ def rel_err(a, b):
 # One multigrid recipe used by both sides of a parity test.
 class Recipe:
     def __init__(self, theta, m0, blocks, ntv, seed=7, sap_block=None, sap_cycles=None,
-                 inner_iters=None, inner_tol=0.0, precision="fp64"):
+                 inner_iters=None, inner_tol=0.0, precision="fp64", mlmc_levels=0):
         self.theta, self.m0, self.blocks, self.ntv, self.seed = theta, m0, blocks, ntv, seed
+        self.mlmc_levels = mlmc_levels
         L = len(blocks) + 1
         self.L = L
         self.sap_block = sap_block or [blocks[0]] + [(1, 1)] * (L - 1)
@@ -49,7 +50,7 @@ class Recipe:
         ctx.setup_mg(gid, mg_params(self.L, self.blocks, self.ntv, sap_block=self.sap_block,
                                     sap_cycles=self.sap_cycles, inner_iters=self.inner_iters,
                                     inner_tol=self.inner_tol, seed=self.seed,
-                                    precision=self.precision))
+                                    precision=self.precision, mlmc_levels=self.mlmc_levels))
         return gid
 
     def oracle(self):

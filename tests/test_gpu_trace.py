@@ -110,6 +110,31 @@ def test_three_level_mlmcpp_parity(ctx, s32):
     assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
 
 
+def test_solver_only_coarse_level_and_vcycles(ctx):
+    """A 4-level solver hierarchy whose MLMC sum closes on level 2 (exact
+    dense trace there); level 3 only serves the preconditioner, and levels 1-2
+    use plain V-cycles instead of inner FGMRES."""
+    th = metropolis_u1(32, 32, 3.0, 100, 944)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2), (2, 2)], [8, 8, 8], seed=13,
+                 sap_block=[(4, 4), (1, 1), (1, 1), (1, 1)], inner_iters=[0, 0, 0, 0],
+                 mlmc_levels=3)
+    log("setup 4-level / mlmc 3")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    kc = rec.kcycle(hier)
+    from gpu_util import empty, rel_err, to_dev, to_host
+    from lattice_inputs import rhs_vectors
+    r = rhs_vectors(hier.levels[0].n, 2, 5)
+    x = empty(2, hier.levels[0].n)
+    ctx.precondition(gid, 0, to_dev(r), x)
+    assert rel_err(to_host(x), kc.apply(0, r.T).T) < 1e-7
+    kw = dict(variant="mlmcpp", eps=2e-2, d=[8, 8], k_power=2, noise="z2z2", seed=31, levels=3)
+    got = _gpu(ctx, gid, batch=16, **{k: v for k, v in kw.items() if k != "levels"})
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
+    assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
+
+
 def test_fixed_cost_and_full_form_s32(ctx, s32):
     rec, gid, hier = s32
     kw = dict(variant="mlmcpp", form="full", eps=5e-2, d=[4, 4], k_power=1, noise="z2z2", seed=8,
