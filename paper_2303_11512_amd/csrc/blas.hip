@@ -10,10 +10,24 @@ namespace mgm {
 namespace {
 
 constexpr int NT = 256;
-constexpr int EPT = 8;              // elements per thread per chunk
-constexpr int CH = NT * EPT;        // chunk length
 
-inline unsigned nchunks(int64_t n) { return (unsigned)((n + CH - 1) / CH); }
+// Elements per thread of the chunked reductions: the largest of 8, 4, 2, 1
+// that still gives ~1024 workgroups over all RHS (short vectors and few RHS
+// otherwise leave most of the 256 CUs idle).  Chunk length = 256 * EPT.
+inline int pick_ept(int64_t n, int nrhs) {
+  int e = 8;
+  while (e > 1 && ((n + NT * e - 1) / (NT * e)) * (int64_t)nrhs < 1024) e /= 2;
+  return e;
+}
+inline unsigned nchunks(int64_t n, int ept) { return (unsigned)((n + NT * ept - 1) / (NT * ept)); }
+
+#define EPT_DISPATCH(ept, KERNEL, ...)                           \
+  switch (ept) {                                                 \
+    case 8: { constexpr int E = 8; KERNEL; } break;              \
+    case 4: { constexpr int E = 4; KERNEL; } break;              \
+    case 2: { constexpr int E = 2; KERNEL; } break;              \
+    default: { constexpr int E = 1; KERNEL; } break;             \
+  }
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -55,11 +69,12 @@ __device__ __forceinline__ T block_sum_real(T v, T* sh) {
 }
 
 // partial[(r*nv + i)*nch + chunk] = sum_{k in chunk} conj(V_i[r][k]) w[r][k]
-template <class T>
+template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                   int nv, const cx<T>* __restrict__ w, int64_t n,
                                                   cx<T>* __restrict__ partial,
                                                   const int* __restrict__ active) {
+  constexpr int CH = NT * EPT;
   __shared__ T sh[8];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
@@ -102,13 +117,14 @@ __global__ void __launch_bounds__(NT) k_reduce_chunks(const cx<T>* __restrict__ 
 }
 
 // w[r] += sign * sum_i V_i[r] coef[r*ldc + i]; optional partial |w|^2 per chunk
-template <class T>
+template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                      int nv, const cx<T>* __restrict__ coef, int ldc,
                                                      T sign, cx<T>* __restrict__ w, int64_t n,
                                                      T* __restrict__ partial,
                                                      const int* __restrict__ active,
                                                      const int* __restrict__ nlim) {
+  constexpr int CH = NT * EPT;
   __shared__ cx<T> cs[64];
   __shared__ T sh[8];
   const int r = blockIdx.y;
@@ -148,10 +164,11 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
   }
 }
 
-template <class T>
+template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w, int64_t n,
                                                      T* __restrict__ partial,
                                                      const int* __restrict__ active) {
+  constexpr int CH = NT * EPT;
   __shared__ T sh[8];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
@@ -425,9 +442,10 @@ void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                          const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
                          const int* active, cx<T>* partial) {
   if (nv <= 0) return;
-  const unsigned nch = nchunks(n);
-  hipLaunchKernelGGL(k_dot_multi<T>, dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv, w, n, partial,
-                     active);
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_dot_multi<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
+                                       nv, w, n, partial, active));
   KCHK();
   const int64_t tot = (int64_t)nv * nrhs;
   hipLaunchKernelGGL(k_reduce_chunks<T>, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, s, partial,
@@ -441,9 +459,11 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                          const int* active, T* norm_out, T* partial, const int* nlim) {
   require(nv <= 64, "update_multi: at most 64 vectors");
   if (nv <= 0) return;
-  const unsigned nch = nchunks(n);
-  hipLaunchKernelGGL(k_update_multi<T>, dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv, coef, ldc,
-                     sign, w, n, norm_out ? partial : (T*)nullptr, active, nlim);
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
+                                       nv, coef, ldc, sign, w, n, norm_out ? partial : (T*)nullptr,
+                                       active, nlim));
   KCHK();
   if (norm_out) {
     hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
@@ -455,8 +475,10 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
 template <class T>
 void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
                  T* partial) {
-  const unsigned nch = nchunks(n);
-  hipLaunchKernelGGL(k_norm_partial<T>, dim3(nch, nrhs), dim3(NT), 0, s, w, n, partial, active);
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, w, n,
+                                       partial, active));
   KCHK();
   hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
                      nrhs, out, active);

@@ -163,7 +163,7 @@ int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* scratch_out);
 void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out);
 template <class T>
 void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, const cx<T>* x,
-                        cx<T>* y, const int* active);
+                        cx<T>* y, const int* active, DevBuf* scratch);
 
 // ---------------------------------------------------------------- batched BLAS
 // V_i of RHS r sits at V + i*sI + r*sR (complex elements).
@@ -172,7 +172,8 @@ void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                          const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
                          const int* active, cx<T>* partial);
 // number of chunk partials a reduction over n elements produces
-inline int64_t reduce_chunks(int64_t n) { return (n + 2047) / 2048; }
+// (upper bound: the shortest chunk is 256 elements)
+inline int64_t reduce_chunks(int64_t n) { return (n + 255) / 256; }
 // w[r] += sign * sum_{i < min(nv, nlim[r])} V_i[r] coef[r*ldc + i]; optional ||w||
 template <class T>
 void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,

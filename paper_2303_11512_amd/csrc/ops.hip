@@ -620,14 +620,17 @@ __global__ void __launch_bounds__(NT) k_diag_sum(const cd* __restrict__ A, int64
   if (tid == 0) *out = part[0];
 }
 
-// y[r][i] = sum_j A[i][j] x[r][j]: tiles of 64 rows x 16 RHS, 32-wide k steps.
+// y[r][i] = sum_j A[i][j] x[r][j]: tiles of 64 rows x 16 RHS, 32-wide k steps,
+// the k range split over gridDim.z workgroups.  With a split, every
+// workgroup writes its partial sums to part[z][r][i] and k_dense_reduce adds
+// them in z order (deterministic); without, the tile is written to y.
 template <class T>
 __global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A, int64_t n, int nrhs,
-                                                    const cx<T>* __restrict__ x,
-                                                    cx<T>* __restrict__ y,
+                                                    int64_t klen, const cx<T>* __restrict__ x,
+                                                    cx<T>* __restrict__ y, cx<T>* __restrict__ part,
                                                     const int* __restrict__ active) {
   constexpr int TI = 64, TR = 16, TJ = 32;
-  __shared__ cx<T> As[TI][TJ + 1];
+  __shared__ cx<T> As[TJ][TI + 1];
   __shared__ cx<T> Xs[TR][TJ + 1];
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * TI;
@@ -638,25 +641,27 @@ __global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A,
     for (int q = 0; q < TR; ++q) any = any || (r0 + q < nrhs && active[r0 + q]);
     if (!any) return;
   }
+  const int64_t kb = (int64_t)blockIdx.z * klen;
+  const int64_t ke = min(n, kb + klen);
   cx<T> acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
-  for (int64_t j0 = 0; j0 < n; j0 += TJ) {
+  for (int64_t j0 = kb; j0 < ke; j0 += TJ) {
     for (int e = tid; e < TI * TJ; e += NT) {
       const int ii = e / TJ, jj = e % TJ;
       const int64_t gi = i0 + ii, gj = j0 + jj;
-      As[ii][jj] = (gi < n && gj < n) ? A[gi * n + gj] : mk<T>(0, 0);
+      As[jj][ii] = (gi < n && gj < ke) ? A[gi * n + gj] : mk<T>(0, 0);
     }
     for (int e = tid; e < TR * TJ; e += NT) {
       const int rr = e / TJ, jj = e % TJ;
       const int gr = r0 + rr;
       const int64_t gj = j0 + jj;
-      Xs[rr][jj] = (gr < nrhs && gj < n) ? x[(int64_t)gr * n + gj] : mk<T>(0, 0);
+      Xs[rr][jj] = (gr < nrhs && gj < ke) ? x[(int64_t)gr * n + gj] : mk<T>(0, 0);
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 8
     for (int jj = 0; jj < TJ; ++jj) {
-      const cx<T> a = As[il][jj];
+      const cx<T> a = As[jj][il];
 #pragma unroll
       for (int q = 0; q < 4; ++q) cfma(acc[q], a, Xs[rg * 4 + q][jj]);
     }
@@ -667,9 +672,24 @@ __global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int gr = r0 + rg * 4 + q;
-      if (gr < nrhs && (!active || active[gr])) y[(int64_t)gr * n + gi] = acc[q];
+      if (gr >= nrhs || (active && !active[gr])) continue;
+      if (gridDim.z == 1) y[(int64_t)gr * n + gi] = acc[q];
+      else part[((int64_t)blockIdx.z * nrhs + gr) * n + gi] = acc[q];
     }
   }
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_dense_reduce(const cx<T>* __restrict__ part, int ks, int64_t n,
+                                                     int nrhs, cx<T>* __restrict__ y,
+                                                     const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  cx<T> acc = mk<T>(0, 0);
+  for (int z = 0; z < ks; ++z) acc = acc + part[((int64_t)z * nrhs + r) * n + i];
+  y[(int64_t)r * n + i] = acc;
 }
 
 // qr+ of the rows of V (columns = test vectors, V[k][n]) belonging to each
@@ -933,14 +953,30 @@ void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out) {
 
 template <class T>
 void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, const cx<T>* x,
-                        cx<T>* y, const int* active) {
-  hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((n + 63) / 64), (nrhs + 15) / 16), dim3(NT), 0, s,
-                     A, n, nrhs, x, y, active);
+                        cx<T>* y, const int* active, DevBuf* scratch) {
+  const unsigned tiles_i = (unsigned)((n + 63) / 64), tiles_r = (unsigned)((nrhs + 15) / 16);
+  // split k until ~1024 workgroups, keeping k ranges of at least 128
+  int ks = 1;
+  while (ks < 16 && (int64_t)tiles_i * tiles_r * ks < 1024 && n / (2 * ks) >= 128) ks *= 2;
+  if (!scratch) ks = 1;
+  const int64_t klen = ((n + ks - 1) / ks + 31) / 32 * 32;
+  ks = (int)((n + klen - 1) / klen);
+  cx<T>* part = nullptr;
+  if (ks > 1) {
+    scratch->ensure(sizeof(cx<T>) * (size_t)ks * nrhs * n);
+    part = scratch->as<cx<T>>();
+  }
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3(tiles_i, tiles_r, ks), dim3(NT), 0, s, A, n, nrhs, klen, x, y,
+                     part, active);
   KCHK();
+  if (ks > 1) {
+    hipLaunchKernelGGL(k_dense_reduce<T>, dim3(grid1(n), nrhs), dim3(NT), 0, s, part, ks, n, nrhs, y, active);
+    KCHK();
+  }
 }
 template void launch_dense_apply<double>(hipStream_t, const cd*, int64_t, int, const cd*, cd*,
-                                         const int*);
+                                         const int*, DevBuf*);
 template void launch_dense_apply<float>(hipStream_t, const cf*, int64_t, int, const cf*, cf*,
-                                        const int*);
+                                        const int*, DevBuf*);
 
 }  // namespace mgm

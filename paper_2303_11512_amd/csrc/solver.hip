@@ -80,7 +80,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   Level& L = *g.levels[l];
   LevelData<T>& D = ldata<T>(L);
   if (L.is_coarsest) {
-    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act);
+    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &c->scratch);
     return;
   }
   if (L.has_coarse) {
@@ -92,7 +92,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     cx<T>* ec = W.ec.template as<cx<T>>();
     launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
     if (C.is_coarsest) {
-      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act);
+      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &c->scratch);
     } else if (C.inner_iters <= 0) {
       precond<T>(c, g, l + 1, nrhs, rc, ec, act);  // plain V-cycle on the coarse level
     } else {
@@ -225,7 +225,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
   if (L.has_dense) {
-    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr);
+    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &c->scratch);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
       // r0 = b - D x ; v0 = r0 / ||r0||

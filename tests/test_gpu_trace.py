@@ -135,6 +135,30 @@ def test_solver_only_coarse_level_and_vcycles(ctx):
     assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
 
 
+def test_fp32_preconditioner_keeps_fp64_results(ctx):
+    """Mixed precision: the whole multigrid cycle in FP32 inside FP64 FGMRES.
+    Every solve still meets its FP64 residual tolerance, so the estimate
+    matches the FP64 oracle on the same seeds."""
+    th = metropolis_u1(32, 32, 3.0, 100, 932)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (1, 1), (1, 1)],
+                 inner_iters=[0, 4, 4], precision="fp32")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    from gpu_util import empty, to_dev, to_host
+    from lattice_inputs import rhs_vectors
+    from paper_2303_11512_amd import solve_params
+    lev = hier.levels[0]
+    b = rhs_vectors(lev.n, 6, 17)
+    x = empty(6, lev.n)
+    st, its, rel = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=24))
+    res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
+    assert np.all(res <= 1e-10)
+    kw = dict(variant="mlmcpp", eps=2e-2, d=[8, 8], k_power=2, noise="z2z2", seed=21)
+    got = _gpu(ctx, gid, batch=32, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
+
+
 def test_fixed_cost_and_full_form_s32(ctx, s32):
     rec, gid, hier = s32
     kw = dict(variant="mlmcpp", form="full", eps=5e-2, d=[4, 4], k_power=1, noise="z2z2", seed=8,
