@@ -53,24 +53,35 @@ def trace_kwargs(cfg, step):
                 noise=cfg["noise"], targets="optimal", seed=cfg["trace_seed"] + step, batch=64)
 
 
-def time_apply(ctx, gid, level, nrhs, reps=20):
-    """Average duration (s) of one mgm_apply_D launch, HIP events on the
-    stream the library launches on (torch's current stream)."""
-    import torch
-    from lattice_inputs import rhs_vectors
-    n = ctx.level_info(gid, level)["n"]
-    x = torch.from_numpy(rhs_vectors(n, nrhs, 1)).to("cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        ctx.apply_D(gid, level, x, y)
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        ctx.apply_D(gid, level, x, y)
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+KERNEL_RHS = 64
+# the kernel with the largest share of the step's GPU time (rocprofv3 of the
+# 128^2 step): one colour of the fine-level SAP sweep
+DOMINANT = "sap_l0"
+
+
+def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None):
+    """Average launch duration (HIP events on the library's stream, 50
+    back-to-back launches), algorithmic bytes and flops of the step's hot
+    kernels at the step's shape."""
+    L = 0
+    while True:
+        try:
+            ctx.level_info(gid, L + 1)
+            L += 1
+        except Exception:
+            break
+    t = {
+        "stencil_l0": ctx.time_kernel(gid, "stencil", 0, nrhs),
+        "sap_l0": ctx.time_kernel(gid, "sap", 0, nrhs),
+        "sap_l1": ctx.time_kernel(gid, "sap", 1, nrhs),
+        "stencil_l1": ctx.time_kernel(gid, "stencil", 1, nrhs),
+        "cgs16_l0": ctx.time_kernel(gid, "cgs", 0, nrhs),
+        "copy_l0": ctx.time_kernel(gid, "copy", 0, nrhs),
+        "dense_l%d" % L: ctx.time_kernel(gid, "dense", L, nrhs),
+    }
+    if mlmc_coarsest is not None and mlmc_coarsest != L:
+        t["dense_l%d" % mlmc_coarsest] = ctx.time_kernel(gid, "dense", mlmc_coarsest, nrhs, reps=10)
+    return t
 
 
 def cpu_baseline(cfg, gpu_samples, budget_s=25.0):
@@ -134,6 +145,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="schwinger128")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the multigrid preconditioner (outer FGMRES is FP64)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="set up, time the hot kernels and exit (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -148,10 +163,15 @@ def main():
     ctx = Context(0)
     gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), cfg["m0"], True)
     t0 = time.perf_counter()
-    ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg)))
+    ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg), precision=args.precision))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"# setup done in {setup_s:.2f}s", file=sys.stderr, flush=True)
+    mlmc_coarsest = len(cfg["blocks"])
+    if args.roofline_only:
+        print(json.dumps(kernel_table(ctx, gid, mlmc_coarsest=mlmc_coarsest)))
+        ctx.close()
+        return
 
     sp = solve_params(tol=1e-10, restart=32, max_restarts=50)
     for w in range(args.warmup):
@@ -168,12 +188,9 @@ def main():
     dt = time.perf_counter() - t0
     solves = sum(sum(o["solves"]) for o in outs)
 
-    # roofline of the fine stencil at the step's RHS block (64)
-    nrhs = 64
-    t_k = time_apply(ctx, gid, 0, nrhs)
-    V = cfg["Lx"] * cfg["Lt"]
-    alg_bytes = V * (64 * nrhs + 32)
-    achieved = alg_bytes / t_k / 1e9
+    kern = kernel_table(ctx, gid, mlmc_coarsest=mlmc_coarsest)
+    dom = kern[DOMINANT]
+    achieved = dom["bytes"] / (dom["us"] * 1e-6) / 1e9
 
     samples = [int(sum(o["level_samples"][l] for o in outs) / len(outs)) for l in range(len(outs[0]["level_samples"]))]
     cpu = None
@@ -199,18 +216,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['Lx']}x{cfg['Lt']} Schwinger, beta {cfg['beta']}, "
                                f"m0 {cfg['m0']}, {len(cfg['blocks']) + 1}-level MG, Hutch++ d={cfg['d']}, "
                                f"{cfg['noise']} noise, eps {cfg['eps']}, FGMRES tol 1e-10",
                    "solves_per_s": solves / dt, "setup_s": setup_s,
+                   "preconditioner": args.precision,
+                   "solver_levels": mg_setup_kwargs(cfg)["nlevels"],
                    "iters_per_solve": [round(sum(o["iters"][l] for o in outs) / max(1, sum(o["solves"][l] for o in outs)), 2)
                                        for l in range(len(cfg["blocks"]) + 1)],
                    "level_samples": samples, "tau": [outs[-1]["tau"].real, outs[-1]["tau"].imag]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_wilson (fine stencil, 64 RHS)", "launch_us": t_k * 1e6},
+                     "kernel": f"k_sap_sweep<double> (level 0, one colour, {KERNEL_RHS} RHS)",
+                     "launch_us": dom["us"], "alg_bytes": dom["bytes"],
+                     "others": {k: {"us": round(v["us"], 2),
+                                    "GB/s": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1),
+                                    "TFLOP/s": round(v["flops"] / (v["us"] * 1e-6) / 1e12, 2)}
+                                for k, v in kern.items() if k != DOMINANT}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

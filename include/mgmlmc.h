@@ -239,6 +239,29 @@ typedef struct {
 int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
                        mgm_trace_result *res);
 
+/* ---------------------------------------------------------------------------
+ * time_kernel -- measurement helper for rooflines: launches one kernel of the
+ * path `reps` times back to back on the context stream (inputs: seeded noise
+ * vectors allocated by the library) and returns, between two HIP events, the
+ * average duration per launch in microseconds (*us_out), the algorithmic
+ * bytes one launch moves (*bytes_out: every operand counted once) and its
+ * algorithmic flops (*flops_out).  Synchronises.
+ *   MGM_KERNEL_STENCIL  y = D_level x
+ *   MGM_KERNEL_SAP      one red/black SAP colour sweep on `level`
+ *   MGM_KERNEL_DENSE    y = D_level^{-1} x with the dense inverse (level must
+ *                       have one)
+ *   MGM_KERNEL_CGS      one Gram-Schmidt projection pass against 16 vectors
+ *   MGM_KERNEL_COPY     y = x, a plain copy of nrhs * n_level complex128
+ * ------------------------------------------------------------------------- */
+#define MGM_KERNEL_STENCIL 0
+#define MGM_KERNEL_SAP 1
+#define MGM_KERNEL_DENSE 2
+#define MGM_KERNEL_CGS 3
+#define MGM_KERNEL_COPY 4
+
+int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
+                    double *us_out, double *bytes_out, double *flops_out);
+
 #ifdef __cplusplus
 }
 #endif

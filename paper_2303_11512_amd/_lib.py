@@ -116,7 +116,11 @@ SIGNATURES = {
                             _P]),
     "mgm_orthonormalize": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
     "mgm_trace_estimate": (C.c_int, [_P, C.c_int, C.POINTER(TraceParams), C.POINTER(TraceResult)]),
+    "mgm_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
+
+KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4}
 
 _lib = None
 
@@ -284,6 +288,14 @@ class Context:
         k = NOISES[kind] if isinstance(kind, str) else kind
         self._chk(self.lib.mgm_noise(self.h, k, C.c_uint64(seed), purpose, level, index0,
                                      out.shape[1], out.shape[0], _P(_ptr(out))), "noise")
+
+    def time_kernel(self, gid, kind, level, nrhs, reps=50) -> dict:
+        """Average launch duration (us), algorithmic bytes and flops of one
+        kernel of the path, timed with HIP events on the library's stream."""
+        us, by, fl = C.c_double(), C.c_double(), C.c_double()
+        self._chk(self.lib.mgm_time_kernel(self.h, gid, KERNELS[kind], level, nrhs, reps, C.byref(us),
+                                           C.byref(by), C.byref(fl)), "time_kernel")
+        return dict(us=us.value, bytes=by.value, flops=fl.value)
 
     def orthonormalize(self, Y, Q):
         self._chk(self.lib.mgm_orthonormalize(self.h, Y.shape[1], Y.shape[0], _P(_ptr(Y)),

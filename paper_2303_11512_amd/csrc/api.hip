@@ -2,6 +2,7 @@
 // validates its arguments, runs on the context's stream and converts internal
 // errors into status codes; nothing here aborts the process.
 #include <cstring>
+#include <functional>
 
 #include "internal.h"
 
@@ -237,6 +238,97 @@ int mgm_orthonormalize(mgm_ctx* c, int64_t n, int d, const void* Y, void* Q) {
   return guarded(c, [&] {
     require(Y && Q && Y != Q, "bad arguments");
     orthonormalize(c, n, d, static_cast<const cd*>(Y), static_cast<cd*>(Q));
+    return MGM_OK;
+  });
+}
+
+int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int reps,
+                    double* us_out, double* bytes_out, double* flops_out) {
+  return guarded(c, [&] {
+    require(us_out && bytes_out && flops_out && nrhs > 0 && reps > 0, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    Level& L = level_of(g, level);
+    hipStream_t s = c->stream;
+    const int64_t n = L.n;
+    const double b = nrhs;
+    c->scratch2.ensure(sizeof(cd) * (size_t)nrhs * n * 3);
+    cd* x = c->scratch2.as<cd>();
+    cd* y = x + (int64_t)nrhs * n;
+    cd* r = y + (int64_t)nrhs * n;
+    launch_noise<double>(s, x, n, nrhs, MGM_NOISE_Z2Z2, 11, 0, 0, 0);
+    launch_noise<double>(s, r, n, nrhs, MGM_NOISE_Z2Z2, 12, 0, 0, 0);
+    HIPCHK(hipMemcpyAsync(y, x, sizeof(cd) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, s));
+    std::function<void()> launch;
+    double bytes = 0, flops = 0;
+    switch (kind) {
+      case MGM_KERNEL_STENCIL:
+        // every lambda captures pointers and sizes by value: some of them
+        // are block-scoped and gone by the time launch() runs
+        launch = [=, &g] { apply_level(c, g, level, nrhs, x, y); };
+        if (level == 0) {
+          bytes = (double)L.sites * (64.0 * b + 32.0);
+          flops = (double)L.sites * b * 8.0 * 2.0 * 9.0;
+        } else {
+          bytes = 32.0 * n * b + 16.0 * L.sites * 5.0 * L.M * L.M;
+          flops = 8.0 * L.sites * 5.0 * L.M * L.M * b;
+        }
+        break;
+      case MGM_KERNEL_SAP: {
+        require(g.mg_ready && L.ncolor[0] > 0, "SAP needs setup_mg on this level", MGM_ESTATE);
+        launch = [=, &L] {
+          launch_sap_sweep<double>(s, L.d.B(), L.d.sapinv.as<cd>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
+                                   L.color_list[0].as<int>(), L.ncolor[0], nrhs, r, y, nullptr);
+        };
+        const double nb = L.ncolor[0], nsb = (double)L.sbx * L.sbt;
+        const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // neighbour dofs per block
+        bytes = 16.0 * b * nb * (3.0 * L.K + halo) + 16.0 * nb * ((double)L.K * L.K + nsb * 5.0 * L.M * L.M);
+        flops = 8.0 * b * nb * ((double)L.K * L.K + nsb * 5.0 * L.M * L.M);
+        break;
+      }
+      case MGM_KERNEL_DENSE:
+        require(L.has_dense, "level has no dense inverse", MGM_ESTATE);
+        launch = [=, &L] {
+          launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, x, y, nullptr, &c->scratch);
+        };
+        bytes = 16.0 * n * n + 32.0 * n * b;
+        flops = 8.0 * n * n * b;
+        break;
+      case MGM_KERNEL_CGS: {
+        const int nv = 16;
+        c->scratch3.ensure(sizeof(cd) * (size_t)nrhs * (nv + 1) * reduce_chunks(n) + sizeof(cd) * nrhs * nv);
+        cd* out = c->scratch3.as<cd>();
+        cd* part = out + (int64_t)nrhs * nv;
+        // V_i of RHS r = x shifted by i elements (in bounds: i <= 15 < n)
+        require(n > 16, "level too small for the CGS probe");
+        launch = [=] {
+          launch_dot_multi_ld<double>(s, x, 1, n, nv, y, n - nv, nrhs, out, nv, 0, nullptr, part);
+        };
+        bytes = 16.0 * (nv + 1) * n * b;
+        flops = 8.0 * nv * n * b;
+        break;
+      }
+      case MGM_KERNEL_COPY:
+        launch = [=] { launch_axpby<double>(s, 1.0, x, 0.0, nullptr, y, n, nrhs, nullptr); };
+        bytes = 32.0 * n * b;
+        break;
+      default:
+        throw Error(MGM_EINVAL, "unknown kernel kind");
+    }
+    launch();  // warm up
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us_out = 1e3 * ms / reps;
+    *bytes_out = bytes;
+    *flops_out = flops;
     return MGM_OK;
   });
 }

@@ -102,6 +102,20 @@ def test_preconditioner_matches_reference_kcycle(ctx, built):
         assert rel_err(to_host(x), want) < 1e-7, (name, l)
 
 
+def test_time_kernel_helper(ctx, built):
+    """The measurement helper runs every kernel kind and reports positive
+    durations and the algorithmic byte counts of its formula."""
+    name, rec, gid, hier = built
+    L = hier.L - 1
+    n0 = hier.levels[0].n
+    for kind, level in [("stencil", 0), ("sap", 0), ("stencil", L), ("cgs", 0), ("copy", 0),
+                        ("dense", L)]:
+        log(f"{name}: time_kernel {kind} level {level}")
+        t = ctx.time_kernel(gid, kind, level, 3, reps=3)
+        assert t["us"] > 0 and t["bytes"] > 0
+    assert ctx.time_kernel(gid, "copy", 0, 3, reps=2)["bytes"] == 32.0 * n0 * 3
+
+
 @pytest.mark.parametrize("nrhs", [1, 5])
 def test_solves_reach_tolerance(ctx, built, nrhs):
     from paper_2303_11512_amd import solve_params
