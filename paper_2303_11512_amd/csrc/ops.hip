@@ -192,15 +192,15 @@ __global__ void __launch_bounds__(NT) k_stencil_lds(const cx<T>* __restrict__ B,
                                                     int nrhs, int rpc, const cx<T>* __restrict__ x,
                                                     cx<T>* __restrict__ y, const cx<T>* __restrict__ b,
                                                     const int* __restrict__ active) {
-  __shared__ cx<T> BT[5 * M * M];
   constexpr int RPW = NT / M;
+  __shared__ cx<T> BT[5 * M * M];
+  __shared__ cx<T> XS[RPW * 5 * M];  // the five neighbour sites' dofs of RPW RHS
   const int tid = threadIdx.x;
   const int64_t u = blockIdx.x;
   for (int e = tid; e < 5 * M * M; e += NT) {
     const int j = e % M, i = (e / M) % M, d = e / (M * M);
     BT[(d * M + j) * M + i] = B[u * 5 * M * M + e];
   }
-  __syncthreads();
   const int i = tid % M, rl = tid / M;
   const int64_t n = (int64_t)Nx * Nt * M;
   int64_t nbs[5];
@@ -208,20 +208,29 @@ __global__ void __launch_bounds__(NT) k_stencil_lds(const cx<T>* __restrict__ B,
   for (int d = 0; d < 5; ++d) nbs[d] = nb_site(u, d, Nx, Nt) * M;
   const int rbeg = blockIdx.y * rpc;
   const int rend = min(nrhs, rbeg + rpc);
-  for (int r = rbeg + rl; r < rend; r += RPW) {
-    if (active && !active[r]) continue;
-    const cx<T>* __restrict__ xr = x + (int64_t)r * n;
-    cx<T> acc = mk<T>(0, 0);
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      const cx<T>* __restrict__ xv = xr + nbs[d];
-      const cx<T>* bt = BT + d * M * M + i;
-#pragma unroll
-      for (int j = 0; j < M; ++j) cfma(acc, bt[j * M], xv[j]);
+  for (int r0 = rbeg; r0 < rend; r0 += RPW) {
+    // cooperative, row-contiguous load of the neighbour dofs of this round's RHS
+    for (int e = tid; e < RPW * 5 * M; e += NT) {
+      const int j = e % M, d = (e / M) % 5, rr = e / (5 * M);
+      const int r = r0 + rr;
+      XS[e] = (r < rend) ? x[(int64_t)r * n + nbs[d] + j] : mk<T>(0, 0);
     }
-    const int64_t o = (int64_t)r * n + u * M + i;
-    if (b) acc = b[o] - acc;
-    y[o] = acc;
+    __syncthreads();
+    const int r = r0 + rl;
+    if (r < rend && (!active || active[r])) {
+      const cx<T>* xs = XS + rl * 5 * M;
+      cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        const cx<T>* bt = BT + d * M * M + i;
+#pragma unroll
+        for (int j = 0; j < M; ++j) cfma(acc, bt[j * M], xs[d * M + j]);
+      }
+      const int64_t o = (int64_t)r * n + u * M + i;
+      if (b) acc = b[o] - acc;
+      y[o] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -512,6 +521,40 @@ __global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ MFMA variants
+// 16x16x4 matrix-core step in the precision of the cycle.  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; element v of its result is
+// D[out_row(l, v)][l%16]: rows l/16 + 4v for FP64, 4(l/16) + v for FP32
+// (both measured on gfx950 with an in-bounds probe).
+template <class T>
+struct MF;
+template <>
+struct MF<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MF<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Complex products as real GEMMs: a complex K x K matrix A and a block of
+// complex vectors X (K x R) give Y = A X through the real matrices
+//   Ar[i][2j] = Re A[i][j],  Ar[i][2j+1] = Im A[i][j]
+//   Xr[2j][2r] = Re x,  Xr[2j+1][2r] = -Im x,  Xr[2j][2r+1] = Im x,  Xr[2j+1][2r+1] = Re x
+// so that (Ar Xr)[i][2r] = Re y[r][i] and (Ar Xr)[i][2r+1] = Im y[r][i].
+template <class T>
+__device__ __forceinline__ T xr_elem(cx<T> v, int q, int p) {
+  return p == 0 ? (q == 0 ? v.re : -v.im) : (q == 0 ? v.im : v.re);
 }
 
 // ------------------------------------------------------------------ dense coarsest level
@@ -812,9 +855,8 @@ void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, i
   const int64_t n = (int64_t)Nx * Nt * M;
   const int64_t sites = (int64_t)Nx * Nt;
   dim3 g(grid1(n), nrhs);
-  // LDS-staged variant: RHS per workgroup chosen to give ~1024 workgroups
-  int rpc = std::min(nrhs, 64);
-  if (sites < 1024) rpc = std::max(1, std::min(rpc, (int)(nrhs * sites / 1024 + 1)));
+  // LDS-staged variant: RHS per workgroup chosen to give ~2048 workgroups
+  int rpc = (int)std::min<int64_t>(std::min(nrhs, 64), std::max<int64_t>(1, (int64_t)nrhs * sites / 2048));
   const int rpw = M > 0 ? NT / M : 1;
   rpc = std::min(((rpc + rpw - 1) / rpw) * rpw, std::max(nrhs, 1));
   dim3 gl((unsigned)sites, (nrhs + rpc - 1) / rpc);
@@ -888,10 +930,11 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   const int K = sbx * sbt * M;
   require(K <= 32, "SAP block too large");
   const int rpw = NT / K;
-  // RHS per workgroup: all of them (up to 64) when there are enough blocks to
-  // fill the chip, fewer when the level is small
-  int rpc = std::min(nrhs, 64);
-  if (nb < 512) rpc = std::max(rpw, std::min(rpc, (int)((int64_t)nrhs * nb / 512 + 1)));
+  // RHS per workgroup: enough workgroups (~2048, 8 per CU) to hide the
+  // memory latency of each round, at the price of re-reading the block's
+  // matrices from L2 once per workgroup
+  int rpc = (int)std::min<int64_t>(std::min(nrhs, 64), std::max<int64_t>(1, (int64_t)nrhs * nb / 2048));
+  rpc = std::max(rpc, rpw);
   rpc = ((rpc + rpw - 1) / rpw) * rpw;
   hipLaunchKernelGGL(k_sap_sweep<T>, dim3(nb, (nrhs + rpc - 1) / rpc), dim3(NT), 0, s, B, inv, Nx, Nt,
                      M, sbx, sbt, blist, nrhs, rpc, r, x, active);
