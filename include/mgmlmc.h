@@ -114,6 +114,8 @@ typedef struct {
                                          for its exact trace and exact
                                          solves.  Coarser levels only serve
                                          the preconditioner.  0 = nlevels.  */
+  int graphs;                         /* 1: replay preconditioner
+                                         applications as captured HIP graphs */
 } mgm_mg_params;
 
 int mgm_setup_mg(mgm_ctx *ctx, int gauge_id, const mgm_mg_params *prm);
@@ -160,7 +162,8 @@ typedef struct {
   double tol;        /* relative residual, e.g. 1e-10 */
   int restart;       /* FGMRES restart length m       */
   int max_restarts;
-  int rhs_block;     /* RHS solved together (0 = all) */
+  int rhs_block;     /* RHS solved together (0 = all, -1 = the autotuned
+                        width of the level, all if none) */
 } mgm_solve_params;
 
 typedef struct {
@@ -170,6 +173,29 @@ typedef struct {
 
 int mgm_solve_batch(mgm_ctx *ctx, int gauge_id, int level, int nrhs, const void *b, void *x,
                     const mgm_solve_params *prm, mgm_solve_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * solve_jobs -- many independent solve batches, possibly on different gauge
+ * fields and lattice sizes, in one call.  Each gauge field owns a HIP stream
+ * and its workspaces; the jobs of one field run in order on its stream, the
+ * fields run concurrently (one host thread each), so small lattices share the
+ * GPU.  Every RHS meets prm->tol as in mgm_solve_batch.  iters (optional,
+ * HOST, sum of nrhs entries in job order) receives FGMRES iterations.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int gauge_id, level, nrhs;
+  const void *b;  /* DEVICE [nrhs][n_level] */
+  void *x;        /* DEVICE [nrhs][n_level] */
+} mgm_job;
+
+int mgm_solve_jobs(mgm_ctx *ctx, int njobs, const mgm_job *jobs, const mgm_solve_params *prm,
+                   int *iters);
+
+/* autotune_rhs_block -- time solves of nrhs noise vectors on `level` with RHS
+ * block widths 8, 16, 32 and 64 (up to nrhs) and keep the fastest for
+ * rhs_block = -1; the width is written to *best. */
+int mgm_autotune_rhs_block(mgm_ctx *ctx, int gauge_id, int level, int nrhs,
+                           const mgm_solve_params *prm, int *best);
 
 /* ---------------------------------------------------------------------------
  * noise -- nrhs isotropic vectors of length n written to DEVICE out

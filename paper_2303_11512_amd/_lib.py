@@ -42,6 +42,7 @@ class MGParams(C.Structure):
         ("seed", C.c_uint64),
         ("precision", C.c_int),
         ("mlmc_levels", C.c_int),
+        ("graphs", C.c_int),
     ]
 
 
@@ -118,7 +119,15 @@ SIGNATURES = {
     "mgm_trace_estimate": (C.c_int, [_P, C.c_int, C.POINTER(TraceParams), C.POINTER(TraceResult)]),
     "mgm_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mgm_solve_jobs": (C.c_int, [_P, C.c_int, _P, C.POINTER(SolveParams), C.POINTER(C.c_int)]),
+    "mgm_autotune_rhs_block": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(SolveParams),
+                                         C.POINTER(C.c_int)]),
 }
+
+
+class Job(C.Structure):
+    _fields_ = [("gauge_id", C.c_int), ("level", C.c_int), ("nrhs", C.c_int),
+                ("b", C.c_void_p), ("x", C.c_void_p)]
 
 KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4}
 
@@ -161,10 +170,12 @@ def _check_vec(t, n: int | None = None):
 
 def mg_params(nlevels, blocks, ntv, sap_block=None, sap_cycles=None, inner_iters=None,
               inner_tol=0.0, setup_iters=3, setup_tol=1e-12, setup_restart=32,
-              setup_max_restarts=200, seed=1, precision="fp64", mlmc_levels=0) -> MGParams:
+              setup_max_restarts=200, seed=1, precision="fp64", mlmc_levels=0,
+              graphs=True) -> MGParams:
     p = MGParams()
     p.nlevels = nlevels
     p.mlmc_levels = mlmc_levels
+    p.graphs = int(bool(graphs))
     for l, (bx, bt) in enumerate(blocks):
         p.block[l][0], p.block[l][1] = bx, bt
     for l, v in enumerate(ntv):
@@ -283,6 +294,30 @@ class Context:
         if check:
             self._chk(st, "solve_batch")
         return st, np.array(its[:]), np.array(rel[:])
+
+    def solve_jobs(self, jobs, prm: SolveParams | None = None, check: bool = True):
+        """jobs: list of (gauge_id, level, b, x) with b, x device tensors
+        (nrhs, n_level).  Returns (status, iterations per RHS in job order)."""
+        prm = prm or solve_params()
+        arr = (Job * len(jobs))()
+        total = 0
+        for k, (gid, level, b, x) in enumerate(jobs):
+            _check_vec(b)
+            _check_vec(x)
+            arr[k] = Job(gid, level, b.shape[0], _ptr(b), _ptr(x))
+            total += b.shape[0]
+        its = (C.c_int * max(1, total))()
+        st = self.lib.mgm_solve_jobs(self.h, len(jobs), C.cast(arr, _P), C.byref(prm), its)
+        if check:
+            self._chk(st, "solve_jobs")
+        return st, np.array(its[:total])
+
+    def autotune_rhs_block(self, gid, level, nrhs, prm: SolveParams | None = None) -> int:
+        prm = prm or solve_params()
+        best = C.c_int()
+        self._chk(self.lib.mgm_autotune_rhs_block(self.h, gid, level, nrhs, C.byref(prm),
+                                                  C.byref(best)), "autotune_rhs_block")
+        return best.value
 
     def noise(self, kind, seed, purpose, level, index0, out):
         k = NOISES[kind] if isinstance(kind, str) else kind

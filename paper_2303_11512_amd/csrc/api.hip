@@ -3,6 +3,7 @@
 // errors into status codes; nothing here aborts the process.
 #include <cstring>
 #include <functional>
+#include <thread>
 
 #include "internal.h"
 
@@ -10,10 +11,15 @@ using namespace mgm;
 
 namespace mgm {
 
-// Solve in chunks of sp.rhs_block right-hand sides (all at once when 0).
+std::atomic<uint64_t> g_alloc_epoch{0};
+
+// Solve in chunks of sp.rhs_block right-hand sides (all at once when 0; the
+// autotuned width of the level when -1).
 int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                   const mgm_solve_params& sp, int* iters, double* relres) {
-  const int blk = (sp.rhs_block > 0 && sp.rhs_block < nrhs) ? sp.rhs_block : nrhs;
+  int want = sp.rhs_block;
+  if (want < 0) want = g.tuned_block[l];
+  const int blk = (want > 0 && want < nrhs) ? want : nrhs;
   const int64_t n = g.levels[l]->n;
   int status = MGM_OK;
   for (int r0 = 0; r0 < nrhs; r0 += blk) {
@@ -56,6 +62,24 @@ Level& level_of(Gauge& g, int level) {
           "level out of range (call setup_mg for coarse levels)");
   return *g.levels[level];
 }
+
+// Runs a call's work on the field's stream, ordered after everything already
+// enqueued on the caller's stream and before anything enqueued there later.
+struct OnGauge {
+  mgm_ctx* c;
+  Gauge& g;
+  hipStream_t saved;
+  OnGauge(mgm_ctx* c_, Gauge& g_) : c(c_), g(g_), saved(c_->stream) {
+    HIPCHK(hipEventRecord(g.ev_in, saved));
+    HIPCHK(hipStreamWaitEvent(g.stream, g.ev_in, 0));
+    c->stream = g.stream;
+  }
+  ~OnGauge() {
+    c->stream = saved;
+    (void)hipEventRecord(g.ev_out, g.stream);
+    (void)hipStreamWaitEvent(saved, g.ev_out, 0);
+  }
+};
 
 }  // namespace
 
@@ -108,6 +132,10 @@ int mgm_set_gauge(mgm_ctx* c, int Lx, int Lt, const void* links, double m0, int 
     L0->n = 2 * L0->sites;
     g->levels.push_back(std::move(L0));
     HIPCHK(hipStreamSynchronize(c->stream));
+    // the field's own stream (default priority) and its ordering events
+    HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
     c->gauges.push_back(std::move(g));
     *gauge_id = (int)c->gauges.size() - 1;
     return MGM_OK;
@@ -118,6 +146,8 @@ int mgm_setup_mg(mgm_ctx* c, int gauge_id, const mgm_mg_params* prm) {
   return guarded(c, [&] {
     require(prm != nullptr, "null params");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
+    g.clear_graphs();
     setup_hierarchy(c, g, *prm);
     return MGM_OK;
   });
@@ -127,6 +157,7 @@ int mgm_level_info(mgm_ctx* c, int gauge_id, int level, int* info) {
   return guarded(c, [&] {
     require(info != nullptr, "null pointer");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     Level& L = level_of(g, level);
     info[0] = L.Nx;
     info[1] = L.Nt;
@@ -140,6 +171,7 @@ int mgm_apply_D(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, vo
   return guarded(c, [&] {
     require(x && y && nrhs > 0 && x != y, "bad vectors");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     level_of(g, level);
     require(level == 0 || g.mg_ready, "coarse operators need setup_mg", MGM_ESTATE);
     apply_level(c, g, level, nrhs, static_cast<const cd*>(x), static_cast<cd*>(y));
@@ -151,6 +183,7 @@ int mgm_apply_P(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, vo
   return guarded(c, [&] {
     require(x && y && nrhs > 0, "bad vectors");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     Level& L = level_of(g, level);
     require(L.has_coarse, "level has no coarser level");
@@ -164,6 +197,7 @@ int mgm_apply_R(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* x, vo
   return guarded(c, [&] {
     require(x && y && nrhs > 0, "bad vectors");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     Level& L = level_of(g, level);
     require(L.has_coarse, "level has no coarser level");
@@ -177,6 +211,7 @@ int mgm_precondition(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* 
   return guarded(c, [&] {
     require(r && x && nrhs > 0 && r != x, "bad vectors");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     level_of(g, level);
     precondition_d(c, g, level, nrhs, static_cast<const cd*>(r), static_cast<cd*>(x), nullptr);
@@ -189,6 +224,7 @@ int mgm_get_prolongator(mgm_ctx* c, int gauge_id, int level, void* out) {
   return guarded(c, [&] {
     require(out != nullptr, "null pointer");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     Level& L = level_of(g, level);
     require(L.has_coarse, "level has no coarser level");
@@ -203,6 +239,7 @@ int mgm_coarsest_trace(mgm_ctx* c, int gauge_id, double* out) {
   return guarded(c, [&] {
     require(out != nullptr, "null pointer");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     out[0] = g.trL[0];
     out[1] = g.trL[1];
@@ -215,6 +252,7 @@ int mgm_solve_batch(mgm_ctx* c, int gauge_id, int level, int nrhs, const void* b
   return guarded(c, [&] {
     require(b && x && prm && nrhs > 0 && b != x, "bad arguments");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     level_of(g, level);
     return solve_chunked(c, g, level, nrhs, static_cast<const cd*>(b), static_cast<cd*>(x), *prm,
@@ -247,6 +285,7 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
   return guarded(c, [&] {
     require(us_out && bytes_out && flops_out && nrhs > 0 && reps > 0, "bad arguments");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     Level& L = level_of(g, level);
     hipStream_t s = c->stream;
     const int64_t n = L.n;
@@ -287,8 +326,8 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
       }
       case MGM_KERNEL_DENSE:
         require(L.has_dense, "level has no dense inverse", MGM_ESTATE);
-        launch = [=, &L] {
-          launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, x, y, nullptr, &c->scratch);
+        launch = [=, &L, &g] {
+          launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, x, y, nullptr, &g.scratch);
         };
         bytes = 16.0 * n * n + 32.0 * n * b;
         flops = 8.0 * n * n * b;
@@ -333,11 +372,122 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
   });
 }
 
+int mgm_solve_jobs(mgm_ctx* c, int njobs, const mgm_job* jobs, const mgm_solve_params* prm,
+                   int* iters) {
+  return guarded(c, [&] {
+    require(njobs >= 0 && (njobs == 0 || jobs) && prm, "bad arguments");
+    // group the jobs by gauge field, keeping their order inside a group
+    std::map<int, std::vector<int>> groups;
+    std::vector<int64_t> it_off(njobs + 1, 0);
+    for (int j = 0; j < njobs; ++j) {
+      const mgm_job& jb = jobs[j];
+      require(jb.b && jb.x && jb.nrhs > 0 && jb.b != jb.x, "bad job vectors");
+      Gauge& g = gauge_of(c, jb.gauge_id);
+      require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+      level_of(g, jb.level);
+      groups[jb.gauge_id].push_back(j);
+      it_off[j + 1] = it_off[j] + jb.nrhs;
+    }
+    for (auto& kv : groups) {
+      Gauge& g = *c->gauges[kv.first];
+      HIPCHK(hipEventRecord(g.ev_in, c->stream));
+      HIPCHK(hipStreamWaitEvent(g.stream, g.ev_in, 0));
+    }
+    std::vector<int> status(groups.size(), MGM_OK);
+    std::vector<std::string> msg(groups.size());
+    std::vector<std::thread> workers;
+    int gi = 0;
+    for (auto& kv : groups) {
+      const int slot = gi++;
+      workers.emplace_back([&, slot, gid = kv.first, idx = kv.second] {
+        mgm_ctx w;  // per-thread view: the field's stream, private scratch
+        w.device = c->device;
+        Gauge& g = *c->gauges[gid];
+        w.stream = g.stream;
+        try {
+          HIPCHK(hipSetDevice(c->device));
+          for (int j : idx) {
+            const mgm_job& jb = jobs[j];
+            const int st = solve_chunked(&w, g, jb.level, jb.nrhs, static_cast<const cd*>(jb.b),
+                                         static_cast<cd*>(jb.x), *prm,
+                                         iters ? iters + it_off[j] : nullptr, nullptr);
+            if (st != MGM_OK && status[slot] == MGM_OK) status[slot] = st;
+          }
+          HIPCHK(hipStreamSynchronize(g.stream));
+        } catch (const Error& e) {
+          status[slot] = e.code;
+          msg[slot] = e.what();
+        } catch (const std::exception& e) {
+          status[slot] = MGM_EHIP;
+          msg[slot] = e.what();
+        }
+      });
+    }
+    for (auto& t : workers) t.join();
+    for (auto& kv : groups) {
+      Gauge& g = *c->gauges[kv.first];
+      HIPCHK(hipEventRecord(g.ev_out, g.stream));
+      HIPCHK(hipStreamWaitEvent(c->stream, g.ev_out, 0));
+    }
+    for (size_t k = 0; k < status.size(); ++k)
+      if (status[k] != MGM_OK) {
+        if (!msg[k].empty()) throw Error(status[k], msg[k]);
+        c->err = "a job did not converge";
+        return status[k];
+      }
+    return MGM_OK;
+  });
+}
+
+int mgm_autotune_rhs_block(mgm_ctx* c, int gauge_id, int level, int nrhs,
+                           const mgm_solve_params* prm, int* best) {
+  return guarded(c, [&] {
+    require(prm && best && nrhs > 0, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    Level& L = level_of(g, level);
+    hipStream_t s = c->stream;
+    c->scratch2.ensure(sizeof(cd) * (size_t)2 * nrhs * L.n);
+    cd* b = c->scratch2.as<cd>();
+    cd* x = b + (int64_t)nrhs * L.n;
+    launch_noise<double>(s, b, L.n, nrhs, MGM_NOISE_Z2Z2, 97, 0, level, 0);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 0;
+    int best_w = nrhs;
+    for (int w : {8, 16, 32, 64}) {
+      if (w > nrhs && w != 8) break;
+      mgm_solve_params sp = *prm;
+      sp.rhs_block = std::min(w, nrhs);
+      // once untimed (allocations, graph capture), then timed
+      solve_chunked(c, g, level, nrhs, b, x, sp, nullptr, nullptr);
+      HIPCHK(hipEventRecord(e0, s));
+      solve_chunked(c, g, level, nrhs, b, x, sp, nullptr, nullptr);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (best_ms == 0 || ms < best_ms) {
+        best_ms = ms;
+        best_w = sp.rhs_block;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g.tuned_block[level] = best_w;
+    *best = best_w;
+    return MGM_OK;
+  });
+}
+
 int mgm_trace_estimate(mgm_ctx* c, int gauge_id, const mgm_trace_params* prm,
                        mgm_trace_result* res) {
   return guarded(c, [&] {
     require(prm && res, "null pointer");
     Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
     return trace_estimate(c, g, *prm, *res);
   });
 }

@@ -3,11 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mgmlmc.h"
@@ -95,6 +98,10 @@ inline void require(bool ok, const std::string& msg, int code = MGM_EINVAL) {
 }
 
 // ---------------------------------------------------------------- memory
+// Bumped on every device (re)allocation: a captured HIP graph is only valid
+// while the buffers it references keep their addresses.
+extern std::atomic<uint64_t> g_alloc_epoch;
+
 // Owning device buffer (freed with hipFree; never used for host memory).
 struct DevBuf {
   void* p = nullptr;
@@ -111,6 +118,7 @@ struct DevBuf {
   void ensure(size_t b) {
     if (b <= bytes) return;
     release();
+    g_alloc_epoch.fetch_add(1);
     HIPCHK(hipMalloc(&p, b));
     bytes = b;
   }
@@ -243,6 +251,15 @@ struct Level {
   int64_t nagg() const { return bx ? (int64_t)(Nx / bx) * (Nt / bt) : 0; }
 };
 
+// A captured preconditioner application: (level, nrhs, input, output, active
+// flags, precision) -> instantiated graph.
+using GraphKey = std::tuple<int, int, const void*, void*, const int*, int>;
+struct GraphEntry {
+  uint64_t epoch = 0;             // allocation epoch when first run / captured
+  hipGraphExec_t exec = nullptr;  // null until captured
+  bool failed = false;            // capture not possible: always run directly
+};
+
 struct Gauge {
   int Lx = 0, Lt = 0, anti = 1;
   double m0 = 0;
@@ -253,6 +270,25 @@ struct Gauge {
   mgm_mg_params prm{};
   int mlmc_levels = 0;      // levels of the MLMC telescoping sum
   double trL[2] = {0, 0};   // tr(D^{-1}) of level mlmc_levels-1
+  int tuned_block[MGM_MAX_LEVELS] = {0};  // autotuned RHS block per level
+  // all work on this field runs on its own stream, ordered against the
+  // caller's stream with ev_in / ev_out at every entry point
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  DevBuf scratch;  // split-k partials of the dense applies
+  std::map<GraphKey, GraphEntry> graphs;
+  void clear_graphs() {
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+  }
+  ~Gauge() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    clear_graphs();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
 };
 
 }  // namespace mgm
@@ -271,6 +307,9 @@ void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, c
 int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                 const mgm_solve_params& sp, int* iters_out, double* relres_out);
 void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y);
+void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act);
+int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
+                  const mgm_solve_params& sp, int* iters, double* relres);
 void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p);
 void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q);
 int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r);

@@ -80,7 +80,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   Level& L = *g.levels[l];
   LevelData<T>& D = ldata<T>(L);
   if (L.is_coarsest) {
-    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &c->scratch);
+    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &g.scratch);
     return;
   }
   if (L.has_coarse) {
@@ -92,7 +92,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     cx<T>* ec = W.ec.template as<cx<T>>();
     launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
     if (C.is_coarsest) {
-      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &c->scratch);
+      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &g.scratch);
     } else if (C.inner_iters <= 0) {
       precond<T>(c, g, l + 1, nrhs, rc, ec, act);  // plain V-cycle on the coarse level
     } else {
@@ -191,6 +191,68 @@ void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, c
   }
 }
 
+// The preconditioner application has a fixed sequence of launches and no host
+// synchronisation (inner solves run their fixed step counts with device-side
+// masks), so it is replayed as a HIP graph.  A key is first run directly,
+// which performs any buffer allocation; the second time, if no allocation
+// happened since (same epoch), it is captured, instantiated and launched;
+// later calls launch the graph.  Any reallocation anywhere invalidates the
+// graph (its kernel arguments hold buffer addresses).
+void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
+  hipStream_t s = c->stream;
+  if (!g.prm.graphs || !s) {
+    precondition_d(c, g, l, nrhs, r, x, act);
+    return;
+  }
+  const GraphKey key{l, nrhs, (const void*)r, (void*)x, act, g.prm.precision};
+  auto it = g.graphs.find(key);
+  const uint64_t ep = g_alloc_epoch.load();
+  if (it != g.graphs.end() && it->second.exec && it->second.epoch == ep) {
+    HIPCHK(hipGraphLaunch(it->second.exec, s));
+    return;
+  }
+  if (it == g.graphs.end() || it->second.failed || it->second.epoch != ep) {
+    if (it != g.graphs.end() && it->second.exec) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it->second.exec = nullptr;
+    }
+    const bool failed = it != g.graphs.end() && it->second.failed;
+    precondition_d(c, g, l, nrhs, r, x, act);
+    GraphEntry& e = g.graphs[key];
+    e.epoch = g_alloc_epoch.load();
+    e.failed = failed;
+    return;
+  }
+  // second run at an unchanged epoch: capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    it->second.failed = true;
+    precondition_d(c, g, l, nrhs, r, x, act);
+    return;
+  }
+  try {
+    precondition_d(c, g, l, nrhs, r, x, act);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(s, &graph));
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess || g_alloc_epoch.load() != ep) {
+    (void)hipGetLastError();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    it->second.failed = true;
+    precondition_d(c, g, l, nrhs, r, x, act);
+    return;
+  }
+  it->second.exec = exec;
+  HIPCHK(hipGraphLaunch(exec, s));
+}
+
 // Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
 // residual, checked at the end of every cycle); the host polls the active
 // flags after each Arnoldi step to end a cycle once every RHS has converged.
@@ -225,7 +287,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
   if (L.has_dense) {
-    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &c->scratch);
+    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
       // r0 = b - D x ; v0 = r0 / ||r0||
@@ -236,7 +298,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
       launch_scale<double>(s, w, beta, n, nrhs, V, act);
       for (int j = 0; j < m; ++j) {
         arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
-          precondition_d(c, g, l, nrhs, v, z, a);
+          precondition_graph(c, g, l, nrhs, v, z, a);
         });
         HIPCHK(hipMemcpyAsync(hact.data(), act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
