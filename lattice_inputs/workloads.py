@@ -49,6 +49,21 @@ WORKLOADS = {
 }
 
 
+# Batching workload: 8 independent fields on mixed lattices, (beta, m0, L, nRHS)
+# per field, gauge seeds 3000 + i; each field's mass is kept clear of the
+# critical mass of its coupling.
+BATCH8 = [
+    (2.0, -0.12, 256, 64), (2.0, -0.11, 64, 256), (3.0, -0.10, 128, 128), (3.0, -0.09, 256, 256),
+    (4.0, -0.07, 64, 128), (4.0, -0.06, 128, 64), (5.0, -0.05, 256, 128), (5.0, -0.05, 64, 256),
+]
+
+
+def batch8_fields(sweeps: int = 200):
+    """[(theta, m0, nrhs)] for the batching workload."""
+    return [(metropolis_u1(L, L, beta, sweeps, 3000 + i), m0, nrhs)
+            for i, (beta, m0, L, nrhs) in enumerate(BATCH8)]
+
+
 def gauge_for(name_or_cfg) -> np.ndarray:
     cfg = WORKLOADS[name_or_cfg] if isinstance(name_or_cfg, str) else name_or_cfg
     return metropolis_u1(cfg["Lx"], cfg["Lt"], cfg["beta"], cfg["sweeps"], cfg["gauge_seed"])
