@@ -59,6 +59,31 @@ KERNEL_RHS = 64
 # the kernel with the largest share of the step's GPU time (rocprofv3 of the
 # 128^2 step): one colour of the fine-level SAP sweep
 DOMINANT = "sap_l0"
+# counter summary of that kernel (FETCH_SIZE / WRITE_SIZE runs, scaled by the
+# copy-kernel calibration), keyed to the source file it was measured from
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sap_sweep_l0_schwinger128_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_11512_amd", "csrc", "ops.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from its committed counter
+    summary; None when there is none or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        with open(TRAFFIC_SUMMARY) as f:
+            for ln in f:
+                if ":" in ln and not ln.startswith((" ", "#")):
+                    k, v = ln.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        with open(KERNEL_SOURCE, "rb") as f:
+            src = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("source_sha256") != src:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None):
@@ -310,7 +335,7 @@ def main():
                                        for l in range(len(cfg["blocks"]) + 1)],
                    "level_samples": samples, "tau": [outs[-1]["tau"].real, outs[-1]["tau"].imag]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": f"k_sap_sweep<double> (level 0, one colour, {KERNEL_RHS} RHS)",
                      "launch_us": dom["us"], "alg_bytes": dom["bytes"],
                      "others": {k: {"us": round(v["us"], 2),
