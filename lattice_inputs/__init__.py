@@ -14,6 +14,7 @@ from .gauge import (
     free_theta,
 )
 from .workloads import WORKLOADS, gauge_for, rhs_vectors
+from .cnn import cnn_init_params, cnn_param_count
 
 __all__ = [
     "metropolis_u1",
@@ -25,4 +26,6 @@ __all__ = [
     "WORKLOADS",
     "gauge_for",
     "rhs_vectors",
+    "cnn_init_params",
+    "cnn_param_count",
 ]

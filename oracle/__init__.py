@@ -15,7 +15,7 @@ mg      aggregation multigrid setup, Galerkin operators, and the reference
         preconditioner (SAP smoother, K-cycle) used only to pin the HIP solver
 trace   Alg. 1 (plain Hutchinson), Hutch++ (Sec. 2.4), MG-MLMC (Sec. 3.1) and
         MG-MLMC++ (Alg. 2), run step by step in the paper's order
-cnn     the small convolutional preconditioner network (forward/backward)
+cnn     the small convolutional initial-guess network (forward, backward, Adam)
 
 Parity status of each function is stated in its docstring; a function whose
 result nothing in the paper or the mathematics fixes says "parity unpinned".
