@@ -54,6 +54,7 @@ extern "C" {
 #define MGM_PURPOSE_SETUP 1
 #define MGM_PURPOSE_SKETCH 2
 #define MGM_PURPOSE_SAMPLE 3
+#define MGM_PURPOSE_TRAIN 4   /* right-hand sides of the network's training pairs */
 
 /* precision of the multigrid preconditioner (the outer FGMRES is always FP64) */
 #define MGM_PREC_FP64 0
@@ -152,7 +153,8 @@ int mgm_coarsest_trace(mgm_ctx *ctx, int gauge_id, double *out);
  * solve_batch -- x = D_level^{-1} b for nrhs right-hand sides by right-
  * preconditioned FGMRES(restart) in FP64 with the multigrid preconditioner
  * (Alg. 2 "use mg to solve lin. sys.").  Every RHS stops on its true FP64
- * residual ||b - D x|| <= tol ||b||.  x0 = 0.  On the coarsest level the
+ * residual ||b - D x|| <= tol ||b||.  x0 = 0 (or the learned guess, see
+ * mgm_cnn_set_params).  On the coarsest level the
  * dense inverse is applied.  b, x: DEVICE [nrhs][n_level].
  * stats (optional, HOST arrays of nrhs entries, caller-owned): FGMRES
  * iterations and final relative residual per RHS.  On MGM_ENOTCONV x holds
@@ -164,6 +166,8 @@ typedef struct {
   int max_restarts;
   int rhs_block;     /* RHS solved together (0 = all, -1 = the autotuned
                         width of the level, all if none) */
+  int use_cnn;       /* level 0 only: start from the learned guess
+                        (mgm_cnn_*) instead of x0 = 0 */
 } mgm_solve_params;
 
 typedef struct {
@@ -287,6 +291,72 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
 
 int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
                     double *us_out, double *bytes_out, double *flops_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned initial guess.  Not part of the paper's method: it changes where a
+ * fine-level solve starts, never the tolerance it meets, so the estimator is
+ * unchanged (every sample still comes from an FP64 solve to prm->tol).
+ *
+ * The network y = f(b): four 3x3 convolutions on the fine lattice with
+ * 4 -> 32 -> 32 -> 32 -> 4 channels and tanh after the first three.  Its 4
+ * channels are (Re, Im) x 2 spins in the order of a level-0 vector, so a
+ * complex128 vector [n0] is read as [Lt][Lx][4] reals.  Padding is periodic
+ * in x and, in t, follows the field's boundary condition (antiperiodic: a
+ * value fetched across the t boundary changes sign).  The network does not
+ * see the links.  Parameters: MGM_CNN_NPARAMS floats packed
+ * W1 b1 W2 b2 W3 b3 W4 b4 with W[co][ci][dt][dx], where tap (dt, dx) reads
+ * site (t + dt - 1, x + dx - 1).  FP32 storage, FP32 matrix-core
+ * accumulation.  One network per context; Lx and Lt must be multiples of 16.
+ *
+ * With mgm_solve_params.use_cnn = 1, a level-0 solve starts from
+ * x0 = alpha_r f(b_r), alpha_r = <D f(b_r), b_r> / ||D f(b_r)||^2 per RHS (the
+ * minimal residual along f(b_r), so ||b - D x0|| <= ||b||); a zero or
+ * non-finite alpha_r gives x0 = 0, i.e. plain multigrid.
+ * ------------------------------------------------------------------------- */
+#define MGM_CNN_NPARAMS 20836
+
+/* set_params -- copy HOST theta [MGM_CNN_NPARAMS] into the network and reset
+ * the Adam state.  get_params copies the current parameters to HOST theta. */
+int mgm_cnn_set_params(mgm_ctx *ctx, const float *theta);
+int mgm_cnn_get_params(mgm_ctx *ctx, float *theta);
+
+/* apply -- y = f(b) for nb level-0 vectors of gauge field gauge_id (its
+ * lattice size and boundary condition); b, y: DEVICE complex128 [nb][n0]. */
+int mgm_cnn_apply(mgm_ctx *ctx, int gauge_id, int nb, const void *b, void *y);
+
+/* loss_grad -- loss = (1/nb) sum_r ||f(b_r) - x_r||^2 / ||x_r||^2 (written to
+ * HOST *loss) and its gradient with respect to the parameters (HOST grad
+ * [MGM_CNN_NPARAMS], same packing, or NULL).  b, x: DEVICE complex128
+ * [nb][n0]. */
+int mgm_cnn_loss_grad(mgm_ctx *ctx, int gauge_id, int nb, const void *b, const void *x,
+                      double *loss, float *grad);
+
+typedef struct {
+  double lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015), bias-corrected */
+} mgm_adam_params;
+
+/* train_step -- loss_grad on (b, x), then one Adam step; *loss (HOST) is the
+ * loss before the step. */
+int mgm_cnn_train_step(mgm_ctx *ctx, int gauge_id, int nb, const void *b, const void *x,
+                       const mgm_adam_params *adam, double *loss);
+
+typedef struct {
+  int pairs_per_field;      /* Z2xZ2 right-hand sides per field (noise purpose
+                               MGM_PURPOSE_TRAIN, level 0, index = pair) */
+  int batch;                /* pairs per Adam step */
+  int epochs;
+  mgm_adam_params adam;
+  uint64_t seed;            /* noise seed; also orders the pairs each epoch */
+  mgm_solve_params solve;   /* the multigrid solves that make the targets */
+} mgm_cnn_train_params;
+
+/* train -- solve D x = b for pairs_per_field noise vectors on each of the
+ * nfields fields (all of one lattice size, each with its multigrid set up),
+ * keep the pairs in HBM, and run `epochs` passes of Adam over them in a
+ * seeded order.  epoch_loss (HOST [epochs] or NULL) receives each epoch's
+ * mean mini-batch loss.  MGM_ENOTCONV if a target solve did not converge. */
+int mgm_cnn_train(mgm_ctx *ctx, int nfields, const int *gauge_ids, const mgm_cnn_train_params *prm,
+                  double *epoch_loss);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,8 @@ from ._lib import (  # noqa: F401
     load_library,
     mg_params,
     solve_params,
+    adam_params,
+    CNN_NPARAMS,
     PURPOSE_SAMPLE,
     PURPOSE_SETUP,
     PURPOSE_SKETCH,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmgmlmc.so")
 MAX_LEVELS = 6
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 NOISE_RADEMACHER, NOISE_Z2Z2 = 0, 1
-PURPOSE_SETUP, PURPOSE_SKETCH, PURPOSE_SAMPLE = 1, 2, 3
+PURPOSE_SETUP, PURPOSE_SKETCH, PURPOSE_SAMPLE, PURPOSE_TRAIN = 1, 2, 3, 4
 PREC_FP64, PREC_FP32 = 0, 1
 VARIANTS = {"hutchinson": 0, "hutchpp": 1, "mlmc": 2, "mlmcpp": 3}
 FORMS = {"reduced": 0, "full": 1}
@@ -52,6 +52,22 @@ class SolveParams(C.Structure):
         ("restart", C.c_int),
         ("max_restarts", C.c_int),
         ("rhs_block", C.c_int),
+        ("use_cnn", C.c_int),
+    ]
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+class CnnTrainParams(C.Structure):
+    _fields_ = [
+        ("pairs_per_field", C.c_int),
+        ("batch", C.c_int),
+        ("epochs", C.c_int),
+        ("adam", AdamParams),
+        ("seed", C.c_uint64),
+        ("solve", SolveParams),
     ]
 
 
@@ -122,7 +138,18 @@ SIGNATURES = {
     "mgm_solve_jobs": (C.c_int, [_P, C.c_int, _P, C.POINTER(SolveParams), C.POINTER(C.c_int)]),
     "mgm_autotune_rhs_block": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(SolveParams),
                                          C.POINTER(C.c_int)]),
+    "mgm_cnn_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "mgm_cnn_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "mgm_cnn_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
+    "mgm_cnn_loss_grad": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_float)]),
+    "mgm_cnn_train_step": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.POINTER(AdamParams),
+                                     C.POINTER(C.c_double)]),
+    "mgm_cnn_train": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(CnnTrainParams),
+                                C.POINTER(C.c_double)]),
 }
+
+CNN_NPARAMS = 20836
 
 
 class Job(C.Structure):
@@ -197,8 +224,12 @@ def mg_params(nlevels, blocks, ntv, sap_block=None, sap_cycles=None, inner_iters
     return p
 
 
-def solve_params(tol=1e-10, restart=16, max_restarts=50, rhs_block=0) -> SolveParams:
-    return SolveParams(tol, restart, max_restarts, rhs_block)
+def solve_params(tol=1e-10, restart=16, max_restarts=50, rhs_block=0, use_cnn=False) -> SolveParams:
+    return SolveParams(tol, restart, max_restarts, rhs_block, int(bool(use_cnn)))
+
+
+def adam_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> AdamParams:
+    return AdamParams(lr, beta1, beta2, eps)
 
 
 class Context:
@@ -331,6 +362,58 @@ class Context:
         self._chk(self.lib.mgm_time_kernel(self.h, gid, KERNELS[kind], level, nrhs, reps, C.byref(us),
                                            C.byref(by), C.byref(fl)), "time_kernel")
         return dict(us=us.value, bytes=by.value, flops=fl.value)
+
+    # ------------------------------------------------------------ learned guess
+    def cnn_set_params(self, theta):
+        import numpy as np
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.shape != (CNN_NPARAMS,):
+            raise ValueError(f"expected {CNN_NPARAMS} parameters, got {th.shape}")
+        self._chk(self.lib.mgm_cnn_set_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float))),
+                  "cnn_set_params")
+
+    def cnn_get_params(self):
+        import numpy as np
+        th = np.empty(CNN_NPARAMS, dtype=np.float32)
+        self._chk(self.lib.mgm_cnn_get_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float))),
+                  "cnn_get_params")
+        return th
+
+    def cnn_apply(self, gid, b, y):
+        _check_vec(b)
+        _check_vec(y, b.shape[1])
+        self._chk(self.lib.mgm_cnn_apply(self.h, gid, b.shape[0], _P(_ptr(b)), _P(_ptr(y))), "cnn_apply")
+
+    def cnn_loss_grad(self, gid, b, x):
+        """(loss, gradient as float32 numpy array in the parameter packing)."""
+        import numpy as np
+        _check_vec(b)
+        _check_vec(x, b.shape[1])
+        loss = C.c_double()
+        g = np.empty(CNN_NPARAMS, dtype=np.float32)
+        self._chk(self.lib.mgm_cnn_loss_grad(self.h, gid, b.shape[0], _P(_ptr(b)), _P(_ptr(x)),
+                                             C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float))),
+                  "cnn_loss_grad")
+        return loss.value, g
+
+    def cnn_train_step(self, gid, b, x, adam: AdamParams | None = None) -> float:
+        _check_vec(b)
+        _check_vec(x, b.shape[1])
+        loss = C.c_double()
+        self._chk(self.lib.mgm_cnn_train_step(self.h, gid, b.shape[0], _P(_ptr(b)), _P(_ptr(x)),
+                                              C.byref(adam or adam_params()), C.byref(loss)),
+                  "cnn_train_step")
+        return loss.value
+
+    def cnn_train(self, gids, pairs_per_field, batch, epochs, adam: AdamParams | None = None, seed=1,
+                  solve: SolveParams | None = None):
+        """Per-epoch mean losses of training on the fields' own MG solves."""
+        prm = CnnTrainParams(pairs_per_field, batch, epochs, adam or adam_params(), C.c_uint64(seed),
+                             solve or solve_params())
+        ids = (C.c_int * len(gids))(*gids)
+        out = (C.c_double * max(1, epochs))()
+        self._chk(self.lib.mgm_cnn_train(self.h, len(gids), ids, C.byref(prm), out), "cnn_train")
+        return [out[i] for i in range(epochs)]
 
     def orthonormalize(self, Y, Q):
         self._chk(self.lib.mgm_orthonormalize(self.h, Y.shape[1], Y.shape[0], _P(_ptr(Y)),

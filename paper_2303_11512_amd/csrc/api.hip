@@ -404,6 +404,7 @@ int mgm_solve_jobs(mgm_ctx* c, int njobs, const mgm_job* jobs, const mgm_solve_p
         w.device = c->device;
         Gauge& g = *c->gauges[gid];
         w.stream = g.stream;
+        w.cnn = c->cnn;
         try {
           HIPCHK(hipSetDevice(c->device));
           for (int j : idx) {
@@ -478,6 +479,182 @@ int mgm_autotune_rhs_block(mgm_ctx* c, int gauge_id, int level, int nrhs,
     (void)hipEventDestroy(e1);
     g.tuned_block[level] = best_w;
     *best = best_w;
+    return MGM_OK;
+  });
+}
+
+// ---------------------------------------------------------------- learned initial guess
+namespace {
+Cnn& cnn_of(mgm_ctx* c) {
+  require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
+  return *c->cnn;
+}
+}  // namespace
+
+int mgm_cnn_set_params(mgm_ctx* c, const float* theta) {
+  return guarded(c, [&] {
+    require(theta != nullptr, "null pointer");
+    if (!c->cnn) {
+      c->cnn = std::make_shared<Cnn>();
+      c->cnn->init();
+    }
+    Cnn& net = *c->cnn;
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(net.theta.p, theta, sizeof(float) * MGM_CNN_NPARAMS, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(net.m.p, 0, sizeof(float) * MGM_CNN_NPARAMS, s));
+    HIPCHK(hipMemsetAsync(net.v.p, 0, sizeof(float) * MGM_CNN_NPARAMS, s));
+    net.t = 0;
+    net.pack(s);
+    HIPCHK(hipStreamSynchronize(s));
+    net.ready = true;
+    return MGM_OK;
+  });
+}
+
+int mgm_cnn_get_params(mgm_ctx* c, float* theta) {
+  return guarded(c, [&] {
+    require(theta != nullptr, "null pointer");
+    Cnn& net = cnn_of(c);
+    HIPCHK(hipMemcpyAsync(theta, net.theta.p, sizeof(float) * MGM_CNN_NPARAMS, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+int mgm_cnn_apply(mgm_ctx* c, int gauge_id, int nb, const void* b, void* y) {
+  return guarded(c, [&] {
+    require(b && y && nb > 0, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
+    cnn_apply(c->stream, cnn_of(c), g, nb, static_cast<const cd*>(b), static_cast<cd*>(y), g.cnn);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+namespace {
+// channel-last FP32 copy of b and the loss/gradient of the pairs (b, x)
+const double* loss_grad_pairs(mgm_ctx* c, Gauge& g, int nb, const void* b, const void* x) {
+  cnn_check_lattice(g);
+  Cnn& net = cnn_of(c);
+  const int64_t n = g.levels[0]->n;
+  g.cnn.x0.ensure(sizeof(float) * nb * n * 2);
+  cnn_to_channels(c->stream, static_cast<const cd*>(b), nb * n, g.cnn.x0.as<float>());
+  return cnn_loss_grad<double>(c->stream, net, g, nb, g.cnn.x0.as<float>(),
+                               static_cast<const double*>(x), g.cnn);
+}
+}  // namespace
+
+int mgm_cnn_loss_grad(mgm_ctx* c, int gauge_id, int nb, const void* b, const void* x, double* loss,
+                      float* grad) {
+  return guarded(c, [&] {
+    require(b && x && loss && nb > 0, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
+    const double* ld = loss_grad_pairs(c, g, nb, b, x);
+    HIPCHK(hipMemcpyAsync(loss, ld, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (grad)
+      HIPCHK(hipMemcpyAsync(grad, c->cnn->grad.p, sizeof(float) * MGM_CNN_NPARAMS, hipMemcpyDeviceToHost,
+                            c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+int mgm_cnn_train_step(mgm_ctx* c, int gauge_id, int nb, const void* b, const void* x,
+                       const mgm_adam_params* adam, double* loss) {
+  return guarded(c, [&] {
+    require(b && x && loss && adam && nb > 0, "bad arguments");
+    Gauge& g = gauge_of(c, gauge_id);
+    OnGauge og(c, g);
+    const double* ld = loss_grad_pairs(c, g, nb, b, x);
+    HIPCHK(hipMemcpyAsync(loss, ld, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    cnn_adam(c->stream, *c->cnn, *adam);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MGM_OK;
+  });
+}
+
+int mgm_cnn_train(mgm_ctx* c, int nfields, const int* gauge_ids, const mgm_cnn_train_params* prm,
+                  double* epoch_loss) {
+  return guarded(c, [&] {
+    require(gauge_ids && prm && nfields > 0, "bad arguments");
+    require(prm->pairs_per_field > 0 && prm->batch > 0 && prm->epochs >= 0, "bad training sizes");
+    Cnn& net = cnn_of(c);
+    Gauge& g0 = gauge_of(c, gauge_ids[0]);
+    cnn_check_lattice(g0);
+    for (int f = 0; f < nfields; ++f) {
+      Gauge& g = gauge_of(c, gauge_ids[f]);
+      require(g.Lx == g0.Lx && g.Lt == g0.Lt && g.anti == g0.anti,
+              "training fields must share lattice size and boundary condition");
+      require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    }
+    const int64_t n = g0.levels[0]->n;
+    const int P = prm->pairs_per_field;
+    const int64_t npairs = (int64_t)nfields * P;
+    CnnWork& w = g0.cnn;
+    w.pairs_b.ensure(sizeof(float) * npairs * n * 2);
+    w.pairs_x.ensure(sizeof(float) * npairs * n * 2);
+    // targets: multigrid solves on each field's own stream, in chunks
+    const int chunk = std::min(P, 256);
+    int status = MGM_OK;
+    for (int f = 0; f < nfields; ++f) {
+      Gauge& g = gauge_of(c, gauge_ids[f]);
+      OnGauge og(c, g);
+      hipStream_t s = c->stream;
+      c->scratch2.ensure(sizeof(cd) * (size_t)2 * chunk * n);
+      cd* bb = c->scratch2.as<cd>();
+      cd* xx = bb + (int64_t)chunk * n;
+      for (int p0 = 0; p0 < P; p0 += chunk) {
+        const int k = std::min(chunk, P - p0);
+        launch_noise<double>(s, bb, n, k, MGM_NOISE_Z2Z2, prm->seed, MGM_PURPOSE_TRAIN, 0, p0);
+        mgm_solve_params sp = prm->solve;
+        sp.use_cnn = 0;
+        const int st = solve_chunked(c, g, 0, k, bb, xx, sp, nullptr, nullptr);
+        if (st != MGM_OK) status = st;
+        const int64_t at = ((int64_t)f * P + p0) * n * 2;
+        cnn_to_channels(s, bb, (int64_t)k * n, w.pairs_b.as<float>() + at);
+        cnn_to_channels(s, xx, (int64_t)k * n, w.pairs_x.as<float>() + at);
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (status != MGM_OK) throw Error(status, "a training target solve did not converge");
+    // epochs over the pairs in a seeded order (Fisher-Yates on SplitMix64)
+    OnGauge og(c, g0);
+    hipStream_t s = c->stream;
+    const int B = (int)std::min<int64_t>(prm->batch, npairs);
+    w.batch_b.ensure(sizeof(float) * B * n * 2);
+    w.batch_x.ensure(sizeof(float) * B * n * 2);
+    std::vector<int64_t> order(npairs);
+    for (int e = 0; e < prm->epochs; ++e) {
+      for (int64_t i = 0; i < npairs; ++i) order[i] = i;
+      const uint64_t key = mix64(prm->seed + kGolden) ^ ((uint64_t)MGM_PURPOSE_TRAIN << 56) ^ (uint64_t)e;
+      for (int64_t i = npairs - 1; i > 0; --i) {
+        const uint64_t z = mix64(key + (uint64_t)i * kGolden);
+        std::swap(order[i], order[(int64_t)(z % (uint64_t)(i + 1))]);
+      }
+      double sum = 0.0;
+      int nsteps = 0;
+      for (int64_t p0 = 0; p0 + B <= npairs; p0 += B) {
+        for (int j = 0; j < B; ++j) {
+          const int64_t src = order[p0 + j] * n * 2;
+          HIPCHK(hipMemcpyAsync(w.batch_b.as<float>() + (int64_t)j * n * 2, w.pairs_b.as<float>() + src,
+                                sizeof(float) * n * 2, hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(w.batch_x.as<float>() + (int64_t)j * n * 2, w.pairs_x.as<float>() + src,
+                                sizeof(float) * n * 2, hipMemcpyDeviceToDevice, s));
+        }
+        const double* ld = cnn_loss_grad<float>(s, net, g0, B, w.batch_b.as<float>(),
+                                                w.batch_x.as<float>(), w);
+        double l = 0;
+        HIPCHK(hipMemcpyAsync(&l, ld, sizeof(double), hipMemcpyDeviceToHost, s));
+        cnn_adam(s, net, prm->adam);
+        HIPCHK(hipStreamSynchronize(s));
+        sum += l;
+        ++nsteps;
+      }
+      if (epoch_loss) epoch_loss[e] = nsteps ? sum / nsteps : 0.0;
+    }
     return MGM_OK;
   });
 }

@@ -260,6 +260,24 @@ struct GraphEntry {
   bool failed = false;            // capture not possible: always run directly
 };
 
+// Learned initial guess: parameters (FP32 master copy, Adam moments, last
+// gradient) and the per-layer packed weights the convolution kernels read.
+struct Cnn {
+  DevBuf theta, m, v, grad;
+  DevBuf wf[4], wb[4];
+  int64_t t = 0;  // Adam steps taken
+  bool ready = false;
+  void init();
+  void pack(hipStream_t s);
+  const float* bias(int l) const;
+};
+
+// Per-field network workspaces (activations of the RHS chunk in flight).
+struct CnnWork {
+  DevBuf x0, y, gy, a[3], g[2], part, lpart, mr;
+  DevBuf pairs_b, pairs_x, batch_b, batch_x, idx;
+};
+
 struct Gauge {
   int Lx = 0, Lt = 0, anti = 1;
   double m0 = 0;
@@ -276,6 +294,7 @@ struct Gauge {
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   DevBuf scratch;  // split-k partials of the dense applies
+  CnnWork cnn;
   std::map<GraphKey, GraphEntry> graphs;
   void clear_graphs() {
     for (auto& kv : graphs)
@@ -299,6 +318,7 @@ struct mgm_ctx {
   std::string err;
   std::vector<std::unique_ptr<mgm::Gauge>> gauges;
   mgm::DevBuf scratch, scratch2, scratch3, ibuf;
+  std::shared_ptr<mgm::Cnn> cnn;  // shared with the per-field worker views
 };
 
 namespace mgm {
@@ -313,4 +333,16 @@ int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p);
 void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q);
 int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r);
+// learned initial guess (cnn.hip)
+void cnn_check_lattice(const Gauge& g);
+void cnn_forward(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const float* x0, CnnWork& w,
+                 float* y);
+template <class TT>
+const double* cnn_loss_grad(hipStream_t s, Cnn& net, const Gauge& g, int nb, const float* x0,
+                            const TT* target, CnnWork& w);
+void cnn_adam(hipStream_t s, Cnn& net, const mgm_adam_params& ap);
+void cnn_to_channels(hipStream_t s, const cd* in, int64_t ndof, float* out);
+void cnn_from_channels(hipStream_t s, const float* in, int64_t ndof, cd* out);
+void cnn_apply(hipStream_t s, const Cnn& net, const Gauge& g, int nrhs, const cd* b, cd* y, CnnWork& w);
+void cnn_initial_guess(mgm_ctx* c, Gauge& g, int nrhs, const cd* b, cd* x, cd* u);
 }  // namespace mgm

@@ -284,7 +284,10 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
     hdone[r] = hb[r] == 0.0;
   }
   HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-  launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
+  if (sp.use_cnn && l == 0 && !L.has_dense)
+    cnn_initial_guess(c, g, nrhs, b, x, w);
+  else
+    launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
   if (L.has_dense) {
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch);

@@ -57,7 +57,8 @@ def _c_layout(struct, fields):
 @pytest.mark.parametrize("cname,pyname", [
     ("mgm_mg_params", "MGParams"), ("mgm_solve_params", "SolveParams"),
     ("mgm_solve_stats", "SolveStats"), ("mgm_trace_params", "TraceParams"),
-    ("mgm_trace_result", "TraceResult")])
+    ("mgm_trace_result", "TraceResult"), ("mgm_adam_params", "AdamParams"),
+    ("mgm_cnn_train_params", "CnnTrainParams"), ("mgm_job", "Job")])
 def test_struct_layout_matches_header(cname, pyname, tmp_path):
     from paper_2303_11512_amd import _lib
     py = getattr(_lib, pyname)

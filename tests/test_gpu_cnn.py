@@ -1,0 +1,185 @@
+"""The learned initial guess on the GPU: forward pass, loss and gradients of
+the HIP kernels against the oracle network (FP64), Adam steps, training on the
+field's own multigrid solves, and solves that start from the guess (which must
+still meet the FP64 tolerance, and fall back to x0 = 0 for a broken network)."""
+import numpy as np
+import pytest
+
+from gpu_util import Recipe, empty, log, to_dev, to_host
+from lattice_inputs import cnn_init_params, links_from_theta, metropolis_u1, rhs_vectors
+from oracle import cnn as ocnn
+from oracle import dirac
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2303_11512_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _theta(seed):
+    th = cnn_init_params(seed)
+    rng = np.random.default_rng(seed)
+    for p in ocnn.unpack(th):
+        if p.ndim == 1:
+            p[:] = 0.1 * rng.standard_normal(p.shape)
+    # the network runs in FP32: compare against the FP32-rounded parameters
+    return th.astype(np.float32).astype(np.float64)
+
+
+def _field(ctx, Lx, Lt, anti, seed):
+    th = metropolis_u1(Lx, Lt, 3.0, 20, seed)
+    return ctx.set_gauge(to_dev(links_from_theta(th)), -0.05, anti), th
+
+
+def _oracle_y(theta, b, Lx, Lt, anti):
+    y, _ = ocnn.forward(theta, ocnn.complex_to_channels(b, Lx, Lt), anti)
+    return ocnn.channels_to_complex(y)
+
+
+@pytest.mark.parametrize("Lx,Lt,anti,nb", [(16, 16, True, 3), (32, 16, False, 2), (48, 32, True, 1)])
+def test_forward_matches_oracle(ctx, Lx, Lt, anti, nb):
+    gid, _ = _field(ctx, Lx, Lt, anti, 11)
+    theta = _theta(3)
+    ctx.cnn_set_params(theta)
+    b = rhs_vectors(2 * Lx * Lt, nb, 5) * 0.7
+    b = b.astype(np.complex64).astype(np.complex128)
+    y = empty(nb, 2 * Lx * Lt)
+    log(f"cnn forward {Lx}x{Lt} anti={anti} nb={nb}")
+    ctx.cnn_apply(gid, to_dev(b), y)
+    want = _oracle_y(theta, b, Lx, Lt, anti)
+    err = np.linalg.norm(to_host(y) - want) / np.linalg.norm(want)
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("anti", [True, False])
+def test_loss_and_gradient_match_oracle(ctx, anti):
+    Lx, Lt, nb = 32, 16, 3
+    gid, _ = _field(ctx, Lx, Lt, anti, 12)
+    theta = _theta(4)
+    ctx.cnn_set_params(theta)
+    rng = np.random.default_rng(9)
+    b = rhs_vectors(2 * Lx * Lt, nb, 6).astype(np.complex64).astype(np.complex128)
+    x = (rng.standard_normal((nb, 2 * Lx * Lt)) + 1j * rng.standard_normal((nb, 2 * Lx * Lt)))
+    log(f"cnn loss/grad anti={anti}")
+    loss, g = ctx.cnn_loss_grad(gid, to_dev(b), to_dev(x))
+    wl, wg = ocnn.loss_and_grad(theta, ocnn.complex_to_channels(b, Lx, Lt),
+                                ocnn.complex_to_channels(x, Lx, Lt), anti)
+    assert abs(loss - wl) <= 1e-6 * abs(wl), (loss, wl)
+    # every layer's weights and biases, norm-wise
+    off = 0
+    for shape in ocnn.param_shapes():
+        k = int(np.prod(shape))
+        gw, ww = g[off:off + k].astype(np.float64), wg[off:off + k]
+        err = np.linalg.norm(gw - ww) / np.linalg.norm(ww)
+        assert err < 1e-4, (shape, err)
+        off += k
+
+
+def test_adam_steps_follow_the_update_rule(ctx):
+    from paper_2303_11512_amd import adam_params
+    Lx = Lt = 16
+    gid, _ = _field(ctx, Lx, Lt, True, 13)
+    theta = _theta(5)
+    ctx.cnn_set_params(theta)
+    b = rhs_vectors(2 * Lx * Lt, 2, 7).astype(np.complex64).astype(np.complex128)
+    x = rhs_vectors(2 * Lx * Lt, 2, 8) * 3.0
+    bd, xd = to_dev(b), to_dev(x)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    th = ctx.cnn_get_params().astype(np.float64)
+    lr = 1e-3
+    for t in range(1, 4):
+        _, g = ctx.cnn_loss_grad(gid, bd, xd)
+        loss = ctx.cnn_train_step(gid, bd, xd, adam_params(lr=lr))
+        want, m, v = ocnn.adam_step(th, m, v, g.astype(np.float64), t, lr)
+        got = ctx.cnn_get_params().astype(np.float64)
+        assert np.max(np.abs(got - want)) < 1e-6, t
+        assert np.isfinite(loss)
+        th = got
+
+
+@pytest.fixture(scope="module")
+def trained(ctx):
+    """A 32x32 field with its multigrid and a network trained on its solves."""
+    from paper_2303_11512_amd import adam_params, solve_params
+    th = metropolis_u1(32, 32, 3.0, 100, 5003)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=3, sap_block=[(4, 4), (1, 1), (1, 1)],
+                 inner_iters=[0, 3, 3])
+    gid = rec.gpu(ctx)
+    ctx.cnn_set_params(cnn_init_params(21))
+    log("cnn_train 32x32: 96 pairs, 12 epochs")
+    losses = ctx.cnn_train([gid], pairs_per_field=96, batch=16, epochs=12,
+                           adam=adam_params(lr=2e-3), seed=77, solve=solve_params(tol=1e-10, restart=16))
+    return rec, gid, losses
+
+
+def test_training_lowers_the_loss(trained):
+    _, _, losses = trained
+    log(f"epoch losses {losses}")
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.9 * losses[0]
+
+
+def test_solves_from_the_guess_meet_the_tolerance(ctx, trained):
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    D = dirac.wilson_dirac(rec.theta, rec.m0)
+    n = D.shape[0]
+    b = rhs_vectors(n, 12, 901)
+    out = {}
+    for use in (False, True):
+        x = empty(12, n)
+        _, its, _ = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=16, use_cnn=use))
+        xh = to_host(x)
+        res = np.linalg.norm(b - (D @ xh.T).T, axis=1) / np.linalg.norm(b, axis=1)
+        assert np.all(res <= 1e-10), (use, res)
+        out[use] = its
+    log(f"iterations plain {np.mean(out[False]):.2f} with guess {np.mean(out[True]):.2f}")
+
+
+def test_guess_has_minimal_residual_along_the_network_output(ctx, trained):
+    rec, gid, _ = trained
+    D = dirac.wilson_dirac(rec.theta, rec.m0)
+    n = D.shape[0]
+    b = rhs_vectors(n, 4, 902)
+    y = empty(4, n)
+    ctx.cnn_apply(gid, to_dev(b), y)
+    yh = to_host(y)
+    for r in range(4):
+        u = D @ yh[r]
+        alpha = np.vdot(u, b[r]) / np.vdot(u, u)
+        assert np.linalg.norm(b[r] - alpha * u) <= np.linalg.norm(b[r])
+
+
+def test_broken_network_falls_back_to_plain_multigrid(ctx, trained):
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    good = ctx.cnn_get_params()
+    n = 2 * 32 * 32
+    b = to_dev(rhs_vectors(n, 6, 903))
+    x0 = empty(6, n)
+    ctx.solve_batch(gid, 0, b, x0, solve_params(tol=1e-10, restart=16))
+    try:
+        bad = good.copy()
+        bad[::7] = np.nan
+        ctx.cnn_set_params(bad)
+        x1 = empty(6, n)
+        ctx.solve_batch(gid, 0, b, x1, solve_params(tol=1e-10, restart=16, use_cnn=True))
+        # the guess is rejected, so the solve is the plain one, bit for bit
+        assert np.array_equal(to_host(x1), to_host(x0))
+    finally:
+        ctx.cnn_set_params(good)
+
+
+def test_lattice_must_tile_by_16(ctx):
+    from paper_2303_11512_amd import MGMError
+    gid, _ = _field(ctx, 24, 16, True, 14)
+    ctx.cnn_set_params(_theta(6))
+    b = to_dev(rhs_vectors(2 * 24 * 16, 1, 3))
+    with pytest.raises(MGMError):
+        ctx.cnn_apply(gid, b, empty(1, 2 * 24 * 16))
