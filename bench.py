@@ -236,6 +236,93 @@ def run_batch8(args):
     ctx.close()
 
 
+MFMA_FP32_PEAK_TFS = 157.3
+
+
+def run_cnn(args):
+    """Learned initial guess: train the network on quenched 128^2 fields
+    (beta 3.0, m0 -0.10, Z2xZ2 right-hand sides solved to 1e-10 by multigrid),
+    then solve 64 RHS on unseen 256^2 and 512^2 fields with and without it."""
+    import torch
+    from lattice_inputs import cnn_init_params, links_from_theta
+    from lattice_inputs.cnn import EVAL_FIELDS, TRAIN_FIELDS, field
+    from paper_2303_11512_amd import Context, adam_params, mg_params, solve_params
+    ctx = Context(0)
+
+    def setup(spec, seed):
+        blocks, ntv = solver_hierarchy(spec["L"])
+        gid = ctx.set_gauge(torch.from_numpy(links_from_theta(field(spec))).to("cuda"), spec["m0"], True)
+        ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + [(1, 1)] * 5,
+                                    sap_cycles=[3] * 6, inner_iters=[0] * 6, setup_tol=1e-10, seed=seed))
+        return gid
+
+    t0 = time.perf_counter()
+    train = [setup(s, 6000 + i) for i, s in enumerate(TRAIN_FIELDS[:args.train_fields])]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"# {len(train)} training fields set up in {setup_s:.1f}s", file=sys.stderr, flush=True)
+    ctx.cnn_set_params(cnn_init_params(1))
+    t0 = time.perf_counter()
+    losses = ctx.cnn_train(train, pairs_per_field=args.pairs, batch=64, epochs=args.epochs,
+                           adam=adam_params(lr=1e-3), seed=5, solve=solve_params(tol=1e-10, restart=32))
+    train_s = time.perf_counter() - t0
+    print(f"# trained: epoch losses {losses} in {train_s:.1f}s", file=sys.stderr, flush=True)
+    conv = ctx.time_kernel(train[0], "conv", 0, 64)
+    for gid in train:
+        ctx.free_gauge(gid)
+
+    sizes = sorted({s["L"] for s in EVAL_FIELDS})
+    evals = [s for L in sizes for s in [e for e in EVAL_FIELDS if e["L"] == L][:args.eval_fields]]
+    nrhs = 64
+    rows = []
+    for i, spec in enumerate(evals):
+        gid = setup(spec, 7000 + i)
+        n = ctx.level_info(gid, 0)["n"]
+        b = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
+        ctx.noise("z2z2", 11, 0, 0, 0, b)
+        x = torch.empty_like(b)
+        row = dict(L=spec["L"], seed=spec["seed"])
+        for use in (False, True):
+            sp = solve_params(tol=1e-10, restart=16, max_restarts=50, use_cnn=use)
+            ctx.solve_batch(gid, 0, b, x, sp)   # warm-up (workspaces, graphs)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                _, its, rel = ctx.solve_batch(gid, 0, b, x, sp)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / args.steps
+            assert float(np.max(rel)) <= 1e-10
+            key = "cnn" if use else "plain"
+            row[key] = dict(s=dt, iters=float(np.mean(its)))
+        rows.append(row)
+        ctx.free_gauge(gid)
+        print(f"# eval {spec['L']}^2 seed {spec['seed']}: plain {row['plain']['iters']:.2f} it "
+              f"{row['plain']['s'] * 1e3:.1f} ms, guess {row['cnn']['iters']:.2f} it "
+              f"{row['cnn']['s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_plain = sum(r["plain"]["s"] for r in rows)
+    t_cnn = sum(r["cnn"]["s"] for r in rows)
+    achieved = conv["flops"] / (conv["us"] * 1e-6) / 1e12
+    print(json.dumps({
+        "metric": "RHS solves/s (tol 1e-10) from the learned initial guess", "value": nrhs * len(rows) / t_cnn,
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_cnn * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"cnn: train on {len(train)} quenched 128^2 fields (beta 3.0, m0 -0.10, "
+                               f"{args.pairs} Z2xZ2 pairs each, {args.epochs} epochs, batch 64, Adam 1e-3); "
+                               f"evaluate 64 RHS on unseen fields at {sizes}",
+                   "plain_solves_per_s": nrhs * len(rows) / t_plain, "gain": t_plain / t_cnn,
+                   "iters_plain": float(np.mean([r["plain"]["iters"] for r in rows])),
+                   "iters_cnn": float(np.mean([r["cnn"]["iters"] for r in rows])),
+                   "epoch_losses": losses, "train_s": train_s, "setup_s": setup_s, "fields": rows},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_FP32_PEAK_TFS, "traffic": None,
+                     "kernel": "k_conv<32,32,tanh> (one hidden layer, 128^2, 64 fields)",
+                     "launch_us": conv["us"], "alg_flops": conv["flops"]},
+        "cpu_baseline": None,
+    }))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,12 +334,19 @@ def main():
                     help="precision of the multigrid preconditioner (outer FGMRES is FP64)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up, time the hot kernels and exit (for counter runs)")
+    ap.add_argument("--train-fields", type=int, default=20, help="cnn workload: training fields")
+    ap.add_argument("--pairs", type=int, default=1000, help="cnn workload: pairs per training field")
+    ap.add_argument("--epochs", type=int, default=4, help="cnn workload: training epochs")
+    ap.add_argument("--eval-fields", type=int, default=4, help="cnn workload: unseen fields per size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch8":
         run_batch8(args)
+        return
+    if args.workload == "cnn":
+        run_cnn(args)
         return
 
     import torch

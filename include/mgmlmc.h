@@ -82,6 +82,11 @@ const char *mgm_last_error(const mgm_ctx *ctx);
 int mgm_set_gauge(mgm_ctx *ctx, int Lx, int Lt, const void *links, double m0,
                   int bc_t_anti, int *gauge_id);
 
+/* free_gauge -- release a gauge field and everything built on it (multigrid
+ * hierarchy, workspaces, captured graphs) once its queued work has finished.
+ * The id is not reused; later calls with it fail with MGM_EINVAL. */
+int mgm_free_gauge(mgm_ctx *ctx, int gauge_id);
+
 /* ---------------------------------------------------------------------------
  * setup_mg -- aggregation multigrid hierarchy with R_l = P_l^H, P_l^H P_l = I
  * and Galerkin coarse operators D_{l+1} = P_l^H D_l P_l (Sec. 3.1), built by
@@ -282,12 +287,16 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
  *                       have one)
  *   MGM_KERNEL_CGS      one Gram-Schmidt projection pass against 16 vectors
  *   MGM_KERNEL_COPY     y = x, a plain copy of nrhs * n_level complex128
+ *   MGM_KERNEL_CONV     one hidden 32 -> 32 3x3 convolution (+ tanh) of the
+ *                       learned guess on nrhs fields of level 0 (FP32 matrix
+ *                       cores; needs mgm_cnn_set_params)
  * ------------------------------------------------------------------------- */
 #define MGM_KERNEL_STENCIL 0
 #define MGM_KERNEL_SAP 1
 #define MGM_KERNEL_DENSE 2
 #define MGM_KERNEL_CGS 3
 #define MGM_KERNEL_COPY 4
+#define MGM_KERNEL_CONV 5
 
 int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
                     double *us_out, double *bytes_out, double *flops_out);

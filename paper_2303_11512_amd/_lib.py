@@ -120,6 +120,7 @@ SIGNATURES = {
     "mgm_last_error": (C.c_char_p, [_P]),
     "mgm_set_gauge": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "mgm_setup_mg": (C.c_int, [_P, C.c_int, C.POINTER(MGParams)]),
+    "mgm_free_gauge": (C.c_int, [_P, C.c_int]),
     "mgm_level_info": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "mgm_apply_D": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P]),
     "mgm_apply_P": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P]),
@@ -156,7 +157,7 @@ class Job(C.Structure):
     _fields_ = [("gauge_id", C.c_int), ("level", C.c_int), ("nrhs", C.c_int),
                 ("b", C.c_void_p), ("x", C.c_void_p)]
 
-KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4}
+KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4, "conv": 5}
 
 _lib = None
 
@@ -277,6 +278,9 @@ class Context:
         self._chk(self.lib.mgm_set_gauge(self.h, Lx, Lt, _P(_ptr(links)), float(m0),
                                          int(bool(bc_t_anti)), C.byref(gid)), "set_gauge")
         return gid.value
+
+    def free_gauge(self, gid):
+        self._chk(self.lib.mgm_free_gauge(self.h, gid), "free_gauge")
 
     def setup_mg(self, gid: int, prm: MGParams):
         self._chk(self.lib.mgm_setup_mg(self.h, gid, C.byref(prm)), "setup_mg")

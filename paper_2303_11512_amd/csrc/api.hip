@@ -57,6 +57,11 @@ Gauge& gauge_of(mgm_ctx* c, int id) {
   return *c->gauges[id];
 }
 
+Cnn& cnn_of(mgm_ctx* c) {
+  require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
+  return *c->cnn;
+}
+
 Level& level_of(Gauge& g, int level) {
   require(level >= 0 && level < (int)g.levels.size(),
           "level out of range (call setup_mg for coarse levels)");
@@ -138,6 +143,15 @@ int mgm_set_gauge(mgm_ctx* c, int Lx, int Lt, const void* links, double m0, int 
     HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
     c->gauges.push_back(std::move(g));
     *gauge_id = (int)c->gauges.size() - 1;
+    return MGM_OK;
+  });
+}
+
+int mgm_free_gauge(mgm_ctx* c, int gauge_id) {
+  return guarded(c, [&] {
+    (void)gauge_of(c, gauge_id);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->gauges[gauge_id].reset();  // waits for the field's stream, frees its memory
     return MGM_OK;
   });
 }
@@ -350,6 +364,21 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         launch = [=] { launch_axpby<double>(s, 1.0, x, 0.0, nullptr, y, n, nrhs, nullptr); };
         bytes = 32.0 * n * b;
         break;
+      case MGM_KERNEL_CONV: {
+        require(level == 0, "the network runs on level 0");
+        cnn_check_lattice(g);
+        const Cnn* net = &cnn_of(c);
+        const int64_t V = (int64_t)g.Lx * g.Lt;
+        g.cnn.a[0].ensure(sizeof(float) * V * 32 * nrhs);
+        g.cnn.a[1].ensure(sizeof(float) * V * 32 * nrhs);
+        const float* in = g.cnn.a[0].as<float>();
+        float* out = g.cnn.a[1].as<float>();
+        HIPCHK(hipMemsetAsync(g.cnn.a[0].p, 0, sizeof(float) * V * 32 * nrhs, s));
+        launch = [=, &g] { cnn_time_conv(s, *net, g, nrhs, in, out); };
+        bytes = 4.0 * V * b * 64 + 4.0 * 32 * 289;
+        flops = 2.0 * V * b * 32 * 288;
+        break;
+      }
       default:
         throw Error(MGM_EINVAL, "unknown kernel kind");
     }
@@ -484,12 +513,6 @@ int mgm_autotune_rhs_block(mgm_ctx* c, int gauge_id, int level, int nrhs,
 }
 
 // ---------------------------------------------------------------- learned initial guess
-namespace {
-Cnn& cnn_of(mgm_ctx* c) {
-  require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
-  return *c->cnn;
-}
-}  // namespace
 
 int mgm_cnn_set_params(mgm_ctx* c, const float* theta) {
   return guarded(c, [&] {
@@ -597,7 +620,7 @@ int mgm_cnn_train(mgm_ctx* c, int nfields, const int* gauge_ids, const mgm_cnn_t
     w.pairs_b.ensure(sizeof(float) * npairs * n * 2);
     w.pairs_x.ensure(sizeof(float) * npairs * n * 2);
     // targets: multigrid solves on each field's own stream, in chunks
-    const int chunk = std::min(P, 256);
+    const int chunk = std::min(P, 64);
     int status = MGM_OK;
     for (int f = 0; f < nfields; ++f) {
       Gauge& g = gauge_of(c, gauge_ids[f]);

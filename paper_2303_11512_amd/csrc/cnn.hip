@@ -429,6 +429,15 @@ void cnn_forward(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const fl
   KCHK();
 }
 
+// One hidden 32 -> 32 convolution with tanh (the network's dominant kernel),
+// for timing.
+void cnn_time_conv(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const float* in, float* out) {
+  const dim3 grid(g.Lx / TE, g.Lt / TE, nb);
+  hipLaunchKernelGGL((k_conv<32, 32, EPI_TANH>), grid, dim3(CNT), 0, s, in, g.Lx, g.Lt, g.anti,
+                     net.wf[1].as<float>(), net.bias(1), nullptr, out);
+  KCHK();
+}
+
 namespace {
 template <int CIN, int COUT>
 void wgrad(hipStream_t s, const Gauge& g, int nb, const float* X, const float* G, CnnWork& w,

@@ -345,4 +345,5 @@ void cnn_to_channels(hipStream_t s, const cd* in, int64_t ndof, float* out);
 void cnn_from_channels(hipStream_t s, const float* in, int64_t ndof, cd* out);
 void cnn_apply(hipStream_t s, const Cnn& net, const Gauge& g, int nrhs, const cd* b, cd* y, CnnWork& w);
 void cnn_initial_guess(mgm_ctx* c, Gauge& g, int nrhs, const cd* b, cd* x, cd* u);
+void cnn_time_conv(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const float* in, float* out);
 }  // namespace mgm

@@ -88,3 +88,17 @@ def test_autotuner_picks_a_width_and_solves(ctx, fields):
     ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=16, rhs_block=-1))
     res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
     assert np.all(res <= 1e-10)
+
+
+def test_free_gauge_releases_the_field(ctx):
+    from paper_2303_11512_amd import MGMError, mg_params
+    th = metropolis_u1(16, 16, 3.0, 20, 7200)
+    gid = ctx.set_gauge(to_dev(np.exp(1j * th)), -0.05, True)
+    ctx.setup_mg(gid, mg_params(2, [(4, 4)], [4], seed=2))
+    ctx.free_gauge(gid)
+    with pytest.raises(MGMError):
+        ctx.level_info(gid, 0)
+    with pytest.raises(MGMError):
+        ctx.free_gauge(gid)
+    gid2 = ctx.set_gauge(to_dev(np.exp(1j * th)), -0.05, True)
+    assert gid2 != gid and ctx.level_info(gid2, 0)["n"] == 2 * 16 * 16
