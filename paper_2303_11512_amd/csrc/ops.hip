@@ -640,6 +640,107 @@ __global__ void __launch_bounds__(NT) k_gj_eliminate(cd* __restrict__ A, int64_t
   *o = base - fi * A[k * n + j];
 }
 
+// ---- blocked Gauss-Jordan: the steps of a 64-column panel run on the panel
+// only; the rest of the matrix then takes the panel's row swaps and one
+// rank-64 update on the FP64 matrix cores.
+constexpr int GJ_NB = 64;
+
+// swap rows k and perm[k], then scale row k, on the columns [c0, c0 + GJ_NB)
+__global__ void __launch_bounds__(NT) k_gj_swap_scale_panel(cd* __restrict__ A, int64_t n, int64_t k,
+                                                            int64_t c0, const int* __restrict__ perm,
+                                                            const cd* __restrict__ pivinv) {
+  const int t = threadIdx.x;
+  if (t >= GJ_NB) return;
+  const int64_t j = c0 + t;
+  const int64_t p = perm[k];
+  const cd vk = A[k * n + j], vp = A[p * n + j];
+  if (p != k) A[p * n + j] = vk;
+  A[k * n + j] = ((j == k) ? mk(1.0, 0.0) : vp) * (*pivinv);
+}
+
+// elimination of column k on the panel columns: thread e -> (row e / 64, column c0 + e % 64)
+__global__ void __launch_bounds__(NT) k_gj_eliminate_panel(cd* __restrict__ A, int64_t n, int64_t k,
+                                                           int64_t c0, const cd* __restrict__ f) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t i = e / GJ_NB, j = c0 + e % GJ_NB;
+  if (i >= n || i == k) return;
+  const cd fi = f[i];
+  if (fi.re == 0.0 && fi.im == 0.0) return;
+  cd* o = A + i * n + j;
+  const cd base = (j == k) ? mk(0.0, 0.0) : *o;
+  *o = base - fi * A[k * n + j];
+}
+
+// the panel's row swaps on the other columns, in step order; T = the panel
+// rows of those columns (zero on the panel columns)
+__global__ void __launch_bounds__(NT) k_gj_swaps_rest(cd* __restrict__ A, int64_t n, int64_t c0,
+                                                      const int* __restrict__ perm, cd* __restrict__ T) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  const bool panel = j >= c0 && j < c0 + GJ_NB;
+  if (!panel) {
+    for (int q = 0; q < GJ_NB; ++q) {
+      const int64_t k = c0 + q, p = perm[k];
+      if (p != k) {
+        const cd a = A[k * n + j];
+        A[k * n + j] = A[p * n + j];
+        A[p * n + j] = a;
+      }
+    }
+  }
+  for (int q = 0; q < GJ_NB; ++q) T[(int64_t)q * n + j] = panel ? mk(0.0, 0.0) : A[(c0 + q) * n + j];
+}
+
+// A[i][j] = (i in panel rows ? 0 : A[i][j]) + sum_q A[i][c0 + q] T[q][j] for
+// the columns j outside the panel.  64 x 64 output tiles, each wave a 32 x 32
+// quarter as 2 x 2 blocks of 16 x 16; complex products as four real FP64 MFMAs.
+__global__ void __launch_bounds__(NT) k_gj_update(cd* __restrict__ A, int64_t n, int64_t c0,
+                                                  const cd* __restrict__ T) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
+  const int64_t j0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  if (j0 + 32 > c0 && j0 < c0 + GJ_NB) return;  // panel columns (uniform per wave)
+  typedef MF<double>::v4 v4;
+  v4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = v4{0, 0, 0, 0};
+      ci[a][b] = v4{0, 0, 0, 0};
+    }
+  const int r = lane & 15, q4 = lane >> 4;
+  for (int kk = 0; kk < GJ_NB; kk += 4) {
+    const int q = kk + q4;
+    cd av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = A[(i0 + a * 16 + r) * n + c0 + q];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = T[(int64_t)q * n + j0 + b * 16 + r];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = MF<double>::mma(av[a].re, bv[b].re, cr[a][b]);
+        cr[a][b] = MF<double>::mma(-av[a].im, bv[b].im, cr[a][b]);
+        ci[a][b] = MF<double>::mma(av[a].re, bv[b].im, ci[a][b]);
+        ci[a][b] = MF<double>::mma(av[a].im, bv[b].re, ci[a][b]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + a * 16 + MF<double>::out_row(lane, v);
+        const int64_t j = j0 + b * 16 + r;
+        cd* o = A + i * n + j;
+        const cd base = (i >= c0 && i < c0 + GJ_NB) ? mk(0.0, 0.0) : *o;
+        *o = mk(base.re + cr[a][b][v], base.im + ci[a][b][v]);
+      }
+}
+
 __global__ void __launch_bounds__(NT) k_gather_cols(const cd* __restrict__ W, int64_t n,
                                                     const int* __restrict__ pi, cd* __restrict__ out) {
   const int64_t i = blockIdx.y;
@@ -952,8 +1053,9 @@ void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M
   KCHK();
 }
 
-// In-place Gauss-Jordan with partial pivoting; the column unscrambling is a
-// gather into `out`.  Returns 0, or 1 on a zero pivot.
+// In-place Gauss-Jordan with partial pivoting (blocked for n a multiple of 64,
+// n >= 512); the column unscrambling is a gather into `out`.  Returns 0, or 1
+// on a zero pivot.
 int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* out) {
   DevBuf perm, piv, fcol, fail, pi;
   perm.ensure(sizeof(int) * n);
@@ -962,15 +1064,37 @@ int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* out) {
   fail.ensure(sizeof(int));
   pi.ensure(sizeof(int) * n);
   HIPCHK(hipMemsetAsync(fail.p, 0, sizeof(int), s));
-  for (int64_t k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, s, A, n, k, perm.as<int>(), piv.as<cd>(),
-                       fail.as<int>());
-    hipLaunchKernelGGL(k_gj_swap_scale, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, perm.as<int>(),
-                       piv.as<cd>());
-    hipLaunchKernelGGL(k_gj_col, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, fcol.as<cd>());
-    hipLaunchKernelGGL(k_gj_eliminate, dim3(grid1(n), (unsigned)n), dim3(NT), 0, s, A, n, k,
-                       fcol.as<cd>());
-    KCHK();
+  if (n % GJ_NB == 0 && n >= 8 * GJ_NB) {
+    // blocked: panel steps on 64 columns, then swaps and a rank-64 update
+    DevBuf T;
+    T.ensure(sizeof(cd) * GJ_NB * n);
+    const unsigned tiles = (unsigned)(n / 64);
+    for (int64_t c0 = 0; c0 < n; c0 += GJ_NB) {
+      for (int64_t k = c0; k < c0 + GJ_NB; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, s, A, n, k, perm.as<int>(), piv.as<cd>(),
+                           fail.as<int>());
+        hipLaunchKernelGGL(k_gj_swap_scale_panel, dim3(1), dim3(NT), 0, s, A, n, k, c0, perm.as<int>(),
+                           piv.as<cd>());
+        hipLaunchKernelGGL(k_gj_col, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, fcol.as<cd>());
+        hipLaunchKernelGGL(k_gj_eliminate_panel, dim3(grid1(n * GJ_NB)), dim3(NT), 0, s, A, n, k, c0,
+                           fcol.as<cd>());
+      }
+      hipLaunchKernelGGL(k_gj_swaps_rest, dim3(grid1(n)), dim3(NT), 0, s, A, n, c0, perm.as<int>(),
+                         T.as<cd>());
+      hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles), dim3(NT), 0, s, A, n, c0, T.as<cd>());
+      KCHK();
+    }
+  } else {
+    for (int64_t k = 0; k < n; ++k) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(NT), 0, s, A, n, k, perm.as<int>(), piv.as<cd>(),
+                         fail.as<int>());
+      hipLaunchKernelGGL(k_gj_swap_scale, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, perm.as<int>(),
+                         piv.as<cd>());
+      hipLaunchKernelGGL(k_gj_col, dim3(grid1(n)), dim3(NT), 0, s, A, n, k, fcol.as<cd>());
+      hipLaunchKernelGGL(k_gj_eliminate, dim3(grid1(n), (unsigned)n), dim3(NT), 0, s, A, n, k,
+                         fcol.as<cd>());
+      KCHK();
+    }
   }
   std::vector<int> hperm(n), hpi(n);
   int hfail = 0;

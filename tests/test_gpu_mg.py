@@ -130,3 +130,25 @@ def test_solves_reach_tolerance(ctx, built, nrhs):
         assert np.all(res <= 1e-10), (name, l, res)
         exact = lev.solve(b.T).T
         assert rel_err(xs, exact) < 1e-6
+
+
+@pytest.mark.parametrize("L", [32, 64])
+def test_blocked_dense_inverse(ctx, L):
+    """Coarsest levels of n = 1024 and 4096 take the blocked Gauss-Jordan path
+    (64-column panels, rank-64 MFMA updates): exact trace and the dense coarse
+    solve against the oracle."""
+    from oracle import mg
+    th = metropolis_u1(L, L, 3.0, 100, 900 + L)
+    rec = Recipe(th, -0.05, [(4, 4)], [8], seed=11, sap_block=[(4, 4), (1, 1)], inner_iters=[4, 4])
+    log(f"blocked GJ: {L}^2, coarsest n = {(L // 4) ** 2 * 16}")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    coarse = hier.levels[-1]
+    want = mg.coarsest_trace(coarse)
+    got = ctx.coarsest_trace(gid)
+    assert abs(got - want) < 1e-9 * abs(want), (got, want)
+    r = rhs_vectors(coarse.n, 3, 91)
+    x = empty(3, coarse.n)
+    ctx.precondition(gid, 1, to_dev(r), x)
+    ref = np.linalg.solve(coarse.D.toarray(), r.T).T
+    assert rel_err(to_host(x), ref) < 1e-9
