@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 def mg_setup_kwargs(cfg):
-    """The workload's MLMC hierarchy plus, when its coarsest level is large,
-    one solver-only 2x2 coarsening below it (the MLMC sum still closes on the
+    """The workload's MLMC hierarchy plus, while its coarsest level is large,
+    solver-only 2x2 coarsenings below it (the MLMC sum still closes on the
     workload's coarsest level, whose trace is computed exactly); plain
     V-cycles with 3 red/black SAP cycles per level."""
     blocks, ntv = list(cfg["blocks"]), list(cfg["ntv"])
@@ -37,9 +37,10 @@ def mg_setup_kwargs(cfg):
     Nx, Nt = cfg["Lx"], cfg["Lt"]
     for (bx, bt) in blocks:
         Nx, Nt = Nx // bx, Nt // bt
-    if Nx * Nt * 2 * ntv[-1] > 2048 and Nx % 4 == 0 and Nt % 4 == 0:
+    while Nx * Nt * 2 * ntv[-1] > 2048 and Nx % 4 == 0 and Nt % 4 == 0 and len(blocks) < 5:
         blocks.append((2, 2))
         ntv.append(ntv[-1])
+        Nx, Nt = Nx // 2, Nt // 2
     L = len(blocks) + 1
     return dict(
         nlevels=L, blocks=blocks, ntv=ntv, mlmc_levels=mlmc,
@@ -239,6 +240,69 @@ def run_batch8(args):
 MFMA_FP32_PEAK_TFS = 157.3
 
 
+def run_mixed(args):
+    """Mixed precision at 512^2 (beta 4.0, m0 -0.08): 256 Z2xZ2 RHS solved to
+    1e-10 with the FP64 and with the FP32 preconditioner (outer FGMRES FP64 in
+    both), and one MG-MLMC++ estimate to 1e-3 in each precision."""
+    import torch
+    from lattice_inputs import WORKLOADS, gauge_for, links_from_theta
+    from paper_2303_11512_amd import Context, mg_params, solve_params
+    cfg = dict(WORKLOADS["schwinger512"], name="schwinger512")
+    th = gauge_for(cfg)
+    ctx = Context(0)
+    gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), cfg["m0"], True)
+    kw = mg_setup_kwargs(cfg)
+    t0 = time.perf_counter()
+    ctx.setup_mg(gid, mg_params(**kw))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"# setup {setup_s:.2f}s, levels {kw['blocks']}", file=sys.stderr, flush=True)
+    n = ctx.level_info(gid, 0)["n"]
+    nrhs = 256
+    b = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
+    ctx.noise("z2z2", 13, 0, 0, 0, b)
+    sp = solve_params(tol=1e-10, restart=16, max_restarts=50, rhs_block=64)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        ctx.set_precision(gid, prec)
+        x = torch.empty_like(b)
+        ctx.solve_batch(gid, 0, b, x, sp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, its, rel = ctx.solve_batch(gid, 0, b, x, sp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        t1 = time.perf_counter()
+        est = ctx.trace_estimate(gid, solve=solve_params(tol=1e-10, restart=16, rhs_block=64),
+                                 **trace_kwargs(cfg, 0))
+        torch.cuda.synchronize()
+        res[prec] = dict(solve_s=dt, solves_per_s=nrhs / dt, iters=float(np.mean(its)),
+                         max_relres=float(np.max(rel)), x=x,
+                         trace_s=time.perf_counter() - t1, tau=est["tau"],
+                         samples=est["level_samples"])
+        print(f"# {prec}: {nrhs / dt:.1f} solves/s, {np.mean(its):.2f} it, max relres {np.max(rel):.2e}, "
+              f"estimate {est['tau']:.6f} in {res[prec]['trace_s']:.2f}s", file=sys.stderr, flush=True)
+    dx = float(torch.linalg.norm(res["fp32"]["x"] - res["fp64"]["x"]) / torch.linalg.norm(res["fp64"]["x"]))
+    tau64, tau32 = res["fp64"]["tau"], res["fp32"]["tau"]
+    for r in res.values():
+        r.pop("x")
+        r["tau"] = [r["tau"].real, r["tau"].imag]
+    print(json.dumps({
+        "metric": "RHS solves/s (tol 1e-10), FP32 preconditioner in FP64 FGMRES", "value": res["fp32"]["solves_per_s"],
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": res["fp32"]["solve_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"mixed512: 512x512 Schwinger, beta {cfg['beta']}, m0 {cfg['m0']}, MG "
+                               f"{kw['blocks']} (MLMC closes on level {kw['mlmc_levels'] - 1}), 256 Z2xZ2 RHS "
+                               f"in blocks of 64, FGMRES(16) tol 1e-10; one MG-MLMC++ estimate to {cfg['eps']}",
+                   "fp64": res["fp64"], "fp32": res["fp32"], "speedup": res["fp64"]["solve_s"] / res["fp32"]["solve_s"],
+                   "x_rel_diff": dx, "tau_rel_diff": abs(tau32 - tau64) / abs(tau64), "setup_s": setup_s},
+        "roofline": None, "cpu_baseline": None,
+    }))
+    ctx.close()
+
+
 def run_cnn(args):
     """Learned initial guess: train the network on quenched 128^2 fields
     (beta 3.0, m0 -0.10, Z2xZ2 right-hand sides solved to 1e-10 by multigrid),
@@ -347,6 +411,9 @@ def main():
         return
     if args.workload == "cnn":
         run_cnn(args)
+        return
+    if args.workload == "mixed512":
+        run_mixed(args)
         return
 
     import torch

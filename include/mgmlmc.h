@@ -126,6 +126,11 @@ typedef struct {
 
 int mgm_setup_mg(mgm_ctx *ctx, int gauge_id, const mgm_mg_params *prm);
 
+/* set_precision -- switch the preconditioner of a set-up field between
+ * MGM_PREC_FP64 and MGM_PREC_FP32 without a new setup (setup_mg keeps both
+ * copies of every level); the outer FGMRES stays FP64. */
+int mgm_set_precision(mgm_ctx *ctx, int gauge_id, int precision);
+
 /* Level geometry: info[0..3] = Nx, Nt, dof per site M, n = Nx*Nt*M. */
 int mgm_level_info(mgm_ctx *ctx, int gauge_id, int level, int *info);
 

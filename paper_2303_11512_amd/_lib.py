@@ -121,6 +121,7 @@ SIGNATURES = {
     "mgm_set_gauge": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_double, C.c_int, C.POINTER(C.c_int)]),
     "mgm_setup_mg": (C.c_int, [_P, C.c_int, C.POINTER(MGParams)]),
     "mgm_free_gauge": (C.c_int, [_P, C.c_int]),
+    "mgm_set_precision": (C.c_int, [_P, C.c_int, C.c_int]),
     "mgm_level_info": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "mgm_apply_D": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P]),
     "mgm_apply_P": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P]),
@@ -278,6 +279,10 @@ class Context:
         self._chk(self.lib.mgm_set_gauge(self.h, Lx, Lt, _P(_ptr(links)), float(m0),
                                          int(bool(bc_t_anti)), C.byref(gid)), "set_gauge")
         return gid.value
+
+    def set_precision(self, gid, precision: str):
+        self._chk(self.lib.mgm_set_precision(self.h, gid, {"fp64": PREC_FP64, "fp32": PREC_FP32}[precision]),
+                  "set_precision")
 
     def free_gauge(self, gid):
         self._chk(self.lib.mgm_free_gauge(self.h, gid), "free_gauge")

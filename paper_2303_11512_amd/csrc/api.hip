@@ -167,6 +167,19 @@ int mgm_setup_mg(mgm_ctx* c, int gauge_id, const mgm_mg_params* prm) {
   });
 }
 
+int mgm_set_precision(mgm_ctx* c, int gauge_id, int precision) {
+  return guarded(c, [&] {
+    require(precision == MGM_PREC_FP64 || precision == MGM_PREC_FP32, "unknown precision");
+    Gauge& g = gauge_of(c, gauge_id);
+    require(g.mg_ready, "setup_mg first", MGM_ESTATE);
+    OnGauge og(c, g);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    g.clear_graphs();
+    g.prm.precision = precision;
+    return MGM_OK;
+  });
+}
+
 int mgm_level_info(mgm_ctx* c, int gauge_id, int level, int* info) {
   return guarded(c, [&] {
     require(info != nullptr, "null pointer");

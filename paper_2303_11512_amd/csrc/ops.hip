@@ -557,6 +557,176 @@ __device__ __forceinline__ T xr_elem(cx<T> v, int q, int p) {
   return p == 0 ? (q == 0 ? v.re : -v.im) : (q == 0 ? v.im : v.re);
 }
 
+// ------------------------------------------------------------------ coarse levels on the matrix cores
+// Levels with 16 dofs per site (8 test vectors x 2 chiralities).  A wave owns
+// a 16 (dofs) x 16 (RHS) complex tile; a complex product is four real MFMAs.
+// In K-chunk c, lane l takes the K index kc(l, c) = out_row(l, c), so that the
+// result tile of one product (element c of a lane = row kc(l, c)) is already
+// the B operand of the next one, with no shuffle.
+constexpr int CM = 16;
+
+template <class T>
+struct CAcc {
+  typename MF<T>::v4 re, im;
+};
+
+template <class T>
+__device__ __forceinline__ void cmma(cx<T> a, cx<T> b, CAcc<T>& acc) {
+  acc.re = MF<T>::mma(a.re, b.re, acc.re);
+  acc.re = MF<T>::mma(-a.im, b.im, acc.re);
+  acc.im = MF<T>::mma(a.re, b.im, acc.im);
+  acc.im = MF<T>::mma(a.im, b.re, acc.im);
+}
+
+// acc += sum_d B_d x_{nb(u, d)} for the RHS column of this lane (zero operand
+// for lanes past the last RHS); Bs = the site's 5 blocks in LDS, row-major.
+template <class T>
+__device__ __forceinline__ void coarse_hops(const cx<T>* Bs, const cx<T>* __restrict__ x, int64_t n,
+                                            int64_t u, int Nx, int Nt, int64_t rrow, bool ok, int lane,
+                                            CAcc<T>& acc) {
+  const int i = lane & 15;
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    const cx<T>* xv = x + rrow * n + nb_site(u, d, Nx, Nt) * CM;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = MF<T>::out_row(lane, c);
+      const cx<T> xb = ok ? xv[k] : mk<T>(0, 0);
+      cmma(Bs[(d * CM + i) * CM + k], xb, acc);
+    }
+  }
+}
+
+// y = D x or y = b - D x on a coarse level (16 dofs per site); one workgroup
+// per site and 64 RHS (a wave per 16).
+template <class T>
+__global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B, int Nx, int Nt, int nrhs,
+                                                     const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                     const cx<T>* __restrict__ b,
+                                                     const int* __restrict__ active) {
+  __shared__ cx<T> Bs[5 * CM * CM];
+  const int64_t u = blockIdx.x;
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  for (int e = threadIdx.x; e < 5 * CM * CM; e += NT) Bs[e] = B[u * 5 * CM * CM + e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.y * 4 + wave) * 16;
+  if (r0 >= nrhs) return;
+  const int r = r0 + (lane & 15);
+  const bool ok = r < nrhs;
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hops(Bs, x, n, u, Nx, Nt, ok ? r : r0, ok, lane, acc);
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t o = (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
+    const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
+    y[o] = b ? b[o] - val : val;
+  }
+}
+
+// One colour of the coarse SAP sweep with one-site blocks: for each site u of
+// the colour and each RHS, t = r_u - (D x)_u, x_u += inv_u t.
+template <class T>
+__global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
+                                                 int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                 const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
+                                                 const int* __restrict__ active) {
+  __shared__ cx<T> Bs[5 * CM * CM];
+  __shared__ cx<T> Is[CM * CM];
+  const int64_t u = blist[blockIdx.x];
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  for (int e = threadIdx.x; e < 5 * CM * CM; e += NT) Bs[e] = B[u * 5 * CM * CM + e];
+  for (int e = threadIdx.x; e < CM * CM; e += NT) Is[e] = inv[u * CM * CM + e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.y * 4 + wave) * 16;
+  if (r0 >= nrhs) return;
+  const int i = lane & 15;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hops(Bs, x, n, u, Nx, Nt, rrow, ok, lane, acc);
+  // t = r - D x in the result layout: element c = row out_row(lane, c)
+  cx<T> t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const cx<T> rv = ok ? rr[rrow * n + u * CM + MF<T>::out_row(lane, c)] : mk<T>(0, 0);
+    t[c] = mk<T>(rv.re - acc.re[c], rv.im - acc.im[c]);
+  }
+  CAcc<T> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cmma(Is[i * CM + MF<T>::out_row(lane, c)], t[c], cor);
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    cx<T>* o = x + (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
+    *o = *o + mk<T>(cor.re[v], cor.im[v]);
+  }
+}
+
+// y[r] = A x[r] for a dense n x n A (n a multiple of 16): a wave owns 16 rows
+// x 16 RHS over a quarter of the workgroup's k range; the quarters are summed
+// in LDS, and k ranges split over gridDim.z go to part[z] (k_dense_reduce).
+template <class T>
+__global__ void __launch_bounds__(NT) k_dense_mfma(const cx<T>* __restrict__ A, int64_t n, int nrhs,
+                                                   int64_t klen, const cx<T>* __restrict__ x,
+                                                   cx<T>* __restrict__ y, cx<T>* __restrict__ part,
+                                                   const int* __restrict__ active) {
+  __shared__ T red[2][3][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 16;
+  const int r0 = blockIdx.y * 16;
+  const int i = lane & 15;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  const int64_t kb = (int64_t)blockIdx.z * klen;
+  const int64_t ke = min(n, kb + klen);
+  // the workgroup's k range in 16-wide steps, split over the 4 waves
+  const int64_t steps = (ke - kb + 15) / 16, per = (steps + 3) / 4;
+  const int64_t kw0 = min(ke, kb + per * 16 * wave);
+  const int64_t kw1 = min(ke, kw0 + per * 16);
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const cx<T>* Ar = A + (i0 + i) * n;
+  const cx<T>* xr = x + rrow * n;
+  for (int64_t k0 = kw0; k0 < kw1; k0 += 16) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t k = k0 + MF<T>::out_row(lane, c);
+      const bool in = k < kw1;
+      const cx<T> a = in ? Ar[k] : mk<T>(0, 0);
+      const cx<T> xb = (ok && in) ? xr[k] : mk<T>(0, 0);
+      cmma(a, xb, acc);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[0][wave - 1][v][lane] = acc.re[v];
+      red[1][wave - 1][v][lane] = acc.im[v];
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc.re[v] += red[0][w][v][lane];
+      acc.im[v] += red[1][w][v][lane];
+    }
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = i0 + MF<T>::out_row(lane, v);
+    const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
+    if (gridDim.z == 1) y[(int64_t)r * n + row] = val;
+    else part[((int64_t)blockIdx.z * nrhs + r) * n + row] = val;
+  }
+}
+
 // ------------------------------------------------------------------ dense coarsest level
 __global__ void __launch_bounds__(NT) k_dense_from_stencil(const cd* __restrict__ B, int Nx, int Nt,
                                                            int M, cd* __restrict__ A) {
@@ -965,7 +1135,10 @@ void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, i
     case 2: hipLaunchKernelGGL((k_stencil<T, 2>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
     case 4: hipLaunchKernelGGL((k_stencil_lds<T, 4>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 8: hipLaunchKernelGGL((k_stencil_lds<T, 8>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
-    case 16: hipLaunchKernelGGL((k_stencil_lds<T, 16>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
+    case 16:
+      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites, (nrhs + 63) / 64), dim3(NT), 0, s, blocks,
+                         Nx, Nt, nrhs, x, y, b, active);
+      break;
     case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
     default: throw Error(MGM_EINVAL, "block stencil: dofs per site must be 2, 4, 8, 16 or 32");
   }
@@ -1030,6 +1203,12 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   if (nb <= 0) return;
   const int K = sbx * sbt * M;
   require(K <= 32, "SAP block too large");
+  if (M == CM && sbx == 1 && sbt == 1) {
+    hipLaunchKernelGGL(k_sap_mfma<T>, dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
+                       nrhs, r, x, active);
+    KCHK();
+    return;
+  }
   const int rpw = NT / K;
   // RHS per workgroup: enough workgroups (~2048, 8 per CU) to hide the
   // memory latency of each round, at the price of re-reading the block's
@@ -1121,6 +1300,29 @@ void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out) {
 template <class T>
 void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, const cx<T>* x,
                         cx<T>* y, const int* active, DevBuf* scratch) {
+  if (n % 16 == 0 && scratch) {
+    // matrix cores: 16 x 16 tiles, k split over 4 waves and then over
+    // workgroups until ~1024 workgroups (k ranges of at least 256)
+    const unsigned ti = (unsigned)(n / 16), tr = (unsigned)((nrhs + 15) / 16);
+    int ks = 1;
+    while (ks < 32 && (int64_t)ti * tr * ks < 1024 && n / (2 * ks) >= 256) ks *= 2;
+    const int64_t klen = ((n + ks - 1) / ks + 15) / 16 * 16;
+    ks = (int)((n + klen - 1) / klen);
+    cx<T>* part = nullptr;
+    if (ks > 1) {
+      scratch->ensure(sizeof(cx<T>) * (size_t)ks * nrhs * n);
+      part = scratch->as<cx<T>>();
+    }
+    hipLaunchKernelGGL(k_dense_mfma<T>, dim3(ti, tr, ks), dim3(NT), 0, s, A, n, nrhs, klen, x, y, part,
+                       active);
+    KCHK();
+    if (ks > 1) {
+      hipLaunchKernelGGL(k_dense_reduce<T>, dim3(grid1(n), nrhs), dim3(NT), 0, s, part, ks, n, nrhs, y,
+                         active);
+      KCHK();
+    }
+    return;
+  }
   const unsigned tiles_i = (unsigned)((n + 63) / 64), tiles_r = (unsigned)((nrhs + 15) / 16);
   // split k until ~1024 workgroups, keeping k ranges of at least 128
   int ks = 1;
