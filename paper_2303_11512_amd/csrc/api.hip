@@ -345,10 +345,12 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
           launch_sap_sweep<double>(s, L.d.B(), L.d.sapinv.as<cd>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
                                    L.color_list[0].as<int>(), L.ncolor[0], nrhs, r, y, nullptr);
         };
-        const double nb = L.ncolor[0], nsb = (double)L.sbx * L.sbt;
+        // with the exact block inverse a sweep is x_B = inv_B (r_B - D_BH x_H):
+        // r_B and the halo read, x_B written, inv_B and the outward hops read
+        const double nb = L.ncolor[0];
         const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // neighbour dofs per block
-        bytes = 16.0 * b * nb * (3.0 * L.K + halo) + 16.0 * nb * ((double)L.K * L.K + nsb * 5.0 * L.M * L.M);
-        flops = 8.0 * b * nb * ((double)L.K * L.K + nsb * 5.0 * L.M * L.M);
+        bytes = 16.0 * b * nb * (2.0 * L.K + halo) + 16.0 * nb * ((double)L.K * L.K + halo * L.M);
+        flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
         break;
       }
       case MGM_KERNEL_DENSE:

@@ -578,15 +578,16 @@ __device__ __forceinline__ void cmma(cx<T> a, cx<T> b, CAcc<T>& acc) {
   acc.im = MF<T>::mma(a.im, b.re, acc.im);
 }
 
-// acc += sum_d B_d x_{nb(u, d)} for the RHS column of this lane (zero operand
-// for lanes past the last RHS); Bs = the site's 5 blocks in LDS, row-major.
-template <class T>
+// acc += sum_{d >= D0} B_d x_{nb(u, d)} for the RHS column of this lane (zero
+// operand for lanes past the last RHS); Bs = the site's 5 blocks in LDS,
+// row-major; D0 = 1 leaves out the site's own block.
+template <int D0, class T>
 __device__ __forceinline__ void coarse_hops(const cx<T>* Bs, const cx<T>* __restrict__ x, int64_t n,
                                             int64_t u, int Nx, int Nt, int64_t rrow, bool ok, int lane,
                                             CAcc<T>& acc) {
   const int i = lane & 15;
 #pragma unroll
-  for (int d = 0; d < 5; ++d) {
+  for (int d = D0; d < 5; ++d) {
     const cx<T>* xv = x + rrow * n + nb_site(u, d, Nx, Nt) * CM;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -615,7 +616,7 @@ __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B
   const int r = r0 + (lane & 15);
   const bool ok = r < nrhs;
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hops(Bs, x, n, u, Nx, Nt, ok ? r : r0, ok, lane, acc);
+  coarse_hops<0>(Bs, x, n, u, Nx, Nt, ok ? r : r0, ok, lane, acc);
   if (!ok || (active && !active[r])) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -626,7 +627,8 @@ __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B
 }
 
 // One colour of the coarse SAP sweep with one-site blocks: for each site u of
-// the colour and each RHS, t = r_u - (D x)_u, x_u += inv_u t.
+// the colour and each RHS, x_u = inv_u (r_u - sum_{d > 0} B_d x_{nb(u, d)}),
+// which equals x_u + inv_u (r - D x)_u for the exact inverse of the self block.
 template <class T>
 __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
                                                  int Nx, int Nt, const int* __restrict__ blist, int nrhs,
@@ -647,8 +649,8 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hops(Bs, x, n, u, Nx, Nt, rrow, ok, lane, acc);
-  // t = r - D x in the result layout: element c = row out_row(lane, c)
+  coarse_hops<1>(Bs, x, n, u, Nx, Nt, rrow, ok, lane, acc);
+  // t = r_u - (hops) in the result layout: element c = row out_row(lane, c)
   cx<T> t[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -660,9 +662,84 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
   for (int c = 0; c < 4; ++c) cmma(Is[i * CM + MF<T>::out_row(lane, c)], t[c], cor);
   if (!ok || (active && !active[r])) return;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    cx<T>* o = x + (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
-    *o = *o + mk<T>(cor.re[v], cor.im[v]);
+  for (int v = 0; v < 4; ++v)
+    x[(int64_t)r * n + u * CM + MF<T>::out_row(lane, v)] = mk<T>(cor.re[v], cor.im[v]);
+}
+
+// One colour of the fine-level SAP sweep with 4x4-site blocks (K = 32 dofs).
+// With the exact block inverse, x_B + inv_B (r - D x)_B = inv_B (r_B - D_BH x_H):
+// only the hops that leave the block (x of the other colour) enter, and the
+// old x_B is not read.  One workgroup per block and 64 RHS (a wave per 16):
+// the halo term on the vector units, the 32 x 32 solve as two 16-row tiles
+// of complex MFMAs over 8 K-chunks.
+template <class T>
+__global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
+                                                  int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                  const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
+                                                  const int* __restrict__ active) {
+  constexpr int SB = 4, NS = SB * SB, K = 2 * NS;
+  __shared__ cx<T> Is[K * K];
+  __shared__ cx<T> Bs[NS * 5 * 4];
+  const int blk = blist[blockIdx.x];
+  const int NBx = Nx / SB;
+  const int bx = (blk % NBx) * SB, bt = (blk / NBx) * SB;
+  for (int e = threadIdx.x; e < K * K; e += NT) Is[e] = inv[(int64_t)blk * K * K + e];
+  for (int e = threadIdx.x; e < NS * 20; e += NT) {
+    const int s = e / 20;
+    const int64_t us = (int64_t)(bt + s / SB) * Nx + bx + s % SB;
+    Bs[e] = B[us * 20 + e % 20];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.y * 4 + wave) * 16;
+  if (r0 >= nrhs) return;
+  const int i = lane & 15;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t n = (int64_t)Nx * Nt * 2;
+  const cx<T>* xr = x + (int64_t)(ok ? r : r0) * n;
+  const cx<T>* rv = rr + (int64_t)(ok ? r : r0) * n;
+  // h = r_B - D_BH x_H at this lane's 8 K indices (chunk c: k = 16 (c / 4) + out_row(lane, c % 4))
+  cx<T> h[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int k = 16 * (c >> 2) + MF<T>::out_row(lane, c & 3);
+    const int s = k >> 1, a = k & 1, sx = s & 3, st = s >> 2;
+    const int gx = bx + sx, gt = bt + st;
+    cx<T> acc = mk<T>(0, 0);
+    if (ok) {
+      acc = rv[((int64_t)gt * Nx + gx) * 2 + a];
+      int nbs[2], dirs[2], nh = 0;
+      if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
+      if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
+      if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
+      if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
+      for (int j = 0; j < nh; ++j) {
+        const cx<T>* bb = Bs + (s * 5 + dirs[j]) * 4 + a * 2;
+        const cx<T>* xv = xr + (int64_t)nbs[j] * 2;
+        acc = acc - bb[0] * xv[0] - bb[1] * xv[1];
+      }
+    }
+    h[c] = acc;
+  }
+  const bool store = ok && !(active && !active[r]);
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int kcol = 16 * (c >> 2) + MF<T>::out_row(lane, c & 3);
+      cmma(Is[(half * 16 + i) * K + kcol], h[c], acc);
+    }
+    if (store) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = half * 16 + MF<T>::out_row(lane, v);
+        const int s = row >> 1;
+        const int64_t us = (int64_t)(bt + (s >> 2)) * Nx + bx + (s & 3);
+        x[(int64_t)r * n + us * 2 + (row & 1)] = mk<T>(acc.re[v], acc.im[v]);
+      }
+    }
   }
 }
 
@@ -1205,6 +1282,12 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   require(K <= 32, "SAP block too large");
   if (M == CM && sbx == 1 && sbt == 1) {
     hipLaunchKernelGGL(k_sap_mfma<T>, dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
+                       nrhs, r, x, active);
+    KCHK();
+    return;
+  }
+  if (M == 2 && sbx == 4 && sbt == 4) {
+    hipLaunchKernelGGL(k_sap0_mfma<T>, dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
                        nrhs, r, x, active);
     KCHK();
     return;
