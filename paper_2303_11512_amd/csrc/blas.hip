@@ -322,6 +322,13 @@ __global__ void __launch_bounds__(NT) k_fgmres_init(int nrhs, const T* __restric
   thr[r] = tol * (bnorm ? bnorm[r] : beta[r]);
 }
 
+template <class T>
+__global__ void __launch_bounds__(NT) k_done_from_norm(const T* __restrict__ bnorm, int nrhs,
+                                                       int* __restrict__ done) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r < nrhs) done[r] = bnorm[r] == (T)0 ? 1 : 0;
+}
+
 // ------------------------------------------------------------------ CholQR2 pieces
 // partial[chunk][i][j] = sum_{k in chunk} conj(Y_i[k]) Y_j[k], d <= 64
 constexpr int GS = 32;     // elements per LDS stage
@@ -538,6 +545,13 @@ void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* paren
                      done, tol, bnorm, m, active, nit, g, thr);
   KCHK();
 }
+
+template <class T>
+void launch_done_from_norm(hipStream_t s, const T* bnorm, int nrhs, int* done) {
+  hipLaunchKernelGGL(k_done_from_norm<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, bnorm, nrhs, done);
+  KCHK();
+}
+template void launch_done_from_norm<double>(hipStream_t, const double*, int, int*);
 
 void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial) {
   require(d >= 1 && d <= 64, "orthonormalize: 1 <= d <= 64");

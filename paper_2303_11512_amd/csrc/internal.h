@@ -179,6 +179,9 @@ template <class T>
 void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
                          const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
                          const int* active, cx<T>* partial);
+// done[r] = (bnorm[r] == 0)
+template <class T>
+void launch_done_from_norm(hipStream_t s, const T* bnorm, int nrhs, int* done);
 // number of chunk partials a reduction over n elements produces
 // (upper bound: the shortest chunk is 256 elements)
 inline int64_t reduce_chunks(int64_t n) { return (n + 255) / 256; }
@@ -226,12 +229,41 @@ struct LevelData {
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 
+// Pinned host copies of per-RHS flags with two completion events, so the host
+// can read step j's flags while step j + 1 is already queued.
+struct PinnedFlags {
+  int* h = nullptr;
+  int cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  PinnedFlags() = default;
+  PinnedFlags(const PinnedFlags&) = delete;
+  PinnedFlags& operator=(const PinnedFlags&) = delete;
+  void ensure(int n) {
+    if (!ev[0]) {
+      HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    }
+    if (n <= cap) return;
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(int) * 2 * (size_t)n, hipHostMallocDefault));
+    cap = n;
+  }
+  ~PinnedFlags() {
+    if (h) (void)hipHostFree(h);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 template <class T>
 struct Work {  // FGMRES + multigrid workspace of one level in one precision
   int cap = 0, mcap = 0;
   int64_t n = 0;
   DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, coef, coef2;
   DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
+  PinnedFlags flags;                 // active flags read back during FGMRES
 };
 
 struct Level {

@@ -254,8 +254,10 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
 }
 
 // Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
-// residual, checked at the end of every cycle); the host polls the active
-// flags after each Arnoldi step to end a cycle once every RHS has converged.
+// residual, checked at the end of every cycle).  Inside a cycle the host reads
+// the active flags of step j - 1 while step j is already queued, and ends the
+// cycle once every RHS has converged (the one extra step is a no-op: every
+// kernel of a step skips inactive RHS).
 int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                 const mgm_solve_params& sp, int* iters_out, double* relres_out) {
   hipStream_t s = c->stream;
@@ -266,6 +268,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   require(sp.tol > 0, "tolerance must be positive");
   ensure_work<double>(L, nrhs, m);
   Work<double>& W = L.wd;
+  W.flags.ensure(nrhs);
   cd* V = W.V.as<cd>();
   cd* Z = W.Z.as<cd>();
   cd* w = W.w.as<cd>();
@@ -273,22 +276,26 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   int* done = act + nrhs;
   double* bnorm = W.bnorm.as<double>();
   double* beta = W.beta.as<double>();
-  std::vector<int> hact(nrhs), hdone(nrhs, 0), hnit(nrhs), its(nrhs, 0);
+  std::vector<int> hdone(nrhs, 0), hnit(nrhs), its(nrhs, 0);
   std::vector<double> hb(nrhs), hr(nrhs);
+  bool have_hb = false;
+  auto read_hb = [&] {  // ||b|| per RHS, fetched with the first residual read-back
+    if (have_hb) return;
+    have_hb = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(hb[r])) throw Error(MGM_ENONFINITE, "non-finite right-hand side");
+      hdone[r] = hb[r] == 0.0;
+    }
+  };
 
   launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p);
-  HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int r = 0; r < nrhs; ++r) {
-    if (!std::isfinite(hb[r])) throw Error(MGM_ENONFINITE, "non-finite right-hand side");
-    hdone[r] = hb[r] == 0.0;
-  }
-  HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+  launch_done_from_norm<double>(s, bnorm, nrhs, done);  // zero right-hand sides are solved
   if (sp.use_cnn && l == 0 && !L.has_dense)
     cnn_initial_guess(c, g, nrhs, b, x, w);
   else
     launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
+  bool final_known = false;  // hr holds the residuals of the returned x
   if (L.has_dense) {
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch);
   } else {
@@ -303,9 +310,14 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
           precondition_graph(c, g, l, nrhs, v, z, a);
         });
-        HIPCHK(hipMemcpyAsync(hact.data(), act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (std::all_of(hact.begin(), hact.end(), [](int a) { return a == 0; })) break;
+        const int slot = j & 1;
+        HIPCHK(hipMemcpyAsync(W.flags.h + slot * nrhs, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(W.flags.ev[slot], s));
+        if (j == 0) continue;
+        const int prev = slot ^ 1;
+        HIPCHK(hipEventSynchronize(W.flags.ev[prev]));
+        const int* f = W.flags.h + prev * nrhs;
+        if (std::all_of(f, f + nrhs, [](int a) { return a == 0; })) break;
       }
       launch_backsolve<double>(s, m, nrhs, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(), W.y.as<cd>());
       launch_update_multi<double>(s, Z, (int64_t)nrhs * n, n, m, W.y.as<cd>(), m, 1.0, x, n, nrhs,
@@ -315,7 +327,10 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
       launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
       HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(hnit.data(), W.nit.p, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+      if (!have_hb)
+        HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      read_hb();
       bool all = true;
       for (int r = 0; r < nrhs; ++r) {
         if (hdone[r]) continue;
@@ -324,15 +339,21 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         if (hr[r] <= sp.tol * hb[r]) hdone[r] = 1;
         else all = false;
       }
-      if (all) break;
+      if (all) {
+        final_known = true;
+        break;
+      }
       HIPCHK(hipMemcpyAsync(done, hdone.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     }
   }
-  // final relative residuals
-  apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
-  launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
-  HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  if (!final_known) {
+    apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
+    launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+    HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    if (!have_hb) HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    read_hb();
+  }
   bool ok = true;
   for (int r = 0; r < nrhs; ++r) {
     const double rel = hb[r] > 0 ? hr[r] / hb[r] : 0.0;
