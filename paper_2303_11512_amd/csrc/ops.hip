@@ -578,45 +578,70 @@ __device__ __forceinline__ void cmma(cx<T> a, cx<T> b, CAcc<T>& acc) {
   acc.im = MF<T>::mma(a.im, b.re, acc.im);
 }
 
-// acc += sum_{d >= D0} B_d x_{nb(u, d)} for the RHS column of this lane (zero
-// operand for lanes past the last RHS); Bs = the site's 5 blocks in LDS,
-// row-major; D0 = 1 leaves out the site's own block.
-template <int D0, class T>
-__device__ __forceinline__ void coarse_hops(const cx<T>* Bs, const cx<T>* __restrict__ x, int64_t n,
-                                            int64_t u, int Nx, int Nt, int64_t rrow, bool ok, int lane,
-                                            CAcc<T>& acc) {
+// acc += B_d x_{nb(u, d)} for one direction d and the RHS column of this lane
+// (zero operand for lanes past the last RHS); the block is read straight from
+// the stencil B [site][5][16][16] (row-major) as the MFMA A operand.
+template <class T>
+__device__ __forceinline__ void coarse_hop(const cx<T>* __restrict__ B, const cx<T>* __restrict__ x,
+                                           int64_t n, int64_t u, int d, int Nx, int Nt, int64_t rrow,
+                                           bool ok, int lane, CAcc<T>& acc) {
   const int i = lane & 15;
+  const cx<T>* xv = x + rrow * n + nb_site(u, d, Nx, Nt) * CM;
+  const cx<T>* Bd = B + ((u * 5 + d) * CM + i) * CM;
+  cx<T> a[4], xb[4];
 #pragma unroll
-  for (int d = D0; d < 5; ++d) {
-    const cx<T>* xv = x + rrow * n + nb_site(u, d, Nx, Nt) * CM;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = MF<T>::out_row(lane, c);
-      const cx<T> xb = ok ? xv[k] : mk<T>(0, 0);
-      cmma(Bs[(d * CM + i) * CM + k], xb, acc);
-    }
+  for (int c = 0; c < 4; ++c) {
+    const int k = MF<T>::out_row(lane, c);
+    a[c] = Bd[k];
+    xb[c] = ok ? xv[k] : mk<T>(0, 0);
   }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cmma(a[c], xb[c], acc);
 }
 
-// y = D x or y = b - D x on a coarse level (16 dofs per site); one workgroup
-// per site and 64 RHS (a wave per 16).
+// Sum the partial tiles of waves 1..3 into wave 0 (LDS); returns false on
+// the waves that are done.
+template <class T>
+__device__ __forceinline__ bool reduce_waves(CAcc<T>& acc, T (*red)[8][64], int wave, int lane) {
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[wave - 1][v][lane] = acc.re[v];
+      red[wave - 1][4 + v][lane] = acc.im[v];
+    }
+  }
+  __syncthreads();
+  if (wave > 0) return false;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc.re[v] += red[w][v][lane];
+      acc.im[v] += red[w][4 + v][lane];
+    }
+  return true;
+}
+
+// y = D x or y = b - D x on a coarse level (16 dofs per site).  One workgroup
+// per (site, 16 RHS); wave w takes the hop in direction w + 1 (wave 0 also the
+// site's own block), and the partial tiles are summed in LDS.
 template <class T>
 __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B, int Nx, int Nt, int nrhs,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                      const cx<T>* __restrict__ b,
                                                      const int* __restrict__ active) {
-  __shared__ cx<T> Bs[5 * CM * CM];
+  __shared__ T red[3][8][64];
   const int64_t u = blockIdx.x;
   const int64_t n = (int64_t)Nx * Nt * CM;
-  for (int e = threadIdx.x; e < 5 * CM * CM; e += NT) Bs[e] = B[u * 5 * CM * CM + e];
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.y * 4 + wave) * 16;
-  if (r0 >= nrhs) return;
+  const int r0 = blockIdx.y * 16;
   const int r = r0 + (lane & 15);
   const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hops<0>(Bs, x, n, u, Nx, Nt, ok ? r : r0, ok, lane, acc);
+  coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  if (wave == 0) coarse_hop(B, x, n, u, 0, Nx, Nt, rrow, ok, lane, acc);
+  if (!reduce_waves(acc, red, wave, lane)) return;
   if (!ok || (active && !active[r])) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -629,37 +654,38 @@ __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B
 // One colour of the coarse SAP sweep with one-site blocks: for each site u of
 // the colour and each RHS, x_u = inv_u (r_u - sum_{d > 0} B_d x_{nb(u, d)}),
 // which equals x_u + inv_u (r - D x)_u for the exact inverse of the self block.
+// One workgroup per (site, 16 RHS): wave w takes the hop in direction w + 1,
+// wave 0 sums them (LDS) and applies inv_u.
 template <class T>
 __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
                                                  int Nx, int Nt, const int* __restrict__ blist, int nrhs,
                                                  const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
                                                  const int* __restrict__ active) {
-  __shared__ cx<T> Bs[5 * CM * CM];
-  __shared__ cx<T> Is[CM * CM];
+  __shared__ T red[3][8][64];
   const int64_t u = blist[blockIdx.x];
   const int64_t n = (int64_t)Nx * Nt * CM;
-  for (int e = threadIdx.x; e < 5 * CM * CM; e += NT) Bs[e] = B[u * 5 * CM * CM + e];
-  for (int e = threadIdx.x; e < CM * CM; e += NT) Is[e] = inv[u * CM * CM + e];
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.y * 4 + wave) * 16;
-  if (r0 >= nrhs) return;
   const int i = lane & 15;
+  const int r0 = blockIdx.y * 16;
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hops<1>(Bs, x, n, u, Nx, Nt, rrow, ok, lane, acc);
+  coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  if (!reduce_waves(acc, red, wave, lane)) return;
   // t = r_u - (hops) in the result layout: element c = row out_row(lane, c)
-  cx<T> t[4];
+  cx<T> t[4], a[4];
+  const cx<T>* Iu = inv + (u * CM + i) * CM;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const cx<T> rv = ok ? rr[rrow * n + u * CM + MF<T>::out_row(lane, c)] : mk<T>(0, 0);
+    const int k = MF<T>::out_row(lane, c);
+    const cx<T> rv = ok ? rr[rrow * n + u * CM + k] : mk<T>(0, 0);
     t[c] = mk<T>(rv.re - acc.re[c], rv.im - acc.im[c]);
+    a[c] = Iu[k];
   }
   CAcc<T> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-  for (int c = 0; c < 4; ++c) cmma(Is[i * CM + MF<T>::out_row(lane, c)], t[c], cor);
+  for (int c = 0; c < 4; ++c) cmma(a[c], t[c], cor);
   if (!ok || (active && !active[r])) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -1213,7 +1239,7 @@ void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, i
     case 4: hipLaunchKernelGGL((k_stencil_lds<T, 4>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 8: hipLaunchKernelGGL((k_stencil_lds<T, 8>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 16:
-      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites, (nrhs + 63) / 64), dim3(NT), 0, s, blocks,
+      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites, (nrhs + 15) / 16), dim3(NT), 0, s, blocks,
                          Nx, Nt, nrhs, x, y, b, active);
       break;
     case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
@@ -1281,7 +1307,7 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   const int K = sbx * sbt * M;
   require(K <= 32, "SAP block too large");
   if (M == CM && sbx == 1 && sbt == 1) {
-    hipLaunchKernelGGL(k_sap_mfma<T>, dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
+    hipLaunchKernelGGL(k_sap_mfma<T>, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
                        nrhs, r, x, active);
     KCHK();
     return;
