@@ -242,8 +242,8 @@ MFMA_FP32_PEAK_TFS = 157.3
 
 def run_mixed(args):
     """Mixed precision at 512^2 (beta 4.0, m0 -0.08): 256 Z2xZ2 RHS solved to
-    1e-10 with the FP64 and with the FP32 preconditioner (outer FGMRES FP64 in
-    both), and one MG-MLMC++ estimate to 1e-3 in each precision."""
+    1e-10 with the FP64, FP32 and FP16-coarse-block preconditioners (outer
+    FGMRES FP64 in all), and one MG-MLMC++ estimate to 1e-3 in each."""
     import torch
     from lattice_inputs import WORKLOADS, gauge_for, links_from_theta
     from paper_2303_11512_amd import Context, mg_params, solve_params
@@ -263,7 +263,7 @@ def run_mixed(args):
     ctx.noise("z2z2", 13, 0, 0, 0, b)
     sp = solve_params(tol=1e-10, restart=16, max_restarts=50, rhs_block=64)
     res = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp16"):
         ctx.set_precision(gid, prec)
         x = torch.empty_like(b)
         ctx.solve_batch(gid, 0, b, x, sp)
@@ -283,21 +283,25 @@ def run_mixed(args):
                          samples=est["level_samples"])
         print(f"# {prec}: {nrhs / dt:.1f} solves/s, {np.mean(its):.2f} it, max relres {np.max(rel):.2e}, "
               f"estimate {est['tau']:.6f} in {res[prec]['trace_s']:.2f}s", file=sys.stderr, flush=True)
-    dx = float(torch.linalg.norm(res["fp32"]["x"] - res["fp64"]["x"]) / torch.linalg.norm(res["fp64"]["x"]))
-    tau64, tau32 = res["fp64"]["tau"], res["fp32"]["tau"]
+    xn = torch.linalg.norm(res["fp64"]["x"])
+    tau64 = res["fp64"]["tau"]
+    for p in ("fp32", "fp16"):
+        res[p]["x_rel_diff_vs_fp64"] = float(torch.linalg.norm(res[p]["x"] - res["fp64"]["x"]) / xn)
+        res[p]["tau_rel_diff_vs_fp64"] = abs(res[p]["tau"] - tau64) / abs(tau64)
+        res[p]["speedup_vs_fp64"] = res["fp64"]["solve_s"] / res[p]["solve_s"]
     for r in res.values():
         r.pop("x")
         r["tau"] = [r["tau"].real, r["tau"].imag]
     print(json.dumps({
-        "metric": "RHS solves/s (tol 1e-10), FP32 preconditioner in FP64 FGMRES", "value": res["fp32"]["solves_per_s"],
+        "metric": "RHS solves/s (tol 1e-10), FP32/FP16 preconditioner in FP64 FGMRES",
+        "value": res["fp16"]["solves_per_s"],
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": res["fp32"]["solve_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "ms_per_step": res["fp16"]["solve_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32+f16", "data": "synthetic",
         "config": {"workload": f"mixed512: 512x512 Schwinger, beta {cfg['beta']}, m0 {cfg['m0']}, MG "
                                f"{kw['blocks']} (MLMC closes on level {kw['mlmc_levels'] - 1}), 256 Z2xZ2 RHS "
                                f"in blocks of 64, FGMRES(16) tol 1e-10; one MG-MLMC++ estimate to {cfg['eps']}",
-                   "fp64": res["fp64"], "fp32": res["fp32"], "speedup": res["fp64"]["solve_s"] / res["fp32"]["solve_s"],
-                   "x_rel_diff": dx, "tau_rel_diff": abs(tau32 - tau64) / abs(tau64), "setup_s": setup_s},
+                   "fp64": res["fp64"], "fp32": res["fp32"], "fp16": res["fp16"], "setup_s": setup_s},
         "roofline": None, "cpu_baseline": None,
     }))
     ctx.close()
@@ -394,7 +398,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="schwinger128")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16"],
                     help="precision of the multigrid preconditioner (outer FGMRES is FP64)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up, time the hot kernels and exit (for counter runs)")

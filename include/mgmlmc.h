@@ -56,9 +56,18 @@ extern "C" {
 #define MGM_PURPOSE_SAMPLE 3
 #define MGM_PURPOSE_TRAIN 4   /* right-hand sides of the network's training pairs */
 
-/* precision of the multigrid preconditioner (the outer FGMRES is always FP64) */
+/* precision of the multigrid preconditioner (the outer FGMRES, its residuals,
+ * orthogonalisation and every trace sum are always FP64):
+ *   FP64  the whole cycle in FP64;
+ *   FP32  the whole cycle in FP32 (vectors and operators);
+ *   FP16  as FP32, but coarse levels with 16 dofs per site keep their stencil
+ *         blocks and SAP block inverses in FP16 and apply them with FP16
+ *         matrix-core products (vector operands rounded to FP16, FP32
+ *         accumulation).  Vectors whose entries exceed the FP16 range
+ *         (|v| > 65504) in the cycle are not supported in this mode. */
 #define MGM_PREC_FP64 0
 #define MGM_PREC_FP32 1
+#define MGM_PREC_FP16 2
 
 typedef struct mgm_ctx mgm_ctx;
 
@@ -113,7 +122,7 @@ typedef struct {
   int setup_restart;                  /* FGMRES restart length in the setup  */
   int setup_max_restarts;
   uint64_t seed;                      /* seed of the SETUP noise             */
-  int precision;                      /* MGM_PREC_FP64 | MGM_PREC_FP32       */
+  int precision;                      /* MGM_PREC_FP64 | _FP32 | _FP16      */
   int mlmc_levels;                    /* levels 0..mlmc_levels-1 form the
                                          MLMC telescoping sum; level
                                          mlmc_levels-1 is inverted densely
@@ -127,8 +136,8 @@ typedef struct {
 int mgm_setup_mg(mgm_ctx *ctx, int gauge_id, const mgm_mg_params *prm);
 
 /* set_precision -- switch the preconditioner of a set-up field between
- * MGM_PREC_FP64 and MGM_PREC_FP32 without a new setup (setup_mg keeps both
- * copies of every level); the outer FGMRES stays FP64. */
+ * MGM_PREC_FP64, MGM_PREC_FP32 and MGM_PREC_FP16 without a new setup
+ * (setup_mg keeps every copy); the outer FGMRES stays FP64. */
 int mgm_set_precision(mgm_ctx *ctx, int gauge_id, int precision);
 
 /* Level geometry: info[0..3] = Nx, Nt, dof per site M, n = Nx*Nt*M. */

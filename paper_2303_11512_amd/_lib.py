@@ -19,7 +19,8 @@ MAX_LEVELS = 6
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 NOISE_RADEMACHER, NOISE_Z2Z2 = 0, 1
 PURPOSE_SETUP, PURPOSE_SKETCH, PURPOSE_SAMPLE, PURPOSE_TRAIN = 1, 2, 3, 4
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_FP16 = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16": PREC_FP16}
 VARIANTS = {"hutchinson": 0, "hutchpp": 1, "mlmc": 2, "mlmcpp": 3}
 FORMS = {"reduced": 0, "full": 1}
 TARGETS = {"optimal": 0, "uniform": 1}
@@ -222,7 +223,7 @@ def mg_params(nlevels, blocks, ntv, sap_block=None, sap_cycles=None, inner_iters
     p.setup_restart = setup_restart
     p.setup_max_restarts = setup_max_restarts
     p.seed = seed
-    p.precision = {"fp64": PREC_FP64, "fp32": PREC_FP32}[precision]
+    p.precision = PRECISIONS[precision]
     return p
 
 
@@ -281,7 +282,7 @@ class Context:
         return gid.value
 
     def set_precision(self, gid, precision: str):
-        self._chk(self.lib.mgm_set_precision(self.h, gid, {"fp64": PREC_FP64, "fp32": PREC_FP32}[precision]),
+        self._chk(self.lib.mgm_set_precision(self.h, gid, PRECISIONS[precision]),
                   "set_precision")
 
     def free_gauge(self, gid):

@@ -169,7 +169,8 @@ int mgm_setup_mg(mgm_ctx* c, int gauge_id, const mgm_mg_params* prm) {
 
 int mgm_set_precision(mgm_ctx* c, int gauge_id, int precision) {
   return guarded(c, [&] {
-    require(precision == MGM_PREC_FP64 || precision == MGM_PREC_FP32, "unknown precision");
+    require(precision == MGM_PREC_FP64 || precision == MGM_PREC_FP32 || precision == MGM_PREC_FP16,
+            "unknown precision");
     Gauge& g = gauge_of(c, gauge_id);
     require(g.mg_ready, "setup_mg first", MGM_ESTATE);
     OnGauge og(c, g);

@@ -24,6 +24,10 @@ struct alignas(2 * sizeof(T)) cx {
 };
 using cd = cx<double>;
 using cf = cx<float>;
+// complex FP16 storage (coarse stencil blocks and inverses of the FP16 mode)
+struct alignas(4) chalf {
+  _Float16 re, im;
+};
 
 template <class T>
 __host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
@@ -166,6 +170,13 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
                       int sbx, int sbt, const int* blist, int nb, int nrhs, const cx<T>* r,
                       cx<T>* x, const int* active);
 void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M, cd* A);
+// FP16-block variants for coarse levels with 16 dofs per site (FP32 vectors,
+// FP16 matrix-core products, FP32 accumulation)
+void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count);
+void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nrhs, const cf* x, cf* y,
+                      const cf* b, const int* active);
+void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, const int* blist,
+                  int nb, int nrhs, const cf* r, cf* x, const int* active);
 // In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A.
 int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* scratch_out);
 void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out);
@@ -226,6 +237,7 @@ struct LevelData {
   DevBuf P;        // [nagg][2][nrow][ntv]   (level -> level+1)
   DevBuf sapinv;   // [nblk][K][K]
   DevBuf dinv;     // coarsest: [n][n]
+  DevBuf hblocks, hsapinv;  // FP16 copies of blocks / sapinv (16-dof coarse levels)
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 

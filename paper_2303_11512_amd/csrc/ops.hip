@@ -692,6 +692,104 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
     x[(int64_t)r * n + u * CM + MF<T>::out_row(lane, v)] = mk<T>(cor.re[v], cor.im[v]);
 }
 
+// ---- FP16 blocks: one 16x16x16 FP16 MFMA covers a whole 16 x 16 block.
+// Lane l supplies A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16] (j = 0..3);
+// element v of its FP32 result is D[4(l/16) + v][l%16] (measured on gfx950).
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void hmma(h4 ar, h4 ai, h4 br, h4 bi, CAcc<float>& acc) {
+  acc.re = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, acc.re, 0, 0, 0);
+  acc.re = __builtin_amdgcn_mfma_f32_16x16x16f16(-ai, bi, acc.re, 0, 0, 0);
+  acc.im = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, bi, acc.im, 0, 0, 0);
+  acc.im = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, acc.im, 0, 0, 0);
+}
+
+// acc += B_d x_{nb(u, d)} with the block in FP16 and x rounded to FP16
+__device__ __forceinline__ void coarse_hop_h(const chalf* __restrict__ B, const cf* __restrict__ x, int64_t n,
+                                             int64_t u, int d, int Nx, int Nt, int64_t rrow, bool ok, int lane,
+                                             CAcc<float>& acc) {
+  const int i = lane & 15, q = lane >> 4;
+  const chalf* row = B + ((u * 5 + d) * CM + i) * CM + 4 * q;
+  const cf* xv = x + rrow * n + nb_site(u, d, Nx, Nt) * CM + 4 * q;
+  h4 ar, ai, br, bi;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const chalf a = row[j];
+    const cf v = ok ? xv[j] : mk<float>(0, 0);
+    ar[j] = a.re;
+    ai[j] = a.im;
+    br[j] = (_Float16)v.re;
+    bi[j] = (_Float16)v.im;
+  }
+  hmma(ar, ai, br, bi, acc);
+}
+
+__global__ void __launch_bounds__(NT) k_stencil_h(const chalf* __restrict__ B, int Nx, int Nt, int nrhs,
+                                                  const cf* __restrict__ x, cf* __restrict__ y,
+                                                  const cf* __restrict__ b, const int* __restrict__ active) {
+  __shared__ float red[3][8][64];
+  const int64_t u = blockIdx.x;
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + (lane & 15);
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  if (wave == 0) coarse_hop_h(B, x, n, u, 0, Nx, Nt, rrow, ok, lane, acc);
+  if (!reduce_waves(acc, red, wave, lane)) return;
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t o = (int64_t)r * n + u * CM + 4 * (lane >> 4) + v;
+    const cf val = mk<float>(acc.re[v], acc.im[v]);
+    y[o] = b ? b[o] - val : val;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const chalf* __restrict__ inv,
+                                              int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                              const cf* __restrict__ rr, cf* __restrict__ x,
+                                              const int* __restrict__ active) {
+  __shared__ float red[3][8][64];
+  const int64_t u = blist[blockIdx.x];
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  if (!reduce_waves(acc, red, wave, lane)) return;
+  // t = r_u - hops: element j of this lane is row 4q + j, which is also the
+  // B operand layout of the next product
+  h4 tr, ti, ar, ai;
+  const chalf* Iu = inv + (u * CM + i) * CM + 4 * q;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const cf rv = ok ? rr[rrow * n + u * CM + 4 * q + j] : mk<float>(0, 0);
+    tr[j] = (_Float16)(rv.re - acc.re[j]);
+    ti[j] = (_Float16)(rv.im - acc.im[j]);
+    ar[j] = Iu[j].re;
+    ai[j] = Iu[j].im;
+  }
+  CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  hmma(ar, ai, tr, ti, cor);
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[(int64_t)r * n + u * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
+}
+
+__global__ void __launch_bounds__(NT) k_to_half(const cd* __restrict__ in, chalf* __restrict__ out,
+                                                int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= count) return;
+  out[e] = chalf{(_Float16)in[e].re, (_Float16)in[e].im};
+}
+
 // One colour of the fine-level SAP sweep with 4x4-site blocks (K = 32 dofs).
 // With the exact block inverse, x_B + inv_B (r - D x)_B = inv_B (r_B - D_BH x_H):
 // only the hops that leave the block (x of the other colour) enter, and the
@@ -1251,6 +1349,26 @@ template void launch_stencil<double>(hipStream_t, const cd*, int, int, int, int,
                                      const cd*, const int*);
 template void launch_stencil<float>(hipStream_t, const cf*, int, int, int, int, const cf*, cf*,
                                     const cf*, const int*);
+
+void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count) {
+  hipLaunchKernelGGL(k_to_half, dim3(grid1(count)), dim3(NT), 0, s, in, out, count);
+  KCHK();
+}
+
+void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nrhs, const cf* x, cf* y,
+                      const cf* b, const int* active) {
+  hipLaunchKernelGGL(k_stencil_h, dim3((unsigned)((int64_t)Nx * Nt), (nrhs + 15) / 16), dim3(NT), 0, s,
+                     blocks, Nx, Nt, nrhs, x, y, b, active);
+  KCHK();
+}
+
+void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, const int* blist,
+                  int nb, int nrhs, const cf* r, cf* x, const int* active) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_sap_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs, r,
+                     x, active);
+  KCHK();
+}
 
 template <class T>
 void launch_restrict(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,

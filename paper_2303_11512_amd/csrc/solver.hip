@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mgm {
@@ -57,12 +59,22 @@ void ensure_work(Level& L, int nrhs, int m) {
   W.coef2.ensure(c * (size_t)nrhs * (m + 1));
 }
 
+// FP16 mode: coarse levels with 16 dofs per site apply their blocks in FP16
+bool half_blocks(const Gauge& g, const Level& L) {
+  return g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.f.hblocks.p != nullptr;
+}
+
 template <class T>
 void apply_op(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* x, cx<T>* y, const cx<T>* b,
               const int* act) {
   Level& L = *g.levels[l];
   if (l == 0) {
     launch_wilson<T>(c->stream, links_of<T>(g), (T)(g.m0 + 2.0), g.Lx, g.Lt, nrhs, x, y, b, act);
+  } else if constexpr (std::is_same<T, float>::value) {
+    if (half_blocks(g, L))
+      launch_stencil_h(c->stream, L.f.hblocks.as<chalf>(), L.Nx, L.Nt, nrhs, x, y, b, act);
+    else
+      launch_stencil<T>(c->stream, ldata<T>(L).B(), L.Nx, L.Nt, L.M, nrhs, x, y, b, act);
   } else {
     launch_stencil<T>(c->stream, ldata<T>(L).B(), L.Nx, L.Nt, L.M, nrhs, x, y, b, act);
   }
@@ -102,10 +114,20 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   } else {
     launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
   }
+  bool half = false;
+  if constexpr (std::is_same<T, float>::value) half = half_blocks(g, L) && L.sbx == 1 && L.sbt == 1;
   for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
-    for (int col = 0; col < 2; ++col)
+    for (int col = 0; col < 2; ++col) {
+      if constexpr (std::is_same<T, float>::value) {
+        if (half) {
+          launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt,
+                       L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
+          continue;
+        }
+      }
       launch_sap_sweep<T>(s, D.B(), D.sapinv.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
                           L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
+    }
 }
 
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
@@ -178,7 +200,7 @@ void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y) {
 // whole multigrid cycle runs in FP32, and the correction is widened again.
 void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
   Level& L = *g.levels[l];
-  if (g.prm.precision == MGM_PREC_FP32 && g.mg_ready) {
+  if (g.prm.precision != MGM_PREC_FP64 && g.mg_ready) {
     Work<double>& W = L.wd;
     const int64_t cnt = (int64_t)nrhs * L.n;
     W.cvt_in.ensure(sizeof(cf) * cnt);
@@ -447,6 +469,8 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
   hipStream_t s = c->stream;
   const int Lv = p.nlevels;
   require(Lv >= 1 && Lv <= MGM_MAX_LEVELS, "nlevels out of range");
+  require(p.precision == MGM_PREC_FP64 || p.precision == MGM_PREC_FP32 || p.precision == MGM_PREC_FP16,
+          "unknown precision");
   g.prm = p;
   g.mg_ready = false;
   g.levels.clear();
@@ -539,6 +563,14 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
     copy_convert<float>(c, L.d.P, L.f.P);
     copy_convert<float>(c, L.d.sapinv, L.f.sapinv);
     copy_convert<float>(c, L.d.dinv, L.f.dinv);
+    if (L.M == 16 && L.d.sapinv.p) {  // FP16 blocks for the FP16 mode
+      const int64_t nbk = (int64_t)(L.d.blocks.bytes / sizeof(cd));
+      const int64_t nin = (int64_t)(L.d.sapinv.bytes / sizeof(cd));
+      L.f.hblocks.ensure(sizeof(chalf) * nbk);
+      L.f.hsapinv.ensure(sizeof(chalf) * nin);
+      launch_to_half(s, L.d.blocks.as<cd>(), L.f.hblocks.as<chalf>(), nbk);
+      launch_to_half(s, L.d.sapinv.as<cd>(), L.f.hsapinv.as<chalf>(), nin);
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   g.mg_ready = true;

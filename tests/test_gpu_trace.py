@@ -135,13 +135,15 @@ def test_solver_only_coarse_level_and_vcycles(ctx):
     assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
 
 
-def test_fp32_preconditioner_keeps_fp64_results(ctx):
-    """Mixed precision: the whole multigrid cycle in FP32 inside FP64 FGMRES.
-    Every solve still meets its FP64 residual tolerance, so the estimate
-    matches the FP64 oracle on the same seeds."""
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_low_precision_preconditioner_keeps_fp64_results(ctx, precision):
+    """Mixed precision: the whole multigrid cycle in FP32 (and, for fp16, the
+    coarse blocks in FP16 on the matrix cores) inside FP64 FGMRES.  Every
+    solve still meets its FP64 residual tolerance, so the estimate matches
+    the FP64 oracle on the same seeds."""
     th = metropolis_u1(32, 32, 3.0, 100, 932)
     rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (1, 1), (1, 1)],
-                 inner_iters=[0, 4, 4], precision="fp32")
+                 inner_iters=[0, 4, 4], precision=precision)
     gid = rec.gpu(ctx)
     hier = rec.oracle()
     from gpu_util import empty, to_dev, to_host
@@ -164,5 +166,55 @@ def test_fixed_cost_and_full_form_s32(ctx, s32):
     kw = dict(variant="mlmcpp", form="full", eps=5e-2, d=[4, 4], k_power=1, noise="z2z2", seed=8,
               fixed_cost=[3.0, 1.0], fixed_samples=[12, 20])
     got = _gpu(ctx, gid, batch=8, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    _cmp(got, want)
+
+
+def test_fp16_blocks_change_only_the_preconditioner(ctx):
+    """The FP16 mode differs from the FP32 one in the coarse blocks only: its
+    preconditioner output moves by about FP16 rounding (not more), and its
+    solves still reach the FP64 tolerance."""
+    from gpu_util import empty, to_dev, to_host
+    from lattice_inputs import rhs_vectors
+    from paper_2303_11512_amd import solve_params
+    th = metropolis_u1(32, 32, 3.0, 100, 933)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (1, 1), (1, 1)],
+                 inner_iters=[0, 0, 0], precision="fp64")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    lev = hier.levels[0]
+    r = to_dev(rhs_vectors(lev.n, 5, 19))
+    out = {}
+    for prec in ("fp64", "fp32", "fp16"):
+        ctx.set_precision(gid, prec)
+        z = empty(5, lev.n)
+        ctx.precondition(gid, 0, r, z)
+        out[prec] = to_host(z)
+    ref = np.linalg.norm(out["fp64"])
+    e32 = np.linalg.norm(out["fp32"] - out["fp64"]) / ref
+    e16 = np.linalg.norm(out["fp16"] - out["fp64"]) / ref
+    log(f"preconditioner rel. change: fp32 {e32:.2e}, fp16 {e16:.2e}")
+    assert e32 < 1e-5 and 1e-6 < e16 < 2e-2
+    b = rhs_vectors(lev.n, 6, 23)
+    x = empty(6, lev.n)
+    st, its, rel = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=24))
+    res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
+    assert np.all(res <= 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_mixed_precision_cut_of_the_512_workload(ctx, precision):
+    """The 64^2 cut of the 512^2 mixed-precision workload (beta 4.0, m0 -0.08,
+    gauge seed 4001, 4x4 then 2x2 aggregation): the estimate with the low
+    precision preconditioner equals the FP64 oracle's on the same seeds."""
+    th = metropolis_u1(64, 64, 4.0, 200, 4001)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=4018, sap_block=[(4, 4), (1, 1), (1, 1)],
+                 sap_cycles=[3, 3, 3], inner_iters=[0, 0, 0], precision=precision)
+    log(f"cut 64^2 {precision}: setup")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    kw = dict(variant="mlmcpp", eps=1e-2, d=[16, 16], k_power=2, noise="z2z2", seed=5,
+              fixed_samples=[6, 10])
+    got = _gpu(ctx, gid, batch=16, **kw)
     want = otr.estimate(hier, otr.TraceParams(**kw))
     _cmp(got, want)
