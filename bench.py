@@ -25,6 +25,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# red/black SAP cycles per level of the V-cycle (fine, first coarse, deeper):
+# a sweep on the 128^2 workload puts the minimum of time per estimate at
+# heavy smoothing of the first coarse level
+SAP_CYCLES = (3, 10, 4, 4, 4, 4)
 
 
 def mg_setup_kwargs(cfg):
@@ -45,7 +49,7 @@ def mg_setup_kwargs(cfg):
     return dict(
         nlevels=L, blocks=blocks, ntv=ntv, mlmc_levels=mlmc,
         sap_block=[blocks[0]] + [(1, 1)] * L,
-        sap_cycles=[3] * 6, inner_iters=[0] * 6, inner_tol=0.0,
+        sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, inner_tol=0.0,
         setup_iters=3, setup_tol=1e-10, setup_restart=32, setup_max_restarts=200,
         seed=cfg["gauge_seed"] + 17,
     )
@@ -58,22 +62,25 @@ def trace_kwargs(cfg, step):
 
 KERNEL_RHS = 64
 # the kernel with the largest share of the step's GPU time (rocprofv3 of the
-# 128^2 step): one colour of the fine-level SAP sweep
-DOMINANT = "sap_l0"
-# counter summary of that kernel (FETCH_SIZE / WRITE_SIZE runs, scaled by the
-# copy-kernel calibration), keyed to the source file it was measured from
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sap_sweep_l0_schwinger128_traffic.txt")
+# 128^2 step) per preconditioner precision: one colour of the SAP sweep on the
+# first coarse level (16 dofs per site)
+DOMINANT = {"fp64": "sap_l1", "fp32": "saplow_l1", "fp16": "saplow_l1"}
+KERNEL_NAME = {"fp64": "k_sap_mfma<double>", "fp32": "k_sap_mfma<float>", "fp16": "k_sap_h"}
+# counter summaries of those kernels (FETCH_SIZE / WRITE_SIZE runs, scaled by
+# the copy-kernel calibration), keyed to the source file they were measured from
+TRAFFIC_SUMMARY = {p: os.path.join(ROOT, "profiles", f"{KERNEL_NAME[p].replace('<', '_').replace('>', '')}"
+                                                     f"_l1_schwinger128_traffic.txt") for p in DOMINANT}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_11512_amd", "csrc", "ops.hip")
 
 
-def measured_traffic():
+def measured_traffic(precision):
     """HBM bytes per launch of the dominant kernel from its committed counter
     summary; None when there is none or the kernel source has changed since
     the counters were taken."""
     import hashlib
     try:
         fields = {}
-        with open(TRAFFIC_SUMMARY) as f:
+        with open(TRAFFIC_SUMMARY[precision]) as f:
             for ln in f:
                 if ":" in ln and not ln.startswith((" ", "#")):
                     k, v = ln.split(":", 1)
@@ -87,7 +94,7 @@ def measured_traffic():
         return None
 
 
-def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None):
+def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None, precision="fp64"):
     """Average launch duration (HIP events on the library's stream, 50
     back-to-back launches), algorithmic bytes and flops of the step's hot
     kernels at the step's shape."""
@@ -109,6 +116,9 @@ def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None):
     }
     if mlmc_coarsest is not None and mlmc_coarsest != L:
         t["dense_l%d" % mlmc_coarsest] = ctx.time_kernel(gid, "dense", mlmc_coarsest, nrhs, reps=10)
+    if precision != "fp64":
+        for l in range(min(L, 3)):
+            t["saplow_l%d" % l] = ctx.time_kernel(gid, "sap_low", l, nrhs)
     return t
 
 
@@ -193,7 +203,7 @@ def run_batch8(args):
         blocks, ntv = solver_hierarchy(L)
         gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), m0, True)
         ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + [(1, 1)] * 5,
-                                    sap_cycles=[3] * 6, inner_iters=[0] * 6, setup_tol=1e-10,
+                                    sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, setup_tol=1e-10,
                                     seed=3100 + i))
         n = ctx.level_info(gid, 0)["n"]
         b = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
@@ -321,7 +331,7 @@ def run_cnn(args):
         blocks, ntv = solver_hierarchy(spec["L"])
         gid = ctx.set_gauge(torch.from_numpy(links_from_theta(field(spec))).to("cuda"), spec["m0"], True)
         ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + [(1, 1)] * 5,
-                                    sap_cycles=[3] * 6, inner_iters=[0] * 6, setup_tol=1e-10, seed=seed))
+                                    sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, setup_tol=1e-10, seed=seed))
         return gid
 
     t0 = time.perf_counter()
@@ -398,8 +408,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="schwinger128")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16"],
-                    help="precision of the multigrid preconditioner (outer FGMRES is FP64)")
+    ap.add_argument("--precision", default="fp16", choices=["fp64", "fp32", "fp16"],
+                    help="precision of the multigrid preconditioner (outer FGMRES is FP64); fp16 = "
+                         "FP32 cycle with FP16 coarse blocks")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP64-preconditioner timing reported next to the value")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up, time the hot kernels and exit (for counter runs)")
     ap.add_argument("--train-fields", type=int, default=20, help="cnn workload: training fields")
@@ -441,7 +454,7 @@ def main():
     print(f"# setup done in {setup_s:.2f}s", file=sys.stderr, flush=True)
     mlmc_coarsest = len(cfg["blocks"])
     if args.roofline_only:
-        print(json.dumps(kernel_table(ctx, gid)))
+        print(json.dumps(kernel_table(ctx, gid, precision=args.precision)))
         ctx.close()
         return
 
@@ -460,9 +473,25 @@ def main():
     dt = time.perf_counter() - t0
     solves = sum(sum(o["solves"]) for o in outs)
 
-    kern = kernel_table(ctx, gid, mlmc_coarsest=mlmc_coarsest)
-    dom = kern[DOMINANT]
+    kern = kernel_table(ctx, gid, mlmc_coarsest=mlmc_coarsest, precision=args.precision)
+    dom_key = DOMINANT[args.precision]
+    dom = kern[dom_key]
     achieved = dom["bytes"] / (dom["us"] * 1e-6) / 1e9
+
+    # the same estimates with the plain FP64 preconditioner, for comparison
+    plain = None
+    if args.precision != "fp64" and not args.no_compare:
+        ctx.set_precision(gid, "fp64")
+        ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, 1000))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pouts = [ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, k)) for k in range(args.steps)]
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t1
+        plain = {"estimates_per_s": args.steps / pdt, "ms_per_step": pdt / args.steps * 1e3,
+                 "max_tau_rel_diff": max(abs(a["tau"] - b["tau"]) / abs(b["tau"]) for a, b in zip(outs, pouts))}
+        ctx.set_precision(gid, args.precision)
+        print(f"# plain FP64 preconditioner: {plain}", file=sys.stderr, flush=True)
 
     samples = [int(sum(o["level_samples"][l] for o in outs) / len(outs)) for l in range(len(outs[0]["level_samples"]))]
     cpu = None
@@ -488,25 +517,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "fp16": "f64+f32+f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['Lx']}x{cfg['Lt']} Schwinger, beta {cfg['beta']}, "
                                f"m0 {cfg['m0']}, {len(cfg['blocks']) + 1}-level MG, Hutch++ d={cfg['d']}, "
                                f"{cfg['noise']} noise, eps {cfg['eps']}, FGMRES tol 1e-10",
                    "solves_per_s": solves / dt, "setup_s": setup_s,
-                   "preconditioner": args.precision,
+                   "preconditioner": args.precision, "sap_cycles": list(SAP_CYCLES[:4]),
+                   "plain_fp64_preconditioner": plain,
                    "solver_levels": mg_setup_kwargs(cfg)["nlevels"],
                    "iters_per_solve": [round(sum(o["iters"][l] for o in outs) / max(1, sum(o["solves"][l] for o in outs)), 2)
                                        for l in range(len(cfg["blocks"]) + 1)],
                    "level_samples": samples, "tau": [outs[-1]["tau"].real, outs[-1]["tau"].imag]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": f"k_sap_sweep<double> (level 0, one colour, {KERNEL_RHS} RHS)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
+                     "kernel": f"{KERNEL_NAME[args.precision]} (level 1, one colour, {KERNEL_RHS} RHS)",
                      "launch_us": dom["us"], "alg_bytes": dom["bytes"],
                      "others": {k: {"us": round(v["us"], 2),
                                     "GB/s": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1),
                                     "TFLOP/s": round(v["flops"] / (v["us"] * 1e-6) / 1e12, 2)}
-                                for k, v in kern.items() if k != DOMINANT}},
+                                for k, v in kern.items() if k != dom_key}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

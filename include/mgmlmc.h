@@ -304,6 +304,9 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
  *   MGM_KERNEL_CONV     one hidden 32 -> 32 3x3 convolution (+ tanh) of the
  *                       learned guess on nrhs fields of level 0 (FP32 matrix
  *                       cores; needs mgm_cnn_set_params)
+ *   MGM_KERNEL_SAP_LOW  one SAP colour sweep of the low-precision cycle at the
+ *                       field's current precision (FP32 vectors; FP16 blocks on
+ *                       16-dof levels in FP16 mode)
  * ------------------------------------------------------------------------- */
 #define MGM_KERNEL_STENCIL 0
 #define MGM_KERNEL_SAP 1
@@ -311,6 +314,7 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
 #define MGM_KERNEL_CGS 3
 #define MGM_KERNEL_COPY 4
 #define MGM_KERNEL_CONV 5
+#define MGM_KERNEL_SAP_LOW 6
 
 int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
                     double *us_out, double *bytes_out, double *flops_out);

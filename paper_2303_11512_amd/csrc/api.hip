@@ -327,6 +327,7 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
     HIPCHK(hipMemcpyAsync(y, x, sizeof(cd) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, s));
     std::function<void()> launch;
     double bytes = 0, flops = 0;
+    DevBuf lowbuf;  // FP32 copies of the vectors for the low-precision kinds
     switch (kind) {
       case MGM_KERNEL_STENCIL:
         // every lambda captures pointers and sizes by value: some of them
@@ -351,6 +352,35 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         const double nb = L.ncolor[0];
         const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // neighbour dofs per block
         bytes = 16.0 * b * nb * (2.0 * L.K + halo) + 16.0 * nb * ((double)L.K * L.K + halo * L.M);
+        flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
+        break;
+      }
+      case MGM_KERNEL_SAP_LOW: {
+        require(g.mg_ready && L.ncolor[0] > 0, "SAP needs setup_mg on this level", MGM_ESTATE);
+        require(g.prm.precision != MGM_PREC_FP64, "the preconditioner runs in FP64 (mgm_set_precision)",
+                MGM_ESTATE);
+        lowbuf.ensure(sizeof(cf) * 2 * (size_t)nrhs * n);
+        cf* xf = lowbuf.as<cf>();
+        cf* rf = xf + (int64_t)nrhs * n;
+        launch_convert<float, double>(s, x, xf, (int64_t)nrhs * n);
+        launch_convert<float, double>(s, r, rf, (int64_t)nrhs * n);
+        const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.sbx == 1 && L.sbt == 1 &&
+                          L.f.hblocks.p != nullptr;
+        if (half) {
+          launch = [=, &L] {
+            launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt,
+                         L.color_list[0].as<int>(), L.ncolor[0], nrhs, rf, xf, nullptr);
+          };
+        } else {
+          launch = [=, &L] {
+            launch_sap_sweep<float>(s, L.f.B(), L.f.sapinv.as<cf>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
+                                    L.color_list[0].as<int>(), L.ncolor[0], nrhs, rf, xf, nullptr);
+          };
+        }
+        const double nb = L.ncolor[0];
+        const double halo = 2.0 * (L.sbx + L.sbt) * L.M;
+        const double mb = half ? 4.0 : 8.0;  // bytes per complex matrix entry
+        bytes = 8.0 * b * nb * (2.0 * L.K + halo) + mb * nb * ((double)L.K * L.K + halo * L.M);
         flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
         break;
       }

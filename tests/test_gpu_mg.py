@@ -114,6 +114,18 @@ def test_time_kernel_helper(ctx, built):
         t = ctx.time_kernel(gid, kind, level, 3, reps=3)
         assert t["us"] > 0 and t["bytes"] > 0
     assert ctx.time_kernel(gid, "copy", 0, 3, reps=2)["bytes"] == 32.0 * n0 * 3
+    # the low-precision SAP needs the field in a low-precision mode
+    from paper_2303_11512_amd import MGMError
+    with pytest.raises(MGMError):
+        ctx.time_kernel(gid, "sap_low", 0, 3, reps=2)
+    try:
+        for prec in ("fp32", "fp16"):
+            ctx.set_precision(gid, prec)
+            for level in range(L):
+                t = ctx.time_kernel(gid, "sap_low", level, 3, reps=2)
+                assert t["us"] > 0 and t["bytes"] > 0
+    finally:
+        ctx.set_precision(gid, "fp64")
 
 
 @pytest.mark.parametrize("nrhs", [1, 5])
