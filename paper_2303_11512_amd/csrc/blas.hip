@@ -330,39 +330,34 @@ __global__ void __launch_bounds__(NT) k_done_from_norm(const T* __restrict__ bno
 }
 
 // ------------------------------------------------------------------ CholQR2 pieces
-// partial[chunk][i][j] = sum_{k in chunk} conj(Y_i[k]) Y_j[k], d <= 64
-constexpr int GS = 32;     // elements per LDS stage
-constexpr int GCH = 512;   // elements per chunk
+// Gram partials on the FP64 matrix cores: partial[chunk][i][j] = sum over the
+// chunk's k of conj(Y_i[k]) Y_j[k], d <= 64.  A workgroup owns GCH elements
+// of k; its waves take the 16 x 16 output tiles (i-tile, j-tile) in turn.
+constexpr int GCH = 256;
 __global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, int64_t n, int d,
                                                      cd* __restrict__ partial) {
-  __shared__ cd Ys[64][GS + 1];
-  const int tid = threadIdx.x;
-  const int npair = d * d;
-  cd acc[16];
-#pragma unroll
-  for (int p = 0; p < 16; ++p) acc[p] = mk(0.0, 0.0);
-  const int64_t c0 = (int64_t)blockIdx.x * GCH;
-  for (int64_t s0 = c0; s0 < c0 + GCH && s0 < n; s0 += GS) {
-    for (int e = tid; e < d * GS; e += NT) {
-      const int i = e / GS, kk = e % GS;
-      const int64_t k = s0 + kk;
-      Ys[i][kk] = (k < n) ? Y[(int64_t)i * n + k] : mk(0.0, 0.0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15;
+  const int nt = (d + 15) / 16;
+  const int64_t k0 = (int64_t)blockIdx.x * GCH;
+  const int64_t k1 = min(n, k0 + GCH);
+  for (int tile = wave; tile < nt * nt; tile += 4) {
+    const int i0 = (tile / nt) * 16, j0 = (tile % nt) * 16;
+    const int i = i0 + r, j = j0 + r;
+    CAcc<double> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int64_t kc = k0; kc < k1; kc += 4) {
+      const int64_t k = kc + (lane >> 4);
+      const bool in = k < k1;
+      const cd a = (in && i < d) ? Y[(int64_t)i * n + k] : mk(0.0, 0.0);
+      const cd b = (in && j < d) ? Y[(int64_t)j * n + k] : mk(0.0, 0.0);
+      cmma(conj(a), b, acc);
     }
-    __syncthreads();
+    // element v: row i0 + out_row(lane, v), column j0 + lane % 16
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int pr = tid + p * NT;
-      if (pr < npair) {
-        const int i = pr / d, j = pr % d;
-        for (int kk = 0; kk < GS; ++kk) cjfma(acc[p], Ys[i][kk], Ys[j][kk]);
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int ii = i0 + MF<double>::out_row(lane, v);
+      if (ii < d && j < d) partial[((int64_t)blockIdx.x * d + ii) * d + j] = mk(acc.re[v], acc.im[v]);
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < 16; ++p) {
-    const int pr = tid + p * NT;
-    if (pr < npair) partial[(int64_t)blockIdx.x * npair + pr] = acc[p];
   }
 }
 
@@ -375,68 +370,93 @@ __global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ parti
   G[pr] = acc;
 }
 
-// G + shift * tr(G)/d * I = R^H R (R upper, positive real diagonal); on exit G
-// holds R^{-1} (upper).
-// One wave (64 threads, d <= 64): right-looking Cholesky in R, then every
-// thread back-substitutes one column of R^{-1}.
-__global__ void __launch_bounds__(64) k_cholesky_rinv(cd* __restrict__ G, cd* __restrict__ R, int d,
-                                                      double shift, int* __restrict__ fail) {
-  __shared__ int bad;
+// G + shift * tr(G) * I = R^H R (R upper, positive real diagonal); on exit G
+// holds R^{-1} (upper).  One workgroup, the matrix in LDS: right-looking
+// Cholesky with the trailing update spread over the threads, then thread t
+// back-substitutes column t of R^{-1}.  *fail is set on a non-positive pivot.
+__global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d, double shift,
+                                                      int* __restrict__ fail) {
+  __shared__ cd R[64][65];
+  __shared__ cd X[64][65];
+  __shared__ double trs;
   const int t = threadIdx.x;
   if (t == 0) {
-    bad = 0;
-    if (shift > 0.0) {
-      double tr = 0.0;
-      for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
-      for (int j = 0; j < d; ++j) G[j * d + j].re += shift * tr;
-    }
+    double tr = 0.0;
+    for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
+    trs = shift * tr;
   }
   __syncthreads();
-  for (int e = t; e < d * d; e += 64) R[e] = ((e % d) >= (e / d)) ? G[e] : mk(0.0, 0.0);
+  for (int e = t; e < d * d; e += NT) {
+    const int a = e / d, b = e % d;
+    cd v = b >= a ? G[e] : mk(0.0, 0.0);
+    if (a == b) v.re += trs;
+    R[a][b] = v;
+  }
   __syncthreads();
+  bool failed = false;
   for (int j = 0; j < d; ++j) {
-    if (t == 0) {
-      const double s = R[j * d + j].re;
-      if (!(s > 0.0)) bad = 1;
-      R[j * d + j] = mk(s > 0.0 ? sqrt(s) : 1.0, 0.0);
+    const double s = R[j][j].re;
+    if (!(s > 0.0)) {  // uniform: every thread reads the same s
+      failed = true;
+      break;
     }
+    const double rjj = sqrt(s);
     __syncthreads();
-    if (bad) break;
-    const double rjj = R[j * d + j].re;
-    for (int i = j + 1 + t; i < d; i += 64) R[j * d + i] = (1.0 / rjj) * R[j * d + i];
+    // row j of R: R[j][i] /= rjj (i > j); R[j][j] = rjj
+    for (int i = j + 1 + t; i < d; i += NT) R[j][i] = (1.0 / rjj) * R[j][i];
+    if (t == 0) R[j][j] = mk(rjj, 0.0);
     __syncthreads();
     const int m = d - j - 1;
-    for (int e = t; e < m * m; e += 64) {
+    for (int e = t; e < m * m; e += NT) {
       const int k = j + 1 + e / m, i = j + 1 + e % m;
-      if (i >= k) R[k * d + i] = R[k * d + i] - cjmul(R[j * d + k], R[j * d + i]);
+      if (i >= k) R[k][i] = R[k][i] - cjmul(R[j][k], R[j][i]);
     }
     __syncthreads();
   }
-  if (bad) {
-    if (t == 0) *fail = 1;
+  if (failed) {
+    if (t == 0) atomicOr(fail, 1);
     return;
   }
-  // column t of R^{-1}: R x = e_t by back substitution, written to G
+  // column t of R^{-1}: R x = e_t by back substitution
   if (t < d) {
-    for (int i = d - 1; i > t; --i) G[i * d + t] = mk(0.0, 0.0);
-    G[t * d + t] = mk(1.0 / R[t * d + t].re, 0.0);
+    for (int i = d - 1; i > t; --i) X[i][t] = mk(0.0, 0.0);
+    X[t][t] = mk(1.0 / R[t][t].re, 0.0);
     for (int i = t - 1; i >= 0; --i) {
       cd acc = mk(0.0, 0.0);
-      for (int k = i + 1; k <= t; ++k) cfma(acc, R[i * d + k], G[k * d + t]);
-      G[i * d + t] = (-1.0 / R[i * d + i].re) * acc;
+      for (int k = i + 1; k <= t; ++k) cfma(acc, R[i][k], X[k][t]);
+      X[i][t] = (-1.0 / R[i][i].re) * acc;
     }
   }
+  __syncthreads();
+  for (int e = t; e < d * d; e += NT) G[e] = X[e / d][e % d];
 }
 
-// Q_j[k] = sum_{i <= j} Y_i[k] Rinv[i][j]
+// Q_j[k] = sum_{i <= j} Y_i[k] Rinv[i][j] on the FP64 matrix cores: a wave
+// owns 16 values of k x 16 columns j; K runs over i in chunks of 4.
 __global__ void __launch_bounds__(NT) k_right_tri(const cd* __restrict__ Y, const cd* __restrict__ Rinv,
                                                   int64_t n, int d, cd* __restrict__ Q) {
-  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
-  for (int j = 0; j < d; ++j) {
-    cd acc = mk(0.0, 0.0);
-    for (int i = 0; i <= j; ++i) cfma(acc, Y[(int64_t)i * n + k], Rinv[i * d + j]);
-    Q[(int64_t)j * n + k] = acc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (k0 >= n) return;
+  const int64_t k = k0 + r;
+  const int nt = (d + 15) / 16;
+  for (int jt = 0; jt < nt; ++jt) {
+    const int j = jt * 16 + r;
+    CAcc<double> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+    const int iend = min(d, jt * 16 + 16);  // Rinv is upper: rows i <= j only
+    for (int ic = 0; ic < iend; ic += 4) {
+      const int ia = ic + q;  // A[k][i] = Y_i[k], B[i][j] = Rinv[i][j]
+      const cd a = (ia < d && k < n) ? Y[(int64_t)ia * n + k] : mk(0.0, 0.0);
+      const cd b = (ia < d && j < d) ? Rinv[ia * d + j] : mk(0.0, 0.0);
+      cmma(a, b, acc);
+    }
+    // element v: row k0 + out_row(lane, v), column j
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t kk = k0 + MF<double>::out_row(lane, v);
+      if (kk < n && j < d) Q[(int64_t)j * n + kk] = mk(acc.re[v], acc.im[v]);
+    }
   }
 }
 
@@ -562,20 +582,16 @@ void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partia
   KCHK();
 }
 
-int cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev) {
-  DevBuf R;
-  R.ensure(sizeof(cd) * d * d);
-  HIPCHK(hipMemsetAsync(fail_dev, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_cholesky_rinv, dim3(1), dim3(64), 0, s, G, R.as<cd>(), d, shift, fail_dev);
+int64_t gram_partials(int64_t n) { return (n + GCH - 1) / GCH; }
+
+void launch_cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev) {
+  require(d >= 1 && d <= 64, "orthonormalize: 1 <= d <= 64");
+  hipLaunchKernelGGL(k_cholesky_rinv, dim3(1), dim3(NT), 0, s, G, d, shift, fail_dev);
   KCHK();
-  int fail = 0;
-  HIPCHK(hipMemcpyAsync(&fail, fail_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return fail;
 }
 
 void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int d, cd* Q) {
-  hipLaunchKernelGGL(k_right_tri, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, Y, Rinv, n, d, Q);
+  hipLaunchKernelGGL(k_right_tri, dim3((unsigned)((n + 63) / 64)), dim3(NT), 0, s, Y, Rinv, n, d, Q);
   KCHK();
 }
 

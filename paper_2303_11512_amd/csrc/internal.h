@@ -81,6 +81,43 @@ __host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
+// ---------------------------------------------------------------- matrix cores
+// 16x16x4 matrix-core step in the precision of the cycle.  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; element v of its result is
+// D[out_row(l, v)][l%16]: rows l/16 + 4v for FP64, 4(l/16) + v for FP32
+// (both measured on gfx950 with an in-bounds probe).
+template <class T>
+struct MF;
+template <>
+struct MF<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MF<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <class T>
+struct CAcc {
+  typename MF<T>::v4 re, im;
+};
+
+template <class T>
+__device__ __forceinline__ void cmma(cx<T> a, cx<T> b, CAcc<T>& acc) {
+  acc.re = MF<T>::mma(a.re, b.re, acc.re);
+  acc.re = MF<T>::mma(-a.im, b.im, acc.re);
+  acc.im = MF<T>::mma(a.re, b.im, acc.im);
+  acc.im = MF<T>::mma(a.im, b.re, acc.im);
+}
+
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
   int code;
@@ -225,7 +262,10 @@ template <class T>
 void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
                         T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr);
 void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial);
-int cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev);
+// G + shift tr(G) I = R^H R; G <- R^{-1}; *fail_dev |= 1 if not positive definite
+void launch_cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev);
+// number of Gram partials launch_gram writes (each d x d)
+int64_t gram_partials(int64_t n);
 void launch_local_qr(hipStream_t s, const cd* V, int64_t n, int Nx, int Nt, int M, int bx, int bt,
                      int ntv, cd* P);
 void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int d, cd* Q);
@@ -322,6 +362,13 @@ struct CnnWork {
   DevBuf pairs_b, pairs_x, batch_b, batch_x, idx;
 };
 
+// Trace-estimator workspaces, kept with the field so that repeated estimates
+// reuse them (no reallocation, so captured graphs stay valid).
+struct EstWork {
+  DevBuf t1, t2, t3, t4, dots, part, zb, xb, cb, sb, yb;
+  DevBuf Q[MGM_MAX_LEVELS];
+};
+
 struct Gauge {
   int Lx = 0, Lt = 0, anti = 1;
   double m0 = 0;
@@ -339,6 +386,7 @@ struct Gauge {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   DevBuf scratch;  // split-k partials of the dense applies
   CnnWork cnn;
+  EstWork est;
   std::map<GraphKey, GraphEntry> graphs;
   void clear_graphs() {
     for (auto& kv : graphs)
@@ -362,6 +410,7 @@ struct mgm_ctx {
   std::string err;
   std::vector<std::unique_ptr<mgm::Gauge>> gauges;
   mgm::DevBuf scratch, scratch2, scratch3, ibuf;
+  mgm::DevBuf qr_tmp, qr_G, qr_part, qr_fail;  // orthonormalize workspace
   std::shared_ptr<mgm::Cnn> cnn;  // shared with the per-field worker views
 };
 

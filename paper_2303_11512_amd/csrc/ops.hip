@@ -523,30 +523,6 @@ __global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
   }
 }
 
-// ------------------------------------------------------------------ MFMA variants
-// 16x16x4 matrix-core step in the precision of the cycle.  Lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; element v of its result is
-// D[out_row(l, v)][l%16]: rows l/16 + 4v for FP64, 4(l/16) + v for FP32
-// (both measured on gfx950 with an in-bounds probe).
-template <class T>
-struct MF;
-template <>
-struct MF<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-template <>
-struct MF<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-
 // Complex products as real GEMMs: a complex K x K matrix A and a block of
 // complex vectors X (K x R) give Y = A X through the real matrices
 //   Ar[i][2j] = Re A[i][j],  Ar[i][2j+1] = Im A[i][j]
@@ -564,19 +540,6 @@ __device__ __forceinline__ T xr_elem(cx<T> v, int q, int p) {
 // result tile of one product (element c of a lane = row kc(l, c)) is already
 // the B operand of the next one, with no shuffle.
 constexpr int CM = 16;
-
-template <class T>
-struct CAcc {
-  typename MF<T>::v4 re, im;
-};
-
-template <class T>
-__device__ __forceinline__ void cmma(cx<T> a, cx<T> b, CAcc<T>& acc) {
-  acc.re = MF<T>::mma(a.re, b.re, acc.re);
-  acc.re = MF<T>::mma(-a.im, b.im, acc.re);
-  acc.im = MF<T>::mma(a.re, b.im, acc.im);
-  acc.im = MF<T>::mma(a.im, b.re, acc.im);
-}
 
 // acc += B_d x_{nb(u, d)} for one direction d and the RHS column of this lane
 // (zero operand for lanes past the last RHS); the block is read straight from
@@ -670,19 +633,24 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
+  // the second product's operands are loaded first (latency overlaps the hops)
+  cx<T> rv[4], a[4];
+  if (wave == 0) {
+    const cx<T>* Iu = inv + (u * CM + i) * CM;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = MF<T>::out_row(lane, c);
+      rv[c] = ok ? rr[rrow * n + u * CM + k] : mk<T>(0, 0);
+      a[c] = Iu[k];
+    }
+  }
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
   if (!reduce_waves(acc, red, wave, lane)) return;
   // t = r_u - (hops) in the result layout: element c = row out_row(lane, c)
-  cx<T> t[4], a[4];
-  const cx<T>* Iu = inv + (u * CM + i) * CM;
+  cx<T> t[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int k = MF<T>::out_row(lane, c);
-    const cx<T> rv = ok ? rr[rrow * n + u * CM + k] : mk<T>(0, 0);
-    t[c] = mk<T>(rv.re - acc.re[c], rv.im - acc.im[c]);
-    a[c] = Iu[k];
-  }
+  for (int c = 0; c < 4; ++c) t[c] = mk<T>(rv[c].re - acc.re[c], rv[c].im - acc.im[c]);
   CAcc<T> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
   for (int c = 0; c < 4; ++c) cmma(a[c], t[c], cor);
@@ -761,20 +729,30 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
+  // the second product's operands are loaded first, so that their latency
+  // overlaps the hops
+  cf rv[4];
+  chalf iv[4];
+  if (wave == 0) {
+    const chalf* Iu = inv + (u * CM + i) * CM + 4 * q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rv[j] = ok ? rr[rrow * n + u * CM + 4 * q + j] : mk<float>(0, 0);
+      iv[j] = Iu[j];
+    }
+  }
   CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
   if (!reduce_waves(acc, red, wave, lane)) return;
   // t = r_u - hops: element j of this lane is row 4q + j, which is also the
   // B operand layout of the next product
   h4 tr, ti, ar, ai;
-  const chalf* Iu = inv + (u * CM + i) * CM + 4 * q;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const cf rv = ok ? rr[rrow * n + u * CM + 4 * q + j] : mk<float>(0, 0);
-    tr[j] = (_Float16)(rv.re - acc.re[j]);
-    ti[j] = (_Float16)(rv.im - acc.im[j]);
-    ar[j] = Iu[j].re;
-    ai[j] = Iu[j].im;
+    tr[j] = (_Float16)(rv[j].re - acc.re[j]);
+    ti[j] = (_Float16)(rv[j].im - acc.im[j]);
+    ar[j] = iv[j].re;
+    ai[j] = iv[j].im;
   }
   CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
   hmma(ar, ai, tr, ti, cor);

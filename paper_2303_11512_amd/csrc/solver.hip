@@ -393,30 +393,35 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
   hipStream_t s = c->stream;
   require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
-  DevBuf tmp, G, part, fail;
-  tmp.ensure(sizeof(cd) * (size_t)d * n);
-  G.ensure(sizeof(cd) * d * d);
-  part.ensure(sizeof(cd) * (size_t)d * d * ((n + 511) / 512));
-  fail.ensure(sizeof(int));
+  c->qr_tmp.ensure(sizeof(cd) * (size_t)d * n);
+  c->qr_G.ensure(sizeof(cd) * d * d);
+  c->qr_part.ensure(sizeof(cd) * (size_t)d * d * gram_partials(n));
+  c->qr_fail.ensure(sizeof(int));
+  cd* tmp = c->qr_tmp.as<cd>();
+  cd* G = c->qr_G.as<cd>();
+  int* fail = c->qr_fail.as<int>();
+  HIPCHK(hipMemsetAsync(fail, 0, sizeof(int), s));
   // pass 0: Y -> tmp (shifted Gram), pass 1: tmp -> Q, pass 2: copy of Q -> Q
   const double shifts[3] = {1e-14, 0.0, 0.0};
   for (int pass = 0; pass < 3; ++pass) {
     const cd* src = Y;
-    cd* dst = tmp.as<cd>();
+    cd* dst = tmp;
     if (pass == 1) {
-      src = tmp.as<cd>();
+      src = tmp;
       dst = Q;
     } else if (pass == 2) {
-      HIPCHK(hipMemcpyAsync(tmp.p, Q, sizeof(cd) * (size_t)d * n, hipMemcpyDeviceToDevice, s));
-      src = tmp.as<cd>();
+      HIPCHK(hipMemcpyAsync(tmp, Q, sizeof(cd) * (size_t)d * n, hipMemcpyDeviceToDevice, s));
+      src = tmp;
       dst = Q;
     }
-    launch_gram(s, src, n, d, G.as<cd>(), part.as<cd>());
-    if (cholesky_rinv(s, G.as<cd>(), d, shifts[pass], fail.as<int>()))
-      throw Error(MGM_ENONFINITE, "CholQR: Gram matrix not positive definite (rank-deficient block)");
-    launch_right_tri(s, src, G.as<cd>(), n, d, dst);
+    launch_gram(s, src, n, d, G, c->qr_part.as<cd>());
+    launch_cholesky_rinv(s, G, d, shifts[pass], fail);
+    launch_right_tri(s, src, G, n, d, dst);
   }
+  int hfail = 0;
+  HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (hfail) throw Error(MGM_ENONFINITE, "CholQR: Gram matrix not positive definite (rank-deficient block)");
 }
 
 // ------------------------------------------------------------------ setup

@@ -31,7 +31,7 @@ struct StochLevel {
   zc tau_lr = 0;
   std::vector<zc> samples;
   bool active = true;
-  DevBuf Q;            // [d][n]
+  DevBuf* Q = nullptr; // [d][n], owned by the field's estimator workspace
   int s() const { return (int)samples.size(); }
   zc mean() const {
     if (samples.empty()) return 0.0;
@@ -56,12 +56,14 @@ struct Estimator {
   int L;                 // number of levels of the hierarchy
   bool full;             // full (hatted) form
   bool hutch;            // single-level variants on D^{-1}
-  DevBuf t1, t2, t3, t4; // scratch vectors
-  DevBuf dots, part;
-  DevBuf zb, xb, cb, sb, yb;  // noise, A*noise, projection coefficients, sketch, sketch images
+  // workspaces of the field (scratch vectors; noise, A*noise, projection
+  // coefficients, sketch, sketch images)
+  DevBuf &t1, &t2, &t3, &t4, &dots, &part, &zb, &xb, &cb, &sb, &yb;
 
   Estimator(mgm_ctx* c_, Gauge& g_, const mgm_trace_params& p_, mgm_trace_result& r_)
-      : c(c_), g(g_), p(p_), res(r_) {
+      : c(c_), g(g_), p(p_), res(r_), t1(g_.est.t1), t2(g_.est.t2), t3(g_.est.t3), t4(g_.est.t4),
+        dots(g_.est.dots), part(g_.est.part), zb(g_.est.zb), xb(g_.est.xb), cb(g_.est.cb), sb(g_.est.sb),
+        yb(g_.est.yb) {
     L = g.mlmc_levels;
     full = p.form == MGM_FORM_FULL;
     hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
@@ -164,17 +166,17 @@ struct Estimator {
     DevBuf& Y = yb;
     S.ensure(sizeof(cd) * (size_t)d * n);
     Y.ensure(sizeof(cd) * (size_t)d * n);
-    sl.Q.ensure(sizeof(cd) * (size_t)d * n);
+    sl.Q->ensure(sizeof(cd) * (size_t)d * n);
     launch_noise<double>(c->stream, S.as<cd>(), n, d, p.noise, p.seed, MGM_PURPOSE_SKETCH, idx, 0);
     const cd* src = S.as<cd>();
     for (int it = 0; it < std::max(1, p.k_power); ++it) {
       applyA(sl, d, src, Y.as<cd>());
-      orthonormalize(c, n, d, Y.as<cd>(), sl.Q.as<cd>());
-      src = sl.Q.as<cd>();
+      orthonormalize(c, n, d, Y.as<cd>(), sl.Q->as<cd>());
+      src = sl.Q->as<cd>();
     }
-    applyA(sl, d, sl.Q.as<cd>(), Y.as<cd>());
+    applyA(sl, d, sl.Q->as<cd>(), Y.as<cd>());
     std::vector<zc> v;
-    dots_host(sl.Q.as<cd>(), Y.as<cd>(), n, d, v);
+    dots_host(sl.Q->as<cd>(), Y.as<cd>(), n, d, v);
     zc acc = 0;
     for (const zc& x : v) acc += x;
     sl.tau_lr = acc;
@@ -194,9 +196,9 @@ struct Estimator {
     if (sl.d > 0) {
       C.ensure(sizeof(cd) * (size_t)b * sl.d);
       part.ensure(sizeof(cd) * (size_t)b * sl.d * reduce_chunks(n) + 64);
-      launch_dot_multi_ld<double>(s, sl.Q.as<cd>(), n, 0, sl.d, Z.as<cd>(), n, b, C.as<cd>(), sl.d, 0,
+      launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z.as<cd>(), n, b, C.as<cd>(), sl.d, 0,
                                   nullptr, part.as<cd>());
-      launch_update_multi<double>(s, sl.Q.as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z.as<cd>(), n, b,
+      launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z.as<cd>(), n, b,
                                   nullptr, nullptr, nullptr);
     }
     dots_host(Z.as<cd>(), X.as<cd>(), n, b, out);
@@ -232,6 +234,7 @@ struct Estimator {
     std::vector<StochLevel> lv(nst);
     for (int i = 0; i < nst; ++i) {
       StochLevel& sl = lv[i];
+      sl.Q = &g.est.Q[i];
       sl.level = hutch ? 0 : i;
       sl.n = (hutch || full) ? g.levels[0]->n : g.levels[i]->n;
       sl.d = lr ? p.d[i] : 0;
