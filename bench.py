@@ -25,10 +25,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# red/black SAP cycles per level of the V-cycle (fine, first coarse, deeper):
-# a sweep on the 128^2 workload puts the minimum of time per estimate at
-# heavy smoothing of the first coarse level
-SAP_CYCLES = (3, 10, 4, 4, 4, 4)
+# red/black SAP cycles per level of the V-cycle (fine, first coarse, deeper)
+# and the SAP blocks below the fine level (2x1 sites on the first coarse level,
+# single sites deeper): a sweep on the 128^2 workload puts the minimum of time
+# per estimate at heavy smoothing of the first coarse level
+SAP_CYCLES = (3, 8, 3, 3, 3, 3)
+COARSE_SAP_BLOCKS = [(2, 1), (1, 1), (1, 1), (1, 1), (1, 1)]
 
 
 def mg_setup_kwargs(cfg):
@@ -48,7 +50,7 @@ def mg_setup_kwargs(cfg):
     L = len(blocks) + 1
     return dict(
         nlevels=L, blocks=blocks, ntv=ntv, mlmc_levels=mlmc,
-        sap_block=[blocks[0]] + [(1, 1)] * L,
+        sap_block=[blocks[0]] + COARSE_SAP_BLOCKS,
         sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, inner_tol=0.0,
         setup_iters=3, setup_tol=1e-10, setup_restart=32, setup_max_restarts=200,
         seed=cfg["gauge_seed"] + 17,
@@ -202,7 +204,7 @@ def run_batch8(args):
         L = th.shape[1]
         blocks, ntv = solver_hierarchy(L)
         gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), m0, True)
-        ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + [(1, 1)] * 5,
+        ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + COARSE_SAP_BLOCKS,
                                     sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, setup_tol=1e-10,
                                     seed=3100 + i))
         n = ctx.level_info(gid, 0)["n"]
@@ -330,7 +332,7 @@ def run_cnn(args):
     def setup(spec, seed):
         blocks, ntv = solver_hierarchy(spec["L"])
         gid = ctx.set_gauge(torch.from_numpy(links_from_theta(field(spec))).to("cuda"), spec["m0"], True)
-        ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + [(1, 1)] * 5,
+        ctx.setup_mg(gid, mg_params(len(blocks) + 1, blocks, ntv, sap_block=[(4, 4)] + COARSE_SAP_BLOCKS,
                                     sap_cycles=list(SAP_CYCLES), inner_iters=[0] * 6, setup_tol=1e-10, seed=seed))
         return gid
 

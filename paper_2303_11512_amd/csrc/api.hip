@@ -364,11 +364,11 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         cf* rf = xf + (int64_t)nrhs * n;
         launch_convert<float, double>(s, x, xf, (int64_t)nrhs * n);
         launch_convert<float, double>(s, r, rf, (int64_t)nrhs * n);
-        const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.sbx == 1 && L.sbt == 1 &&
-                          L.f.hblocks.p != nullptr;
+        const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.sbt == 1 &&
+                          (L.sbx == 1 || L.sbx == 2) && L.f.hblocks.p != nullptr;
         if (half) {
           launch = [=, &L] {
-            launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt,
+            launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.sbx, L.sbt,
                          L.color_list[0].as<int>(), L.ncolor[0], nrhs, rf, xf, nullptr);
           };
         } else {

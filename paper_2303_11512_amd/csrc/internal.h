@@ -212,8 +212,8 @@ void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M
 void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count);
 void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nrhs, const cf* x, cf* y,
                       const cf* b, const int* active);
-void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, const int* blist,
-                  int nb, int nrhs, const cf* r, cf* x, const int* active);
+void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
+                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active);
 // In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A.
 int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* scratch_out);
 void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out);
@@ -281,25 +281,24 @@ struct LevelData {
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 
-// Pinned host copies of per-RHS flags with two completion events, so the host
-// can read step j's flags while step j + 1 is already queued.
+// Pinned host copies of per-RHS flags with kDepth completion events, so the
+// host can read step j's flags while the following steps are already queued.
 struct PinnedFlags {
+  static constexpr int kDepth = 3;
   int* h = nullptr;
   int cap = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[kDepth] = {nullptr, nullptr, nullptr};
   PinnedFlags() = default;
   PinnedFlags(const PinnedFlags&) = delete;
   PinnedFlags& operator=(const PinnedFlags&) = delete;
   void ensure(int n) {
-    if (!ev[0]) {
-      HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    }
+    if (!ev[0])
+      for (hipEvent_t& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (n <= cap) return;
     if (h) (void)hipHostFree(h);
     h = nullptr;
     cap = 0;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(int) * 2 * (size_t)n, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(int) * kDepth * (size_t)n, hipHostMallocDefault));
     cap = n;
   }
   ~PinnedFlags() {

@@ -761,11 +761,141 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   for (int v = 0; v < 4; ++v) x[(int64_t)r * n + u * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
 }
 
+// Two-site blocks along x with FP16 blocks (see k_sap2_mfma).
+__global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, const chalf* __restrict__ inv,
+                                               int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                               const cf* __restrict__ rr, cf* __restrict__ x,
+                                               const int* __restrict__ active) {
+  __shared__ float red[4][8][64];
+  const int blk = blist[blockIdx.x];
+  const int NBx = Nx / 2;
+  const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  cf rv[2][4];
+  chalf iv[2][4];
+  if (wave < 2) {
+    const chalf* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32 + 4 * q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rv[0][j] = ok ? rr[rrow * n + u0 * CM + 4 * q + j] : mk<float>(0, 0);
+      rv[1][j] = ok ? rr[rrow * n + u1 * CM + 4 * q + j] : mk<float>(0, 0);
+      iv[0][j] = Ih[j];
+      iv[1][j] = Ih[16 + j];
+    }
+  }
+  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const int64_t us = wave < 2 ? u0 : u1;
+  if (wave == 0 || wave == 2) {
+    coarse_hop_h(B, x, n, us, wave == 0 ? 2 : 1, Nx, Nt, rrow, ok, lane, acc);
+    coarse_hop_h(B, x, n, us, 3, Nx, Nt, rrow, ok, lane, acc);
+  } else {
+    coarse_hop_h(B, x, n, us, 4, Nx, Nt, rrow, ok, lane, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[wave][v][lane] = acc.re[v];
+    red[wave][4 + v][lane] = acc.im[v];
+  }
+  __syncthreads();
+  if (wave >= 2) return;
+  CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int sidx = 0; sidx < 2; ++sidx) {
+    h4 tr, ti, ar, ai;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      tr[j] = (_Float16)(rv[sidx][j].re - red[2 * sidx][j][lane] - red[2 * sidx + 1][j][lane]);
+      ti[j] = (_Float16)(rv[sidx][j].im - red[2 * sidx][4 + j][lane] - red[2 * sidx + 1][4 + j][lane]);
+      ar[j] = iv[sidx][j].re;
+      ai[j] = iv[sidx][j].im;
+    }
+    hmma(ar, ai, tr, ti, cor);
+  }
+  if (!ok || (active && !active[r])) return;
+  const int64_t uo = wave == 0 ? u0 : u1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[(int64_t)r * n + uo * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
+}
+
 __global__ void __launch_bounds__(NT) k_to_half(const cd* __restrict__ in, chalf* __restrict__ out,
                                                 int64_t count) {
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (e >= count) return;
   out[e] = chalf{(_Float16)in[e].re, (_Float16)in[e].im};
+}
+
+// One colour of the coarse SAP sweep with two-site blocks along x (sites u0,
+// u1 = u0 + x^, K = 32): x_B = inv_B (r_B - outward hops).  One workgroup per
+// (block, 16 RHS); the six outward hops are spread over the four waves
+// (u0: -x, +t | -t; u1: +x, +t | -t), summed per site in LDS, and waves 0 and
+// 1 apply the two row halves of inv_B.
+template <class T>
+__global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
+                                                  int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                  const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
+                                                  const int* __restrict__ active) {
+  __shared__ T red[4][8][64];
+  const int blk = blist[blockIdx.x];
+  const int NBx = Nx / 2;
+  const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  // operands of the block solve, loaded first (waves 0 and 1: row half = wave)
+  cx<T> rv[2][4], a[2][4];
+  if (wave < 2) {
+    const cx<T>* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = MF<T>::out_row(lane, c);
+      rv[0][c] = ok ? rr[rrow * n + u0 * CM + k] : mk<T>(0, 0);
+      rv[1][c] = ok ? rr[rrow * n + u1 * CM + k] : mk<T>(0, 0);
+      a[0][c] = Ih[k];
+      a[1][c] = Ih[16 + k];
+    }
+  }
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const int64_t us = wave < 2 ? u0 : u1;
+  if (wave == 0 || wave == 2) {
+    coarse_hop(B, x, n, us, wave == 0 ? 2 : 1, Nx, Nt, rrow, ok, lane, acc);
+    coarse_hop(B, x, n, us, 3, Nx, Nt, rrow, ok, lane, acc);
+  } else {
+    coarse_hop(B, x, n, us, 4, Nx, Nt, rrow, ok, lane, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[wave][v][lane] = acc.re[v];
+    red[wave][4 + v][lane] = acc.im[v];
+  }
+  __syncthreads();
+  if (wave >= 2) return;
+  cx<T> t[2][4];
+#pragma unroll
+  for (int sidx = 0; sidx < 2; ++sidx)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      t[sidx][c] = mk<T>(rv[sidx][c].re - red[2 * sidx][c][lane] - red[2 * sidx + 1][c][lane],
+                         rv[sidx][c].im - red[2 * sidx][4 + c][lane] - red[2 * sidx + 1][4 + c][lane]);
+  CAcc<T> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int sidx = 0; sidx < 2; ++sidx)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cmma(a[sidx][c], t[sidx][c], cor);
+  if (!ok || (active && !active[r])) return;
+  const int64_t uo = wave == 0 ? u0 : u1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    x[(int64_t)r * n + uo * CM + MF<T>::out_row(lane, v)] = mk<T>(cor.re[v], cor.im[v]);
 }
 
 // One colour of the fine-level SAP sweep with 4x4-site blocks (K = 32 dofs).
@@ -1340,11 +1470,17 @@ void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nr
   KCHK();
 }
 
-void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, const int* blist,
-                  int nb, int nrhs, const cf* r, cf* x, const int* active) {
+void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
+                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_sap_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs, r,
-                     x, active);
+  if (sbx == 2 && sbt == 1)
+    hipLaunchKernelGGL(k_sap2_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs,
+                       r, x, active);
+  else if (sbx == 1 && sbt == 1)
+    hipLaunchKernelGGL(k_sap_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs,
+                       r, x, active);
+  else
+    throw Error(MGM_EINVAL, "FP16 SAP: blocks must be 1x1 or 2x1 sites");
   KCHK();
 }
 
@@ -1404,6 +1540,12 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   require(K <= 32, "SAP block too large");
   if (M == CM && sbx == 1 && sbt == 1) {
     hipLaunchKernelGGL(k_sap_mfma<T>, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
+                       nrhs, r, x, active);
+    KCHK();
+    return;
+  }
+  if (M == CM && sbx == 2 && sbt == 1) {
+    hipLaunchKernelGGL(k_sap2_mfma<T>, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
                        nrhs, r, x, active);
     KCHK();
     return;

@@ -115,12 +115,13 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
   }
   bool half = false;
-  if constexpr (std::is_same<T, float>::value) half = half_blocks(g, L) && L.sbx == 1 && L.sbt == 1;
+  if constexpr (std::is_same<T, float>::value)
+    half = half_blocks(g, L) && L.sbt == 1 && (L.sbx == 1 || L.sbx == 2);
   for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
     for (int col = 0; col < 2; ++col) {
       if constexpr (std::is_same<T, float>::value) {
         if (half) {
-          launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt,
+          launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.sbx, L.sbt,
                        L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
           continue;
         }
@@ -277,9 +278,9 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
 
 // Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
 // residual, checked at the end of every cycle).  Inside a cycle the host reads
-// the active flags of step j - 1 while step j is already queued, and ends the
-// cycle once every RHS has converged (the one extra step is a no-op: every
-// kernel of a step skips inactive RHS).
+// the active flags of step j - 2 while steps j - 1 and j are already queued,
+// and ends the cycle once every RHS has converged (the extra steps are
+// no-ops: every kernel of a step skips inactive RHS).
 int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                 const mgm_solve_params& sp, int* iters_out, double* relres_out) {
   hipStream_t s = c->stream;
@@ -332,11 +333,11 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
           precondition_graph(c, g, l, nrhs, v, z, a);
         });
-        const int slot = j & 1;
+        const int slot = j % PinnedFlags::kDepth;
         HIPCHK(hipMemcpyAsync(W.flags.h + slot * nrhs, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(W.flags.ev[slot], s));
-        if (j == 0) continue;
-        const int prev = slot ^ 1;
+        if (j + 1 < PinnedFlags::kDepth) continue;
+        const int prev = (j + 1) % PinnedFlags::kDepth;  // step j - (kDepth - 1)
         HIPCHK(hipEventSynchronize(W.flags.ev[prev]));
         const int* f = W.flags.h + prev * nrhs;
         if (std::all_of(f, f + nrhs, [](int a) { return a == 0; })) break;

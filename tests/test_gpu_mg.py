@@ -164,3 +164,29 @@ def test_blocked_dense_inverse(ctx, L):
     ctx.precondition(gid, 1, to_dev(r), x)
     ref = np.linalg.solve(coarse.D.toarray(), r.T).T
     assert rel_err(to_host(x), ref) < 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4), ("fp16", 3e-2)])
+def test_two_site_sap_blocks(ctx, precision, tol):
+    """Coarse SAP with 2x1-site blocks (K = 32, matrix-core kernels in every
+    precision) inside a V-cycle, against the oracle's cycle."""
+    from paper_2303_11512_amd import solve_params
+    th = metropolis_u1(32, 32, 3.0, 100, 955)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (2, 1), (1, 1)],
+                 sap_cycles=[2, 3, 2], inner_iters=[0, 0, 0], precision=precision)
+    log(f"2x1 SAP blocks, {precision}")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    kc = rec.kcycle(hier)
+    for l in range(2):
+        lev = hier.levels[l]
+        r = rhs_vectors(lev.n, 20, 80 + l)
+        x = empty(20, lev.n)
+        ctx.precondition(gid, l, to_dev(r), x)
+        assert rel_err(to_host(x), kc.apply(l, r.T).T) < tol, (precision, l)
+    lev = hier.levels[0]
+    b = rhs_vectors(lev.n, 6, 27)
+    x = empty(6, lev.n)
+    ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=24))
+    res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
+    assert np.all(res <= 1e-10)
