@@ -62,6 +62,32 @@ Cnn& cnn_of(mgm_ctx* c) {
   return *c->cnn;
 }
 
+// Distinct sites outside the colour-0 SAP blocks that neighbour one of them:
+// the x values one colour sweep must read (each once).
+int64_t sap_halo_sites(const Level& L) {
+  const int NBx = L.Nx / L.sbx;
+  std::vector<int> blocks(L.ncolor[0]);
+  HIPCHK(hipMemcpy(blocks.data(), L.color_list[0].p, sizeof(int) * blocks.size(), hipMemcpyDeviceToHost));
+  std::vector<char> in(L.sites, 0), mark(L.sites, 0);
+  auto site = [&](int x, int t) { return (int64_t)((t + L.Nt) % L.Nt) * L.Nx + (x + L.Nx) % L.Nx; };
+  for (int b : blocks)
+    for (int st = 0; st < L.sbt; ++st)
+      for (int sx = 0; sx < L.sbx; ++sx) in[site((b % NBx) * L.sbx + sx, (b / NBx) * L.sbt + st)] = 1;
+  int64_t cnt = 0;
+  for (int b : blocks)
+    for (int st = 0; st < L.sbt; ++st)
+      for (int sx = 0; sx < L.sbx; ++sx) {
+        const int x = (b % NBx) * L.sbx + sx, t = (b / NBx) * L.sbt + st;
+        const int64_t nb[4] = {site(x + 1, t), site(x - 1, t), site(x, t + 1), site(x, t - 1)};
+        for (int64_t v : nb)
+          if (!in[v] && !mark[v]) {
+            mark[v] = 1;
+            ++cnt;
+          }
+      }
+  return cnt;
+}
+
 Level& level_of(Gauge& g, int level) {
   require(level >= 0 && level < (int)g.levels.size(),
           "level out of range (call setup_mg for coarse levels)");
@@ -348,10 +374,12 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
                                    L.color_list[0].as<int>(), L.ncolor[0], nrhs, r, y, nullptr);
         };
         // with the exact block inverse a sweep is x_B = inv_B (r_B - D_BH x_H):
-        // r_B and the halo read, x_B written, inv_B and the outward hops read
+        // r_B and the distinct halo values read, x_B written, inv_B and the
+        // outward hops read (each once)
         const double nb = L.ncolor[0];
-        const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // neighbour dofs per block
-        bytes = 16.0 * b * nb * (2.0 * L.K + halo) + 16.0 * nb * ((double)L.K * L.K + halo * L.M);
+        const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // outward hop dofs per block
+        const double hx = (double)sap_halo_sites(L) * L.M;
+        bytes = 16.0 * b * (2.0 * nb * L.K + hx) + 16.0 * nb * ((double)L.K * L.K + halo * L.M);
         flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
         break;
       }
@@ -379,8 +407,9 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         }
         const double nb = L.ncolor[0];
         const double halo = 2.0 * (L.sbx + L.sbt) * L.M;
+        const double hx = (double)sap_halo_sites(L) * L.M;
         const double mb = half ? 4.0 : 8.0;  // bytes per complex matrix entry
-        bytes = 8.0 * b * nb * (2.0 * L.K + halo) + mb * nb * ((double)L.K * L.K + halo * L.M);
+        bytes = 8.0 * b * (2.0 * nb * L.K + hx) + mb * nb * ((double)L.K * L.K + halo * L.M);
         flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
         break;
       }

@@ -523,16 +523,6 @@ __global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
   }
 }
 
-// Complex products as real GEMMs: a complex K x K matrix A and a block of
-// complex vectors X (K x R) give Y = A X through the real matrices
-//   Ar[i][2j] = Re A[i][j],  Ar[i][2j+1] = Im A[i][j]
-//   Xr[2j][2r] = Re x,  Xr[2j+1][2r] = -Im x,  Xr[2j][2r+1] = Im x,  Xr[2j+1][2r+1] = Re x
-// so that (Ar Xr)[i][2r] = Re y[r][i] and (Ar Xr)[i][2r+1] = Im y[r][i].
-template <class T>
-__device__ __forceinline__ T xr_elem(cx<T> v, int q, int p) {
-  return p == 0 ? (q == 0 ? v.re : -v.im) : (q == 0 ? v.im : v.re);
-}
-
 // ------------------------------------------------------------------ coarse levels on the matrix cores
 // Levels with 16 dofs per site (8 test vectors x 2 chiralities).  A wave owns
 // a 16 (dofs) x 16 (RHS) complex tile; a complex product is four real MFMAs.
