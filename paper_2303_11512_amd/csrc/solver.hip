@@ -214,20 +214,19 @@ void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, c
   }
 }
 
-// The preconditioner application has a fixed sequence of launches and no host
-// synchronisation (inner solves run their fixed step counts with device-side
-// masks), so it is replayed as a HIP graph.  A key is first run directly,
-// which performs any buffer allocation; the second time, if no allocation
-// happened since (same epoch), it is captured, instantiated and launched;
-// later calls launch the graph.  Any reallocation anywhere invalidates the
-// graph (its kernel arguments hold buffer addresses).
-void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
+// A fixed sequence of launches with no host synchronisation (a preconditioner
+// application, an Arnoldi step) is replayed as a HIP graph.  A key is first
+// run directly, which performs any buffer allocation; the second time, if no
+// allocation happened since (same epoch), it is captured, instantiated and
+// launched; later calls launch the graph.  Any reallocation anywhere
+// invalidates the graph (its kernel arguments hold buffer addresses).
+template <class F>
+void run_graph(mgm_ctx* c, Gauge& g, const GraphKey& key, F&& body) {
   hipStream_t s = c->stream;
   if (!g.prm.graphs || !s) {
-    precondition_d(c, g, l, nrhs, r, x, act);
+    body();
     return;
   }
-  const GraphKey key{l, nrhs, (const void*)r, (void*)x, act, g.prm.precision};
   auto it = g.graphs.find(key);
   const uint64_t ep = g_alloc_epoch.load();
   if (it != g.graphs.end() && it->second.exec && it->second.epoch == ep) {
@@ -240,7 +239,7 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
       it->second.exec = nullptr;
     }
     const bool failed = it != g.graphs.end() && it->second.failed;
-    precondition_d(c, g, l, nrhs, r, x, act);
+    body();
     GraphEntry& e = g.graphs[key];
     e.epoch = g_alloc_epoch.load();
     e.failed = failed;
@@ -252,11 +251,11 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     it->second.failed = true;
-    precondition_d(c, g, l, nrhs, r, x, act);
+    body();
     return;
   }
   try {
-    precondition_d(c, g, l, nrhs, r, x, act);
+    body();
   } catch (...) {
     (void)hipStreamEndCapture(s, &graph);
     if (graph) (void)hipGraphDestroy(graph);
@@ -269,11 +268,16 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
     (void)hipGetLastError();
     if (exec) (void)hipGraphExecDestroy(exec);
     it->second.failed = true;
-    precondition_d(c, g, l, nrhs, r, x, act);
+    body();
     return;
   }
   it->second.exec = exec;
   HIPCHK(hipGraphLaunch(exec, s));
+}
+
+void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
+  const GraphKey key{l, nrhs, (const void*)r, (void*)x, act, g.prm.precision};
+  run_graph(c, g, key, [&] { precondition_d(c, g, l, nrhs, r, x, act); });
 }
 
 // Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
@@ -330,8 +334,16 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                                  W.nit.as<int>(), W.g.as<cd>(), W.thr.as<double>());
       launch_scale<double>(s, w, beta, n, nrhs, V, act);
       for (int j = 0; j < m; ++j) {
-        arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
-          precondition_graph(c, g, l, nrhs, v, z, a);
+        // the whole step is one graph: key level field (m + 1) * 1000 + l
+        // tells it from the preconditioner's own graphs and from other
+        // restart lengths; the step index is in the V / Z addresses
+        const int64_t vs = (int64_t)nrhs * n;
+        const GraphKey key{(m + 1) * 1000 + l, nrhs, (const void*)(V + j * vs), (void*)(Z + j * vs), act,
+                           g.prm.precision};
+        run_graph(c, g, key, [&] {
+          arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
+            precondition_d(c, g, l, nrhs, v, z, a);
+          });
         });
         const int slot = j % PinnedFlags::kDepth;
         HIPCHK(hipMemcpyAsync(W.flags.h + slot * nrhs, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
