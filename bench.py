@@ -362,7 +362,8 @@ def run_cnn(args):
         ctx.noise("z2z2", 11, 0, 0, 0, b)
         x = torch.empty_like(b)
         row = dict(L=spec["L"], seed=spec["seed"])
-        for use in (False, True):
+        for key, use, prec in (("plain", False, "fp32"), ("cnn_fp32", True, "fp32"), ("cnn", True, "fp16")):
+            ctx.cnn_set_precision(prec)
             sp = solve_params(tol=1e-10, restart=16, max_restarts=50, use_cnn=use)
             ctx.solve_batch(gid, 0, b, x, sp)   # warm-up (workspaces, graphs)
             torch.cuda.synchronize()
@@ -372,15 +373,16 @@ def run_cnn(args):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t1) / args.steps
             assert float(np.max(rel)) <= 1e-10
-            key = "cnn" if use else "plain"
             row[key] = dict(s=dt, iters=float(np.mean(its)))
         rows.append(row)
         ctx.free_gauge(gid)
         print(f"# eval {spec['L']}^2 seed {spec['seed']}: plain {row['plain']['iters']:.2f} it "
-              f"{row['plain']['s'] * 1e3:.1f} ms, guess {row['cnn']['iters']:.2f} it "
-              f"{row['cnn']['s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+              f"{row['plain']['s'] * 1e3:.1f} ms, FP16 guess {row['cnn']['iters']:.2f} it "
+              f"{row['cnn']['s'] * 1e3:.1f} ms, FP32 guess {row['cnn_fp32']['s'] * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
     t_plain = sum(r["plain"]["s"] for r in rows)
     t_cnn = sum(r["cnn"]["s"] for r in rows)
+    t_cnn32 = sum(r["cnn_fp32"]["s"] for r in rows)
     achieved = conv["flops"] / (conv["us"] * 1e-6) / 1e12
     print(json.dumps({
         "metric": "RHS solves/s (tol 1e-10) from the learned initial guess", "value": nrhs * len(rows) / t_cnn,
@@ -390,7 +392,9 @@ def run_cnn(args):
         "config": {"workload": f"cnn: train on {len(train)} quenched 128^2 fields (beta 3.0, m0 -0.10, "
                                f"{args.pairs} Z2xZ2 pairs each, {args.epochs} epochs, batch 64, Adam 1e-3); "
                                f"evaluate 64 RHS on unseen fields at {sizes}",
+                   "guess_precision": "fp16 weights and activations (FP32 accumulation)",
                    "plain_solves_per_s": nrhs * len(rows) / t_plain, "gain": t_plain / t_cnn,
+                   "fp32_guess_solves_per_s": nrhs * len(rows) / t_cnn32,
                    "iters_plain": float(np.mean([r["plain"]["iters"] for r in rows])),
                    "iters_cnn": float(np.mean([r["cnn"]["iters"] for r in rows])),
                    "epoch_losses": losses, "train_s": train_s, "setup_s": setup_s, "fields": rows},

@@ -347,6 +347,13 @@ int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, i
 int mgm_cnn_set_params(mgm_ctx *ctx, const float *theta);
 int mgm_cnn_get_params(mgm_ctx *ctx, float *theta);
 
+/* set_precision -- arithmetic of the network's inference (mgm_cnn_apply and
+ * the initial guess): MGM_PREC_FP32 (default) or MGM_PREC_FP16 (FP16 weights
+ * and activations on the FP16 matrix cores, FP32 accumulation).  Training
+ * (loss_grad, train_step, train) always runs in FP32 on the FP32 master
+ * parameters.  Needs mgm_cnn_set_params first. */
+int mgm_cnn_set_precision(mgm_ctx *ctx, int precision);
+
 /* apply -- y = f(b) for nb level-0 vectors of gauge field gauge_id (its
  * lattice size and boundary condition); b, y: DEVICE complex128 [nb][n0]. */
 int mgm_cnn_apply(mgm_ctx *ctx, int gauge_id, int nb, const void *b, void *y);

@@ -143,6 +143,7 @@ SIGNATURES = {
                                          C.POINTER(C.c_int)]),
     "mgm_cnn_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "mgm_cnn_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "mgm_cnn_set_precision": (C.c_int, [_P, C.c_int]),
     "mgm_cnn_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
     "mgm_cnn_loss_grad": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_double),
                                     C.POINTER(C.c_float)]),
@@ -381,6 +382,9 @@ class Context:
             raise ValueError(f"expected {CNN_NPARAMS} parameters, got {th.shape}")
         self._chk(self.lib.mgm_cnn_set_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float))),
                   "cnn_set_params")
+
+    def cnn_set_precision(self, precision: str):
+        self._chk(self.lib.mgm_cnn_set_precision(self.h, PRECISIONS[precision]), "cnn_set_precision")
 
     def cnn_get_params(self):
         import numpy as np

@@ -609,6 +609,14 @@ int mgm_cnn_set_params(mgm_ctx* c, const float* theta) {
   });
 }
 
+int mgm_cnn_set_precision(mgm_ctx* c, int precision) {
+  return guarded(c, [&] {
+    require(precision == MGM_PREC_FP32 || precision == MGM_PREC_FP16, "network precision must be FP32 or FP16");
+    cnn_of(c).half = precision == MGM_PREC_FP16;
+    return MGM_OK;
+  });
+}
+
 int mgm_cnn_get_params(mgm_ctx* c, float* theta) {
   return guarded(c, [&] {
     require(theta != nullptr, "null pointer");

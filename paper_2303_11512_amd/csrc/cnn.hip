@@ -135,6 +135,106 @@ __global__ void __launch_bounds__(CNT) k_conv(const float* __restrict__ in, int 
   }
 }
 
+// The same convolution with FP16 activations and weights on the 16x16x16
+// FP16 matrix cores (FP32 accumulation; bias, tanh and the output rounding in
+// FP32 -> FP16).  Lane l supplies A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16];
+// element v of its result is D[4(l/16) + v][l%16].  K index k = tap * CIN + ch
+// in chunks of 16 (padded with zeros past 9 * CIN).
+typedef _Float16 hv4 __attribute__((ext_vector_type(4)));
+
+template <int C>
+__device__ __forceinline__ void load_tile_h(const _Float16* __restrict__ in, int Lx, int Lt, int anti, int b,
+                                            int t0, int x0, _Float16* xs) {
+  constexpr int S = C + 4;  // site stride in LDS (halves): 8-byte aligned rows of 4
+  const _Float16* base = in + (int64_t)b * Lx * Lt * C;
+  for (int e = threadIdx.x; e < HE * HE * C; e += CNT) {
+    const int site = e / C, ch = e - site * C;
+    const int r = site / HE, cc = site - r * HE;
+    int t = t0 + r - 1, x = x0 + cc - 1;
+    bool neg = false;
+    if (t < 0) {
+      t += Lt;
+      neg = anti;
+    } else if (t >= Lt) {
+      t -= Lt;
+      neg = anti;
+    }
+    if (x < 0)
+      x += Lx;
+    else if (x >= Lx)
+      x -= Lx;
+    const _Float16 v = base[((int64_t)t * Lx + x) * C + ch];
+    xs[site * S + ch] = neg ? (_Float16)(-v) : v;
+  }
+}
+
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(CNT) k_conv_h(const _Float16* __restrict__ in, int Lx, int Lt, int anti,
+                                                const _Float16* __restrict__ wp, const float* __restrict__ bias,
+                                                _Float16* __restrict__ out) {
+  constexpr int K = 9 * CIN;
+  constexpr int KC = (K + 15) / 16;  // 16-wide K chunks
+  constexpr int KS = KC * 16 + 4;    // LDS row stride of the weights (halves)
+  constexpr int S = CIN + 4;
+  constexpr int NB = (COUT + 15) / 16;
+  __shared__ __attribute__((aligned(16))) _Float16 xs[HE * HE * S];
+  __shared__ __attribute__((aligned(16))) _Float16 ws[COUT * KS];
+  const int x0 = blockIdx.x * TE, t0 = blockIdx.y * TE, b = blockIdx.z;
+  load_tile_h<CIN>(in, Lx, Lt, anti, b, t0, x0, xs);
+  for (int e = threadIdx.x; e < COUT * KC * 16; e += CNT) {
+    const int n = e / (KC * 16), k = e - n * KC * 16;
+    ws[n * KS + k] = k < K ? wp[n * K + k] : (_Float16)0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v acc[4][NB];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < KC; ++kc) {
+    const int k = kc * 16 + 4 * q;  // this lane's 4 consecutive K indices
+    hv4 bw[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int n = nb * 16 + i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bw[nb][j] = n < COUT ? ws[n * KS + k + j] : (_Float16)0;
+    }
+    const bool inK = k < K;
+    const int tap = inK ? k / CIN : 0, ch = inK ? k - tap * CIN : 0;
+    const int dt = tap / 3, dx = tap - 3 * dt;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      hv4 a;
+      const _Float16* xr = xs + ((wave * 4 + rr + dt) * HE + i + dx) * S + ch;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = inK ? xr[j] : (_Float16)0;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[rr][nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bw[nb], acc[rr][nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int n = nb * 16 + i;
+    if (n >= COUT) continue;
+    const float bn = bias[n];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t row = ((int64_t)b * Lt + t0 + wave * 4 + rr) * Lx + x0 + 4 * q;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float z = acc[rr][nb][v] + bn;
+        if (EPI == EPI_TANH) z = tanhf(z);
+        out[(row + v) * COUT + n] = (_Float16)z;
+      }
+    }
+  }
+}
+
 // Partial weight and bias gradients of one layer over the tiles a workgroup
 // visits: part[wg][co][k] = sum_sites G[site][co] X[site + off(tap)][c] for
 // k = tap*CIN + c < 9*CIN, and sum_sites G[site][co] for k = 9*CIN.  The
@@ -242,6 +342,12 @@ __global__ void __launch_bounds__(CNT) k_pack(const float* __restrict__ W, int c
   const float w = W[e];
   wf[co * 9 * cin + tap * cin + ci] = w;
   wb[ci * 9 * cout + (8 - tap) * cout + co] = w;
+}
+
+__global__ void __launch_bounds__(CNT) k_pack_half(const float* __restrict__ wf, int cnt,
+                                                   _Float16* __restrict__ wh) {
+  const int e = blockIdx.x * CNT + threadIdx.x;
+  if (e < cnt) wh[e] = (_Float16)wf[e];
 }
 
 __global__ void __launch_bounds__(CNT) k_adam(float* __restrict__ th, float* __restrict__ m,
@@ -390,6 +496,7 @@ void Cnn::init() {
     const size_t w = sizeof(float) * 9 * WIDTH[l] * WIDTH[l + 1];
     wf[l].ensure(w);
     wb[l].ensure(w);
+    wh[l].ensure(w / 2);
   }
 }
 
@@ -399,6 +506,8 @@ void Cnn::pack(hipStream_t s) {
     hipLaunchKernelGGL(k_pack, dim3(blocks_for(9 * cin * cout)), dim3(CNT), 0, s,
                        theta.as<float>() + param_offset(l), cin, cout, wf[l].as<float>(),
                        wb[l].as<float>());
+    hipLaunchKernelGGL(k_pack_half, dim3(blocks_for(9 * cin * cout)), dim3(CNT), 0, s, wf[l].as<float>(),
+                       9 * cin * cout, wh[l].as<_Float16>());
     KCHK();
   }
 }
@@ -533,13 +642,48 @@ void cnn_from_channels(hipStream_t s, const float* in, int64_t ndof, cd* out) {
   KCHK();
 }
 
+// FP16 forward pass: x0 and y are FP16 channel-last [nb][V][4]; the hidden
+// activations go to w.h[0..1] (ping-pong).
+void cnn_forward_h(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const _Float16* x0, CnnWork& w,
+                   _Float16* y) {
+  const int64_t V = (int64_t)g.Lx * g.Lt;
+  for (int l = 0; l < 2; ++l) w.h[l].ensure(sizeof(_Float16) * nb * V * 32);
+  _Float16* h0 = w.h[0].as<_Float16>();
+  _Float16* h1 = w.h[1].as<_Float16>();
+  const dim3 grid(g.Lx / TE, g.Lt / TE, nb);
+  hipLaunchKernelGGL((k_conv_h<4, 32, EPI_TANH>), grid, dim3(CNT), 0, s, x0, g.Lx, g.Lt, g.anti,
+                     net.wh[0].as<_Float16>(), net.bias(0), h0);
+  hipLaunchKernelGGL((k_conv_h<32, 32, EPI_TANH>), grid, dim3(CNT), 0, s, h0, g.Lx, g.Lt, g.anti,
+                     net.wh[1].as<_Float16>(), net.bias(1), h1);
+  hipLaunchKernelGGL((k_conv_h<32, 32, EPI_TANH>), grid, dim3(CNT), 0, s, h1, g.Lx, g.Lt, g.anti,
+                     net.wh[2].as<_Float16>(), net.bias(2), h0);
+  hipLaunchKernelGGL((k_conv_h<32, 4, EPI_NONE>), grid, dim3(CNT), 0, s, h0, g.Lx, g.Lt, g.anti,
+                     net.wh[3].as<_Float16>(), net.bias(3), y);
+  KCHK();
+}
+
 // y = f(b) for complex128 vectors, in RHS chunks that keep the hidden
-// activations under ~512 MB.
+// activations under ~512 MB; FP32 or FP16 network (net.half).
 void cnn_apply(hipStream_t s, const Cnn& net, const Gauge& g, int nrhs, const cd* b, cd* y,
                CnnWork& w) {
   cnn_check_lattice(g);
   const int64_t V = (int64_t)g.Lx * g.Lt, n = 2 * V;
   const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, (int64_t(512) << 20) / (V * 32 * 4)));
+  if (net.half) {
+    w.hx0.ensure(sizeof(_Float16) * chunk * V * 4);
+    w.hy.ensure(sizeof(_Float16) * chunk * V * 4);
+    for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+      const int k = std::min(chunk, nrhs - r0);
+      hipLaunchKernelGGL((k_cast<double, _Float16>), dim3(blocks_for(2 * (int64_t)k * n)), dim3(CNT), 0, s,
+                         reinterpret_cast<const double*>(b + (int64_t)r0 * n), w.hx0.as<_Float16>(),
+                         2 * (int64_t)k * n);
+      cnn_forward_h(s, net, g, k, w.hx0.as<_Float16>(), w, w.hy.as<_Float16>());
+      hipLaunchKernelGGL((k_cast<_Float16, double>), dim3(blocks_for(2 * (int64_t)k * n)), dim3(CNT), 0, s,
+                         w.hy.as<_Float16>(), reinterpret_cast<double*>(y + (int64_t)r0 * n), 2 * (int64_t)k * n);
+      KCHK();
+    }
+    return;
+  }
   w.x0.ensure(sizeof(float) * chunk * V * 4);
   w.y.ensure(sizeof(float) * chunk * V * 4);
   for (int r0 = 0; r0 < nrhs; r0 += chunk) {

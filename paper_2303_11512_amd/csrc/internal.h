@@ -347,9 +347,10 @@ struct GraphEntry {
 // gradient) and the per-layer packed weights the convolution kernels read.
 struct Cnn {
   DevBuf theta, m, v, grad;
-  DevBuf wf[4], wb[4];
+  DevBuf wf[4], wb[4], wh[4];  // FP32 forward / transposed, FP16 forward copies
   int64_t t = 0;  // Adam steps taken
   bool ready = false;
+  bool half = false;  // inference (mgm_cnn_apply, initial guess) in FP16
   void init();
   void pack(hipStream_t s);
   const float* bias(int l) const;
@@ -358,6 +359,7 @@ struct Cnn {
 // Per-field network workspaces (activations of the RHS chunk in flight).
 struct CnnWork {
   DevBuf x0, y, gy, a[3], g[2], part, lpart, mr;
+  DevBuf hx0, hy, h[2];  // FP16 inference buffers
   DevBuf pairs_b, pairs_x, batch_b, batch_x, idx;
 };
 

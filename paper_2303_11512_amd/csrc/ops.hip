@@ -623,7 +623,9 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
-  // the second product's operands are loaded first (latency overlaps the hops)
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  // the block solve's operands, loaded after the hops
   cx<T> rv[4], a[4];
   if (wave == 0) {
     const cx<T>* Iu = inv + (u * CM + i) * CM;
@@ -634,8 +636,6 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
       a[c] = Iu[k];
     }
   }
-  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
   if (!reduce_waves(acc, red, wave, lane)) return;
   // t = r_u - (hops) in the result layout: element c = row out_row(lane, c)
   cx<T> t[4];
@@ -719,8 +719,10 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
-  // the second product's operands are loaded first, so that their latency
-  // overlaps the hops
+  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  // the block solve's operands are loaded after the hops (measured faster
+  // than loading them first)
   cf rv[4];
   chalf iv[4];
   if (wave == 0) {
@@ -731,8 +733,6 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
       iv[j] = Iu[j];
     }
   }
-  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
   if (!reduce_waves(acc, red, wave, lane)) return;
   // t = r_u - hops: element j of this lane is row 4q + j, which is also the
   // B operand layout of the next product
@@ -751,66 +751,109 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   for (int v = 0; v < 4; ++v) x[(int64_t)r * n + u * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
 }
 
-// Two-site blocks along x with FP16 blocks (see k_sap2_mfma).
+// Two-site blocks along x with FP16 blocks (see k_sap2_mfma).  Each wave loads
+// its hop blocks, then the x operands, and only after its hops the operands of
+// the block solve (waves 0 and 1).
 __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, const chalf* __restrict__ inv,
                                                int Nx, int Nt, const int* __restrict__ blist, int nrhs,
                                                const cf* __restrict__ rr, cf* __restrict__ x,
                                                const int* __restrict__ active) {
-  __shared__ float red[4][8][64];
+  constexpr int RT = 1;  // RHS tiles of 16 per workgroup (2 and 4 measured slower)
+  __shared__ float red[RT][4][8][64];
   const int blk = blist[blockIdx.x];
   const int NBx = Nx / 2;
   const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
-  const int r0 = blockIdx.y * 16;
-  const int r = r0 + i;
-  const bool ok = r < nrhs;
-  const int64_t rrow = ok ? r : r0;
-  cf rv[2][4];
-  chalf iv[2][4];
-  if (wave < 2) {
-    const chalf* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32 + 4 * q;
+  // hop directions of this wave (u0: -x, +t | -t; u1: +x, +t | -t)
+  const int64_t us = wave < 2 ? u0 : u1;
+  const int nh = (wave == 0 || wave == 2) ? 2 : 1;
+  const int dirs[2] = {wave == 0 ? 2 : (wave == 2 ? 1 : 4), 3};
+  h4 bar[2], bai[2];
+  int64_t nbo[2];
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+    if (hh >= nh) break;
+    const chalf* row = B + ((us * 5 + dirs[hh]) * CM + i) * CM + 4 * q;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      rv[0][j] = ok ? rr[rrow * n + u0 * CM + 4 * q + j] : mk<float>(0, 0);
-      rv[1][j] = ok ? rr[rrow * n + u1 * CM + 4 * q + j] : mk<float>(0, 0);
-      iv[0][j] = Ih[j];
-      iv[1][j] = Ih[16 + j];
+      bar[hh][j] = row[j].re;
+      bai[hh][j] = row[j].im;
     }
-  }
-  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  const int64_t us = wave < 2 ? u0 : u1;
-  if (wave == 0 || wave == 2) {
-    coarse_hop_h(B, x, n, us, wave == 0 ? 2 : 1, Nx, Nt, rrow, ok, lane, acc);
-    coarse_hop_h(B, x, n, us, 3, Nx, Nt, rrow, ok, lane, acc);
-  } else {
-    coarse_hop_h(B, x, n, us, 4, Nx, Nt, rrow, ok, lane, acc);
+    nbo[hh] = nb_site(us, dirs[hh], Nx, Nt) * CM + 4 * q;
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    red[wave][v][lane] = acc.re[v];
-    red[wave][4 + v][lane] = acc.im[v];
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r0 = (blockIdx.y * RT + rt) * 16;
+    const int r = r0 + i;
+    const bool ok = r < nrhs;
+    const int64_t rrow = ok ? r : 0;
+    CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      if (hh >= nh) break;
+      const cf* xv = x + rrow * n + nbo[hh];
+      h4 br, bi;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cf v = ok ? xv[j] : mk<float>(0, 0);
+        br[j] = (_Float16)v.re;
+        bi[j] = (_Float16)v.im;
+      }
+      hmma(bar[hh], bai[hh], br, bi, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[rt][wave][v][lane] = acc.re[v];
+      red[rt][wave][4 + v][lane] = acc.im[v];
+    }
+  }
+  if (wave >= 2) {
+    __syncthreads();
+    return;
+  }
+  h4 iar[2], iai[2];
+  const chalf* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32 + 4 * q;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    iar[0][j] = Ih[j].re;
+    iai[0][j] = Ih[j].im;
+    iar[1][j] = Ih[16 + j].re;
+    iai[1][j] = Ih[16 + j].im;
+  }
+  cf rv[RT][2][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = (blockIdx.y * RT + rt) * 16 + i;
+    const bool ok = r < nrhs;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rv[rt][0][j] = ok ? rr[(int64_t)r * n + u0 * CM + 4 * q + j] : mk<float>(0, 0);
+      rv[rt][1][j] = ok ? rr[(int64_t)r * n + u1 * CM + 4 * q + j] : mk<float>(0, 0);
+    }
   }
   __syncthreads();
-  if (wave >= 2) return;
-  CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-  for (int sidx = 0; sidx < 2; ++sidx) {
-    h4 tr, ti, ar, ai;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      tr[j] = (_Float16)(rv[sidx][j].re - red[2 * sidx][j][lane] - red[2 * sidx + 1][j][lane]);
-      ti[j] = (_Float16)(rv[sidx][j].im - red[2 * sidx][4 + j][lane] - red[2 * sidx + 1][4 + j][lane]);
-      ar[j] = iv[sidx][j].re;
-      ai[j] = iv[sidx][j].im;
-    }
-    hmma(ar, ai, tr, ti, cor);
-  }
-  if (!ok || (active && !active[r])) return;
   const int64_t uo = wave == 0 ? u0 : u1;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) x[(int64_t)r * n + uo * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = (blockIdx.y * RT + rt) * 16 + i;
+    CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      h4 tr, ti;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        tr[j] = (_Float16)(rv[rt][sidx][j].re - red[rt][2 * sidx][j][lane] - red[rt][2 * sidx + 1][j][lane]);
+        ti[j] = (_Float16)(rv[rt][sidx][j].im - red[rt][2 * sidx][4 + j][lane] - red[rt][2 * sidx + 1][4 + j][lane]);
+      }
+      hmma(iar[sidx], iai[sidx], tr, ti, cor);
+    }
+    if (r < nrhs && !(active && !active[r])) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[(int64_t)r * n + uo * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(NT) k_to_half(const cd* __restrict__ in, chalf* __restrict__ out,
@@ -841,19 +884,6 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
   const int r = r0 + i;
   const bool ok = r < nrhs;
   const int64_t rrow = ok ? r : r0;
-  // operands of the block solve, loaded first (waves 0 and 1: row half = wave)
-  cx<T> rv[2][4], a[2][4];
-  if (wave < 2) {
-    const cx<T>* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = MF<T>::out_row(lane, c);
-      rv[0][c] = ok ? rr[rrow * n + u0 * CM + k] : mk<T>(0, 0);
-      rv[1][c] = ok ? rr[rrow * n + u1 * CM + k] : mk<T>(0, 0);
-      a[0][c] = Ih[k];
-      a[1][c] = Ih[16 + k];
-    }
-  }
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   const int64_t us = wave < 2 ? u0 : u1;
   if (wave == 0 || wave == 2) {
@@ -866,6 +896,20 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
   for (int v = 0; v < 4; ++v) {
     red[wave][v][lane] = acc.re[v];
     red[wave][4 + v][lane] = acc.im[v];
+  }
+  // operands of the block solve, loaded after the hops (waves 0 and 1: row
+  // half = wave)
+  cx<T> rv[2][4], a[2][4];
+  if (wave < 2) {
+    const cx<T>* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = MF<T>::out_row(lane, c);
+      rv[0][c] = ok ? rr[rrow * n + u0 * CM + k] : mk<T>(0, 0);
+      rv[1][c] = ok ? rr[rrow * n + u1 * CM + k] : mk<T>(0, 0);
+      a[0][c] = Ih[k];
+      a[1][c] = Ih[16 + k];
+    }
   }
   __syncthreads();
   if (wave >= 2) return;

@@ -56,6 +56,26 @@ def test_forward_matches_oracle(ctx, Lx, Lt, anti, nb):
     assert err < 2e-6, err
 
 
+@pytest.mark.parametrize("Lx,Lt,anti", [(16, 16, True), (32, 16, False)])
+def test_fp16_forward_matches_oracle(ctx, Lx, Lt, anti):
+    """FP16 weights and activations (FP32 accumulation): within FP16 rounding
+    of the FP64 oracle network."""
+    gid, _ = _field(ctx, Lx, Lt, anti, 15)
+    theta = _theta(7)
+    ctx.cnn_set_params(theta)
+    ctx.cnn_set_precision("fp16")
+    try:
+        b = rhs_vectors(2 * Lx * Lt, 3, 5) * 0.7
+        y = empty(3, 2 * Lx * Lt)
+        ctx.cnn_apply(gid, to_dev(b), y)
+        want = _oracle_y(theta, b, Lx, Lt, anti)
+        err = np.linalg.norm(to_host(y) - want) / np.linalg.norm(want)
+        log(f"fp16 forward rel. error {err:.2e}")
+        assert 1e-6 < err < 1e-2, err
+    finally:
+        ctx.cnn_set_precision("fp32")
+
+
 @pytest.mark.parametrize("anti", [True, False])
 def test_loss_and_gradient_match_oracle(ctx, anti):
     Lx, Lt, nb = 32, 16, 3
@@ -125,20 +145,26 @@ def test_training_lowers_the_loss(trained):
     assert losses[-1] < 0.9 * losses[0]
 
 
-def test_solves_from_the_guess_meet_the_tolerance(ctx, trained):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_solves_from_the_guess_meet_the_tolerance(ctx, trained, precision):
     from paper_2303_11512_amd import solve_params
     rec, gid, _ = trained
     D = dirac.wilson_dirac(rec.theta, rec.m0)
     n = D.shape[0]
     b = rhs_vectors(n, 12, 901)
     out = {}
-    for use in (False, True):
-        x = empty(12, n)
-        _, its, _ = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=16, use_cnn=use))
-        xh = to_host(x)
-        res = np.linalg.norm(b - (D @ xh.T).T, axis=1) / np.linalg.norm(b, axis=1)
-        assert np.all(res <= 1e-10), (use, res)
-        out[use] = its
+    ctx.cnn_set_precision(precision)
+    try:
+        for use in (False, True):
+            x = empty(12, n)
+            _, its, _ = ctx.solve_batch(gid, 0, to_dev(b), x,
+                                        solve_params(tol=1e-10, restart=16, use_cnn=use))
+            xh = to_host(x)
+            res = np.linalg.norm(b - (D @ xh.T).T, axis=1) / np.linalg.norm(b, axis=1)
+            assert np.all(res <= 1e-10), (use, res)
+            out[use] = its
+    finally:
+        ctx.cnn_set_precision("fp32")
     log(f"iterations plain {np.mean(out[False]):.2f} with guess {np.mean(out[True]):.2f}")
 
 
