@@ -387,7 +387,7 @@ def run_cnn(args):
     print(json.dumps({
         "metric": "RHS solves/s (tol 1e-10) from the learned initial guess", "value": nrhs * len(rows) / t_cnn,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_cnn * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+f16",
         "data": "synthetic",
         "config": {"workload": f"cnn: train on {len(train)} quenched 128^2 fields (beta 3.0, m0 -0.10, "
                                f"{args.pairs} Z2xZ2 pairs each, {args.epochs} epochs, batch 64, Adam 1e-3); "
