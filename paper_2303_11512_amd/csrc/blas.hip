@@ -68,55 +68,98 @@ __device__ __forceinline__ T block_sum_real(T v, T* sh) {
   return r;
 }
 
-// partial[(r*nv + i)*nch + chunk] = sum_{k in chunk} conj(V_i[r][k]) w[r][k]
+// partial[(r*nv + i)*nch + chunk] = sum_{k in chunk} conj(V_i[r][k]) w[r][k].
+// Vectors go in groups of DG so that DG * EPT loads are in flight at once; each
+// wave reduces its share with shuffles only and the four wave sums meet in LDS
+// once per 64 vectors (one barrier pair instead of one per vector).
+constexpr int DG = 4;
+
 template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                   int nv, const cx<T>* __restrict__ w, int64_t n,
                                                   cx<T>* __restrict__ partial,
                                                   const int* __restrict__ active) {
   constexpr int CH = NT * EPT;
-  __shared__ T sh[8];
+  __shared__ cx<T> sh[4][64];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   const int nch = gridDim.x;
+  const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
   const cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
   cx<T> wv[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
     wv[e] = (k < n) ? wr[k] : mk<T>(0, 0);
   }
-  for (int i = 0; i < nv; ++i) {
-    const cx<T>* __restrict__ vi = V + (int64_t)i * sI + (int64_t)r * sR;
-    cx<T> acc = mk<T>(0, 0);
+  auto put = [&](int slot, cx<T> acc) {
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) sh[wv_id][slot] = acc;
+  };
+  for (int i0 = 0; i0 < nv; i0 += 64) {
+    const int nb = min(64, nv - i0);
+    int j = 0;
+    for (; j + DG <= nb; j += DG) {
+      cx<T> acc[DG];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int64_t k = base + (int64_t)e * NT;
-      if (k < n) cjfma(acc, vi[k], wv[e]);
+      for (int g = 0; g < DG; ++g) {
+        const cx<T>* __restrict__ vi = Vr + (int64_t)(i0 + j + g) * sI;
+        acc[g] = mk<T>(0, 0);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int64_t k = base + (int64_t)e * NT;
+          if (k < n) cjfma(acc[g], vi[k], wv[e]);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < DG; ++g) put(j + g, acc[g]);
     }
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[((int64_t)r * nv + i) * nch + blockIdx.x] = acc;
+    for (; j < nb; ++j) {
+      const cx<T>* __restrict__ vi = Vr + (int64_t)(i0 + j) * sI;
+      cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = base + (int64_t)e * NT;
+        if (k < n) cjfma(acc, vi[k], wv[e]);
+      }
+      put(j, acc);
+    }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      const int t = threadIdx.x;
+      partial[((int64_t)r * nv + i0 + t) * nch + blockIdx.x] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    }
+    __syncthreads();
   }
 }
 
-// out[r*ldo + i] (=|+=) sum_chunks partial
+// out[r*ldo + i] (=|+=) sum_chunks partial: one wave per output, lane l adds
+// chunks l, l+64, ... in order, then a fixed shuffle tree.
 template <class T>
 __global__ void __launch_bounds__(NT) k_reduce_chunks(const cx<T>* __restrict__ partial, int nv, int nch,
                                                       int nrhs, cx<T>* __restrict__ out, int ldo,
                                                       int accumulate, const int* __restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t t = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (t >= (int64_t)nv * nrhs) return;
   const int r = (int)(t / nv), i = (int)(t % nv);
   if (active && !active[r]) return;
   const cx<T>* p = partial + ((int64_t)r * nv + i) * nch;
   cx<T> acc = mk<T>(0, 0);
-  for (int c = 0; c < nch; ++c) acc = acc + p[c];
-  cx<T>* o = out + (int64_t)r * ldo + i;
-  *o = accumulate ? (*o + acc) : acc;
+  for (int c = lane; c < nch; c += 64) acc = acc + p[c];
+  acc.re = wave_sum(acc.re);
+  acc.im = wave_sum(acc.im);
+  if (lane == 0) {
+    cx<T>* o = out + (int64_t)r * ldo + i;
+    *o = accumulate ? (*o + acc) : acc;
+  }
 }
 
-// w[r] += sign * sum_i V_i[r] coef[r*ldc + i]; optional partial |w|^2 per chunk
+// w[r] += sign * sum_i V_i[r] coef[r*ldc + i]; optional partial |w|^2 per chunk.
+// Vectors are added in index order, a few of them loaded together.
 template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                      int nv, const cx<T>* __restrict__ coef, int ldc,
@@ -134,14 +177,35 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
   cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
   cx<T> acc[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
     acc[e] = (k < n) ? wr[k] : mk<T>(0, 0);
   }
-  for (int i = 0; i < nv; ++i) {
-    const cx<T>* __restrict__ vi = V + (int64_t)i * sI + (int64_t)r * sR;
+  constexpr int G = EPT >= 8 ? 2 : DG;  // G * EPT loads in flight, within the register budget
+  int i = 0;
+  for (; i + G <= nv; i += G) {
+    cx<T> vv[G][EPT];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const cx<T>* __restrict__ vi = Vr + (int64_t)(i + g) * sI;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = base + (int64_t)e * NT;
+        vv[g][e] = (k < n) ? vi[k] : mk<T>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const cx<T> c = cs[i + g];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) cfma(acc[e], vv[g][e], c);
+    }
+  }
+  for (; i < nv; ++i) {
+    const cx<T>* __restrict__ vi = Vr + (int64_t)i * sI;
     const cx<T> c = cs[i];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -184,15 +248,18 @@ __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w
   if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = acc;
 }
 
+// out[r] = sqrt(sum_chunks partial): one wave per RHS, as k_reduce_chunks.
 template <class T>
 __global__ void __launch_bounds__(NT) k_norm_reduce(const T* __restrict__ partial, int nch, int nrhs,
                                                     T* __restrict__ out, const int* __restrict__ active) {
-  const int r = blockIdx.x * NT + threadIdx.x;
+  const int r = (int)(((int64_t)blockIdx.x * NT + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   if (r >= nrhs) return;
   if (active && !active[r]) return;
   T acc = 0;
-  for (int c = 0; c < nch; ++c) acc += partial[(int64_t)r * nch + c];
-  out[r] = sqrt(acc);
+  for (int c = lane; c < nch; c += 64) acc += partial[(int64_t)r * nch + c];
+  acc = wave_sum(acc);
+  if (lane == 0) out[r] = sqrt(acc);
 }
 
 template <class T>
@@ -475,7 +542,7 @@ void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                                        nv, w, n, partial, active));
   KCHK();
   const int64_t tot = (int64_t)nv * nrhs;
-  hipLaunchKernelGGL(k_reduce_chunks<T>, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, s, partial,
+  hipLaunchKernelGGL(k_reduce_chunks<T>, dim3((unsigned)((tot + 3) / 4)), dim3(NT), 0, s, partial,
                      nv, (int)nch, nrhs, out, ldo, accumulate, active);
   KCHK();
 }
@@ -493,7 +560,7 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                                        active, nlim));
   KCHK();
   if (norm_out) {
-    hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
+    hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch,
                        nrhs, norm_out, active);
     KCHK();
   }
@@ -507,7 +574,7 @@ void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, con
   EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, w, n,
                                        partial, active));
   KCHK();
-  hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch,
+  hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch,
                      nrhs, out, active);
   KCHK();
 }

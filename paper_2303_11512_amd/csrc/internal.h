@@ -59,6 +59,20 @@ __host__ __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
   return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 // acc += a * b
+// The chip hands workgroups to its eight XCDs round-robin by linear
+// workgroup id, and each XCD has its own L2.  xcd_tile(b, G) renumbers b in
+// [0, G) so that the ids one XCD receives cover one contiguous range of tiles;
+// neighbouring tiles, and the halo values they share, then meet in the same
+// L2 instead of being fetched from HBM once per XCD.  It is a bijection on
+// [0, G) for every G; the ranges line up with the XCDs exactly when the
+// grid's x extent is a multiple of eight.
+__host__ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+  constexpr int64_t NXCD = 8;
+  const int64_t q = G / NXCD, rem = G % NXCD;
+  const int64_t x = b % NXCD, loc = b / NXCD;
+  return x * q + (x < rem ? x : rem) + loc;
+}
+
 template <class T>
 __host__ __device__ __forceinline__ void cfma(cx<T>& acc, cx<T> a, cx<T> b) {
   acc.re += a.re * b.re - a.im * b.im;

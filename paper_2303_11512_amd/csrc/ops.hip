@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T di
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   const int64_t V = (int64_t)Lx * Lt;
-  const int64_t site = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t site = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (site >= V) return;
   const int xx = (int)(site % Lx), tt = (int)(site / Lx);
   const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(NT) k_stencil_lds(const cx<T>* __restrict__ B,
   __shared__ cx<T> BT[5 * M * M];
   __shared__ cx<T> XS[RPW * 5 * M];  // the five neighbour sites' dofs of RPW RHS
   const int tid = threadIdx.x;
-  const int64_t u = blockIdx.x;
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
   for (int e = tid; e < 5 * M * M; e += NT) {
     const int j = e % M, i = (e / M) % M, d = e / (M * M);
     BT[(d * M + j) * M + i] = B[u * 5 * M * M + e];
@@ -297,6 +297,76 @@ __global__ void __launch_bounds__(NT) k_prolong(const cx<T>* __restrict__ P, int
   for (int k = 0; k < ntv; ++k) cfma(acc, Pr[k], xv[k]);
   cx<T>* o = yf + (int64_t)r * n + row;
   *o = accumulate ? (*o + acc) : acc;
+}
+
+// The same two maps for a hierarchy shape fixed at compile time (M dofs per
+// site, BX x BT aggregates, NTV test vectors per chirality).  Every index is a
+// shift or a multiply and the row loop is unrolled, so a thread issues all of
+// its loads at once instead of one dependent round trip per aggregate row;
+// the generic kernels above are latency bound for exactly that reason.
+template <class T, int M, int BX, int BT, int NTV>
+__global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, int Nx, int Nt,
+                                                   const cx<T>* __restrict__ xf, cx<T>* __restrict__ xc,
+                                                   const int* __restrict__ active) {
+  constexpr int Mh = M / 2, NROW = BX * BT * Mh;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int NAx = Nx / BX;
+  const int64_t nc = (int64_t)NAx * (Nt / BT) * 2 * NTV;
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nc) return;
+  const int64_t Ac = idx / NTV;  // aggregate * 2 + chirality
+  const int k = (int)(idx % NTV);
+  const int64_t A = Ac / 2;
+  const int c = (int)(Ac % 2);
+  const int Ax = (int)(A % NAx), At = (int)(A / NAx);
+  const cx<T>* __restrict__ xr =
+      xf + (int64_t)r * Nx * Nt * M + ((int64_t)At * BT * Nx + (int64_t)Ax * BX) * M + c * Mh;
+  const cx<T>* __restrict__ Pc = P + Ac * NROW * NTV + k;
+  cx<T> pv[NROW], xv[NROW];
+#pragma unroll
+  for (int s = 0; s < NROW; ++s) {
+    const int sl = s / Mh, a = s % Mh;
+    pv[s] = Pc[s * NTV];
+    xv[s] = xr[((int64_t)(sl / BX) * Nx + sl % BX) * M + a];
+  }
+  cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+  for (int s = 0; s < NROW; ++s) cjfma(acc, pv[s], xv[s]);
+  xc[(int64_t)r * nc + idx] = acc;
+}
+
+template <class T, int M, int BX, int BT, int NTV>
+__global__ void __launch_bounds__(NT) k_prolong_t(const cx<T>* __restrict__ P, int Nx, int Nt,
+                                                  const cx<T>* __restrict__ xc, cx<T>* __restrict__ yf,
+                                                  int accumulate, const int* __restrict__ active) {
+  constexpr int Mh = M / 2, NROW = BX * BT * Mh;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int64_t n = (int64_t)Nx * Nt * M;
+  const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (row >= n) return;
+  const int NAx = Nx / BX;
+  const int64_t nc = (int64_t)NAx * (Nt / BT) * 2 * NTV;
+  const int64_t site = row / M;
+  const int alpha = (int)(row % M);
+  const int c = alpha / Mh, a = alpha % Mh;
+  const int sx = (int)(site % Nx), st = (int)(site / Nx);
+  const int64_t Ac = ((int64_t)(st / BT) * NAx + sx / BX) * 2 + c;
+  const int s = ((st % BT) * BX + (sx % BX)) * Mh + a;
+  const cx<T>* __restrict__ Pr = P + (Ac * NROW + s) * NTV;
+  const cx<T>* __restrict__ xv = xc + (int64_t)r * nc + Ac * NTV;
+  cx<T> pv[NTV], cv[NTV];
+#pragma unroll
+  for (int k = 0; k < NTV; ++k) {
+    pv[k] = Pr[k];
+    cv[k] = xv[k];
+  }
+  cx<T>* o = yf + (int64_t)r * n + row;
+  cx<T> acc = accumulate ? *o : mk<T>(0, 0);
+#pragma unroll
+  for (int k = 0; k < NTV; ++k) cfma(acc, pv[k], cv[k]);
+  *o = acc;
 }
 
 // ------------------------------------------------------------------ Galerkin
@@ -465,7 +535,7 @@ __global__ void __launch_bounds__(NT) k_sap_sweep(const cx<T>* __restrict__ B,
   const int rpw = NT / K;
   const int tid = threadIdx.x;
   const int q = tid % K, rl = tid / K;
-  const int blk = blist[blockIdx.x];
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / sbx;
   const int ibx = blk % NBx, ibt = blk / NBx;
   // stage inv^T and the block's stencil rows (B^T per direction)
@@ -584,7 +654,7 @@ __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B
                                                      const cx<T>* __restrict__ b,
                                                      const int* __restrict__ active) {
   __shared__ T red[3][8][64];
-  const int64_t u = blockIdx.x;
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 16;
@@ -615,7 +685,7 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
                                                  const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
                                                  const int* __restrict__ active) {
   __shared__ T red[3][8][64];
-  const int64_t u = blist[blockIdx.x];
+  const int64_t u = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15;
@@ -686,7 +756,7 @@ __global__ void __launch_bounds__(NT) k_stencil_h(const chalf* __restrict__ B, i
                                                   const cf* __restrict__ x, cf* __restrict__ y,
                                                   const cf* __restrict__ b, const int* __restrict__ active) {
   __shared__ float red[3][8][64];
-  const int64_t u = blockIdx.x;
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 16;
@@ -711,7 +781,7 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
                                               const cf* __restrict__ rr, cf* __restrict__ x,
                                               const int* __restrict__ active) {
   __shared__ float red[3][8][64];
-  const int64_t u = blist[blockIdx.x];
+  const int64_t u = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
@@ -760,7 +830,7 @@ __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, cons
                                                const int* __restrict__ active) {
   constexpr int RT = 1;  // RHS tiles of 16 per workgroup (2 and 4 measured slower)
   __shared__ float red[RT][4][8][64];
-  const int blk = blist[blockIdx.x];
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / 2;
   const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
   const int64_t n = (int64_t)Nx * Nt * CM;
@@ -874,7 +944,7 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
                                                   const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
                                                   const int* __restrict__ active) {
   __shared__ T red[4][8][64];
-  const int blk = blist[blockIdx.x];
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / 2;
   const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
   const int64_t n = (int64_t)Nx * Nt * CM;
@@ -946,7 +1016,7 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   constexpr int SB = 4, NS = SB * SB, K = 2 * NS;
   __shared__ cx<T> Is[K * K];
   __shared__ cx<T> Bs[NS * 5 * 4];
-  const int blk = blist[blockIdx.x];
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / SB;
   const int bx = (blk % NBx) * SB, bt = (blk / NBx) * SB;
   for (int e = threadIdx.x; e < K * K; e += NT) Is[e] = inv[(int64_t)blk * K * K + e];
@@ -1522,8 +1592,13 @@ template <class T>
 void launch_restrict(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
                      int nrhs, const cx<T>* xf, cx<T>* xc, const int* active) {
   const int64_t nc = (int64_t)(Nx / bx) * (Nt / bt) * 2 * ntv;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(grid1(nc), nrhs), dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv,
-                     xf, xc, active);
+  const dim3 g(grid1(nc), nrhs);
+  if (M == 2 && bx == 4 && bt == 4 && ntv == 8)
+    hipLaunchKernelGGL((k_restrict_t<T, 2, 4, 4, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xf, xc, active);
+  else if (M == 16 && bx == 2 && bt == 2 && ntv == 8)
+    hipLaunchKernelGGL((k_restrict_t<T, 16, 2, 2, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xf, xc, active);
+  else
+    hipLaunchKernelGGL(k_restrict<T>, g, dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv, xf, xc, active);
   KCHK();
 }
 template void launch_restrict<double>(hipStream_t, const cd*, int, int, int, int, int, int, int,
@@ -1535,8 +1610,16 @@ template <class T>
 void launch_prolong(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int bx, int bt, int ntv,
                     int nrhs, const cx<T>* xc, cx<T>* yf, int accumulate, const int* active) {
   const int64_t n = (int64_t)Nx * Nt * M;
-  hipLaunchKernelGGL(k_prolong<T>, dim3(grid1(n), nrhs), dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv, xc,
-                     yf, accumulate, active);
+  const dim3 g(grid1(n), nrhs);
+  if (M == 2 && bx == 4 && bt == 4 && ntv == 8)
+    hipLaunchKernelGGL((k_prolong_t<T, 2, 4, 4, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xc, yf, accumulate,
+                       active);
+  else if (M == 16 && bx == 2 && bt == 2 && ntv == 8)
+    hipLaunchKernelGGL((k_prolong_t<T, 16, 2, 2, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xc, yf, accumulate,
+                       active);
+  else
+    hipLaunchKernelGGL(k_prolong<T>, g, dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv, xc, yf, accumulate,
+                       active);
   KCHK();
 }
 template void launch_prolong<double>(hipStream_t, const cd*, int, int, int, int, int, int, int,
