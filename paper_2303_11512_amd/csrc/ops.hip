@@ -7,6 +7,9 @@
 // index t * Nx + x).  The block stencil stores, per site u, five M x M blocks
 // B[u][d] (d = 0 self, 1 +x, 2 -x, 3 +t, 4 -t) with
 //     (D x)_u = sum_d B[u][d] x_{nb(u, d)},   periodic neighbours.
+#include <algorithm>
+#include <atomic>
+
 #include "internal.h"
 
 namespace mgm {
@@ -65,15 +68,59 @@ __global__ void __launch_bounds__(NT) k_noise(cx<T>* out, int64_t n, int kind, u
 //   -t: h = c0 - i c1, contributes (-h/2, -i h/2) * U^*
 // The antiperiodic t boundary is folded into the links.  y = D x, or
 // y = b - D x when b is given.
+// One site: o = own spinor, e/w = +x/-x neighbours with the links ue (own)
+// and uw (the -x neighbour's, conjugated inside), n/s = +t/-t neighbours with
+// un (own) and us (the -t neighbour's).
+template <class T>
+__device__ __forceinline__ void wilson_site(T diag, cx<T> o0, cx<T> o1, cx<T> e0, cx<T> e1, cx<T> ue,
+                                            cx<T> w0, cx<T> w1, cx<T> uw, cx<T> n0, cx<T> n1, cx<T> un,
+                                            cx<T> s0, cx<T> s1, cx<T> us, cx<T>& a0, cx<T>& a1) {
+  const T half = (T)0.5;
+  a0 = diag * o0;
+  a1 = diag * o1;
+  {
+    const cx<T> h = ue * (e0 - e1);
+    a0 = a0 - half * h;
+    a1 = a1 + half * h;
+  }
+  {
+    const cx<T> h = cjmul(uw, w0 + w1);
+    a0 = a0 - half * h;
+    a1 = a1 - half * h;
+  }
+  {
+    const cx<T> h = un * mk<T>(n0.re - n1.im, n0.im + n1.re);
+    a0 = a0 - half * h;
+    a1 = a1 + half * mk<T>(-h.im, h.re);
+  }
+  {
+    const cx<T> h = cjmul(us, mk<T>(s0.re + s1.im, s0.im - s1.re));
+    a0 = a0 - half * h;
+    a1 = a1 - half * mk<T>(-h.im, h.re);
+  }
+}
+
+// The output is written once and not read again by this kernel: streaming
+// stores keep it from displacing the input's halo rows in L2.
+template <class T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  __builtin_nontemporal_store(v.re, &p->re);
+  __builtin_nontemporal_store(v.im, &p->im);
+}
+
+// Thread per site, for any lattice.  The (tile, RHS) grid is renumbered as a
+// whole, so an XCD takes whole right-hand sides and their halos stay in its L2.
 template <class T>
 __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T diag, int Lx, int Lt,
                                                const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                const cx<T>* __restrict__ b,
                                                const int* __restrict__ active) {
-  const int r = blockIdx.y;
+  const int64_t G = gridDim.x;
+  const int64_t Lg = xcd_tile(blockIdx.x + G * blockIdx.y, G * gridDim.y);
+  const int r = (int)(Lg / G);
   if (active && !active[r]) return;
   const int64_t V = (int64_t)Lx * Lt;
-  const int64_t site = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  const int64_t site = (Lg % G) * NT + threadIdx.x;
   if (site >= V) return;
   const int xx = (int)(site % Lx), tt = (int)(site / Lx);
   const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
@@ -81,44 +128,78 @@ __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T di
   const int64_t sxm = (int64_t)tt * Lx + (xx == 0 ? Lx - 1 : xx - 1);
   const int64_t stp = (int64_t)(tt + 1 == Lt ? 0 : tt + 1) * Lx + xx;
   const int64_t stm = (int64_t)(tt == 0 ? Lt - 1 : tt - 1) * Lx + xx;
-  const cx<T>* __restrict__ U0 = U;
-  const cx<T>* __restrict__ U1 = U + V;
-  const T half = (T)0.5;
-
-  cx<T> a0 = diag * xr[2 * site];
-  cx<T> a1 = diag * xr[2 * site + 1];
-  {
-    const cx<T> c0 = xr[2 * sxp], c1 = xr[2 * sxp + 1];
-    const cx<T> h = U0[site] * (c0 - c1);
-    a0 = a0 - half * h;
-    a1 = a1 + half * h;
-  }
-  {
-    const cx<T> c0 = xr[2 * sxm], c1 = xr[2 * sxm + 1];
-    const cx<T> h = cjmul(U0[sxm], c0 + c1);
-    a0 = a0 - half * h;
-    a1 = a1 - half * h;
-  }
-  {
-    const cx<T> c0 = xr[2 * stp], c1 = xr[2 * stp + 1];
-    const cx<T> h = U1[site] * mk<T>(c0.re - c1.im, c0.im + c1.re);
-    a0 = a0 - half * h;
-    a1 = a1 + half * mk<T>(-h.im, h.re);
-  }
-  {
-    const cx<T> c0 = xr[2 * stm], c1 = xr[2 * stm + 1];
-    const cx<T> h = cjmul(U1[stm], mk<T>(c0.re + c1.im, c0.im - c1.re));
-    a0 = a0 - half * h;
-    a1 = a1 - half * mk<T>(-h.im, h.re);
-  }
+  cx<T> a0, a1;
+  wilson_site<T>(diag, xr[2 * site], xr[2 * site + 1], xr[2 * sxp], xr[2 * sxp + 1], U[site],
+                 xr[2 * sxm], xr[2 * sxm + 1], U[sxm], xr[2 * stp], xr[2 * stp + 1], U[V + site],
+                 xr[2 * stm], xr[2 * stm + 1], U[V + stm], a0, a1);
   cx<T>* yr = y + (int64_t)r * 2 * V;
   if (b) {
     const cx<T>* br = b + (int64_t)r * 2 * V;
     a0 = br[2 * site] - a0;
     a1 = br[2 * site + 1] - a1;
   }
-  yr[2 * site] = a0;
-  yr[2 * site + 1] = a1;
+  store_stream(yr + 2 * site, a0);
+  store_stream(yr + 2 * site + 1, a1);
+}
+
+// Row strips for lattices with Lx a multiple of 64 up to 256: a workgroup of
+// Lx threads (thread = column) walks TR consecutive time slices of one RHS.
+// Each spinor is loaded from global memory once per strip (plus the two rows
+// bordering it): the -t/own/+t rows roll through registers, and the +-x
+// neighbours of the current row come from a double-buffered LDS row, so one
+// barrier per row suffices (a buffer is rewritten two rows later, after every
+// thread has passed the barrier in between).
+template <class T, int TR>
+__global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U, T diag, int Lx, int Lt,
+                                                     const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                     const cx<T>* __restrict__ b,
+                                                     const int* __restrict__ active) {
+  __shared__ cx<T> sx[2][2][NT];
+  __shared__ cx<T> su[2][NT];
+  const int64_t G = gridDim.x;
+  const int64_t Lg = xcd_tile(blockIdx.x + G * blockIdx.y, G * gridDim.y);
+  const int r = (int)(Lg / G);
+  const int strip = (int)(Lg % G);
+  if (active && !active[r]) return;
+  const int64_t V = (int64_t)Lx * Lt;
+  const int xx = threadIdx.x;
+  const int xp = xx + 1 == Lx ? 0 : xx + 1, xm = xx == 0 ? Lx - 1 : xx - 1;
+  const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
+  const cx<T>* __restrict__ U1 = U + V;
+  cx<T>* __restrict__ yr = y + (int64_t)r * 2 * V;
+  const int t0 = strip * TR;
+  const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+  cx<T> m0 = xr[2 * ((int64_t)tm * Lx + xx)], m1 = xr[2 * ((int64_t)tm * Lx + xx) + 1];
+  cx<T> c0 = xr[2 * ((int64_t)t0 * Lx + xx)], c1 = xr[2 * ((int64_t)t0 * Lx + xx) + 1];
+  cx<T> u1m = U1[(int64_t)tm * Lx + xx];
+#pragma unroll 2
+  for (int i = 0; i < TR; ++i) {
+    const int t = t0 + i;
+    const int tp = t + 1 == Lt ? 0 : t + 1;
+    const int64_t site = (int64_t)t * Lx + xx;
+    const cx<T> p0 = xr[2 * ((int64_t)tp * Lx + xx)], p1 = xr[2 * ((int64_t)tp * Lx + xx) + 1];
+    const cx<T> u0 = U[site], u1 = U1[site];
+    const int bs = i & 1;
+    sx[bs][0][xx] = c0;
+    sx[bs][1][xx] = c1;
+    su[bs][xx] = u0;
+    __syncthreads();
+    cx<T> a0, a1;
+    wilson_site<T>(diag, c0, c1, sx[bs][0][xp], sx[bs][1][xp], u0, sx[bs][0][xm], sx[bs][1][xm],
+                   su[bs][xm], p0, p1, u1, m0, m1, u1m, a0, a1);
+    if (b) {
+      const cx<T>* br = b + (int64_t)r * 2 * V;
+      a0 = br[2 * site] - a0;
+      a1 = br[2 * site + 1] - a1;
+    }
+    yr[2 * site] = a0;
+    yr[2 * site + 1] = a1;
+    m0 = c0;
+    m1 = c1;
+    c0 = p0;
+    c1 = p1;
+    u1m = u1;
+  }
 }
 
 // The fine operator written as a block stencil (2x2 blocks), for the setup.
@@ -1514,12 +1595,52 @@ void launch_noise(hipStream_t s, cx<T>* out, int64_t n, int nrhs, int kind, uint
 template void launch_noise<double>(hipStream_t, cd*, int64_t, int, int, uint64_t, int, int, int64_t);
 template void launch_noise<float>(hipStream_t, cf*, int64_t, int, int, uint64_t, int, int, int64_t);
 
+// Workgroups of k_wilson_strip (128 threads, its LDS rows) the device keeps
+// resident at once, from the runtime's occupancy calculator; per device.
+template <class T>
+int64_t strip_capacity() {
+  static std::atomic<int64_t> cap[64];
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  require(dev >= 0 && dev < 64, "device index out of range");
+  int64_t c = cap[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    int per_cu = 0, cus = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_wilson_strip<T, 8>, 128, 0));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    c = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+    cap[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
 template <class T>
 void launch_wilson(hipStream_t s, const cx<T>* links, T diag, int Lx, int Lt, int nrhs,
                    const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active) {
   const int64_t V = (int64_t)Lx * Lt;
-  hipLaunchKernelGGL(k_wilson<T>, dim3(grid1(V), nrhs), dim3(NT), 0, s, links, diag, Lx, Lt, x, y, b,
-                     active);
+  if (Lx % 64 == 0 && Lx <= NT) {
+    // strip height: the smallest that keeps every workgroup resident at once
+    // (more, shorter strips hide more latency; a second round of workgroups
+    // costs more than it hides)
+    const int64_t cap = strip_capacity<T>();
+    int tr = 0;
+    for (int c : {1, 2, 4, 8, 16})
+      if (Lt % c == 0) {
+        tr = c;
+        if ((int64_t)(Lt / c) * nrhs <= cap) break;
+      }
+    const dim3 g(Lt / tr, nrhs), blk(Lx);
+    switch (tr) {
+      case 1: hipLaunchKernelGGL((k_wilson_strip<T, 1>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+      case 2: hipLaunchKernelGGL((k_wilson_strip<T, 2>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+      case 4: hipLaunchKernelGGL((k_wilson_strip<T, 4>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+      case 8: hipLaunchKernelGGL((k_wilson_strip<T, 8>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+      default: hipLaunchKernelGGL((k_wilson_strip<T, 16>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    }
+  } else {
+    hipLaunchKernelGGL(k_wilson<T>, dim3(grid1(V), nrhs), dim3(NT), 0, s, links, diag, Lx, Lt, x, y, b,
+                       active);
+  }
   KCHK();
 }
 template void launch_wilson<double>(hipStream_t, const cd*, double, int, int, int, const cd*, cd*,

@@ -32,8 +32,15 @@ def test_noise_bit_exact(ctx, kind):
         assert np.array_equal(got, want)
 
 
+# Lx a multiple of 64 (<= 256) takes the row-strip kernel, whose strip height
+# (1..16 rows) follows Lt and the RHS count: the cases below reach every height
+# on MI355X, including a ragged count of strips (Lt = 40) and the fallback
+# when no height keeps every workgroup resident (Lt = 12, 700 RHS).
 @pytest.mark.parametrize("Lx,Lt,nrhs,m0", [(8, 8, 1, -0.05), (10, 6, 5, 0.2), (34, 18, 3, -0.1),
-                                           (128, 128, 64, -0.1)])
+                                           (128, 128, 64, -0.1), (64, 64, 16, -0.1),
+                                           (192, 24, 7, 0.1), (64, 40, 200, -0.05),
+                                           (64, 256, 96, -0.1), (128, 12, 700, 0.0),
+                                           (256, 32, 3, -0.08)])
 def test_wilson_apply_matches_oracle(ctx, Lx, Lt, nrhs, m0):
     log(f"wilson apply {Lx}x{Lt} nrhs={nrhs}")
     th = metropolis_u1(Lx, Lt, 3.0, 30, 17 + Lx)
@@ -47,11 +54,13 @@ def test_wilson_apply_matches_oracle(ctx, Lx, Lt, nrhs, m0):
     assert rel_err(to_host(y), want) < 1e-14
 
 
-def test_wilson_periodic_bc(ctx):
-    th = metropolis_u1(8, 8, 2.0, 20, 3)
+@pytest.mark.parametrize("Lx,Lt", [(8, 8), (64, 16)])
+def test_wilson_periodic_bc(ctx, Lx, Lt):
+    th = metropolis_u1(Lx, Lt, 2.0, 20, 3)
     gid = ctx.set_gauge(to_dev(links_from_theta(th)), 0.3, False)
-    x = rhs_vectors(128, 2, 9)
-    y = empty(2, 128)
+    n = 2 * Lx * Lt
+    x = rhs_vectors(n, 2, 9)
+    y = empty(2, n)
     ctx.apply_D(gid, 0, to_dev(x), y)
     assert rel_err(to_host(y), (wilson_dirac(th, 0.3, bc_t_anti=False) @ x.T).T) < 1e-14
 
