@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U
       a0 = br[2 * site] - a0;
       a1 = br[2 * site + 1] - a1;
     }
-    yr[2 * site] = a0;
-    yr[2 * site + 1] = a1;
+    store_stream(yr + 2 * site, a0);
+    store_stream(yr + 2 * site + 1, a1);
     m0 = c0;
     m1 = c1;
     c0 = p0;
@@ -727,31 +727,73 @@ __device__ __forceinline__ bool reduce_waves(CAcc<T>& acc, T (*red)[8][64], int 
 }
 
 // y = D x or y = b - D x on a coarse level (16 dofs per site).  One workgroup
-// per (site, 16 RHS); wave w takes the hop in direction w + 1 (wave 0 also the
-// site's own block), and the partial tiles are summed in LDS.
+// per site.  The product is 5 blocks x 4 K-chunks = 20 chunk products per RHS
+// tile; wave w takes chunks 5w .. 5w+4 (in (direction, chunk) order), so the
+// four waves carry equal matrix-core work.  A wave keeps its five A operands
+// in registers and walks the RHS in tiles of 16, so each block is read once
+// per call.  The partial tiles meet in a double-buffered LDS area (one barrier
+// per tile); the next tile's x is loaded before that barrier.
 template <class T>
 __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B, int Nx, int Nt, int nrhs,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                      const cx<T>* __restrict__ b,
                                                      const int* __restrict__ active) {
-  __shared__ T red[3][8][64];
+  constexpr int QW = 5;  // chunk products per wave
+  __shared__ T red[2][3][8][64];
   const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.y * 16;
-  const int r = r0 + (lane & 15);
-  const bool ok = r < nrhs;
-  const int64_t rrow = ok ? r : r0;
-  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  coarse_hop(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
-  if (wave == 0) coarse_hop(B, x, n, u, 0, Nx, Nt, rrow, ok, lane, acc);
-  if (!reduce_waves(acc, red, wave, lane)) return;
-  if (!ok || (active && !active[r])) return;
+  const int i = lane & 15;
+  cx<T> a[QW], xq[QW];
+  int64_t xo[QW];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t o = (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
-    const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
-    y[o] = b ? b[o] - val : val;
+  for (int q = 0; q < QW; ++q) {
+    const int g = wave * QW + q, d = g >> 2;
+    const int k = MF<T>::out_row(lane, g & 3);
+    a[q] = B[((u * 5 + d) * CM + i) * CM + k];
+    xo[q] = nb_site(u, d, Nx, Nt) * CM + k;
+  }
+  auto load_x = [&](int r0) {
+    const int r = r0 + i;
+    const bool ok = r < nrhs;
+    const int64_t rrow = ok ? r : r0;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) xq[q] = ok ? x[rrow * n + xo[q]] : mk<T>(0, 0);
+  };
+  load_x(0);
+  const int ntile = (nrhs + 15) / 16;
+  for (int t = 0; t < ntile; ++t) {
+    CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int q = 0; q < QW; ++q) cmma(a[q], xq[q], acc);
+    if (t + 1 < ntile) load_x((t + 1) * 16);
+    T (*rb)[8][64] = red[t & 1];
+    if (wave > 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        rb[wave - 1][v][lane] = acc.re[v];
+        rb[wave - 1][4 + v][lane] = acc.im[v];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc.re[v] += rb[w][v][lane];
+          acc.im[v] += rb[w][4 + v][lane];
+        }
+      const int r = t * 16 + i;
+      if (r < nrhs && !(active && !active[r])) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t o = (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
+          const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
+          y[o] = b ? b[o] - val : val;
+        }
+      }
+    }
   }
 }
 
@@ -1185,15 +1227,24 @@ __global__ void __launch_bounds__(NT) k_dense_mfma(const cx<T>* __restrict__ A, 
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   const cx<T>* Ar = A + (i0 + i) * n;
   const cx<T>* xr = x + rrow * n;
-  for (int64_t k0 = kw0; k0 < kw1; k0 += 16) {
+  // SU 16-wide steps per round, all their loads issued before the products
+  // (steps past the wave's range load zeros)
+  constexpr int SU = sizeof(T) == 8 ? 2 : 4;
+  for (int64_t k0 = kw0; k0 < kw1; k0 += 16 * SU) {
+    cx<T> a[SU][4], xb[SU][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t k = k0 + MF<T>::out_row(lane, c);
-      const bool in = k < kw1;
-      const cx<T> a = in ? Ar[k] : mk<T>(0, 0);
-      const cx<T> xb = (ok && in) ? xr[k] : mk<T>(0, 0);
-      cmma(a, xb, acc);
-    }
+    for (int st = 0; st < SU; ++st)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t k = k0 + 16 * st + MF<T>::out_row(lane, c);
+        const bool in = k < kw1;
+        a[st][c] = in ? Ar[k] : mk<T>(0, 0);
+        xb[st][c] = (ok && in) ? xr[k] : mk<T>(0, 0);
+      }
+#pragma unroll
+    for (int st = 0; st < SU; ++st)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cmma(a[st][c], xb[st][c], acc);
   }
   if (wave > 0) {
 #pragma unroll
@@ -1670,8 +1721,8 @@ void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, i
     case 4: hipLaunchKernelGGL((k_stencil_lds<T, 4>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 8: hipLaunchKernelGGL((k_stencil_lds<T, 8>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 16:
-      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites, (nrhs + 15) / 16), dim3(NT), 0, s, blocks,
-                         Nx, Nt, nrhs, x, y, b, active);
+      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites), dim3(NT), 0, s, blocks, Nx, Nt, nrhs, x,
+                         y, b, active);
       break;
     case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
     default: throw Error(MGM_EINVAL, "block stencil: dofs per site must be 2, 4, 8, 16 or 32");
@@ -1887,10 +1938,10 @@ void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, cons
                         cx<T>* y, const int* active, DevBuf* scratch) {
   if (n % 16 == 0 && scratch) {
     // matrix cores: 16 x 16 tiles, k split over 4 waves and then over
-    // workgroups until ~1024 workgroups (k ranges of at least 256)
+    // workgroups until ~1024 workgroups (k ranges of at least 128)
     const unsigned ti = (unsigned)(n / 16), tr = (unsigned)((nrhs + 15) / 16);
     int ks = 1;
-    while (ks < 32 && (int64_t)ti * tr * ks < 1024 && n / (2 * ks) >= 256) ks *= 2;
+    while (ks < 32 && (int64_t)ti * tr * ks < 1024 && n / (2 * ks) >= 128) ks *= 2;
     const int64_t klen = ((n + ks - 1) / ks + 15) / 16 * 16;
     ks = (int)((n + klen - 1) / klen);
     cx<T>* part = nullptr;
