@@ -145,10 +145,13 @@ __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T di
 // Row strips for lattices with Lx a multiple of 64 up to 256: a workgroup of
 // Lx threads (thread = column) walks TR consecutive time slices of one RHS.
 // Each spinor is loaded from global memory once per strip (plus the two rows
-// bordering it): the -t/own/+t rows roll through registers, and the +-x
-// neighbours of the current row come from a double-buffered LDS row, so one
-// barrier per row suffices (a buffer is rewritten two rows later, after every
-// thread has passed the barrier in between).
+// bordering it): the rows behind, at and ahead of the current one roll
+// through registers, and the +-x neighbours of the current row come from a
+// double-buffered LDS row, so one barrier per row suffices (a buffer is
+// rewritten two rows later, after every thread has passed the barrier in
+// between).  Even strips walk up in t and odd strips down, so the two rows on
+// each strip boundary are read by both neighbouring strips at the same phase
+// (both at the start or both at the end) and the second read hits L2.
 template <class T, int TR>
 __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U, T diag, int Lx, int Lt,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
@@ -167,26 +170,33 @@ __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U
   const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
   const cx<T>* __restrict__ U1 = U + V;
   cx<T>* __restrict__ yr = y + (int64_t)r * 2 * V;
-  const int t0 = strip * TR;
-  const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
-  cx<T> m0 = xr[2 * ((int64_t)tm * Lx + xx)], m1 = xr[2 * ((int64_t)tm * Lx + xx) + 1];
-  cx<T> c0 = xr[2 * ((int64_t)t0 * Lx + xx)], c1 = xr[2 * ((int64_t)t0 * Lx + xx) + 1];
-  cx<T> u1m = U1[(int64_t)tm * Lx + xx];
+  const bool up = (strip & 1) == 0;
+  const int dir = up ? 1 : -1;
+  auto wrap = [Lt](int t) { return t < 0 ? t + Lt : (t >= Lt ? t - Lt : t); };
+  const int tf = up ? strip * TR : strip * TR + TR - 1;  // first row walked
+  const int tb = wrap(tf - dir);
+  // rows behind (t - dir) and at t; ur is U1 of the row below the current
+  // one when walking up, of the current row when walking down
+  cx<T> h0 = xr[2 * ((int64_t)tb * Lx + xx)], h1 = xr[2 * ((int64_t)tb * Lx + xx) + 1];
+  cx<T> c0 = xr[2 * ((int64_t)tf * Lx + xx)], c1 = xr[2 * ((int64_t)tf * Lx + xx) + 1];
+  cx<T> ur = U1[(int64_t)(up ? tb : tf) * Lx + xx];
 #pragma unroll 2
   for (int i = 0; i < TR; ++i) {
-    const int t = t0 + i;
-    const int tp = t + 1 == Lt ? 0 : t + 1;
+    const int t = tf + dir * i;
+    const int ta = wrap(t + dir);
     const int64_t site = (int64_t)t * Lx + xx;
-    const cx<T> p0 = xr[2 * ((int64_t)tp * Lx + xx)], p1 = xr[2 * ((int64_t)tp * Lx + xx) + 1];
-    const cx<T> u0 = U[site], u1 = U1[site];
+    const cx<T> a0x = xr[2 * ((int64_t)ta * Lx + xx)], a1x = xr[2 * ((int64_t)ta * Lx + xx) + 1];
+    const cx<T> ul = U1[(int64_t)(up ? t : ta) * Lx + xx];
+    const cx<T> u0 = U[site];
     const int bs = i & 1;
     sx[bs][0][xx] = c0;
     sx[bs][1][xx] = c1;
     su[bs][xx] = u0;
     __syncthreads();
     cx<T> a0, a1;
-    wilson_site<T>(diag, c0, c1, sx[bs][0][xp], sx[bs][1][xp], u0, sx[bs][0][xm], sx[bs][1][xm],
-                   su[bs][xm], p0, p1, u1, m0, m1, u1m, a0, a1);
+    wilson_site<T>(diag, c0, c1, sx[bs][0][xp], sx[bs][1][xp], u0, sx[bs][0][xm], sx[bs][1][xm], su[bs][xm],
+                   up ? a0x : h0, up ? a1x : h1, up ? ul : ur, up ? h0 : a0x, up ? h1 : a1x, up ? ur : ul, a0,
+                   a1);
     if (b) {
       const cx<T>* br = b + (int64_t)r * 2 * V;
       a0 = br[2 * site] - a0;
@@ -194,11 +204,11 @@ __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U
     }
     store_stream(yr + 2 * site, a0);
     store_stream(yr + 2 * site + 1, a1);
-    m0 = c0;
-    m1 = c1;
-    c0 = p0;
-    c1 = p1;
-    u1m = u1;
+    h0 = c0;
+    h1 = c1;
+    c0 = a0x;
+    c1 = a1x;
+    ur = ul;
   }
 }
 
@@ -727,73 +737,43 @@ __device__ __forceinline__ bool reduce_waves(CAcc<T>& acc, T (*red)[8][64], int 
 }
 
 // y = D x or y = b - D x on a coarse level (16 dofs per site).  One workgroup
-// per site.  The product is 5 blocks x 4 K-chunks = 20 chunk products per RHS
-// tile; wave w takes chunks 5w .. 5w+4 (in (direction, chunk) order), so the
-// four waves carry equal matrix-core work.  A wave keeps its five A operands
-// in registers and walks the RHS in tiles of 16, so each block is read once
-// per call.  The partial tiles meet in a double-buffered LDS area (one barrier
-// per tile); the next tile's x is loaded before that barrier.
+// per (site, 16 RHS).  The product is 5 blocks x 4 K-chunks = 20 chunk
+// products; wave w takes chunks 5w .. 5w+4 (in (direction, chunk) order), so
+// the four waves carry equal matrix-core work, and the partial tiles are
+// summed in LDS.
 template <class T>
 __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B, int Nx, int Nt, int nrhs,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                      const cx<T>* __restrict__ b,
                                                      const int* __restrict__ active) {
   constexpr int QW = 5;  // chunk products per wave
-  __shared__ T red[2][3][8][64];
+  __shared__ T red[3][8][64];
   const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = (int64_t)Nx * Nt * CM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
   cx<T> a[QW], xq[QW];
-  int64_t xo[QW];
 #pragma unroll
   for (int q = 0; q < QW; ++q) {
     const int g = wave * QW + q, d = g >> 2;
     const int k = MF<T>::out_row(lane, g & 3);
     a[q] = B[((u * 5 + d) * CM + i) * CM + k];
-    xo[q] = nb_site(u, d, Nx, Nt) * CM + k;
+    xq[q] = ok ? x[rrow * n + nb_site(u, d, Nx, Nt) * CM + k] : mk<T>(0, 0);
   }
-  auto load_x = [&](int r0) {
-    const int r = r0 + i;
-    const bool ok = r < nrhs;
-    const int64_t rrow = ok ? r : r0;
+  CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-    for (int q = 0; q < QW; ++q) xq[q] = ok ? x[rrow * n + xo[q]] : mk<T>(0, 0);
-  };
-  load_x(0);
-  const int ntile = (nrhs + 15) / 16;
-  for (int t = 0; t < ntile; ++t) {
-    CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int q = 0; q < QW; ++q) cmma(a[q], xq[q], acc);
+  if (!reduce_waves(acc, red, wave, lane)) return;
+  if (!ok || (active && !active[r])) return;
 #pragma unroll
-    for (int q = 0; q < QW; ++q) cmma(a[q], xq[q], acc);
-    if (t + 1 < ntile) load_x((t + 1) * 16);
-    T (*rb)[8][64] = red[t & 1];
-    if (wave > 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        rb[wave - 1][v][lane] = acc.re[v];
-        rb[wave - 1][4 + v][lane] = acc.im[v];
-      }
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-      for (int w = 0; w < 3; ++w)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          acc.re[v] += rb[w][v][lane];
-          acc.im[v] += rb[w][4 + v][lane];
-        }
-      const int r = t * 16 + i;
-      if (r < nrhs && !(active && !active[r])) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t o = (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
-          const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
-          y[o] = b ? b[o] - val : val;
-        }
-      }
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int64_t o = (int64_t)r * n + u * CM + MF<T>::out_row(lane, v);
+    const cx<T> val = mk<T>(acc.re[v], acc.im[v]);
+    y[o] = b ? b[o] - val : val;
   }
 }
 
@@ -1227,24 +1207,15 @@ __global__ void __launch_bounds__(NT) k_dense_mfma(const cx<T>* __restrict__ A, 
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   const cx<T>* Ar = A + (i0 + i) * n;
   const cx<T>* xr = x + rrow * n;
-  // SU 16-wide steps per round, all their loads issued before the products
-  // (steps past the wave's range load zeros)
-  constexpr int SU = sizeof(T) == 8 ? 2 : 4;
-  for (int64_t k0 = kw0; k0 < kw1; k0 += 16 * SU) {
-    cx<T> a[SU][4], xb[SU][4];
+  for (int64_t k0 = kw0; k0 < kw1; k0 += 16) {
 #pragma unroll
-    for (int st = 0; st < SU; ++st)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t k = k0 + 16 * st + MF<T>::out_row(lane, c);
-        const bool in = k < kw1;
-        a[st][c] = in ? Ar[k] : mk<T>(0, 0);
-        xb[st][c] = (ok && in) ? xr[k] : mk<T>(0, 0);
-      }
-#pragma unroll
-    for (int st = 0; st < SU; ++st)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) cmma(a[st][c], xb[st][c], acc);
+    for (int c = 0; c < 4; ++c) {
+      const int64_t k = k0 + MF<T>::out_row(lane, c);
+      const bool in = k < kw1;
+      const cx<T> a = in ? Ar[k] : mk<T>(0, 0);
+      const cx<T> xb = (ok && in) ? xr[k] : mk<T>(0, 0);
+      cmma(a, xb, acc);
+    }
   }
   if (wave > 0) {
 #pragma unroll
@@ -1721,8 +1692,8 @@ void launch_stencil(hipStream_t s, const cx<T>* blocks, int Nx, int Nt, int M, i
     case 4: hipLaunchKernelGGL((k_stencil_lds<T, 4>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 8: hipLaunchKernelGGL((k_stencil_lds<T, 8>), gl, dim3(NT), 0, s, blocks, Nx, Nt, nrhs, rpc, x, y, b, active); break;
     case 16:
-      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites), dim3(NT), 0, s, blocks, Nx, Nt, nrhs, x,
-                         y, b, active);
+      hipLaunchKernelGGL(k_stencil_mfma<T>, dim3((unsigned)sites, (nrhs + 15) / 16), dim3(NT), 0, s, blocks,
+                         Nx, Nt, nrhs, x, y, b, active);
       break;
     case 32: hipLaunchKernelGGL((k_stencil<T, 32>), g, dim3(NT), 0, s, blocks, Nx, Nt, x, y, b, active); break;
     default: throw Error(MGM_EINVAL, "block stencil: dofs per site must be 2, 4, 8, 16 or 32");
@@ -1938,10 +1909,10 @@ void launch_dense_apply(hipStream_t s, const cx<T>* A, int64_t n, int nrhs, cons
                         cx<T>* y, const int* active, DevBuf* scratch) {
   if (n % 16 == 0 && scratch) {
     // matrix cores: 16 x 16 tiles, k split over 4 waves and then over
-    // workgroups until ~1024 workgroups (k ranges of at least 128)
+    // workgroups until ~1024 workgroups (k ranges of at least 256)
     const unsigned ti = (unsigned)(n / 16), tr = (unsigned)((nrhs + 15) / 16);
     int ks = 1;
-    while (ks < 32 && (int64_t)ti * tr * ks < 1024 && n / (2 * ks) >= 128) ks *= 2;
+    while (ks < 32 && (int64_t)ti * tr * ks < 1024 && n / (2 * ks) >= 256) ks *= 2;
     const int64_t klen = ((n + ks - 1) / ks + 15) / 16 * 16;
     ks = (int)((n + klen - 1) / klen);
     cx<T>* part = nullptr;
