@@ -86,7 +86,7 @@ const char *mgm_last_error(const mgm_ctx *ctx);
  * bc_t_anti != 0.
  *   links: DEVICE complex128 [2][Lt][Lx]; links[mu][t][x] = U_mu(x, t), the
  *          link from (x, t) to its neighbour in direction mu.  Copied in.
- *   Lx, Lt even and >= 2.  Returns a gauge handle in *gauge_id.
+ *   Lx, Lt even and >= 2, at most 2^30 sites.  Returns a gauge handle in *gauge_id.
  * ------------------------------------------------------------------------- */
 int mgm_set_gauge(mgm_ctx *ctx, int Lx, int Lt, const void *links, double m0,
                   int bc_t_anti, int *gauge_id);

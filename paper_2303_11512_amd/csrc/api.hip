@@ -143,6 +143,7 @@ int mgm_set_gauge(mgm_ctx* c, int Lx, int Lt, const void* links, double m0, int 
   return guarded(c, [&] {
     require(links && gauge_id, "null pointer");
     require(Lx >= 2 && Lt >= 2 && Lx % 2 == 0 && Lt % 2 == 0, "Lx and Lt must be even and >= 2");
+    require((int64_t)Lx * Lt <= (int64_t)1 << 30, "lattice too large (more than 2^30 sites)");
     auto g = std::make_unique<Gauge>();
     g->Lx = Lx;
     g->Lt = Lt;

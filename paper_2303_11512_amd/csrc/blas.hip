@@ -71,7 +71,10 @@ __device__ __forceinline__ T block_sum_real(T v, T* sh) {
 // partial[(r*nv + i)*nch + chunk] = sum_{k in chunk} conj(V_i[r][k]) w[r][k].
 // Vectors go in groups of DG so that DG * EPT loads are in flight at once; each
 // wave reduces its share with shuffles only and the four wave sums meet in LDS
-// once per 64 vectors (one barrier pair instead of one per vector).
+// once per 64 vectors (one barrier pair instead of one per vector).  Past the
+// end of the vectors w is zero, and the V loads there read element n - 1
+// instead (the index is clamped, the load is not conditional): a conditional
+// load compiles to a branch and a wait for memory per element.
 constexpr int DG = 4;
 
 template <class T, int EPT>
@@ -92,7 +95,7 @@ __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, i
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
-    wv[e] = (k < n) ? wr[k] : mk<T>(0, 0);
+    wv[e] = ld_or0(wr + (k < n ? k : 0), k < n);
   }
   auto put = [&](int slot, cx<T> acc) {
     acc.re = wave_sum(acc.re);
@@ -111,7 +114,7 @@ __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, i
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           const int64_t k = base + (int64_t)e * NT;
-          if (k < n) cjfma(acc[g], vi[k], wv[e]);
+          cjfma(acc[g], vi[k < n ? k : n - 1], wv[e]);
         }
       }
 #pragma unroll
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, i
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int64_t k = base + (int64_t)e * NT;
-        if (k < n) cjfma(acc, vi[k], wv[e]);
+        cjfma(acc, vi[k < n ? k : n - 1], wv[e]);
       }
       put(j, acc);
     }
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
-    acc[e] = (k < n) ? wr[k] : mk<T>(0, 0);
+    acc[e] = wr[k < n ? k : n - 1];  // past n: computed, never stored
   }
   constexpr int G = EPT >= 8 ? 2 : DG;  // G * EPT loads in flight, within the register budget
   int i = 0;
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int64_t k = base + (int64_t)e * NT;
-        vv[g][e] = (k < n) ? vi[k] : mk<T>(0, 0);
+        vv[g][e] = vi[k < n ? k : n - 1];
       }
     }
 #pragma unroll
@@ -210,7 +213,7 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int64_t k = base + (int64_t)e * NT;
-      if (k < n) cfma(acc[e], vi[k], c);
+      cfma(acc[e], vi[k < n ? k : n - 1], c);
     }
   }
   T nrm = 0;
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
-    if (k < n) acc += abs2(wr[k]);
+    acc += abs2(wr[k < n ? k : n - 1]) * (T)(k < n);
   }
   acc = block_sum_real(acc, sh);
   if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = acc;
@@ -415,8 +418,8 @@ __global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, i
     for (int64_t kc = k0; kc < k1; kc += 4) {
       const int64_t k = kc + (lane >> 4);
       const bool in = k < k1;
-      const cd a = (in && i < d) ? Y[(int64_t)i * n + k] : mk(0.0, 0.0);
-      const cd b = (in && j < d) ? Y[(int64_t)j * n + k] : mk(0.0, 0.0);
+      const cd a = ld_or0(Y + (int64_t)(i < d ? i : 0) * n + (in ? k : 0), in && i < d);
+      const cd b = ld_or0(Y + (int64_t)(j < d ? j : 0) * n + (in ? k : 0), in && j < d);
       cmma(conj(a), b, acc);
     }
     // element v: row i0 + out_row(lane, v), column j0 + lane % 16
@@ -514,8 +517,8 @@ __global__ void __launch_bounds__(NT) k_right_tri(const cd* __restrict__ Y, cons
     const int iend = min(d, jt * 16 + 16);  // Rinv is upper: rows i <= j only
     for (int ic = 0; ic < iend; ic += 4) {
       const int ia = ic + q;  // A[k][i] = Y_i[k], B[i][j] = Rinv[i][j]
-      const cd a = (ia < d && k < n) ? Y[(int64_t)ia * n + k] : mk(0.0, 0.0);
-      const cd b = (ia < d && j < d) ? Rinv[ia * d + j] : mk(0.0, 0.0);
+      const cd a = ld_or0(Y + (int64_t)(ia < d ? ia : 0) * n + (k < n ? k : 0), ia < d && k < n);
+      const cd b = ld_or0(Rinv + (ia < d ? ia : 0) * d + (j < d ? j : 0), ia < d && j < d);
       cmma(a, b, acc);
     }
     // element v: row k0 + out_row(lane, v), column j

@@ -59,6 +59,17 @@ __host__ __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
   return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 // acc += a * b
+// ok ? *p : 0 with the load issued unconditionally; p must be a valid address
+// either way (callers clamp their indices).  Written as a conditional load,
+// the compiler branches around the load and waits for memory right after
+// it, which serialises all such loads of a thread; a select after an
+// unconditional load lets them all be in flight together.
+template <class T>
+__device__ __forceinline__ cx<T> ld_or0(const cx<T>* p, bool ok) {
+  const cx<T> v = *p;
+  return ok ? v : mk<T>(0, 0);
+}
+
 // The chip hands workgroups to its eight XCDs round-robin by linear
 // workgroup id, and each XCD has its own L2.  xcd_tile(b, G) renumbers b in
 // [0, G) so that the ids one XCD receives cover one contiguous range of tiles;

@@ -18,8 +18,12 @@ namespace {
 
 constexpr int NT = 256;
 
+// Site indices fit in 32 bits (the host limits lattices to 2^30 sites), so
+// the division is done in 32-bit arithmetic: 64-bit division by a runtime
+// value expands into a long branchy sequence.
 __device__ __forceinline__ int64_t nb_site(int64_t u, int d, int Nx, int Nt) {
-  int x = (int)(u % Nx), t = (int)(u / Nx);
+  const int ui = (int)u;
+  int x = ui % Nx, t = ui / Nx;
   switch (d) {
     case 1: x = (x + 1 == Nx) ? 0 : x + 1; break;
     case 2: x = (x == 0) ? Nx - 1 : x - 1; break;
@@ -304,7 +308,7 @@ __global__ void __launch_bounds__(NT) k_stencil_lds(const cx<T>* __restrict__ B,
     for (int e = tid; e < RPW * 5 * M; e += NT) {
       const int j = e % M, d = (e / M) % 5, rr = e / (5 * M);
       const int r = r0 + rr;
-      XS[e] = (r < rend) ? x[(int64_t)r * n + nbs[d] + j] : mk<T>(0, 0);
+      XS[e] = x[(int64_t)(r < rend ? r : rbeg) * n + nbs[d] + j];  // rows past rend are never used
     }
     __syncthreads();
     const int r = r0 + rl;
@@ -707,7 +711,7 @@ __device__ __forceinline__ void coarse_hop(const cx<T>* __restrict__ B, const cx
   for (int c = 0; c < 4; ++c) {
     const int k = MF<T>::out_row(lane, c);
     a[c] = Bd[k];
-    xb[c] = ok ? xv[k] : mk<T>(0, 0);
+    xb[c] = xv[k];  // lanes past the last RHS read row rrow; their column is never stored
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) cmma(a[c], xb[c], acc);
@@ -762,7 +766,7 @@ __global__ void __launch_bounds__(NT) k_stencil_mfma(const cx<T>* __restrict__ B
     const int g = wave * QW + q, d = g >> 2;
     const int k = MF<T>::out_row(lane, g & 3);
     a[q] = B[((u * 5 + d) * CM + i) * CM + k];
-    xq[q] = ok ? x[rrow * n + nb_site(u, d, Nx, Nt) * CM + k] : mk<T>(0, 0);
+    xq[q] = x[rrow * n + nb_site(u, d, Nx, Nt) * CM + k];
   }
   CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
@@ -805,7 +809,7 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int k = MF<T>::out_row(lane, c);
-      rv[c] = ok ? rr[rrow * n + u * CM + k] : mk<T>(0, 0);
+      rv[c] = rr[rrow * n + u * CM + k];
       a[c] = Iu[k];
     }
   }
@@ -828,6 +832,9 @@ __global__ void __launch_bounds__(NT) k_sap_mfma(const cx<T>* __restrict__ B, co
 // element v of its FP32 result is D[4(l/16) + v][l%16] (measured on gfx950).
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
+// Sixteen complex zeros: the x operand of an unused hop slot.
+__device__ const cf zero_cf[16] = {};
+
 __device__ __forceinline__ void hmma(h4 ar, h4 ai, h4 br, h4 bi, CAcc<float>& acc) {
   acc.re = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, acc.re, 0, 0, 0);
   acc.re = __builtin_amdgcn_mfma_f32_16x16x16f16(-ai, bi, acc.re, 0, 0, 0);
@@ -846,7 +853,7 @@ __device__ __forceinline__ void coarse_hop_h(const chalf* __restrict__ B, const 
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const chalf a = row[j];
-    const cf v = ok ? xv[j] : mk<float>(0, 0);
+    const cf v = xv[j];
     ar[j] = a.re;
     ai[j] = a.im;
     br[j] = (_Float16)v.re;
@@ -902,7 +909,7 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
     const chalf* Iu = inv + (u * CM + i) * CM + 4 * q;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      rv[j] = ok ? rr[rrow * n + u * CM + 4 * q + j] : mk<float>(0, 0);
+      rv[j] = rr[rrow * n + u * CM + 4 * q + j];
       iv[j] = Iu[j];
     }
   }
@@ -945,9 +952,11 @@ __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, cons
   const int dirs[2] = {wave == 0 ? 2 : (wave == 2 ? 1 : 4), 3};
   h4 bar[2], bai[2];
   int64_t nbo[2];
+  // both hop slots are always loaded and multiplied (a wave with one hop
+  // multiplies a zero operand in its second slot): branch-free code keeps
+  // every load of the wave in flight at once
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh) {
-    if (hh >= nh) break;
     const chalf* row = B + ((us * 5 + dirs[hh]) * CM + i) * CM + 4 * q;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -965,12 +974,12 @@ __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, cons
     CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
-      if (hh >= nh) break;
-      const cf* xv = x + rrow * n + nbo[hh];
+      // an unused slot reads zeros (zero_cf), so its product adds exactly 0
+      const cf* xv = hh < nh ? x + rrow * n + nbo[hh] : zero_cf + 4 * q;
       h4 br, bi;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const cf v = ok ? xv[j] : mk<float>(0, 0);
+        const cf v = xv[j];
         br[j] = (_Float16)v.re;
         bi[j] = (_Float16)v.im;
       }
@@ -1002,8 +1011,9 @@ __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, cons
     const bool ok = r < nrhs;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      rv[rt][0][j] = ok ? rr[(int64_t)r * n + u0 * CM + 4 * q + j] : mk<float>(0, 0);
-      rv[rt][1][j] = ok ? rr[(int64_t)r * n + u1 * CM + 4 * q + j] : mk<float>(0, 0);
+      const int64_t rc = ok ? r : 0;
+      rv[rt][0][j] = rr[rc * n + u0 * CM + 4 * q + j];
+      rv[rt][1][j] = rr[rc * n + u1 * CM + 4 * q + j];
     }
   }
   __syncthreads();
@@ -1078,8 +1088,8 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int k = MF<T>::out_row(lane, c);
-      rv[0][c] = ok ? rr[rrow * n + u0 * CM + k] : mk<T>(0, 0);
-      rv[1][c] = ok ? rr[rrow * n + u1 * CM + k] : mk<T>(0, 0);
+      rv[0][c] = rr[rrow * n + u0 * CM + k];
+      rv[1][c] = rr[rrow * n + u1 * CM + k];
       a[0][c] = Ih[k];
       a[1][c] = Ih[16 + k];
     }
@@ -1145,20 +1155,27 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
     const int k = 16 * (c >> 2) + MF<T>::out_row(lane, c & 3);
     const int s = k >> 1, a = k & 1, sx = s & 3, st = s >> 2;
     const int gx = bx + sx, gt = bt + st;
-    cx<T> acc = mk<T>(0, 0);
-    if (ok) {
-      acc = rv[((int64_t)gt * Nx + gx) * 2 + a];
-      int nbs[2], dirs[2], nh = 0;
-      if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
-      if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
-      if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
-      if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
-      for (int j = 0; j < nh; ++j) {
-        const cx<T>* bb = Bs + (s * 5 + dirs[j]) * 4 + a * 2;
-        const cx<T>* xv = xr + (int64_t)nbs[j] * 2;
-        acc = acc - bb[0] * xv[0] - bb[1] * xv[1];
-      }
+    // at most two outward hops per site of a 4x4 block; unused slots point at
+    // the site itself so that every load is unconditional
+    const int own = gt * Nx + gx;
+    int nbs[2] = {own, own}, dirs[2] = {0, 0}, nh = 0;
+    if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
+    if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
+    if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
+    if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
+    cx<T> acc = rv[(int64_t)own * 2 + a];
+    cx<T> xh[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      xh[j][0] = xr[(int64_t)nbs[j] * 2];
+      xh[j][1] = xr[(int64_t)nbs[j] * 2 + 1];
     }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (ok && j < nh) {
+        const cx<T>* bb = Bs + (s * 5 + dirs[j]) * 4 + a * 2;
+        acc = acc - bb[0] * xh[j][0] - bb[1] * xh[j][1];
+      }
     h[c] = acc;
   }
   const bool store = ok && !(active && !active[r]);
@@ -1211,9 +1228,10 @@ __global__ void __launch_bounds__(NT) k_dense_mfma(const cx<T>* __restrict__ A, 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t k = k0 + MF<T>::out_row(lane, c);
-      const bool in = k < kw1;
-      const cx<T> a = in ? Ar[k] : mk<T>(0, 0);
-      const cx<T> xb = (ok && in) ? xr[k] : mk<T>(0, 0);
+      // kw0, kw1 are multiples of 16 (n, klen and so every range bound are),
+      // so k < kw1 here; lanes past the last RHS read row rrow
+      const cx<T> a = Ar[k];
+      const cx<T> xb = xr[k];
       cmma(a, xb, acc);
     }
   }
@@ -1480,13 +1498,13 @@ __global__ void __launch_bounds__(NT) k_dense_apply(const cx<T>* __restrict__ A,
     for (int e = tid; e < TI * TJ; e += NT) {
       const int ii = e / TJ, jj = e % TJ;
       const int64_t gi = i0 + ii, gj = j0 + jj;
-      As[jj][ii] = (gi < n && gj < ke) ? A[gi * n + gj] : mk<T>(0, 0);
+      As[jj][ii] = ld_or0(A + (gi < n ? gi : 0) * n + (gj < ke ? gj : kb), gi < n && gj < ke);
     }
     for (int e = tid; e < TR * TJ; e += NT) {
       const int rr = e / TJ, jj = e % TJ;
       const int gr = r0 + rr;
       const int64_t gj = j0 + jj;
-      Xs[rr][jj] = (gr < nrhs && gj < ke) ? x[(int64_t)gr * n + gj] : mk<T>(0, 0);
+      Xs[rr][jj] = ld_or0(x + (int64_t)(gr < nrhs ? gr : 0) * n + (gj < ke ? gj : kb), gr < nrhs && gj < ke);
     }
     __syncthreads();
 #pragma unroll 8
