@@ -391,8 +391,13 @@ struct CnnWork {
 // Trace-estimator workspaces, kept with the field so that repeated estimates
 // reuse them (no reallocation, so captured graphs stay valid).
 struct EstWork {
-  DevBuf t1, t2, t3, t4, dots, part, zb, xb, cb, sb, yb;
-  DevBuf Q[MGM_MAX_LEVELS];
+  DevBuf t1, t3, t4, dots, part;
+  // per level difference: Hutch++ sketch S, its image Y and basis Q; sample
+  // noise Z, its image X and projection coefficients C
+  DevBuf S[MGM_MAX_LEVELS], Y[MGM_MAX_LEVELS], Q[MGM_MAX_LEVELS];
+  DevBuf Z[MGM_MAX_LEVELS], X[MGM_MAX_LEVELS], C[MGM_MAX_LEVELS];
+  // per operator level: the merged right-hand sides of one solve and its solutions
+  DevBuf lin[MGM_MAX_LEVELS], lout[MGM_MAX_LEVELS];
 };
 
 struct Gauge {

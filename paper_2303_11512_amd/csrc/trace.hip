@@ -9,6 +9,13 @@
 // batching), and the stopping rule is then replayed sample by sample in index
 // order; samples past a level's stopping point are discarded.  The result
 // therefore equals the sequential algorithm's on the same seeds.
+//
+// In the reduced form, difference l needs solves with D_l (its fine part) and
+// with D_{l+1} (its coarse part, on P_l^H of the same vectors), so every
+// inner level is solved for two differences.  Both sets of right-hand sides
+// go into one solve per level: a coarse level is small enough that its
+// kernels cost nearly the same for 32 or 64 right-hand sides, and each
+// right-hand side still has its own Krylov space and stopping test.
 #include <cmath>
 #include <complex>
 
@@ -56,14 +63,13 @@ struct Estimator {
   int L;                 // number of levels of the hierarchy
   bool full;             // full (hatted) form
   bool hutch;            // single-level variants on D^{-1}
-  // workspaces of the field (scratch vectors; noise, A*noise, projection
-  // coefficients, sketch, sketch images)
-  DevBuf &t1, &t2, &t3, &t4, &dots, &part, &zb, &xb, &cb, &sb, &yb;
+  int kmax = 1;          // most vectors one difference hands to a solve
+  // workspaces of the field (scratch vectors, dot products)
+  DevBuf &t1, &t3, &t4, &dots, &part;
 
   Estimator(mgm_ctx* c_, Gauge& g_, const mgm_trace_params& p_, mgm_trace_result& r_)
-      : c(c_), g(g_), p(p_), res(r_), t1(g_.est.t1), t2(g_.est.t2), t3(g_.est.t3), t4(g_.est.t4),
-        dots(g_.est.dots), part(g_.est.part), zb(g_.est.zb), xb(g_.est.xb), cb(g_.est.cb), sb(g_.est.sb),
-        yb(g_.est.yb) {
+      : c(c_), g(g_), p(p_), res(r_), t1(g_.est.t1), t3(g_.est.t3), t4(g_.est.t4),
+        dots(g_.est.dots), part(g_.est.part) {
     L = g.mlmc_levels;
     full = p.form == MGM_FORM_FULL;
     hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
@@ -114,7 +120,8 @@ struct Estimator {
     }
   }
 
-  // Y = A_l X  for k vectors of the level difference sl
+  // Y = A_l X for k vectors of the level difference sl: Hutchinson variants
+  // (A = D^{-1}) and the full form on fine vectors
   void applyA(const StochLevel& sl, int k, const cd* X, cd* Y) {
     hipStream_t s = c->stream;
     const int l = sl.level;
@@ -122,26 +129,78 @@ struct Estimator {
       solve(0, k, X, Y);
       return;
     }
-    if (!full) {
-      Level& F = *g.levels[l];
-      Level& C = *g.levels[l + 1];
-      solve(l, k, X, Y);
-      t1.ensure(sizeof(cd) * (size_t)k * C.n);
-      t2.ensure(sizeof(cd) * (size_t)k * C.n);
-      t3.ensure(sizeof(cd) * (size_t)k * F.n);
-      launch_restrict<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, k, X, t1.as<cd>(),
-                              nullptr);
-      solve(l + 1, k, t1.as<cd>(), t2.as<cd>());
-      launch_prolong<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, k, t2.as<cd>(),
-                             t3.as<cd>(), 0, nullptr);
-      launch_axpby<double>(s, 1.0, Y, -1.0, t3.as<cd>(), Y, F.n, k, nullptr);
-      return;
-    }
     const int64_t n0 = g.levels[0]->n;
     t1.ensure(sizeof(cd) * (size_t)k * n0);
     lift(l, k, X, Y);
     lift(l + 1, k, X, t1.as<cd>());
     launch_axpby<double>(s, 1.0, Y, -1.0, t1.as<cd>(), Y, n0, k, nullptr);
+  }
+
+  // Y_i = A_i X_i for several level differences at once.  Reduced form: the
+  // right-hand sides of each operator level j -- P_{j-1}^H X_{j-1} of
+  // difference j-1, then X_j of difference j -- are solved together; then
+  // Y_i = (D_i^{-1} X_i) - P_i (D_{i+1}^{-1} P_i^H X_i).  Other forms apply
+  // the differences one after the other.
+  struct Item {
+    int i, k;
+    const cd* X;
+    cd* Y;
+  };
+  void applyA_levels(const std::vector<StochLevel>& lv, const std::vector<Item>& items) {
+    if (hutch || full) {
+      for (const Item& it : items) applyA(lv[it.i], it.k, it.X, it.Y);
+      return;
+    }
+    hipStream_t s = c->stream;
+    std::vector<const Item*> own(L, nullptr), crs(L, nullptr);
+    for (const Item& it : items) {
+      const int l = lv[it.i].level;
+      require(l + 1 < L && !own[l], "applyA_levels: bad level difference");
+      require(it.k >= 1 && it.k <= kmax, "applyA_levels: too many vectors");
+      own[l] = &it;
+      crs[l + 1] = &it;
+    }
+    std::vector<int> own_off(L, 0), total(L, 0);
+    for (int j = 0; j < L; ++j) {
+      if (crs[j]) total[j] += crs[j]->k;
+      if (own[j]) {
+        own_off[j] = total[j];
+        total[j] += own[j]->k;
+      }
+      if (!total[j]) continue;
+      Level& Lj = *g.levels[j];
+      const int64_t n = Lj.n;
+      // sized for the most vectors any call can bring, so that later
+      // estimates reuse the buffers (captured graphs stay valid)
+      const size_t cap = sizeof(cd) * (size_t)n * ((crs[j] ? kmax : 0) + (own[j] ? kmax : 0));
+      DevBuf& out = g.est.lout[j];
+      out.ensure(cap);
+      const cd* src = nullptr;
+      if (!crs[j]) {
+        src = own[j]->X;  // only difference j's fine part: no gather needed
+      } else {
+        DevBuf& in = g.est.lin[j];
+        in.ensure(cap);
+        Level& F = *g.levels[j - 1];
+        launch_restrict<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, crs[j]->k, crs[j]->X,
+                                in.as<cd>(), nullptr);
+        if (own[j])
+          HIPCHK(hipMemcpyAsync(in.as<cd>() + (int64_t)own_off[j] * n, own[j]->X,
+                                sizeof(cd) * (size_t)own[j]->k * n, hipMemcpyDeviceToDevice, s));
+        src = in.as<cd>();
+      }
+      solve(j, total[j], src, out.as<cd>());
+    }
+    t3.ensure(sizeof(cd) * (size_t)kmax * g.levels[0]->n);
+    for (const Item& it : items) {
+      const int l = lv[it.i].level;
+      Level& F = *g.levels[l];
+      const cd* fine = g.est.lout[l].as<cd>() + (int64_t)own_off[l] * F.n;
+      const cd* coarse = g.est.lout[l + 1].as<cd>();  // the coarse part comes first
+      launch_prolong<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, it.k, coarse, t3.as<cd>(),
+                             0, nullptr);
+      launch_axpby<double>(s, 1.0, fine, -1.0, t3.as<cd>(), it.Y, F.n, it.k, nullptr);
+    }
   }
 
   // out[r] = x_r^H y_r  (HOST, k values)
@@ -157,51 +216,68 @@ struct Estimator {
     for (int r = 0; r < k; ++r) out[r] = zc(h[r].re, h[r].im);
   }
 
-  // Hutch++ low-rank part: k sweeps of Y = A S, Q = qr(Y), S = Q; then
-  // tau_lr = sum_i q_i^H A q_i.
-  void low_rank(int idx, StochLevel& sl) {
-    const int d = sl.d;
-    const int64_t n = sl.n;
-    DevBuf& S = sb;
-    DevBuf& Y = yb;
-    S.ensure(sizeof(cd) * (size_t)d * n);
-    Y.ensure(sizeof(cd) * (size_t)d * n);
-    sl.Q->ensure(sizeof(cd) * (size_t)d * n);
-    launch_noise<double>(c->stream, S.as<cd>(), n, d, p.noise, p.seed, MGM_PURPOSE_SKETCH, idx, 0);
-    const cd* src = S.as<cd>();
-    for (int it = 0; it < std::max(1, p.k_power); ++it) {
-      applyA(sl, d, src, Y.as<cd>());
-      orthonormalize(c, n, d, Y.as<cd>(), sl.Q->as<cd>());
-      src = sl.Q->as<cd>();
+  // Hutch++ low-rank parts of all differences (d_i > 0), sweep by sweep:
+  // k sweeps of Y = A S, Q = qr(Y), S = Q; then tau_lr = sum_i q_i^H A q_i.
+  void low_rank_all(std::vector<StochLevel>& lv) {
+    std::vector<Item> items;
+    for (int i = 0; i < (int)lv.size(); ++i) {
+      StochLevel& sl = lv[i];
+      if (sl.d <= 0) continue;
+      const size_t bytes = sizeof(cd) * (size_t)sl.d * sl.n;
+      g.est.S[i].ensure(bytes);
+      g.est.Y[i].ensure(bytes);
+      sl.Q->ensure(bytes);
+      launch_noise<double>(c->stream, g.est.S[i].as<cd>(), sl.n, sl.d, p.noise, p.seed, MGM_PURPOSE_SKETCH, i, 0);
+      items.push_back({i, sl.d, g.est.S[i].as<cd>(), g.est.Y[i].as<cd>()});
     }
-    applyA(sl, d, sl.Q->as<cd>(), Y.as<cd>());
-    std::vector<zc> v;
-    dots_host(sl.Q->as<cd>(), Y.as<cd>(), n, d, v);
-    zc acc = 0;
-    for (const zc& x : v) acc += x;
-    sl.tau_lr = acc;
+    if (items.empty()) return;
+    for (int it = 0; it < std::max(1, p.k_power); ++it) {
+      applyA_levels(lv, items);
+      for (Item& x : items) {
+        orthonormalize(c, lv[x.i].n, x.k, x.Y, lv[x.i].Q->as<cd>());
+        x.X = lv[x.i].Q->as<cd>();
+      }
+    }
+    applyA_levels(lv, items);
+    for (const Item& x : items) {
+      std::vector<zc> v;
+      dots_host(x.X, x.Y, lv[x.i].n, x.k, v);
+      zc acc = 0;
+      for (const zc& y : v) acc += y;
+      lv[x.i].tau_lr = acc;
+    }
   }
 
-  // b samples tau_{s,l} = z^H (A zeta), z = zeta - Q (Q^H zeta), indices s0..s0+b-1
-  void sample_batch(int idx, StochLevel& sl, int s0, int b, std::vector<zc>& out) {
+  // samples tau_{s,l} = z^H (A zeta), z = zeta - Q (Q^H zeta), indices
+  // s0[i] .. s0[i]+b[i]-1 of every difference i with b[i] > 0
+  void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b,
+                      std::vector<std::vector<zc>>& out) {
     hipStream_t s = c->stream;
-    const int64_t n = sl.n;
-    DevBuf& Z = zb;
-    DevBuf& X = xb;
-    DevBuf& C = cb;
-    Z.ensure(sizeof(cd) * (size_t)b * n);
-    X.ensure(sizeof(cd) * (size_t)b * n);
-    launch_noise<double>(s, Z.as<cd>(), n, b, p.noise, p.seed, MGM_PURPOSE_SAMPLE, idx, s0);
-    applyA(sl, b, Z.as<cd>(), X.as<cd>());
-    if (sl.d > 0) {
-      C.ensure(sizeof(cd) * (size_t)b * sl.d);
-      part.ensure(sizeof(cd) * (size_t)b * sl.d * reduce_chunks(n) + 64);
-      launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z.as<cd>(), n, b, C.as<cd>(), sl.d, 0,
-                                  nullptr, part.as<cd>());
-      launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z.as<cd>(), n, b,
-                                  nullptr, nullptr, nullptr);
+    std::vector<Item> items;
+    for (int i = 0; i < (int)lv.size(); ++i) {
+      if (b[i] <= 0) continue;
+      StochLevel& sl = lv[i];
+      g.est.Z[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
+      g.est.X[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
+      launch_noise<double>(s, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed, MGM_PURPOSE_SAMPLE, i, sl.s());
+      items.push_back({i, b[i], g.est.Z[i].as<cd>(), g.est.X[i].as<cd>()});
     }
-    dots_host(Z.as<cd>(), X.as<cd>(), n, b, out);
+    applyA_levels(lv, items);
+    for (const Item& it : items) {
+      StochLevel& sl = lv[it.i];
+      const int64_t n = sl.n;
+      cd* Z = g.est.Z[it.i].as<cd>();
+      if (sl.d > 0) {
+        DevBuf& C = g.est.C[it.i];
+        C.ensure(sizeof(cd) * (size_t)kmax * sl.d);
+        part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
+        launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z, n, it.k, C.as<cd>(), sl.d, 0, nullptr,
+                                    part.as<cd>());
+        launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z, n, it.k,
+                                    nullptr, nullptr, nullptr);
+      }
+      dots_host(Z, it.Y, n, it.k, out[it.i]);
+    }
   }
 
   std::vector<double> weights(const std::vector<StochLevel>& lv) {
@@ -247,8 +323,11 @@ struct Estimator {
       }
     }
     const zc tau_exact = hutch ? zc(0) : zc(g.trL[0], g.trL[1]);
-    for (int i = 0; i < nst; ++i)
-      if (lv[i].d > 0) low_rank(i, lv[i]);
+    kmax = std::max(1, p.batch);
+    for (int i = 0; i < nst; ++i) kmax = std::max(kmax, lv[i].d);
+    // every reduction workspace at its largest size up front (no reallocation later)
+    part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
+    low_rank_all(lv);
 
     const int minS = std::max(2, p.min_samples);
     const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
@@ -280,13 +359,14 @@ struct Estimator {
         }
       }
       std::vector<std::vector<zc>> vals(nst);
+      std::vector<int> nb(nst, 0);
       for (int i = 0; i < nst; ++i) {
         if (!lv[i].active) continue;
         int b = common;
         if (p.fixed_samples) b = std::min(b, p.fixed_samples[i] - lv[i].s());
-        b = std::min(b, maxS - lv[i].s());
-        if (b > 0) sample_batch(i, lv[i], lv[i].s(), b, vals[i]);
+        nb[i] = std::min(b, maxS - lv[i].s());
       }
+      sample_batches(lv, nb, vals);
       // replay Alg. 2 sample by sample; stop where an active level has no
       // evaluated sample left (levels advance in lockstep)
       for (int t = 0; t < p.batch; ++t) {
