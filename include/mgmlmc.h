@@ -242,7 +242,9 @@ int mgm_orthonormalize(mgm_ctx *ctx, int64_t n, int d, const void *Y, void *Q);
  * full form with accumulated prolongations (eq. mlmc_decomp_trace).  Samples
  * are drawn `batch` at a time per active level and Alg. 2's stopping rule is
  * replayed sample by sample, so the result equals the sequential algorithm's
- * on the same seeds.
+ * on the same seeds.  In the reduced form all right-hand sides one phase
+ * needs on a level (the fine part of difference l, the coarse part of
+ * difference l-1) are solved as one batch.
  * ------------------------------------------------------------------------- */
 #define MGM_VARIANT_HUTCH 0
 #define MGM_VARIANT_HUTCHPP 1
@@ -268,6 +270,9 @@ typedef struct {
   uint64_t seed;
   int batch;                         /* samples per level per GPU batch      */
   mgm_solve_params solve;
+  int concurrent;                    /* 1: a phase's solves on different
+                                        levels run at once on two streams of
+                                        the field (same results as 0)       */
 } mgm_trace_params;
 
 typedef struct {

@@ -93,6 +93,7 @@ class TraceParams(C.Structure):
         ("seed", C.c_uint64),
         ("batch", C.c_int),
         ("solve", SolveParams),
+        ("concurrent", C.c_int),
     ]
 
 
@@ -436,7 +437,7 @@ class Context:
     def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
                        noise="z2z2", targets="optimal", fixed_cost=None, min_samples=2,
                        max_samples=0, fixed_samples=None, seed=1, batch=64, solve=None,
-                       max_dump=0) -> dict:
+                       max_dump=0, concurrent=True) -> dict:
         p = TraceParams()
         p.variant = VARIANTS[variant]
         p.form = FORMS[form]
@@ -459,6 +460,7 @@ class Context:
         p.seed = seed
         p.batch = batch
         p.solve = solve or solve_params()
+        p.concurrent = int(bool(concurrent))
         r = TraceResult()
         dump = None
         if max_dump > 0:

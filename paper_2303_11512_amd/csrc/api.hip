@@ -417,7 +417,7 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
       case MGM_KERNEL_DENSE:
         require(L.has_dense, "level has no dense inverse", MGM_ESTATE);
         launch = [=, &L, &g] {
-          launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, x, y, nullptr, &g.scratch);
+          launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, x, y, nullptr, &g.scratch[c->wslot]);
         };
         bytes = 16.0 * n * n + 32.0 * n * b;
         flops = 8.0 * n * n * b;

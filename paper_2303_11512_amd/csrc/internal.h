@@ -353,8 +353,10 @@ struct Level {
   int ncolor[2] = {0, 0};
   LevelData<double> d;
   LevelData<float> f;
-  Work<double> wd;
-  Work<float> wf;
+  // two workspace sets: set 1 serves a solve that runs concurrently with
+  // one on set 0 (the estimator's coarse-level solves)
+  Work<double> wd[2];
+  Work<float> wf[2];
   int64_t nrow() const { return (int64_t)bx * bt * (M / 2); }
   int64_t nagg() const { return bx ? (int64_t)(Nx / bx) * (Nt / bt) : 0; }
 };
@@ -415,21 +417,31 @@ struct Gauge {
   // caller's stream with ev_in / ev_out at every entry point
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  DevBuf scratch;  // split-k partials of the dense applies
+  // second stream of the field (default priority) for the concurrent
+  // solves, with its fork / join events; created on first use
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DevBuf scratch[2];  // split-k partials of the dense applies, per workspace set
   CnnWork cnn;
   EstWork est;
-  std::map<GraphKey, GraphEntry> graphs;
+  std::map<GraphKey, GraphEntry> graphs[2];  // per workspace set (one host thread each)
   void clear_graphs() {
-    for (auto& kv : graphs)
-      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    graphs.clear();
+    for (auto& m : graphs) {
+      for (auto& kv : m)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      m.clear();
+    }
   }
   ~Gauge() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (stream2) (void)hipStreamSynchronize(stream2);
     clear_graphs();
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (stream) (void)hipStreamDestroy(stream);
+    if (stream2) (void)hipStreamDestroy(stream2);
   }
 };
 
@@ -438,6 +450,7 @@ struct Gauge {
 struct mgm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  int wslot = 0;  // workspace set of the levels this view solves with (0 or 1)
   std::string err;
   std::vector<std::unique_ptr<mgm::Gauge>> gauges;
   mgm::DevBuf scratch, scratch2, scratch3, ibuf;

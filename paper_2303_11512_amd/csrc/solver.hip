@@ -23,11 +23,11 @@ template <>
 LevelData<float>& ldata<float>(Level& L) { return L.f; }
 
 template <class T>
-Work<T>& work(Level& L);
+Work<T>& work(Level& L, int slot);
 template <>
-Work<double>& work<double>(Level& L) { return L.wd; }
+Work<double>& work<double>(Level& L, int slot) { return L.wd[slot]; }
 template <>
-Work<float>& work<float>(Level& L) { return L.wf; }
+Work<float>& work<float>(Level& L, int slot) { return L.wf[slot]; }
 
 template <class T>
 const cx<T>* links_of(Gauge& g);
@@ -37,8 +37,8 @@ template <>
 const cf* links_of<float>(Gauge& g) { return g.links32.as<cf>(); }
 
 template <class T>
-void ensure_work(Level& L, int nrhs, int m) {
-  Work<T>& W = work<T>(L);
+void ensure_work(Level& L, int slot, int nrhs, int m) {
+  Work<T>& W = work<T>(L, slot);
   const int64_t n = L.n;
   const size_t c = sizeof(cx<T>);
   W.V.ensure(c * (size_t)(m + 1) * nrhs * n);
@@ -92,19 +92,19 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   Level& L = *g.levels[l];
   LevelData<T>& D = ldata<T>(L);
   if (L.is_coarsest) {
-    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &g.scratch);
+    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &g.scratch[c->wslot]);
     return;
   }
   if (L.has_coarse) {
     Level& C = *g.levels[l + 1];
-    Work<T>& W = work<T>(L);
+    Work<T>& W = work<T>(L, c->wslot);
     W.rc.ensure(sizeof(cx<T>) * (size_t)nrhs * C.n);
     W.ec.ensure(sizeof(cx<T>) * (size_t)nrhs * C.n);
     cx<T>* rc = W.rc.template as<cx<T>>();
     cx<T>* ec = W.ec.template as<cx<T>>();
     launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
     if (C.is_coarsest) {
-      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &g.scratch);
+      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &g.scratch[c->wslot]);
     } else if (C.inner_iters <= 0) {
       precond<T>(c, g, l + 1, nrhs, rc, ec, act);  // plain V-cycle on the coarse level
     } else {
@@ -168,8 +168,8 @@ void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* 
   hipStream_t s = c->stream;
   Level& L = *g.levels[l];
   require(m >= 1 && m <= 63, "inner FGMRES length must be in [1, 63]");
-  ensure_work<T>(L, nrhs, m);
-  Work<T>& W = work<T>(L);
+  ensure_work<T>(L, c->wslot, nrhs, m);
+  Work<T>& W = work<T>(L, c->wslot);
   const int64_t n = L.n;
   cx<T>* V = W.V.template as<cx<T>>();
   cx<T>* Z = W.Z.template as<cx<T>>();
@@ -202,7 +202,7 @@ void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y) {
 void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
   Level& L = *g.levels[l];
   if (g.prm.precision != MGM_PREC_FP64 && g.mg_ready) {
-    Work<double>& W = L.wd;
+    Work<double>& W = L.wd[c->wslot];
     const int64_t cnt = (int64_t)nrhs * L.n;
     W.cvt_in.ensure(sizeof(cf) * cnt);
     W.cvt_out.ensure(sizeof(cf) * cnt);
@@ -227,20 +227,21 @@ void run_graph(mgm_ctx* c, Gauge& g, const GraphKey& key, F&& body) {
     body();
     return;
   }
-  auto it = g.graphs.find(key);
+  auto& graphs = g.graphs[c->wslot];
+  auto it = graphs.find(key);
   const uint64_t ep = g_alloc_epoch.load();
-  if (it != g.graphs.end() && it->second.exec && it->second.epoch == ep) {
+  if (it != graphs.end() && it->second.exec && it->second.epoch == ep) {
     HIPCHK(hipGraphLaunch(it->second.exec, s));
     return;
   }
-  if (it == g.graphs.end() || it->second.failed || it->second.epoch != ep) {
-    if (it != g.graphs.end() && it->second.exec) {
+  if (it == graphs.end() || it->second.failed || it->second.epoch != ep) {
+    if (it != graphs.end() && it->second.exec) {
       (void)hipGraphExecDestroy(it->second.exec);
       it->second.exec = nullptr;
     }
-    const bool failed = it != g.graphs.end() && it->second.failed;
+    const bool failed = it != graphs.end() && it->second.failed;
     body();
-    GraphEntry& e = g.graphs[key];
+    GraphEntry& e = graphs[key];
     e.epoch = g_alloc_epoch.load();
     e.failed = failed;
     return;
@@ -265,9 +266,12 @@ void run_graph(mgm_ctx* c, Gauge& g, const GraphKey& key, F&& body) {
   const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess || g_alloc_epoch.load() != ep) {
+    // a failed instantiation is final; a buffer reallocated meanwhile (by
+    // another host thread) only means the next call runs directly again
     (void)hipGetLastError();
     if (exec) (void)hipGraphExecDestroy(exec);
-    it->second.failed = true;
+    it->second.failed = ie != hipSuccess;
+    it->second.epoch = ~0ull;
     body();
     return;
   }
@@ -293,8 +297,8 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   const int m = sp.restart;
   require(m >= 1 && m <= 63, "restart length must be in [1, 63]");
   require(sp.tol > 0, "tolerance must be positive");
-  ensure_work<double>(L, nrhs, m);
-  Work<double>& W = L.wd;
+  ensure_work<double>(L, c->wslot, nrhs, m);
+  Work<double>& W = L.wd[c->wslot];
   W.flags.ensure(nrhs);
   cd* V = W.V.as<cd>();
   cd* Z = W.Z.as<cd>();
@@ -324,7 +328,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 
   bool final_known = false;  // hr holds the residuals of the returned x
   if (L.has_dense) {
-    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch);
+    launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch[c->wslot]);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
       // r0 = b - D x ; v0 = r0 / ||r0||

@@ -16,8 +16,10 @@
 // go into one solve per level: a coarse level is small enough that its
 // kernels cost nearly the same for 32 or 64 right-hand sides, and each
 // right-hand side still has its own Krylov space and stopping test.
+#include <array>
 #include <cmath>
 #include <complex>
+#include <thread>
 
 #include "internal.h"
 
@@ -75,12 +77,20 @@ struct Estimator {
     hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
   }
 
-  void solve(int l, int k, const cd* b, cd* x) {
+  // solve on level l through the view cv (this thread's, or the worker's on
+  // the field's second stream); solve and iteration counts go to cnt[l]
+  void solve_on(mgm_ctx* cv, int l, int k, const cd* b, cd* x, std::vector<std::array<int64_t, 2>>& cnt) {
     std::vector<int> its(k);
-    const int st = solve_chunked(c, g, l, k, b, x, p.solve, its.data(), nullptr);
+    const int st = solve_chunked(cv, g, l, k, b, x, p.solve, its.data(), nullptr);
     if (st != MGM_OK) throw Error(st, "solve on level " + std::to_string(l) + " did not converge");
-    res.lvl_solves[l] += k;
-    for (int v : its) res.lvl_iters[l] += v;
+    cnt[l][0] += k;
+    for (int v : its) cnt[l][1] += v;
+  }
+  void solve(int l, int k, const cd* b, cd* x) {
+    std::vector<std::array<int64_t, 2>> cnt(MGM_MAX_LEVELS, {0, 0});
+    solve_on(c, l, k, b, x, cnt);
+    res.lvl_solves[l] += (int)cnt[l][0];
+    res.lvl_iters[l] += (int)cnt[l][1];
   }
 
   // lift(j, X) = Ph_j D_j^{-1} Ph_j^H X for fine vectors X (full form)
@@ -161,6 +171,7 @@ struct Estimator {
       crs[l + 1] = &it;
     }
     std::vector<int> own_off(L, 0), total(L, 0);
+    std::vector<const cd*> src(L, nullptr);
     for (int j = 0; j < L; ++j) {
       if (crs[j]) total[j] += crs[j]->k;
       if (own[j]) {
@@ -175,9 +186,8 @@ struct Estimator {
       const size_t cap = sizeof(cd) * (size_t)n * ((crs[j] ? kmax : 0) + (own[j] ? kmax : 0));
       DevBuf& out = g.est.lout[j];
       out.ensure(cap);
-      const cd* src = nullptr;
       if (!crs[j]) {
-        src = own[j]->X;  // only difference j's fine part: no gather needed
+        src[j] = own[j]->X;  // only difference j's fine part: no gather needed
       } else {
         DevBuf& in = g.est.lin[j];
         in.ensure(cap);
@@ -187,10 +197,10 @@ struct Estimator {
         if (own[j])
           HIPCHK(hipMemcpyAsync(in.as<cd>() + (int64_t)own_off[j] * n, own[j]->X,
                                 sizeof(cd) * (size_t)own[j]->k * n, hipMemcpyDeviceToDevice, s));
-        src = in.as<cd>();
+        src[j] = in.as<cd>();
       }
-      solve(j, total[j], src, out.as<cd>());
     }
+    solve_levels(total, src);
     t3.ensure(sizeof(cd) * (size_t)kmax * g.levels[0]->n);
     for (const Item& it : items) {
       const int l = lv[it.i].level;
@@ -200,6 +210,69 @@ struct Estimator {
       launch_prolong<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, it.k, coarse, t3.as<cd>(),
                              0, nullptr);
       launch_axpby<double>(s, 1.0, fine, -1.0, t3.as<cd>(), it.Y, F.n, it.k, nullptr);
+    }
+  }
+
+  // Solve level j's total[j] right-hand sides src[j] into g.est.lout[j] for
+  // every j.  The solves are independent: the finest runs on this thread and
+  // the field's stream, the others one after the other on the field's second
+  // stream from a worker thread with its own workspace set, so the
+  // latency-bound coarse-level kernels overlap the fine level's.
+  void solve_levels(const std::vector<int>& total, const std::vector<const cd*>& src) {
+    std::vector<int> todo;
+    for (int j = 0; j < L; ++j)
+      if (total[j] > 0) todo.push_back(j);
+    std::vector<std::array<int64_t, 2>> cnt(MGM_MAX_LEVELS, {0, 0}), wcnt(MGM_MAX_LEVELS, {0, 0});
+    auto out = [&](int j) { return g.est.lout[j].as<cd>(); };
+    if (todo.size() < 2 || !p.concurrent) {
+      for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt);
+    } else {
+      if (!g.stream2) {
+        HIPCHK(hipStreamCreateWithFlags(&g.stream2, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
+      }
+      HIPCHK(hipEventRecord(g.ev_fork, c->stream));
+      HIPCHK(hipStreamWaitEvent(g.stream2, g.ev_fork, 0));
+      int wst = MGM_OK;
+      std::string wmsg;
+      std::thread worker([&] {
+        mgm_ctx w;  // worker view: second stream, workspace set 1, private scratch
+        w.device = c->device;
+        w.stream = g.stream2;
+        w.cnn = c->cnn;
+        w.wslot = 1;
+        try {
+          HIPCHK(hipSetDevice(c->device));
+          for (size_t q = 1; q < todo.size(); ++q) solve_on(&w, todo[q], total[todo[q]], src[todo[q]], out(todo[q]), wcnt);
+        } catch (const Error& e) {
+          wst = e.code;
+          wmsg = e.what();
+        } catch (const std::exception& e) {
+          wst = MGM_EHIP;
+          wmsg = e.what();
+        }
+      });
+      int st = MGM_OK;
+      std::string msg;
+      try {
+        solve_on(c, todo[0], total[todo[0]], src[todo[0]], out(todo[0]), cnt);
+      } catch (const Error& e) {
+        st = e.code;
+        msg = e.what();
+      } catch (const std::exception& e) {
+        st = MGM_EHIP;
+        msg = e.what();
+      }
+      worker.join();
+      HIPCHK(hipEventRecord(g.ev_join, g.stream2));
+      HIPCHK(hipStreamWaitEvent(c->stream, g.ev_join, 0));
+      if (st != MGM_OK) throw Error(st, msg);
+      if (wst != MGM_OK) throw Error(wst, wmsg);
+    }
+    for (int j = 0; j < L; ++j) {
+      res.lvl_solves[j] += (int)(cnt[j][0] + wcnt[j][0]);
+      res.lvl_iters[j] += (int)(cnt[j][1] + wcnt[j][1]);
     }
   }
 
