@@ -27,9 +27,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # red/black SAP cycles per level of the V-cycle (fine, first coarse, deeper)
 # and the SAP blocks below the fine level (2x1 sites on the first coarse level,
-# single sites deeper): a sweep on the 128^2 workload puts the minimum of time
-# per estimate at heavy smoothing of the first coarse level
-SAP_CYCLES = (3, 8, 3, 3, 3, 3)
+# single sites deeper): a sweep on the 128^2 workload (fine-level solves
+# concurrent with the coarse-level ones) puts the minimum of time per
+# estimate at 4 / 8 / 3
+SAP_CYCLES = (4, 8, 3, 3, 3, 3)
 COARSE_SAP_BLOCKS = [(2, 1), (1, 1), (1, 1), (1, 1), (1, 1)]
 
 

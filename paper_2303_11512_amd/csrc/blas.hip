@@ -403,23 +403,28 @@ __global__ void __launch_bounds__(NT) k_done_from_norm(const T* __restrict__ bno
 // Gram partials on the FP64 matrix cores: partial[chunk][i][j] = sum over the
 // chunk's k of conj(Y_i[k]) Y_j[k], d <= 64.  A workgroup owns GCH elements
 // of k; its waves take the 16 x 16 output tiles (i-tile, j-tile) in turn.
-constexpr int GCH = 256;
+// The k loop has a fixed trip count and clamped loads, so a wave keeps
+// several k steps of loads in flight.
+constexpr int GCH = 128;
 __global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, int64_t n, int d,
                                                      cd* __restrict__ partial) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15;
   const int nt = (d + 15) / 16;
   const int64_t k0 = (int64_t)blockIdx.x * GCH;
-  const int64_t k1 = min(n, k0 + GCH);
   for (int tile = wave; tile < nt * nt; tile += 4) {
     const int i0 = (tile / nt) * 16, j0 = (tile % nt) * 16;
     const int i = i0 + r, j = j0 + r;
+    const cd* Yi = Y + (int64_t)(i < d ? i : 0) * n;
+    const cd* Yj = Y + (int64_t)(j < d ? j : 0) * n;
     CAcc<double> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int64_t kc = k0; kc < k1; kc += 4) {
-      const int64_t k = kc + (lane >> 4);
-      const bool in = k < k1;
-      const cd a = ld_or0(Y + (int64_t)(i < d ? i : 0) * n + (in ? k : 0), in && i < d);
-      const cd b = ld_or0(Y + (int64_t)(j < d ? j : 0) * n + (in ? k : 0), in && j < d);
+#pragma unroll 16
+    for (int kk = 0; kk < GCH; kk += 4) {
+      const int64_t k = k0 + kk + (lane >> 4);
+      const bool in = k < n;
+      const int64_t kc = in ? k : 0;
+      const cd a = ld_or0(Yi + kc, in && i < d);
+      const cd b = ld_or0(Yj + kc, in && j < d);
       cmma(conj(a), b, acc);
     }
     // element v: row i0 + out_row(lane, v), column j0 + lane % 16
@@ -431,37 +436,53 @@ __global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, i
   }
 }
 
+// G[e] = sum over chunks of partial[chunk][e]: a workgroup owns 8 consecutive
+// elements (one 128-byte row of every chunk), 32 threads per element stride
+// over the chunks, then the 32 sums are added in a fixed order.
 __global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ partial, int nch, int d,
                                                     cd* __restrict__ G) {
-  const int pr = blockIdx.x * NT + threadIdx.x;
-  if (pr >= d * d) return;
+  __shared__ cd sh[32][8];
+  const int t = threadIdx.x, e8 = t & 7, c0 = t >> 3;
+  const int dd = d * d;
+  const int e = blockIdx.x * 8 + e8;
+  const int ec = e < dd ? e : 0;
   cd acc = mk(0.0, 0.0);
-  for (int c = 0; c < nch; ++c) acc = acc + partial[(int64_t)c * d * d + pr];
-  G[pr] = acc;
+#pragma unroll 4
+  for (int c = c0; c < nch; c += 32) acc = acc + partial[(int64_t)c * dd + ec];
+  sh[c0][e8] = acc;
+  __syncthreads();
+  if (t < 8 && blockIdx.x * 8 + t < dd) {
+    cd sum = mk(0.0, 0.0);
+    for (int q = 0; q < 32; ++q) sum = sum + sh[q][t];
+    G[blockIdx.x * 8 + t] = sum;
+  }
 }
 
 // G + shift * tr(G) * I = R^H R (R upper, positive real diagonal); on exit G
 // holds R^{-1} (upper).  One workgroup, the matrix in LDS: right-looking
-// Cholesky with the trailing update spread over the threads, then thread t
-// back-substitutes column t of R^{-1}.  *fail is set on a non-positive pivot.
+// Cholesky with the trailing update spread over the threads, then R^{-1} by
+// backward Gauss-Jordan.  *fail is set on a non-positive pivot.
 __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d, double shift,
                                                       int* __restrict__ fail) {
   __shared__ cd R[64][65];
   __shared__ cd X[64][65];
   __shared__ double trs;
   const int t = threadIdx.x;
-  if (t == 0) {
-    double tr = 0.0;
-    for (int j = 0; j < d; ++j) tr += G[j * d + j].re;
-    trs = shift * tr;
-  }
-  __syncthreads();
+  // all loads of G issued together (a loop of dependent global loads here
+  // would cost a memory round trip per element)
+#pragma unroll 4
   for (int e = t; e < d * d; e += NT) {
     const int a = e / d, b = e % d;
-    cd v = b >= a ? G[e] : mk(0.0, 0.0);
-    if (a == b) v.re += trs;
-    R[a][b] = v;
+    const cd v = G[e];
+    R[a][b] = b >= a ? v : mk(0.0, 0.0);
   }
+  __syncthreads();
+  if (t < 64) {  // shift * tr(G), summed by wave 0
+    const double tr = wave_sum(t < d ? R[t][t].re : 0.0);
+    if (t == 0) trs = shift * tr;
+  }
+  __syncthreads();
+  if (t < d) R[t][t].re += trs;
   __syncthreads();
   bool failed = false;
   for (int j = 0; j < d; ++j) {
@@ -487,17 +508,23 @@ __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d,
     if (t == 0) atomicOr(fail, 1);
     return;
   }
-  // column t of R^{-1}: R x = e_t by back substitution
-  if (t < d) {
-    for (int i = d - 1; i > t; --i) X[i][t] = mk(0.0, 0.0);
-    X[t][t] = mk(1.0 / R[t][t].re, 0.0);
-    for (int i = t - 1; i >= 0; --i) {
-      cd acc = mk(0.0, 0.0);
-      for (int k = i + 1; k <= t; ++k) cfma(acc, R[i][k], X[k][t]);
-      X[i][t] = (-1.0 / R[i][i].re) * acc;
-    }
-  }
+  // X = R^{-1} by backward Gauss-Jordan on [R | I]: for j = d-1 .. 0, row j
+  // of R is R_jj e_j once the columns right of j are eliminated, so row j of X
+  // is divided by R_jj and R_ij X_j is subtracted from every row i < j (R_ij
+  // itself is never changed by the earlier steps).  Every step spreads over
+  // the whole workgroup; a per-column back substitution would walk up to
+  // d^2/2 dependent LDS reads in one thread.
+  for (int e = t; e < d * d; e += NT) X[e / d][e % d] = mk(e / d == e % d ? 1.0 : 0.0, 0.0);
   __syncthreads();
+  for (int j = d - 1; j >= 0; --j) {
+    if (t >= j && t < d) X[j][t] = (1.0 / R[j][j].re) * X[j][t];
+    __syncthreads();
+    for (int e = t; e < j * d; e += NT) {
+      const int i = e / d, c = e % d;
+      if (c >= j) X[i][c] = X[i][c] - R[i][j] * X[j][c];
+    }
+    __syncthreads();
+  }
   for (int e = t; e < d * d; e += NT) G[e] = X[e / d][e % d];
 }
 
@@ -648,7 +675,7 @@ void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partia
   const unsigned nch = (unsigned)((n + GCH - 1) / GCH);
   hipLaunchKernelGGL(k_gram_partial, dim3(nch), dim3(NT), 0, s, Y, n, d, partial);
   KCHK();
-  hipLaunchKernelGGL(k_gram_reduce, dim3((d * d + NT - 1) / NT), dim3(NT), 0, s, partial, (int)nch, d, G);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((d * d + 7) / 8), dim3(NT), 0, s, partial, (int)nch, d, G);
   KCHK();
 }
 

@@ -418,19 +418,14 @@ void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
   cd* G = c->qr_G.as<cd>();
   int* fail = c->qr_fail.as<int>();
   HIPCHK(hipMemsetAsync(fail, 0, sizeof(int), s));
-  // pass 0: Y -> tmp (shifted Gram), pass 1: tmp -> Q, pass 2: copy of Q -> Q
+  // pass 0: Y -> Q (shifted Gram), pass 1: Q -> tmp, pass 2: tmp -> Q
+  require(Y != Q, "orthonormalize: Y and Q must not overlap");
   const double shifts[3] = {1e-14, 0.0, 0.0};
+  const cd* srcs[3] = {Y, Q, tmp};
+  cd* dsts[3] = {Q, tmp, Q};
   for (int pass = 0; pass < 3; ++pass) {
-    const cd* src = Y;
-    cd* dst = tmp;
-    if (pass == 1) {
-      src = tmp;
-      dst = Q;
-    } else if (pass == 2) {
-      HIPCHK(hipMemcpyAsync(tmp, Q, sizeof(cd) * (size_t)d * n, hipMemcpyDeviceToDevice, s));
-      src = tmp;
-      dst = Q;
-    }
+    const cd* src = srcs[pass];
+    cd* dst = dsts[pass];
     launch_gram(s, src, n, d, G, c->qr_part.as<cd>());
     launch_cholesky_rinv(s, G, d, shifts[pass], fail);
     launch_right_tri(s, src, G, n, d, dst);

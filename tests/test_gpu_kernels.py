@@ -65,7 +65,7 @@ def test_wilson_periodic_bc(ctx, Lx, Lt):
     assert rel_err(to_host(y), (wilson_dirac(th, 0.3, bc_t_anti=False) @ x.T).T) < 1e-14
 
 
-@pytest.mark.parametrize("n,d", [(1000, 7), (4097, 32), (300, 1)])
+@pytest.mark.parametrize("n,d", [(1000, 7), (4097, 32), (300, 1), (70001, 64), (20000, 48), (32768, 32)])
 def test_orthonormalize_is_qr_plus(ctx, n, d):
     log(f"orthonormalize n={n} d={d}")
     rs = np.random.default_rng(n + d)
