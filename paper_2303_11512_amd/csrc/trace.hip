@@ -146,71 +146,90 @@ struct Estimator {
     launch_axpby<double>(s, 1.0, Y, -1.0, t1.as<cd>(), Y, n0, k, nullptr);
   }
 
-  // Y_i = A_i X_i for several level differences at once.  Reduced form: the
-  // right-hand sides of each operator level j -- P_{j-1}^H X_{j-1} of
-  // difference j-1, then X_j of difference j -- are solved together; then
-  // Y_i = (D_i^{-1} X_i) - P_i (D_{i+1}^{-1} P_i^H X_i).  Other forms apply
-  // the differences one after the other.
+  // Y = A_i X for several blocks of vectors, each of one level difference i
+  // (a difference may bring several blocks).  Reduced form: the right-hand
+  // sides of each operator level j -- P_{j-1}^H X of the blocks of difference
+  // j-1, then the X of the blocks of difference j -- are solved together; then
+  // Y = (D_i^{-1} X) - P_i (D_{i+1}^{-1} P_i^H X) per block.  Other forms
+  // apply the blocks one after the other.
   struct Item {
     int i, k;
     const cd* X;
     cd* Y;
   };
+  static constexpr int kSegs = 4;  // most blocks one level's solve gathers
   void applyA_levels(const std::vector<StochLevel>& lv, const std::vector<Item>& items) {
     if (hutch || full) {
       for (const Item& it : items) applyA(lv[it.i], it.k, it.X, it.Y);
       return;
     }
     hipStream_t s = c->stream;
-    std::vector<const Item*> own(L, nullptr), crs(L, nullptr);
-    for (const Item& it : items) {
-      const int l = lv[it.i].level;
-      require(l + 1 < L && !own[l], "applyA_levels: bad level difference");
-      require(it.k >= 1 && it.k <= kmax, "applyA_levels: too many vectors");
-      own[l] = &it;
-      crs[l + 1] = &it;
+    const int ni = (int)items.size();
+    // segments of level j: (block, coarse part?) -- coarse parts first
+    std::vector<std::vector<std::pair<int, bool>>> segs(L);
+    for (int q = 0; q < ni; ++q) {
+      const int l = lv[items[q].i].level;
+      require(l + 1 < L, "applyA_levels: bad level difference");
+      require(items[q].k >= 1 && items[q].k <= kmax, "applyA_levels: too many vectors");
+      segs[l + 1].push_back({q, true});
     }
-    std::vector<int> own_off(L, 0), total(L, 0);
+    for (int q = 0; q < ni; ++q) segs[lv[items[q].i].level].push_back({q, false});
+    std::vector<int> own_off(ni, 0), crs_off(ni, 0), total(L, 0);
     std::vector<const cd*> src(L, nullptr);
     for (int j = 0; j < L; ++j) {
-      if (crs[j]) total[j] += crs[j]->k;
-      if (own[j]) {
-        own_off[j] = total[j];
-        total[j] += own[j]->k;
+      if (segs[j].empty()) continue;
+      require((int)segs[j].size() <= kSegs, "applyA_levels: too many blocks on one level");
+      for (const auto& sg : segs[j]) {
+        (sg.second ? crs_off : own_off)[sg.first] = total[j];
+        total[j] += items[sg.first].k;
       }
-      if (!total[j]) continue;
       Level& Lj = *g.levels[j];
       const int64_t n = Lj.n;
       // sized for the most vectors any call can bring, so that later
       // estimates reuse the buffers (captured graphs stay valid)
-      const size_t cap = sizeof(cd) * (size_t)n * ((crs[j] ? kmax : 0) + (own[j] ? kmax : 0));
-      DevBuf& out = g.est.lout[j];
-      out.ensure(cap);
-      if (!crs[j]) {
-        src[j] = own[j]->X;  // only difference j's fine part: no gather needed
-      } else {
-        DevBuf& in = g.est.lin[j];
-        in.ensure(cap);
-        Level& F = *g.levels[j - 1];
-        launch_restrict<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, crs[j]->k, crs[j]->X,
-                                in.as<cd>(), nullptr);
-        if (own[j])
-          HIPCHK(hipMemcpyAsync(in.as<cd>() + (int64_t)own_off[j] * n, own[j]->X,
-                                sizeof(cd) * (size_t)own[j]->k * n, hipMemcpyDeviceToDevice, s));
-        src[j] = in.as<cd>();
+      const size_t cap = sizeof(cd) * (size_t)n * kSegs * kmax;
+      g.est.lout[j].ensure(cap);
+      if (segs[j].size() == 1 && !segs[j][0].second) {
+        src[j] = items[segs[j][0].first].X;  // one fine-part block: solved in place
+        continue;
       }
+      DevBuf& in = g.est.lin[j];
+      in.ensure(cap);
+      for (const auto& sg : segs[j]) {
+        const Item& it = items[sg.first];
+        cd* dst = in.as<cd>() + (int64_t)total_before(segs[j], items, sg) * n;
+        if (sg.second) {
+          Level& F = *g.levels[j - 1];
+          launch_restrict<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, it.k, it.X, dst, nullptr);
+        } else {
+          HIPCHK(hipMemcpyAsync(dst, it.X, sizeof(cd) * (size_t)it.k * n, hipMemcpyDeviceToDevice, s));
+        }
+      }
+      src[j] = in.as<cd>();
     }
     solve_levels(total, src);
     t3.ensure(sizeof(cd) * (size_t)kmax * g.levels[0]->n);
-    for (const Item& it : items) {
+    for (int q = 0; q < ni; ++q) {
+      const Item& it = items[q];
       const int l = lv[it.i].level;
       Level& F = *g.levels[l];
-      const cd* fine = g.est.lout[l].as<cd>() + (int64_t)own_off[l] * F.n;
-      const cd* coarse = g.est.lout[l + 1].as<cd>();  // the coarse part comes first
+      Level& C = *g.levels[l + 1];
+      const cd* fine = g.est.lout[l].as<cd>() + (int64_t)own_off[q] * F.n;
+      const cd* coarse = g.est.lout[l + 1].as<cd>() + (int64_t)crs_off[q] * C.n;
       launch_prolong<double>(s, F.d.P.as<cd>(), F.Nx, F.Nt, F.M, F.bx, F.bt, F.ntv, it.k, coarse, t3.as<cd>(),
                              0, nullptr);
       launch_axpby<double>(s, 1.0, fine, -1.0, t3.as<cd>(), it.Y, F.n, it.k, nullptr);
     }
+  }
+  // vectors ahead of segment sg in its level's gathered block
+  static int total_before(const std::vector<std::pair<int, bool>>& segs, const std::vector<Item>& items,
+                          const std::pair<int, bool>& sg) {
+    int off = 0;
+    for (const auto& x : segs) {
+      if (x == sg) break;
+      off += items[x.first].k;
+    }
+    return off;
   }
 
   // Solve level j's total[j] right-hand sides src[j] into g.est.lout[j] for
@@ -291,7 +310,12 @@ struct Estimator {
 
   // Hutch++ low-rank parts of all differences (d_i > 0), sweep by sweep:
   // k sweeps of Y = A S, Q = qr(Y), S = Q; then tau_lr = sum_i q_i^H A q_i.
-  void low_rank_all(std::vector<StochLevel>& lv) {
+  // The solves of the last round (A Q) go together with those of the first
+  // stochastic batch (A zeta does not depend on Q; only the projection of
+  // zeta, applied afterwards, does): first[i] samples of difference i,
+  // returned in first_vals.
+  void low_rank_all(std::vector<StochLevel>& lv, const std::vector<int>& first,
+                    std::vector<std::vector<zc>>& first_vals) {
     std::vector<Item> items;
     for (int i = 0; i < (int)lv.size(); ++i) {
       StochLevel& sl = lv[i];
@@ -303,7 +327,10 @@ struct Estimator {
       launch_noise<double>(c->stream, g.est.S[i].as<cd>(), sl.n, sl.d, p.noise, p.seed, MGM_PURPOSE_SKETCH, i, 0);
       items.push_back({i, sl.d, g.est.S[i].as<cd>(), g.est.Y[i].as<cd>()});
     }
-    if (items.empty()) return;
+    if (items.empty()) {
+      sample_batches(lv, first, first_vals);
+      return;
+    }
     for (int it = 0; it < std::max(1, p.k_power); ++it) {
       applyA_levels(lv, items);
       for (Item& x : items) {
@@ -311,31 +338,39 @@ struct Estimator {
         x.X = lv[x.i].Q->as<cd>();
       }
     }
+    const size_t nlr = items.size();
+    sample_start(lv, first, items);
     applyA_levels(lv, items);
-    for (const Item& x : items) {
+    for (size_t q = 0; q < nlr; ++q) {
+      const Item& x = items[q];
       std::vector<zc> v;
       dots_host(x.X, x.Y, lv[x.i].n, x.k, v);
       zc acc = 0;
       for (const zc& y : v) acc += y;
       lv[x.i].tau_lr = acc;
     }
+    sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()), first_vals);
   }
 
-  // samples tau_{s,l} = z^H (A zeta), z = zeta - Q (Q^H zeta), indices
-  // s0[i] .. s0[i]+b[i]-1 of every difference i with b[i] > 0
-  void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b,
-                      std::vector<std::vector<zc>>& out) {
-    hipStream_t s = c->stream;
-    std::vector<Item> items;
+  // noise zeta for samples s .. s+b[i]-1 of every difference i with b[i] > 0
+  // (s = samples taken so far); appends the blocks Y = A zeta to `items`
+  void sample_start(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Item>& items) {
     for (int i = 0; i < (int)lv.size(); ++i) {
       if (b[i] <= 0) continue;
       StochLevel& sl = lv[i];
       g.est.Z[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
       g.est.X[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
-      launch_noise<double>(s, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed, MGM_PURPOSE_SAMPLE, i, sl.s());
+      launch_noise<double>(c->stream, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed, MGM_PURPOSE_SAMPLE, i,
+                           sl.s());
       items.push_back({i, b[i], g.est.Z[i].as<cd>(), g.est.X[i].as<cd>()});
     }
-    applyA_levels(lv, items);
+  }
+
+  // tau_{s,l} = z^H (A zeta) with z = zeta - Q (Q^H zeta), for the blocks
+  // sample_start made (X = zeta, Y = A zeta)
+  void sample_finish(std::vector<StochLevel>& lv, const std::vector<Item>& items,
+                     std::vector<std::vector<zc>>& out) {
+    hipStream_t s = c->stream;
     for (const Item& it : items) {
       StochLevel& sl = lv[it.i];
       const int64_t n = sl.n;
@@ -353,6 +388,14 @@ struct Estimator {
     }
   }
 
+  void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b,
+                      std::vector<std::vector<zc>>& out) {
+    std::vector<Item> items;
+    sample_start(lv, b, items);
+    applyA_levels(lv, items);
+    sample_finish(lv, items, out);
+  }
+
   std::vector<double> weights(const std::vector<StochLevel>& lv) {
     const int nl = (int)lv.size();
     std::vector<double> w(nl, 1.0 / nl);
@@ -366,6 +409,41 @@ struct Estimator {
     if (!std::isfinite(tot) || tot == 0.0) return w;
     for (int i = 0; i < nl; ++i) w[i] = cv[i] / tot;
     return w;
+  }
+
+  // samples of the next speculative batch for every active level.  The
+  // batch length only decides how much work may be discarded, never the
+  // result: in adaptive mode it is the number of samples the current
+  // variances and targets predict are still missing (all active levels
+  // advance together, as in Alg. 2), between 4 and p.batch; s is the number
+  // of samples taken per level so far and tau the current estimate.
+  std::vector<int> batch_sizes(const std::vector<StochLevel>& lv, int s, zc tau, int maxS) {
+    const int nst = (int)lv.size();
+    const int minS = std::max(2, p.min_samples);
+    int common = p.batch;
+    if (!p.fixed_samples) {
+      if (s < 2) {
+        common = std::max(minS, p.batch / 2);
+      } else {
+        const std::vector<double> w = weights(lv);
+        double need = 0;
+        for (int i = 0; i < nst; ++i) {
+          if (!lv[i].active) continue;
+          const double rho2 = w[i] * (p.eps * std::abs(tau)) * (p.eps * std::abs(tau));
+          const double want = rho2 > 0 ? lv[i].var() / rho2 : 1e30;
+          need = std::max(need, std::isfinite(want) ? want - lv[i].s() : 1e30);
+        }
+        common = (int)std::min<double>(p.batch, std::max(4.0, std::ceil(1.15 * need) + 2));
+      }
+    }
+    std::vector<int> nb(nst, 0);
+    for (int i = 0; i < nst; ++i) {
+      if (!lv[i].active) continue;
+      int b = common;
+      if (p.fixed_samples) b = std::min(b, p.fixed_samples[i] - lv[i].s());
+      nb[i] = std::min(b, maxS - lv[i].s());
+    }
+    return nb;
   }
 
   double nnz_model(int j) const {
@@ -400,46 +478,29 @@ struct Estimator {
     for (int i = 0; i < nst; ++i) kmax = std::max(kmax, lv[i].d);
     // every reduction workspace at its largest size up front (no reallocation later)
     part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
-    low_rank_all(lv);
-
     const int minS = std::max(2, p.min_samples);
     const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
     zc tau = 0;
     int s = 0;
+    // the first stochastic batch rides with the last low-rank round
+    std::vector<std::vector<zc>> pre(nst);
+    bool have_pre = false;
+    if (lr) {
+      const std::vector<int> nb = batch_sizes(lv, s, tau, maxS);
+      low_rank_all(lv, nb, pre);
+      have_pre = true;
+    }
     while (true) {
       bool any = false;
       for (auto& sl : lv) any = any || sl.active;
       if (!any) break;
-      // speculative batch for every active level.  The batch length only
-      // decides how much work may be discarded, never the result: in
-      // adaptive mode it is the number of samples the current variances and
-      // targets predict are still missing (all active levels advance
-      // together, as in Alg. 2), between 4 and p.batch.
-      int common = p.batch;
-      if (!p.fixed_samples) {
-        if (s < 2) {
-          common = std::max(minS, p.batch / 2);
-        } else {
-          const std::vector<double> w = weights(lv);
-          double need = 0;
-          for (int i = 0; i < nst; ++i) {
-            if (!lv[i].active) continue;
-            const double rho2 = w[i] * (p.eps * std::abs(tau)) * (p.eps * std::abs(tau));
-            const double want = rho2 > 0 ? lv[i].var() / rho2 : 1e30;
-            need = std::max(need, std::isfinite(want) ? want - lv[i].s() : 1e30);
-          }
-          common = (int)std::min<double>(p.batch, std::max(4.0, std::ceil(1.15 * need) + 2));
-        }
-      }
       std::vector<std::vector<zc>> vals(nst);
-      std::vector<int> nb(nst, 0);
-      for (int i = 0; i < nst; ++i) {
-        if (!lv[i].active) continue;
-        int b = common;
-        if (p.fixed_samples) b = std::min(b, p.fixed_samples[i] - lv[i].s());
-        nb[i] = std::min(b, maxS - lv[i].s());
+      if (have_pre) {
+        vals.swap(pre);
+        have_pre = false;
+      } else {
+        sample_batches(lv, batch_sizes(lv, s, tau, maxS), vals);
       }
-      sample_batches(lv, nb, vals);
       // replay Alg. 2 sample by sample; stop where an active level has no
       // evaluated sample left (levels advance in lockstep)
       for (int t = 0; t < p.batch; ++t) {
