@@ -1129,6 +1129,7 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   constexpr int SB = 4, NS = SB * SB, K = 2 * NS;
   __shared__ cx<T> Is[K * K];
   __shared__ cx<T> Bs[NS * 5 * 4];
+  __shared__ cx<T> Hs[4][16][K + 1];  // per wave: 16 RHS x the block's 32 dofs
   const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / SB;
   const int bx = (blk % NBx) * SB, bt = (blk / NBx) * SB;
@@ -1138,32 +1139,41 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
     const int64_t us = (int64_t)(bt + s / SB) * Nx + bx + s % SB;
     Bs[e] = B[us * 20 + e % 20];
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (blockIdx.y * 4 + wave) * 16;
-  if (r0 >= nrhs) return;
-  const int i = lane & 15;
-  const int r = r0 + i;
-  const bool ok = r < nrhs;
   const int64_t n = (int64_t)Nx * Nt * 2;
-  const cx<T>* xr = x + (int64_t)(ok ? r : r0) * n;
-  const cx<T>* rv = rr + (int64_t)(ok ? r : r0) * n;
-  // h = r_B - D_BH x_H at this lane's 8 K indices (chunk c: k = 16 (c / 4) + out_row(lane, c % 4))
-  cx<T> h[8];
+  // Halo term h = r_B - D_BH x_H on the vector units, lanes along the block's
+  // dofs (k = lane % 32: a time row of the block is 8 consecutive dofs) and
+  // two RHS per pass, so a load instruction covers 8 segments of 64 bytes.
+  // A wave whose RHS are all past nrhs still runs (clamped loads, no stores)
+  // so that every wave reaches the barriers.
+  const int k = lane & 31;
+  const int s = k >> 1, a = k & 1, sx = s & 3, st = s >> 2;
+  const int gx = bx + sx, gt = bt + st;
+  const int own = gt * Nx + gx;
+  // at most two outward hops per site of a 4x4 block; unused slots point at
+  // the site itself so that every load is unconditional
+  int nbs[2] = {own, own}, dirs[2] = {0, 0}, nh = 0;
+  if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
+  if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
+  if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
+  if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
+  __syncthreads();
+  cx<T> bb[2][2];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int k = 16 * (c >> 2) + MF<T>::out_row(lane, c & 3);
-    const int s = k >> 1, a = k & 1, sx = s & 3, st = s >> 2;
-    const int gx = bx + sx, gt = bt + st;
-    // at most two outward hops per site of a 4x4 block; unused slots point at
-    // the site itself so that every load is unconditional
-    const int own = gt * Nx + gx;
-    int nbs[2] = {own, own}, dirs[2] = {0, 0}, nh = 0;
-    if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
-    if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
-    if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
-    if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
-    cx<T> acc = rv[(int64_t)own * 2 + a];
+  for (int j = 0; j < 2; ++j) {
+    const cx<T>* bp = Bs + (s * 5 + dirs[j]) * 4 + a * 2;
+    const bool use = j < nh;
+    bb[j][0] = use ? bp[0] : mk<T>(0, 0);
+    bb[j][1] = use ? bp[1] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int ri = 2 * p + (lane >> 5);
+    const int r = r0 + ri;
+    const int64_t rc = r < nrhs ? r : 0;
+    const cx<T>* xr = x + rc * n;
+    cx<T> acc = rr[rc * n + (int64_t)own * 2 + a];
     cx<T> xh[2][2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -1171,31 +1181,38 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
       xh[j][1] = xr[(int64_t)nbs[j] * 2 + 1];
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (ok && j < nh) {
-        const cx<T>* bb = Bs + (s * 5 + dirs[j]) * 4 + a * 2;
-        acc = acc - bb[0] * xh[j][0] - bb[1] * xh[j][1];
-      }
-    h[c] = acc;
+    for (int j = 0; j < 2; ++j) acc = acc - bb[j][0] * xh[j][0] - bb[j][1] * xh[j][1];
+    Hs[wave][ri][k] = acc;
   }
-  const bool store = ok && !(active && !active[r]);
+  __syncthreads();
+  // x_B = inv_B h: the 32 x 32 solve as two 16-row tiles of complex MFMAs
+  // over 8 K-chunks (B operand: K index x 16 RHS, read back from LDS)
+  const int i = lane & 15;
+  cx<T> h[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) h[c] = Hs[wave][i][16 * (c >> 2) + MF<T>::out_row(lane, c & 3)];
+  CAcc<T> acc[2];
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
-    CAcc<T> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+    acc[half] = CAcc<T>{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int kcol = 16 * (c >> 2) + MF<T>::out_row(lane, c & 3);
-      cmma(Is[(half * 16 + i) * K + kcol], h[c], acc);
+      cmma(Is[(half * 16 + i) * K + kcol], h[c], acc[half]);
     }
-    if (store) {
+  }
+  __syncthreads();  // every lane has read its h before Hs is overwritten
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = half * 16 + MF<T>::out_row(lane, v);
-        const int s = row >> 1;
-        const int64_t us = (int64_t)(bt + (s >> 2)) * Nx + bx + (s & 3);
-        x[(int64_t)r * n + us * 2 + (row & 1)] = mk<T>(acc.re[v], acc.im[v]);
-      }
-    }
+  for (int half = 0; half < 2; ++half)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Hs[wave][i][half * 16 + MF<T>::out_row(lane, v)] = mk<T>(acc[half].re[v], acc[half].im[v]);
+  __syncthreads();
+  // coalesced stores, lanes along the block's dofs as for the loads
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int ri = 2 * p + (lane >> 5);
+    const int r = r0 + ri;
+    if (r < nrhs && !(active && !active[r])) x[(int64_t)r * n + (int64_t)own * 2 + a] = Hs[wave][ri][k];
   }
 }
 
