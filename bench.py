@@ -296,6 +296,15 @@ def run_mixed(args):
                          samples=est["level_samples"])
         print(f"# {prec}: {nrhs / dt:.1f} solves/s, {np.mean(its):.2f} it, max relres {np.max(rel):.2e}, "
               f"estimate {est['tau']:.6f} in {res[prec]['trace_s']:.2f}s", file=sys.stderr, flush=True)
+    # the fine stencil at this size: 64 RHS are 1.07 GB of input, far beyond
+    # the 256 MB Infinity Cache, so this is the HBM-bound figure
+    ctx.set_precision(gid, "fp64")
+    st = ctx.time_kernel(gid, "stencil", 0, KERNEL_RHS)
+    ach = st["bytes"] / (st["us"] * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": f"fine stencil, FP64, 512x512, {KERNEL_RHS} RHS",
+            "launch_us": st["us"], "alg_bytes": st["bytes"]}
+    print(f"# stencil 512^2: {st['us']:.1f} us, {ach:.0f} GB/s", file=sys.stderr, flush=True)
     xn = torch.linalg.norm(res["fp64"]["x"])
     tau64 = res["fp64"]["tau"]
     for p in ("fp32", "fp16"):
@@ -315,7 +324,7 @@ def run_mixed(args):
                                f"{kw['blocks']} (MLMC closes on level {kw['mlmc_levels'] - 1}), 256 Z2xZ2 RHS "
                                f"in blocks of 64, FGMRES(16) tol 1e-10; one MG-MLMC++ estimate to {cfg['eps']}",
                    "fp64": res["fp64"], "fp32": res["fp32"], "fp16": res["fp16"], "setup_s": setup_s},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": None,
     }))
     ctx.close()
 

@@ -146,8 +146,10 @@ __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T di
   store_stream(yr + 2 * site + 1, a1);
 }
 
-// Row strips for lattices with Lx a multiple of 64 up to 256: a workgroup of
-// Lx threads (thread = column) walks TR consecutive time slices of one RHS.
+// Row strips for lattices whose rows split into 64-multiple pieces of at most
+// 256 sites: a workgroup of Lx / SPT threads (thread = SPT columns, blockDim
+// apart, so each column slice of a row is one coalesced segment) walks TR
+// consecutive time slices of one RHS.
 // Each spinor is loaded from global memory once per strip (plus the two rows
 // bordering it): the rows behind, at and ahead of the current one roll
 // through registers, and the +-x neighbours of the current row come from a
@@ -156,21 +158,27 @@ __global__ void __launch_bounds__(NT) k_wilson(const cx<T>* __restrict__ U, T di
 // between).  Even strips walk up in t and odd strips down, so the two rows on
 // each strip boundary are read by both neighbouring strips at the same phase
 // (both at the start or both at the end) and the second read hits L2.
-template <class T, int TR>
+template <class T, int TR, int SPT>
 __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U, T diag, int Lx, int Lt,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                      const cx<T>* __restrict__ b,
                                                      const int* __restrict__ active) {
-  __shared__ cx<T> sx[2][2][NT];
-  __shared__ cx<T> su[2][NT];
+  __shared__ cx<T> sx[2][2][NT * SPT];
+  __shared__ cx<T> su[2][NT * SPT];
   const int64_t G = gridDim.x;
   const int64_t Lg = xcd_tile(blockIdx.x + G * blockIdx.y, G * gridDim.y);
   const int r = (int)(Lg / G);
   const int strip = (int)(Lg % G);
   if (active && !active[r]) return;
   const int64_t V = (int64_t)Lx * Lt;
-  const int xx = threadIdx.x;
-  const int xp = xx + 1 == Lx ? 0 : xx + 1, xm = xx == 0 ? Lx - 1 : xx - 1;
+  const int BD = blockDim.x;
+  int xs[SPT], xp[SPT], xm[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    xs[j] = threadIdx.x + j * BD;
+    xp[j] = xs[j] + 1 == Lx ? 0 : xs[j] + 1;
+    xm[j] = xs[j] == 0 ? Lx - 1 : xs[j] - 1;
+  }
   const cx<T>* __restrict__ xr = x + (int64_t)r * 2 * V;
   const cx<T>* __restrict__ U1 = U + V;
   cx<T>* __restrict__ yr = y + (int64_t)r * 2 * V;
@@ -181,38 +189,52 @@ __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U
   const int tb = wrap(tf - dir);
   // rows behind (t - dir) and at t; ur is U1 of the row below the current
   // one when walking up, of the current row when walking down
-  cx<T> h0 = xr[2 * ((int64_t)tb * Lx + xx)], h1 = xr[2 * ((int64_t)tb * Lx + xx) + 1];
-  cx<T> c0 = xr[2 * ((int64_t)tf * Lx + xx)], c1 = xr[2 * ((int64_t)tf * Lx + xx) + 1];
-  cx<T> ur = U1[(int64_t)(up ? tb : tf) * Lx + xx];
+  cx<T> h0[SPT], h1[SPT], c0[SPT], c1[SPT], ur[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    h0[j] = xr[2 * ((int64_t)tb * Lx + xs[j])];
+    h1[j] = xr[2 * ((int64_t)tb * Lx + xs[j]) + 1];
+    c0[j] = xr[2 * ((int64_t)tf * Lx + xs[j])];
+    c1[j] = xr[2 * ((int64_t)tf * Lx + xs[j]) + 1];
+    ur[j] = U1[(int64_t)(up ? tb : tf) * Lx + xs[j]];
+  }
 #pragma unroll 2
   for (int i = 0; i < TR; ++i) {
     const int t = tf + dir * i;
     const int ta = wrap(t + dir);
-    const int64_t site = (int64_t)t * Lx + xx;
-    const cx<T> a0x = xr[2 * ((int64_t)ta * Lx + xx)], a1x = xr[2 * ((int64_t)ta * Lx + xx) + 1];
-    const cx<T> ul = U1[(int64_t)(up ? t : ta) * Lx + xx];
-    const cx<T> u0 = U[site];
     const int bs = i & 1;
-    sx[bs][0][xx] = c0;
-    sx[bs][1][xx] = c1;
-    su[bs][xx] = u0;
-    __syncthreads();
-    cx<T> a0, a1;
-    wilson_site<T>(diag, c0, c1, sx[bs][0][xp], sx[bs][1][xp], u0, sx[bs][0][xm], sx[bs][1][xm], su[bs][xm],
-                   up ? a0x : h0, up ? a1x : h1, up ? ul : ur, up ? h0 : a0x, up ? h1 : a1x, up ? ur : ul, a0,
-                   a1);
-    if (b) {
-      const cx<T>* br = b + (int64_t)r * 2 * V;
-      a0 = br[2 * site] - a0;
-      a1 = br[2 * site + 1] - a1;
+    cx<T> a0x[SPT], a1x[SPT], ul[SPT], u0[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      a0x[j] = xr[2 * ((int64_t)ta * Lx + xs[j])];
+      a1x[j] = xr[2 * ((int64_t)ta * Lx + xs[j]) + 1];
+      ul[j] = U1[(int64_t)(up ? t : ta) * Lx + xs[j]];
+      u0[j] = U[(int64_t)t * Lx + xs[j]];
+      sx[bs][0][xs[j]] = c0[j];
+      sx[bs][1][xs[j]] = c1[j];
+      su[bs][xs[j]] = u0[j];
     }
-    store_stream(yr + 2 * site, a0);
-    store_stream(yr + 2 * site + 1, a1);
-    h0 = c0;
-    h1 = c1;
-    c0 = a0x;
-    c1 = a1x;
-    ur = ul;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int64_t site = (int64_t)t * Lx + xs[j];
+      cx<T> a0, a1;
+      wilson_site<T>(diag, c0[j], c1[j], sx[bs][0][xp[j]], sx[bs][1][xp[j]], u0[j], sx[bs][0][xm[j]],
+                     sx[bs][1][xm[j]], su[bs][xm[j]], up ? a0x[j] : h0[j], up ? a1x[j] : h1[j],
+                     up ? ul[j] : ur[j], up ? h0[j] : a0x[j], up ? h1[j] : a1x[j], up ? ur[j] : ul[j], a0, a1);
+      if (b) {
+        const cx<T>* br = b + (int64_t)r * 2 * V;
+        a0 = br[2 * site] - a0;
+        a1 = br[2 * site + 1] - a1;
+      }
+      store_stream(yr + 2 * site, a0);
+      store_stream(yr + 2 * site + 1, a1);
+      h0[j] = c0[j];
+      h1[j] = c1[j];
+      c0[j] = a0x[j];
+      c1[j] = a1x[j];
+      ur[j] = ul[j];
+    }
   }
 }
 
@@ -1654,46 +1676,63 @@ template void launch_noise<float>(hipStream_t, cf*, int64_t, int, int, uint64_t,
 
 // Workgroups of k_wilson_strip (128 threads, its LDS rows) the device keeps
 // resident at once, from the runtime's occupancy calculator; per device.
-template <class T>
-int64_t strip_capacity() {
-  static std::atomic<int64_t> cap[64];
+// Workgroups of k_wilson_strip<T, *, SPT> with `threads` threads the whole
+// device holds at once (per device, cached).
+template <class T, int SPT>
+int64_t strip_capacity(int threads) {
+  static std::atomic<int64_t> cap[64][5];
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   require(dev >= 0 && dev < 64, "device index out of range");
-  int64_t c = cap[dev].load(std::memory_order_relaxed);
+  const int slot = threads / 64;  // 1 .. 4
+  int64_t c = cap[dev][slot].load(std::memory_order_relaxed);
   if (c == 0) {
     int per_cu = 0, cus = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_wilson_strip<T, 8>, 128, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_wilson_strip<T, 8, SPT>, threads,
+                                                        0));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     c = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
-    cap[dev].store(c, std::memory_order_relaxed);
+    cap[dev][slot].store(c, std::memory_order_relaxed);
   }
   return c;
+}
+
+template <class T, int SPT>
+void launch_wilson_strip(hipStream_t s, const cx<T>* links, T diag, int Lx, int Lt, int nrhs, const cx<T>* x,
+                         cx<T>* y, const cx<T>* b, const int* active) {
+  // strip height: the smallest that keeps every workgroup resident at once
+  // (more, shorter strips hide more latency; a second round of workgroups
+  // costs more than it hides)
+  const int threads = Lx / SPT;
+  const int64_t cap = strip_capacity<T, SPT>(threads);
+  int tr = 0;
+  for (int c : {1, 2, 4, 8, 16})
+    if (Lt % c == 0) {
+      tr = c;
+      if ((int64_t)(Lt / c) * nrhs <= cap) break;
+    }
+  const dim3 g(Lt / tr, nrhs), blk(threads);
+  switch (tr) {
+    case 1: hipLaunchKernelGGL((k_wilson_strip<T, 1, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    case 2: hipLaunchKernelGGL((k_wilson_strip<T, 2, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    case 4: hipLaunchKernelGGL((k_wilson_strip<T, 4, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    case 8: hipLaunchKernelGGL((k_wilson_strip<T, 8, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    default: hipLaunchKernelGGL((k_wilson_strip<T, 16, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+  }
 }
 
 template <class T>
 void launch_wilson(hipStream_t s, const cx<T>* links, T diag, int Lx, int Lt, int nrhs,
                    const cx<T>* x, cx<T>* y, const cx<T>* b, const int* active) {
   const int64_t V = (int64_t)Lx * Lt;
+  // row strips when a row splits into 1, 2 or 4 slices of a 64-multiple of
+  // at most NT sites; the thread-per-site kernel otherwise
   if (Lx % 64 == 0 && Lx <= NT) {
-    // strip height: the smallest that keeps every workgroup resident at once
-    // (more, shorter strips hide more latency; a second round of workgroups
-    // costs more than it hides)
-    const int64_t cap = strip_capacity<T>();
-    int tr = 0;
-    for (int c : {1, 2, 4, 8, 16})
-      if (Lt % c == 0) {
-        tr = c;
-        if ((int64_t)(Lt / c) * nrhs <= cap) break;
-      }
-    const dim3 g(Lt / tr, nrhs), blk(Lx);
-    switch (tr) {
-      case 1: hipLaunchKernelGGL((k_wilson_strip<T, 1>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
-      case 2: hipLaunchKernelGGL((k_wilson_strip<T, 2>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
-      case 4: hipLaunchKernelGGL((k_wilson_strip<T, 4>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
-      case 8: hipLaunchKernelGGL((k_wilson_strip<T, 8>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
-      default: hipLaunchKernelGGL((k_wilson_strip<T, 16>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
-    }
+    launch_wilson_strip<T, 1>(s, links, diag, Lx, Lt, nrhs, x, y, b, active);
+  } else if (Lx % 128 == 0 && Lx <= 2 * NT) {
+    launch_wilson_strip<T, 2>(s, links, diag, Lx, Lt, nrhs, x, y, b, active);
+  } else if (Lx % 256 == 0 && Lx <= 4 * NT) {
+    launch_wilson_strip<T, 4>(s, links, diag, Lx, Lt, nrhs, x, y, b, active);
   } else {
     hipLaunchKernelGGL(k_wilson<T>, dim3(grid1(V), nrhs), dim3(NT), 0, s, links, diag, Lx, Lt, x, y, b,
                        active);

@@ -35,12 +35,16 @@ def test_noise_bit_exact(ctx, kind):
 # Lx a multiple of 64 (<= 256) takes the row-strip kernel, whose strip height
 # (1..16 rows) follows Lt and the RHS count: the cases below reach every height
 # on MI355X, including a ragged count of strips (Lt = 40) and the fallback
-# when no height keeps every workgroup resident (Lt = 12, 700 RHS).
+# when no height keeps every workgroup resident (Lt = 12, 700 RHS).  Wider rows
+# take the strip kernel with 2 (Lx = 384, 512) or 4 (Lx = 768, 1024) columns
+# per thread; Lx = 640 has no such split and takes the thread-per-site kernel.
 @pytest.mark.parametrize("Lx,Lt,nrhs,m0", [(8, 8, 1, -0.05), (10, 6, 5, 0.2), (34, 18, 3, -0.1),
                                            (128, 128, 64, -0.1), (64, 64, 16, -0.1),
                                            (192, 24, 7, 0.1), (64, 40, 200, -0.05),
                                            (64, 256, 96, -0.1), (128, 12, 700, 0.0),
-                                           (256, 32, 3, -0.08)])
+                                           (256, 32, 3, -0.08), (384, 16, 5, -0.1),
+                                           (512, 64, 9, -0.08), (768, 8, 3, 0.1),
+                                           (1024, 16, 4, -0.05), (640, 8, 2, 0.0)])
 def test_wilson_apply_matches_oracle(ctx, Lx, Lt, nrhs, m0):
     log(f"wilson apply {Lx}x{Lt} nrhs={nrhs}")
     th = metropolis_u1(Lx, Lt, 3.0, 30, 17 + Lx)
@@ -54,7 +58,7 @@ def test_wilson_apply_matches_oracle(ctx, Lx, Lt, nrhs, m0):
     assert rel_err(to_host(y), want) < 1e-14
 
 
-@pytest.mark.parametrize("Lx,Lt", [(8, 8), (64, 16)])
+@pytest.mark.parametrize("Lx,Lt", [(8, 8), (64, 16), (512, 8)])
 def test_wilson_periodic_bc(ctx, Lx, Lt):
     th = metropolis_u1(Lx, Lt, 2.0, 20, 3)
     gid = ctx.set_gauge(to_dev(links_from_theta(th)), 0.3, False)
