@@ -1706,13 +1706,15 @@ void launch_wilson_strip(hipStream_t s, const cx<T>* links, T diag, int Lx, int 
   const int threads = Lx / SPT;
   const int64_t cap = strip_capacity<T, SPT>(threads);
   int tr = 0;
-  for (int c : {1, 2, 4, 8, 16})
+  for (int c : {1, 2, 4, 8, 16, 32, 64})
     if (Lt % c == 0) {
       tr = c;
       if ((int64_t)(Lt / c) * nrhs <= cap) break;
     }
   const dim3 g(Lt / tr, nrhs), blk(threads);
   switch (tr) {
+    case 32: hipLaunchKernelGGL((k_wilson_strip<T, 32, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
+    case 64: hipLaunchKernelGGL((k_wilson_strip<T, 64, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
     case 1: hipLaunchKernelGGL((k_wilson_strip<T, 1, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
     case 2: hipLaunchKernelGGL((k_wilson_strip<T, 2, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;
     case 4: hipLaunchKernelGGL((k_wilson_strip<T, 4, SPT>), g, blk, 0, s, links, diag, Lx, Lt, x, y, b, active); break;

@@ -38,13 +38,15 @@ def test_noise_bit_exact(ctx, kind):
 # when no height keeps every workgroup resident (Lt = 12, 700 RHS).  Wider rows
 # take the strip kernel with 2 (Lx = 384, 512) or 4 (Lx = 768, 1024) columns
 # per thread; Lx = 640 has no such split and takes the thread-per-site kernel.
+# Many RHS on a short lattice (64 x 128, 640 RHS) need strips of 32 or 64 rows.
 @pytest.mark.parametrize("Lx,Lt,nrhs,m0", [(8, 8, 1, -0.05), (10, 6, 5, 0.2), (34, 18, 3, -0.1),
                                            (128, 128, 64, -0.1), (64, 64, 16, -0.1),
                                            (192, 24, 7, 0.1), (64, 40, 200, -0.05),
                                            (64, 256, 96, -0.1), (128, 12, 700, 0.0),
                                            (256, 32, 3, -0.08), (384, 16, 5, -0.1),
                                            (512, 64, 9, -0.08), (768, 8, 3, 0.1),
-                                           (1024, 16, 4, -0.05), (640, 8, 2, 0.0)])
+                                           (1024, 16, 4, -0.05), (640, 8, 2, 0.0),
+                                           (64, 128, 640, -0.1), (512, 128, 64, -0.08)])
 def test_wilson_apply_matches_oracle(ctx, Lx, Lt, nrhs, m0):
     log(f"wilson apply {Lx}x{Lt} nrhs={nrhs}")
     th = metropolis_u1(Lx, Lt, 3.0, 30, 17 + Lx)
