@@ -182,6 +182,39 @@ def test_guess_has_minimal_residual_along_the_network_output(ctx, trained):
         assert np.linalg.norm(b[r] - alpha * u) <= np.linalg.norm(b[r])
 
 
+def test_trained_network_lowers_the_initial_residual(ctx, trained):
+    """What training gains: the minimal-residual guess x0 = alpha f(b) of the
+    trained network against that of the untrained (initial) network and
+    against x0 = 0 (relative residual 1), on right-hand sides it has not seen.
+    The residuals use the oracle's D."""
+    rec, gid, _ = trained
+    D = dirac.wilson_dirac(rec.theta, rec.m0)
+    n = D.shape[0]
+    b = rhs_vectors(n, 16, 904)
+
+    def mean_guess_residual():
+        y = empty(16, n)
+        ctx.cnn_apply(gid, to_dev(b), y)
+        yh = to_host(y)
+        res = []
+        for r in range(16):
+            u = D @ yh[r]
+            alpha = np.vdot(u, b[r]) / np.vdot(u, u)
+            res.append(np.linalg.norm(b[r] - alpha * u) / np.linalg.norm(b[r]))
+        return float(np.mean(res))
+
+    good = ctx.cnn_get_params()
+    trained_res = mean_guess_residual()
+    try:
+        ctx.cnn_set_params(cnn_init_params(21))
+        untrained_res = mean_guess_residual()
+    finally:
+        ctx.cnn_set_params(good)
+    log(f"initial residual: x0 = 0 1.0, untrained {untrained_res:.4f}, trained {trained_res:.4f}")
+    assert trained_res < untrained_res
+    assert trained_res < 0.95
+
+
 def test_broken_network_falls_back_to_plain_multigrid(ctx, trained):
     from paper_2303_11512_amd import solve_params
     rec, gid, _ = trained
