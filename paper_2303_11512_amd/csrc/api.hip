@@ -395,7 +395,15 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         launch_convert<float, double>(s, r, rf, (int64_t)nrhs * n);
         const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.sbt == 1 &&
                           (L.sbx == 1 || L.sbx == 2) && L.f.hblocks.p != nullptr;
-        if (half) {
+        // the premultiplied two-site sweep x_B = rho_B - M_B x_H of the later
+        // cycles (rf stands in for rho)
+        const bool premul = half && L.sbx == 2 && L.f.hsapM.p != nullptr;
+        if (premul) {
+          launch = [=, &L] {
+            launch_sap2p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
+                           L.ncolor[0], nrhs, false, nullptr, rf, xf, nullptr);
+          };
+        } else if (half) {
           launch = [=, &L] {
             launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.sbx, L.sbt,
                          L.color_list[0].as<int>(), L.ncolor[0], nrhs, rf, xf, nullptr);
@@ -410,8 +418,11 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         const double halo = 2.0 * (L.sbx + L.sbt) * L.M;
         const double hx = (double)sap_halo_sites(L) * L.M;
         const double mb = half ? 4.0 : 8.0;  // bytes per complex matrix entry
-        bytes = 8.0 * b * (2.0 * nb * L.K + hx) + mb * nb * ((double)L.K * L.K + halo * L.M);
-        flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
+        // matrix entries per block: inv_B (K^2) and the outward hops (halo M),
+        // or M_B (K x halo) in the premultiplied form
+        const double ment = premul ? (double)L.K * halo : (double)L.K * L.K + halo * L.M;
+        bytes = 8.0 * b * (2.0 * nb * L.K + hx) + mb * nb * ment;
+        flops = 8.0 * b * nb * ment;
         break;
       }
       case MGM_KERNEL_DENSE:

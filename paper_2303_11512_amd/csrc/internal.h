@@ -239,6 +239,13 @@ void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nr
                       const cf* b, const int* active);
 void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
                   const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active);
+// Two-site (2x1) FP16 SAP in premultiplied form: M_B = inv_B D_BH at setup
+// ([nblk][6 hops][32][16] FP16) and a colour sweep x_B = rho_B - M_B x_H; the
+// first sweep of each colour in a visit (`first`) forms rho_B = inv_B r_B
+// from r and stores it in rho ([nrhs][n]) for the later ones
+void launch_sap2_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, chalf* M);
+void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active);
 // In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A.
 int dense_inverse(hipStream_t s, cd* A, int64_t n, cd* scratch_out);
 void launch_diag_sum(hipStream_t s, const cd* A, int64_t n, cd* out);
@@ -303,6 +310,7 @@ struct LevelData {
   DevBuf sapinv;   // [nblk][K][K]
   DevBuf dinv;     // coarsest: [n][n]
   DevBuf hblocks, hsapinv;  // FP16 copies of blocks / sapinv (16-dof coarse levels)
+  DevBuf hsapM;             // FP16 inv_B D_BH of 2x1 SAP blocks (16-dof coarse levels)
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 
@@ -339,6 +347,7 @@ struct Work {  // FGMRES + multigrid workspace of one level in one precision
   int64_t n = 0;
   DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, coef, coef2;
   DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
+  DevBuf rho;                        // inv_B r_B of the premultiplied SAP
   PinnedFlags flags;                 // active flags read back during FGMRES
 };
 

@@ -1061,6 +1061,137 @@ __global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, cons
   }
 }
 
+// ---- Two-site FP16 SAP in premultiplied form.  With the exact block
+// inverse, x_B = inv_B (r_B - D_BH x_H) = rho_B - M_B x_H, where
+// M_B = inv_B D_BH (32 x 96: the six outward hops of the 2x1 block, 16 dofs
+// each) is formed once at setup and rho_B = inv_B r_B by the first sweep of
+// each colour in a smoothing visit (r does not change during the cycles).  A colour sweep is then one
+// dependent stage: each wave owns a 16 x 16 tile of x_B (16 block rows x 16
+// RHS) and sums its six hop products itself, so there is no reduction
+// between waves, no LDS and no barrier.
+// Outward hops h = 0..5: site 0 (-x, +t, -t), site 1 (+x, +t, -t).
+__device__ __forceinline__ int sap2_hop_site(int h) { return h < 3 ? 0 : 1; }
+__device__ __forceinline__ int sap2_hop_dir(int h) { return h == 0 ? 2 : (h == 3 ? 1 : (h % 3 == 1 ? 3 : 4)); }
+
+// M[blk][h][row][col] = sum_k inv[blk][row][16 s(h) + k] B[u_s(h)][dir(h)][k][col], in FP64, stored FP16
+__global__ void __launch_bounds__(NT) k_sap2_premul(const cd* __restrict__ B, const cd* __restrict__ inv,
+                                                    int Nx, int nblk, chalf* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)nblk * 6 * 32 * CM) return;
+  const int col = (int)(e % CM), row = (int)((e / CM) % 32), h = (int)((e / (CM * 32)) % 6);
+  const int blk = (int)(e / (CM * 32 * 6));
+  const int NBx = Nx / 2;
+  const int64_t us = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2 + sap2_hop_site(h);
+  const cd* ir = inv + ((int64_t)blk * 32 + row) * 32 + 16 * sap2_hop_site(h);
+  const cd* bc = B + ((us * 5 + sap2_hop_dir(h)) * CM) * CM + col;
+  cd acc = mk(0.0, 0.0);
+  for (int k = 0; k < CM; ++k) cfma(acc, ir[k], bc[(int64_t)k * CM]);
+  M[e] = chalf{(_Float16)acc.re, (_Float16)acc.im};
+}
+
+// One colour: x_B = rho_B - M_B x_H; wave w owns all 32 block rows of RHS
+// tile 4 blockIdx.y + w, so each halo value is loaded once per RHS tile.
+// FIRST (the colour's first sweep of a smoothing visit): rho_B = inv_B r_B
+// is formed here from r and kept in rho for the later cycles.
+template <bool FIRST>
+__global__ void __launch_bounds__(NT) k_sap2p_h(const chalf* __restrict__ M, const chalf* __restrict__ inv,
+                                                int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                const cf* __restrict__ rr, cf* __restrict__ rho,
+                                                cf* __restrict__ x, const int* __restrict__ active) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int r0 = (blockIdx.y * 4 + wave) * 16;
+  if (r0 >= nrhs) return;
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
+  const int NBx = Nx / 2;
+  const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2;
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  // every load of the wave is issued before the first product
+  h4 br[6], bi[6];
+#pragma unroll
+  for (int h = 0; h < 6; ++h) {
+    const cf* xv = x + rrow * n + nb_site(u0 + sap2_hop_site(h), sap2_hop_dir(h), Nx, Nt) * CM + 4 * q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cf v = xv[j];
+      br[h][j] = (_Float16)v.re;
+      bi[h][j] = (_Float16)v.im;
+    }
+  }
+  h4 ar[2][6], ai[2][6];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+      const chalf* a = M + (((int64_t)blk * 6 + h) * 32 + rt * 16 + i) * CM + 4 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const chalf av = a[j];
+        ar[rt][h][j] = av.re;
+        ai[rt][h][j] = av.im;
+      }
+    }
+  CAcc<float> rv[2];
+  if constexpr (FIRST) {
+    // rho rows rt: sum over the two sites kt of inv_B[rt][kt] r_kt
+    h4 ir[2][2], ii[2][2], sr[2], si[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+      const cf* rv_ = rr + rrow * n + (u0 + kt) * CM + 4 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cf v = rv_[j];
+        sr[kt][j] = (_Float16)v.re;
+        si[kt][j] = (_Float16)v.im;
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const chalf* a = inv + ((int64_t)blk * 32 + rt * 16 + i) * 32 + kt * 16 + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const chalf av = a[j];
+          ir[rt][kt][j] = av.re;
+          ii[rt][kt][j] = av.im;
+        }
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      rv[rt] = CAcc<float>{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) hmma(ir[rt][kt], ii[rt][kt], sr[kt], si[kt], rv[rt]);
+      if (ok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rho[rrow * n + (u0 + rt) * CM + 4 * q + v] = mk<float>(rv[rt].re[v], rv[rt].im[v]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const cf t = rho[rrow * n + (u0 + rt) * CM + 4 * q + v];
+        rv[rt].re[v] = t.re;
+        rv[rt].im[v] = t.im;
+      }
+  }
+  const bool on = ok && (!active || active[rrow] != 0);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int h = 0; h < 6; ++h) hmma(ar[rt][h], ai[rt][h], br[h], bi[h], acc);
+    if (on) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        x[rrow * n + (u0 + rt) * CM + 4 * q + v] = mk<float>(rv[rt].re[v] - acc.re[v], rv[rt].im[v] - acc.im[v]);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(NT) k_to_half(const cd* __restrict__ in, chalf* __restrict__ out,
                                                 int64_t count) {
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -1790,6 +1921,23 @@ void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nr
                       const cf* b, const int* active) {
   hipLaunchKernelGGL(k_stencil_h, dim3((unsigned)((int64_t)Nx * Nt), (nrhs + 15) / 16), dim3(NT), 0, s,
                      blocks, Nx, Nt, nrhs, x, y, b, active);
+  KCHK();
+}
+
+void launch_sap2_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, chalf* M) {
+  const int64_t cnt = (int64_t)nblk * 6 * 32 * CM;
+  hipLaunchKernelGGL(k_sap2_premul, dim3((unsigned)((cnt + NT - 1) / NT)), dim3(NT), 0, s, blocks, inv, Nx, nblk, M);
+  KCHK();
+}
+
+void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active) {
+  if (nb <= 0) return;
+  const dim3 g(nb, ((nrhs + 15) / 16 + 3) / 4);
+  if (first)
+    hipLaunchKernelGGL(k_sap2p_h<true>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+  else
+    hipLaunchKernelGGL(k_sap2p_h<false>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
   KCHK();
 }
 

@@ -115,8 +115,20 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
   }
   bool half = false;
-  if constexpr (std::is_same<T, float>::value)
+  if constexpr (std::is_same<T, float>::value) {
     half = half_blocks(g, L) && L.sbt == 1 && (L.sbx == 1 || L.sbx == 2);
+    if (half && L.sbx == 2 && L.f.hsapM.p && L.sap_cycles > 0) {
+      // premultiplied two-site sweeps x_B = rho_B - M_B x_H; the first cycle
+      // forms rho_B = inv_B r_B and keeps it for the others
+      Work<float>& W = work<float>(L, c->wslot);
+      W.rho.ensure(sizeof(cf) * (size_t)nrhs * L.n);
+      for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
+        for (int col = 0; col < 2; ++col)
+          launch_sap2p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.color_list[col].as<int>(),
+                         L.ncolor[col], nrhs, cyc == 0, r, W.rho.as<cf>(), x, act);
+      return;
+    }
+  }
   for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
     for (int col = 0; col < 2; ++col) {
       if constexpr (std::is_same<T, float>::value) {
@@ -587,6 +599,10 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
       L.f.hsapinv.ensure(sizeof(chalf) * nin);
       launch_to_half(s, L.d.blocks.as<cd>(), L.f.hblocks.as<chalf>(), nbk);
       launch_to_half(s, L.d.sapinv.as<cd>(), L.f.hsapinv.as<chalf>(), nin);
+      if (L.sbx == 2 && L.sbt == 1 && L.nblk > 0) {
+        L.f.hsapM.ensure(sizeof(chalf) * (size_t)L.nblk * 6 * 32 * 16);  // 16 dofs per site
+        launch_sap2_premul(s, L.d.blocks.as<cd>(), L.d.sapinv.as<cd>(), L.Nx, L.nblk, L.f.hsapM.as<chalf>());
+      }
     }
   }
   HIPCHK(hipStreamSynchronize(s));
