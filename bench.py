@@ -68,7 +68,7 @@ KERNEL_RHS = 64
 # 128^2 step) per preconditioner precision: one colour of the SAP sweep on the
 # first coarse level (16 dofs per site)
 DOMINANT = {"fp64": "sap_l1", "fp32": "saplow_l1", "fp16": "saplow_l1"}
-KERNEL_NAME = {"fp64": "k_sap2_mfma<double>", "fp32": "k_sap2_mfma<float>", "fp16": "k_sap2p_h"}
+KERNEL_NAME = {"fp64": "k_sap2_mfma<double>", "fp32": "k_sap2_mfma<float>", "fp16": "k_sap2p_h<false>"}
 # counter summaries of those kernels (FETCH_SIZE / WRITE_SIZE runs, scaled by
 # the copy-kernel calibration), keyed to the source file they were measured from
 TRAFFIC_SUMMARY = {p: os.path.join(ROOT, "profiles", f"{KERNEL_NAME[p].replace('<', '_').replace('>', '')}"
