@@ -953,114 +953,6 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   for (int v = 0; v < 4; ++v) x[(int64_t)r * n + u * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
 }
 
-// Two-site blocks along x with FP16 blocks (see k_sap2_mfma).  Each wave loads
-// its hop blocks, then the x operands, and only after its hops the operands of
-// the block solve (waves 0 and 1).
-__global__ void __launch_bounds__(NT) k_sap2_h(const chalf* __restrict__ B, const chalf* __restrict__ inv,
-                                               int Nx, int Nt, const int* __restrict__ blist, int nrhs,
-                                               const cf* __restrict__ rr, cf* __restrict__ x,
-                                               const int* __restrict__ active) {
-  constexpr int RT = 1;  // RHS tiles of 16 per workgroup (2 and 4 measured slower)
-  __shared__ float red[RT][4][8][64];
-  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
-  const int NBx = Nx / 2;
-  const int64_t u0 = (int64_t)(blk / NBx) * Nx + (blk % NBx) * 2, u1 = u0 + 1;
-  const int64_t n = (int64_t)Nx * Nt * CM;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, q = lane >> 4;
-  // hop directions of this wave (u0: -x, +t | -t; u1: +x, +t | -t)
-  const int64_t us = wave < 2 ? u0 : u1;
-  const int nh = (wave == 0 || wave == 2) ? 2 : 1;
-  const int dirs[2] = {wave == 0 ? 2 : (wave == 2 ? 1 : 4), 3};
-  h4 bar[2], bai[2];
-  int64_t nbo[2];
-  // both hop slots are always loaded and multiplied (a wave with one hop
-  // multiplies a zero operand in its second slot): branch-free code keeps
-  // every load of the wave in flight at once
-#pragma unroll
-  for (int hh = 0; hh < 2; ++hh) {
-    const chalf* row = B + ((us * 5 + dirs[hh]) * CM + i) * CM + 4 * q;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      bar[hh][j] = row[j].re;
-      bai[hh][j] = row[j].im;
-    }
-    nbo[hh] = nb_site(us, dirs[hh], Nx, Nt) * CM + 4 * q;
-  }
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int r0 = (blockIdx.y * RT + rt) * 16;
-    const int r = r0 + i;
-    const bool ok = r < nrhs;
-    const int64_t rrow = ok ? r : 0;
-    CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      // an unused slot reads zeros (zero_cf), so its product adds exactly 0
-      const cf* xv = hh < nh ? x + rrow * n + nbo[hh] : zero_cf + 4 * q;
-      h4 br, bi;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const cf v = xv[j];
-        br[j] = (_Float16)v.re;
-        bi[j] = (_Float16)v.im;
-      }
-      hmma(bar[hh], bai[hh], br, bi, acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      red[rt][wave][v][lane] = acc.re[v];
-      red[rt][wave][4 + v][lane] = acc.im[v];
-    }
-  }
-  if (wave >= 2) {
-    __syncthreads();
-    return;
-  }
-  h4 iar[2], iai[2];
-  const chalf* Ih = inv + ((int64_t)blk * 32 + wave * 16 + i) * 32 + 4 * q;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    iar[0][j] = Ih[j].re;
-    iai[0][j] = Ih[j].im;
-    iar[1][j] = Ih[16 + j].re;
-    iai[1][j] = Ih[16 + j].im;
-  }
-  cf rv[RT][2][4];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int r = (blockIdx.y * RT + rt) * 16 + i;
-    const bool ok = r < nrhs;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t rc = ok ? r : 0;
-      rv[rt][0][j] = rr[rc * n + u0 * CM + 4 * q + j];
-      rv[rt][1][j] = rr[rc * n + u1 * CM + 4 * q + j];
-    }
-  }
-  __syncthreads();
-  const int64_t uo = wave == 0 ? u0 : u1;
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int r = (blockIdx.y * RT + rt) * 16 + i;
-    CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-    for (int sidx = 0; sidx < 2; ++sidx) {
-      h4 tr, ti;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        tr[j] = (_Float16)(rv[rt][sidx][j].re - red[rt][2 * sidx][j][lane] - red[rt][2 * sidx + 1][j][lane]);
-        ti[j] = (_Float16)(rv[rt][sidx][j].im - red[rt][2 * sidx][4 + j][lane] - red[rt][2 * sidx + 1][4 + j][lane]);
-      }
-      hmma(iar[sidx], iai[sidx], tr, ti, cor);
-    }
-    if (r < nrhs && !(active && !active[r])) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) x[(int64_t)r * n + uo * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
-    }
-  }
-}
-
 // ---- Two-site FP16 SAP in premultiplied form.  With the exact block
 // inverse, x_B = inv_B (r_B - D_BH x_H) = rho_B - M_B x_H, where
 // M_B = inv_B D_BH (32 x 96: the six outward hops of the 2x1 block, 16 dofs
@@ -1944,14 +1836,12 @@ void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int
 void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
                   const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active) {
   if (nb <= 0) return;
-  if (sbx == 2 && sbt == 1)
-    hipLaunchKernelGGL(k_sap2_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs,
-                       r, x, active);
-  else if (sbx == 1 && sbt == 1)
+  // (2x1 blocks take the premultiplied sweep, launch_sap2p_h)
+  if (sbx == 1 && sbt == 1)
     hipLaunchKernelGGL(k_sap_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs,
                        r, x, active);
   else
-    throw Error(MGM_EINVAL, "FP16 SAP: blocks must be 1x1 or 2x1 sites");
+    throw Error(MGM_EINVAL, "FP16 SAP: single-site blocks only (2x1 blocks use the premultiplied sweep)");
   KCHK();
 }
 
