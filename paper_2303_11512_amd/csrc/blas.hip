@@ -468,18 +468,21 @@ __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d,
   __shared__ cd X[64][65];
   __shared__ double trs;
   const int t = threadIdx.x;
+  // thread (row slot, column) = (t / 64, t % 64): rows stride 4, so no loop
+  // divides by the runtime size d
+  const int tr = t >> 6, tc = t & 63;
+  const bool col_ok = tc < d;
   // all loads of G issued together (a loop of dependent global loads here
   // would cost a memory round trip per element)
 #pragma unroll 4
-  for (int e = t; e < d * d; e += NT) {
-    const int a = e / d, b = e % d;
-    const cd v = G[e];
-    R[a][b] = b >= a ? v : mk(0.0, 0.0);
+  for (int a = tr; a < d; a += 4) {
+    const cd v = G[(col_ok ? a * d + tc : 0)];
+    if (col_ok) R[a][tc] = tc >= a ? v : mk(0.0, 0.0);
   }
   __syncthreads();
   if (t < 64) {  // shift * tr(G), summed by wave 0
-    const double tr = wave_sum(t < d ? R[t][t].re : 0.0);
-    if (t == 0) trs = shift * tr;
+    const double tr_sum = wave_sum(t < d ? R[t][t].re : 0.0);
+    if (t == 0) trs = shift * tr_sum;
   }
   __syncthreads();
   if (t < d) R[t][t].re += trs;
@@ -491,17 +494,15 @@ __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d,
       failed = true;
       break;
     }
-    const double rjj = sqrt(s);
+    const double rjj = sqrt(s), inv = 1.0 / rjj;
     __syncthreads();
     // row j of R: R[j][i] /= rjj (i > j); R[j][j] = rjj
-    for (int i = j + 1 + t; i < d; i += NT) R[j][i] = (1.0 / rjj) * R[j][i];
+    if (tr == 0 && tc > j && col_ok) R[j][tc] = inv * R[j][tc];
     if (t == 0) R[j][j] = mk(rjj, 0.0);
     __syncthreads();
-    const int m = d - j - 1;
-    for (int e = t; e < m * m; e += NT) {
-      const int k = j + 1 + e / m, i = j + 1 + e % m;
-      if (i >= k) R[k][i] = R[k][i] - cjmul(R[j][k], R[j][i]);
-    }
+    // trailing update of the upper triangle: R[k][i] -= conj(R[j][k]) R[j][i], i >= k > j
+    for (int k = j + 1 + tr; k < d; k += 4)
+      if (tc >= k && col_ok) R[k][tc] = R[k][tc] - cjmul(R[j][k], R[j][tc]);
     __syncthreads();
   }
   if (failed) {
@@ -514,18 +515,18 @@ __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d,
   // itself is never changed by the earlier steps).  Every step spreads over
   // the whole workgroup; a per-column back substitution would walk up to
   // d^2/2 dependent LDS reads in one thread.
-  for (int e = t; e < d * d; e += NT) X[e / d][e % d] = mk(e / d == e % d ? 1.0 : 0.0, 0.0);
+  for (int a = tr; a < d; a += 4)
+    if (col_ok) X[a][tc] = mk(a == tc ? 1.0 : 0.0, 0.0);
   __syncthreads();
   for (int j = d - 1; j >= 0; --j) {
-    if (t >= j && t < d) X[j][t] = (1.0 / R[j][j].re) * X[j][t];
+    if (tr == 0 && tc >= j && col_ok) X[j][tc] = (1.0 / R[j][j].re) * X[j][tc];
     __syncthreads();
-    for (int e = t; e < j * d; e += NT) {
-      const int i = e / d, c = e % d;
-      if (c >= j) X[i][c] = X[i][c] - R[i][j] * X[j][c];
-    }
+    for (int i = tr; i < j; i += 4)
+      if (tc >= j && col_ok) X[i][tc] = X[i][tc] - R[i][j] * X[j][tc];
     __syncthreads();
   }
-  for (int e = t; e < d * d; e += NT) G[e] = X[e / d][e % d];
+  for (int a = tr; a < d; a += 4)
+    if (col_ok) G[a * d + tc] = X[a][tc];
 }
 
 // Q_j[k] = sum_{i <= j} Y_i[k] Rinv[i][j] on the FP64 matrix cores: a wave
