@@ -110,8 +110,8 @@ def test_three_level_mlmcpp_parity(ctx, s32):
     assert abs(got["tau_exact"] - want["tau_exact"]) < 1e-9 * abs(want["tau"])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16"])
-def test_concurrent_level_solves_match_sequential(ctx, precision):
+@pytest.mark.parametrize("precision,mlmc", [("fp64", 3), ("fp16", 3), ("fp64", 4)])
+def test_concurrent_level_solves_match_sequential(ctx, precision, mlmc):
     """The reduced form solves each level once per phase; with `concurrent`
     the coarse levels run on the field's second stream (own workspaces and
     graphs) while the fine level runs on the first.  Per-sample values, the
@@ -120,21 +120,23 @@ def test_concurrent_level_solves_match_sequential(ctx, precision):
     th = metropolis_u1(32, 32, 3.0, 100, 951)
     rec = Recipe(th, -0.08, [(4, 4), (2, 2), (2, 2)], [8, 8, 8], seed=17,
                  sap_block=[(4, 4), (2, 1), (1, 1), (1, 1)], inner_iters=[0, 0, 0, 0],
-                 mlmc_levels=3, precision=precision)
-    log(f"setup concurrent {precision}")
+                 mlmc_levels=mlmc, precision=precision)
+    log(f"setup concurrent {precision} mlmc levels {mlmc}")
     gid = rec.gpu(ctx)
-    kw = dict(variant="mlmcpp", eps=2e-2, d=[8, 8], k_power=2, noise="z2z2", batch=16)
+    nd = mlmc - 1  # level differences
+    kw = dict(variant="mlmcpp", eps=2e-2, d=[8] * nd, k_power=2, noise="z2z2", batch=16)
     for rep in range(3):
         a = _gpu(ctx, gid, seed=40 + rep, concurrent=True, **kw)
         b = _gpu(ctx, gid, seed=40 + rep, concurrent=False, **kw)
         assert a["level_samples"] == b["level_samples"]
         assert abs(a["tau"] - b["tau"]) <= 1e-13 * abs(b["tau"])
-        for l in range(2):
+        for l in range(nd):
             assert np.max(np.abs(a["samples"][l] - b["samples"][l])) <= 1e-12 * np.max(np.abs(b["samples"][l]))
             assert abs(a["level_lr"][l] - b["level_lr"][l]) <= 1e-12 * abs(b["tau"])
     if precision == "fp64":
         hier = rec.oracle()
-        want = otr.estimate(hier, otr.TraceParams(seed=42, **{k: v for k, v in kw.items() if k != "batch"}, levels=3))
+        want = otr.estimate(hier, otr.TraceParams(seed=42, **{k: v for k, v in kw.items() if k != "batch"},
+                                                  levels=mlmc))
         _cmp(a, want)
 
 
