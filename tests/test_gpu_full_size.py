@@ -1,0 +1,69 @@
+"""Solves at the full size of the 128^2 plain-method-at-scale workload (beta
+3.0 Metropolis field, m0 = -0.1, 4x4 then 2x2 aggregates with 8 test
+vectors, solver-only 2x2 coarsenings below), in the hierarchy, SAP schedule
+and 64-RHS batch of the timed estimator step.  The solver stops on its own
+FP64 residual; here every solution's true residual is recomputed on the CPU
+with the oracle's Wilson-Dirac operator (Sec. 4's Schwinger discretisation),
+for the FP16-block preconditioner the step uses and for the plain FP64 one,
+and the two solutions are compared with each other."""
+import numpy as np
+import pytest
+
+from bench import mg_setup_kwargs
+from gpu_util import empty, log, rel_err, to_dev, to_host
+from lattice_inputs import WORKLOADS, gauge_for, links_from_theta, rhs_vectors
+from oracle.dirac import wilson_dirac
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+NRHS = 64
+# the CPU recomputation of ||b - D x|| / ||b|| differs from the GPU's only by
+# summation order: |D| ~ 4 and |x| / |b| < 1e3 here give well under 1e-12
+RES_SLACK = 1e-12
+
+
+@pytest.fixture(scope="module")
+def full128():
+    from paper_2303_11512_amd import Context, mg_params
+    cfg = WORKLOADS["schwinger128"]
+    th = gauge_for(cfg)
+    ctx = Context(0)
+    gid = ctx.set_gauge(to_dev(links_from_theta(th)), cfg["m0"], True)
+    log("setup schwinger128 (fp16 blocks)")
+    ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg), precision="fp16"))
+    D = wilson_dirac(th, cfg["m0"], True)
+    yield ctx, gid, D
+    ctx.close()
+
+
+def _solve(ctx, gid, b):
+    from paper_2303_11512_amd import solve_params
+    x = empty(b.shape[0], b.shape[1])
+    st, its, rel = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=TOL, restart=32, max_restarts=50))
+    return to_host(x), np.asarray(its), np.asarray(rel)
+
+
+def test_full_size_solves_meet_tolerance_with_oracle_operator(full128):
+    ctx, gid, D = full128
+    b = rhs_vectors(D.shape[0], NRHS, 128)
+    xs = {}
+    try:
+        for prec in ("fp16", "fp64"):
+            ctx.set_precision(gid, prec)
+            log(f"schwinger128: solve {NRHS} RHS, {prec} preconditioner")
+            x, its, rel = _solve(ctx, gid, b)
+            res = np.linalg.norm(b - (D @ x.T).T, axis=1) / np.linalg.norm(b, axis=1)
+            log(f"  iterations {its.min()}-{its.max()}, oracle residual max {res.max():.3e}")
+            assert np.all(np.isfinite(x))
+            assert np.all(rel <= TOL), rel.max()
+            assert np.all(res <= TOL + RES_SLACK), res.max()
+            assert np.all(np.abs(res - rel) <= RES_SLACK), np.abs(res - rel).max()
+            xs[prec] = x
+    finally:
+        ctx.set_precision(gid, "fp16")
+    # both solve the same systems to 1e-10: they agree to within the
+    # condition number times the tolerance
+    d = rel_err(xs["fp16"], xs["fp64"])
+    log(f"  fp16 vs fp64 preconditioner solutions: rel. difference {d:.2e}")
+    assert d < 1e-6
