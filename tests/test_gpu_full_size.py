@@ -1,11 +1,15 @@
-"""Solves at the full size of the 128^2 plain-method-at-scale workload (beta
+"""Solves at full workload sizes.  128^2 plain-method-at-scale workload (beta
 3.0 Metropolis field, m0 = -0.1, 4x4 then 2x2 aggregates with 8 test
 vectors, solver-only 2x2 coarsenings below), in the hierarchy, SAP schedule
 and 64-RHS batch of the timed estimator step.  The solver stops on its own
 FP64 residual; here every solution's true residual is recomputed on the CPU
 with the oracle's Wilson-Dirac operator (Sec. 4's Schwinger discretisation),
 for the FP16-block preconditioner the step uses and for the plain FP64 one,
-and the two solutions are compared with each other."""
+and the two solutions are compared with each other.  512^2 mixed-precision
+workload (beta 4.0, m0 = -0.08, 4x4 then 4x4 aggregates): 256 RHS in blocks
+of 64 with the FP64, FP32 and FP16-block preconditioners inside FP64
+FGMRES, the same check per RHS and the low-precision solutions against the
+FP64 one."""
 import numpy as np
 import pytest
 
@@ -67,3 +71,49 @@ def test_full_size_solves_meet_tolerance_with_oracle_operator(full128):
     d = rel_err(xs["fp16"], xs["fp64"])
     log(f"  fp16 vs fp64 preconditioner solutions: rel. difference {d:.2e}")
     assert d < 1e-6
+
+
+@pytest.fixture(scope="module")
+def full512():
+    from paper_2303_11512_amd import Context, mg_params
+    cfg = WORKLOADS["schwinger512"]
+    th = gauge_for(cfg)
+    ctx = Context(0)
+    gid = ctx.set_gauge(to_dev(links_from_theta(th)), cfg["m0"], True)
+    log("setup schwinger512")
+    ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg)))
+    D = wilson_dirac(th, cfg["m0"], True)
+    yield ctx, gid, D
+    ctx.close()
+
+
+def test_full_size_mixed_precision_solves_512(full512):
+    from paper_2303_11512_amd import solve_params
+    ctx, gid, D = full512
+    nrhs = 256
+    b = rhs_vectors(D.shape[0], nrhs, 512)
+    bn = np.linalg.norm(b, axis=1)
+    bd = to_dev(b)
+    xs = {}
+    try:
+        for prec in ("fp64", "fp32", "fp16"):
+            ctx.set_precision(gid, prec)
+            log(f"schwinger512: solve {nrhs} RHS in blocks of 64, {prec} preconditioner")
+            x = empty(nrhs, D.shape[0])
+            st, its, rel = ctx.solve_batch(gid, 0, bd, x, solve_params(tol=TOL, restart=16, max_restarts=50,
+                                                                       rhs_block=64))
+            xh = to_host(x)
+            del x
+            res = np.linalg.norm(b - (D @ xh.T).T, axis=1) / bn
+            its, rel = np.asarray(its), np.asarray(rel)
+            log(f"  iterations {its.min()}-{its.max()}, oracle residual max {res.max():.3e}")
+            assert np.all(np.isfinite(xh))
+            assert np.all(rel <= TOL), rel.max()
+            assert np.all(res <= TOL + RES_SLACK), res.max()
+            xs[prec] = xh
+    finally:
+        ctx.set_precision(gid, "fp64")
+    for prec in ("fp32", "fp16"):
+        d = rel_err(xs[prec], xs["fp64"])
+        log(f"  {prec} vs fp64 preconditioner solutions: rel. difference {d:.2e}")
+        assert d < 1e-6
