@@ -117,3 +117,37 @@ def test_full_size_mixed_precision_solves_512(full512):
         d = rel_err(xs[prec], xs["fp64"])
         log(f"  {prec} vs fp64 preconditioner solutions: rel. difference {d:.2e}")
         assert d < 1e-6
+
+
+def test_full_size_trace_replay_128(full128):
+    """MG-MLMC++ (Alg. 2, reduced form) on the 128^2 workload in the timed
+    step's hierarchy, FP16-block preconditioner and batch of 64, replayed with
+    8 samples per level difference (Hutch++ with 32 vectors and two power
+    steps first): the estimate, the low-rank parts and every sample match the
+    oracle's on identical seeds to 1e-8 relative.  Solves are taken to 1e-12
+    so that solver error stays far below that."""
+    from oracle import mg as omg
+    from oracle import trace as otr
+    from paper_2303_11512_amd import solve_params
+    ctx, gid, D = full128
+    cfg = WORKLOADS["schwinger128"]
+    kw = dict(variant="mlmcpp", form="reduced", eps=cfg["eps"], d=list(cfg["d"]), k_power=cfg["k_power"],
+              noise=cfg["noise"], seed=cfg["trace_seed"] + 40, fixed_samples=[8, 8])
+    log("schwinger128: GPU estimate (replay, 8 samples per level)")
+    got = ctx.trace_estimate(gid, solve=solve_params(tol=1e-12, restart=32, max_restarts=50), batch=64,
+                             max_dump=4096, **kw)
+    log("schwinger128: oracle hierarchy and estimate")
+    hier = omg.setup_hierarchy(gauge_for(cfg), cfg["m0"], cfg["blocks"], cfg["ntv"],
+                               mg_setup_kwargs(cfg)["seed"])
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    scale = abs(want["tau"])
+    log(f"  tau GPU {got['tau']:.10f} oracle {want['tau']:.10f}, "
+        f"rel. difference {abs(got['tau'] - want['tau']) / scale:.2e}")
+    assert abs(got["tau"] - want["tau"]) < 1e-8 * scale
+    for l in range(len(want["level_samples"])):
+        assert got["level_samples"][l] == want["level_samples"][l] == 8
+        assert abs(got["level_lr"][l] - want["level_lr"][l]) < 1e-8 * scale, l
+        ws, gs = np.array(want["samples"][l]), np.asarray(got["samples"][l])
+        sc = max(np.max(np.abs(ws)), scale / len(ws))
+        log(f"  level {l}: max sample difference / scale {np.max(np.abs(gs - ws)) / sc:.2e}")
+        assert np.max(np.abs(gs - ws)) < 1e-8 * sc, l
