@@ -58,9 +58,26 @@ def mg_setup_kwargs(cfg):
     )
 
 
-def trace_kwargs(cfg, step):
+# samples per level per GPU batch (the speculative batch of the estimator)
+BATCH = 64
+# Alg. 2's stop test V_l / s <= rho_l^2 is not applied before this many
+# samples per level: the literal reading allows a test at s = 2, where a
+# 2-sample variance can stop the estimate long before it holds its accuracy
+MIN_SAMPLES = 16
+# the solves of the timed step: FGMRES(32), true FP64 residual 1e-10
+SOLVE = dict(tol=1e-10, restart=32, max_restarts=50)
+
+
+def method_kwargs(cfg, step):
+    """Alg. 2 as timed (MG-MLMC++, reduced form, optimal target variances
+    weighed by the Sec. 4 cost model), the same for the oracle."""
     return dict(variant="mlmcpp", form="reduced", eps=cfg["eps"], d=cfg["d"], k_power=cfg["k_power"],
-                noise=cfg["noise"], targets="optimal", seed=cfg["trace_seed"] + step, batch=64)
+                noise=cfg["noise"], targets="optimal", cost="flops", min_samples=MIN_SAMPLES,
+                seed=cfg["trace_seed"] + step)
+
+
+def trace_kwargs(cfg, step):
+    return dict(method_kwargs(cfg, step), batch=BATCH)
 
 
 KERNEL_RHS = 64
@@ -95,6 +112,65 @@ def measured_traffic(precision):
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+STEP_PROFILE = os.path.join(ROOT, "profiles", "schwinger128_step_kernel_stats.txt")
+
+
+def in_step_average(precision, alg_bytes):
+    """Average duration of the dominant kernel inside the timed step, from
+    the committed rocprofv3 kernel trace of the step (None when it is missing
+    or the kernel source changed since it was taken)."""
+    import hashlib
+    try:
+        with open(KERNEL_SOURCE, "rb") as f:
+            src = hashlib.sha256(f.read()).hexdigest()
+        name = KERNEL_NAME[precision]
+        calls = total = 0.0
+        sha = None
+        in_step = False
+        with open(STEP_PROFILE) as f:
+            for ln in f:
+                if ln.startswith("source_sha256:"):
+                    sha = ln.split(":", 1)[1].strip()
+                if ln.startswith("## "):
+                    in_step = "timed step" in ln
+                    continue
+                parts = ln.split()
+                if in_step and len(parts) >= 4 and " ".join(parts[3:]) == name:
+                    total += float(parts[0])
+                    calls += float(parts[1])
+        if sha != src or calls == 0:
+            return None
+        us = total / calls * 1e3
+        return {"avg_us": us, "calls": int(calls), "GB/s": alg_bytes / (us * 1e-6) / 1e9,
+                "frac": alg_bytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def plain_fp64_run(ctx, th, cfg, mgkw, steps, ref):
+    """Plain FP64 MG-FGMRES on the same GPU and seeds: FP64 preconditioner,
+    no captured graphs, one stream, and Alg. 2's stochastic loop one sample
+    per level at a time (batch 1; the Hutch++ sketch is one block of d
+    vectors, as Alg. 2 writes it)."""
+    import torch
+    from lattice_inputs import links_from_theta
+    from paper_2303_11512_amd import mg_params, solve_params
+    gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), cfg["m0"], True)
+    ctx.setup_mg(gid, mg_params(**dict(mgkw, graphs=False), precision="fp64"))
+    sp = solve_params(**SOLVE)
+    kw = lambda k: dict(trace_kwargs(cfg, k), batch=1, concurrent=False)
+    ctx.trace_estimate(gid, solve=sp, **kw(1000))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [ctx.trace_estimate(gid, solve=sp, **kw(k)) for k in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.free_gauge(gid)
+    return {"what": "FP64 preconditioner, no graphs, one stream, one sample per level at a time",
+            "estimates_per_s": steps / dt, "ms_per_step": dt / steps * 1e3, "steps": steps,
+            "max_tau_rel_diff": max(abs(a["tau"] - b["tau"]) / abs(b["tau"]) for a, b in zip(outs, ref))}
 
 
 def kernel_table(ctx, gid, nrhs=KERNEL_RHS, mlmc_coarsest=None, precision="fp64"):
@@ -428,7 +504,9 @@ def main():
                     help="precision of the multigrid preconditioner (outer FGMRES is FP64); fp16 = "
                          "FP32 cycle with FP16 coarse blocks")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the plain FP64-preconditioner timing reported next to the value")
+                    help="skip the FP64 comparison runs reported next to the value")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="estimates timed with plain FP64 MG-FGMRES, one sample at a time (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up, time the hot kernels and exit (for counter runs)")
     ap.add_argument("--train-fields", type=int, default=20, help="cnn workload: training fields")
@@ -474,7 +552,7 @@ def main():
         ctx.close()
         return
 
-    sp = solve_params(tol=1e-10, restart=32, max_restarts=50)
+    sp = solve_params(**SOLVE)
     for w in range(args.warmup):
         ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, 1000 + w))
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
@@ -494,8 +572,20 @@ def main():
     dom = kern[dom_key]
     achieved = dom["bytes"] / (dom["us"] * 1e-6) / 1e9
 
-    # the same estimates with the plain FP64 preconditioner, for comparison
+    # spread of the timed estimates (each an independent estimate to eps)
+    taus = np.array([o["tau"] for o in outs])
+    tau_mean = complex(np.mean(taus))
+    spread = {"mean": [tau_mean.real, tau_mean.imag],
+              "rel_std": float(np.std(np.abs(taus - tau_mean)) / abs(tau_mean)) if len(outs) > 1 else None,
+              "rel_rms_dev": float(np.sqrt(np.mean(np.abs(taus - tau_mean) ** 2)) / abs(tau_mean)),
+              "max_rel_dev": float(np.max(np.abs(taus - tau_mean)) / abs(tau_mean)),
+              "samples_per_step": [o["level_samples"] for o in outs],
+              "cost_model_mflop_per_step": [round(sum(o["level_work"]) * 8e-6, 1) for o in outs]}
+
+    # the same estimates with only the preconditioner's precision changed to
+    # FP64 (same schedule: phase-batched level solves, two streams, graphs)
     plain = None
+    unbatched = None
     if args.precision != "fp64" and not args.no_compare:
         ctx.set_precision(gid, "fp64")
         ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, 1000))
@@ -504,10 +594,14 @@ def main():
         pouts = [ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, k)) for k in range(args.steps)]
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t1
-        plain = {"estimates_per_s": args.steps / pdt, "ms_per_step": pdt / args.steps * 1e3,
+        plain = {"what": "precision-only comparison: FP64 preconditioner, same batched schedule",
+                 "estimates_per_s": args.steps / pdt, "ms_per_step": pdt / args.steps * 1e3,
                  "max_tau_rel_diff": max(abs(a["tau"] - b["tau"]) / abs(b["tau"]) for a, b in zip(outs, pouts))}
         ctx.set_precision(gid, args.precision)
-        print(f"# plain FP64 preconditioner: {plain}", file=sys.stderr, flush=True)
+        print(f"# FP64 preconditioner, same schedule: {plain}", file=sys.stderr, flush=True)
+        if args.plain_steps > 0:
+            unbatched = plain_fp64_run(ctx, th, cfg, mgkw, args.plain_steps, outs)
+            print(f"# plain FP64 MG-FGMRES, one sample at a time: {unbatched}", file=sys.stderr, flush=True)
 
     samples = [int(sum(o["level_samples"][l] for o in outs) / len(outs)) for l in range(len(outs[0]["level_samples"]))]
     cpu = None
@@ -540,7 +634,9 @@ def main():
                                f"{cfg['noise']} noise, eps {cfg['eps']}, FGMRES tol 1e-10",
                    "solves_per_s": solves / dt, "setup_s": setup_s,
                    "preconditioner": args.precision, "sap_cycles": list(SAP_CYCLES[:4]),
-                   "plain_fp64_preconditioner": plain,
+                   "min_samples": MIN_SAMPLES, "cost_model": "flops (Sec. 4)", "estimates": spread,
+                   "fp64_preconditioner_same_schedule": plain,
+                   "plain_fp64_mg_fgmres": unbatched,
                    "solver_levels": mg_setup_kwargs(cfg)["nlevels"],
                    "iters_per_solve": [round(sum(o["iters"][l] for o in outs) / max(1, sum(o["solves"][l] for o in outs)), 2)
                                        for l in range(len(cfg["blocks"]) + 1)],
@@ -549,6 +645,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
                      "kernel": f"{KERNEL_NAME[args.precision]} (level 1, one colour, {KERNEL_RHS} RHS)",
                      "launch_us": dom["us"], "alg_bytes": dom["bytes"],
+                     "in_step": in_step_average(args.precision, dom["bytes"]),
                      "others": {k: {"us": round(v["us"], 2),
                                     "GB/s": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1),
                                     "TFLOP/s": round(v["flops"] / (v["us"] * 1e-6) / 1e12, 2)}

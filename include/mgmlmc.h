@@ -254,6 +254,24 @@ int mgm_orthonormalize(mgm_ctx *ctx, int64_t n, int d, const void *Y, void *Q);
 #define MGM_FORM_FULL 1
 #define MGM_TARGETS_OPTIMAL 0
 #define MGM_TARGETS_UNIFORM 1
+/* cost C_{s,l} of a stochastic sample (Alg. 2), which weighs the optimal
+ * target variances (Sec. 3, eq. optimal_variance):
+ *   STATIC  one number per level: nnz(D_l) + nnz(D_{l+1}) + 2 n_l d_l;
+ *   FIXED   the given fixed_cost[l];
+ *   FLOPS   the cost model of Sec. 4: complex multiply-adds of every
+ *           matrix-vector product of the sample -- the operators by their
+ *           structural non-zeros (9 per fine row, 5 M^2 per coarse site),
+ *           R_l and P_l (n_l ntv_l each), per SAP cycle the residual rows of
+ *           both colours and one K x K block-inverse product per block, dense
+ *           inverses (n^2), per FGMRES iteration one preconditioner and one
+ *           operator product, per restart cycle two residuals, a solve with a
+ *           dense inverse one dense product and its residual check, and the
+ *           projection 2 n_l d_l.  It depends on the iteration counts of the
+ *           sample's own solves; C_l is the running mean over the samples
+ *           taken, as Alg. 2 prints. */
+#define MGM_COST_STATIC 0
+#define MGM_COST_FIXED 1
+#define MGM_COST_FLOPS 2
 
 typedef struct {
   int variant, form;
@@ -262,9 +280,10 @@ typedef struct {
   int k_power;                       /* block power sweeps                   */
   int noise;                         /* MGM_NOISE_*                          */
   int targets;                       /* MGM_TARGETS_*                        */
-  int use_fixed_cost;                /* 1: cost per sample = fixed_cost[l]   */
-  double fixed_cost[MGM_MAX_LEVELS]; /* else nnz(D_l)+nnz(D_{l+1})+2 n_l d_l */
-  int min_samples;                   /* >= 2                                 */
+  int cost;                          /* MGM_COST_*                           */
+  double fixed_cost[MGM_MAX_LEVELS]; /* cost per sample with MGM_COST_FIXED  */
+  int min_samples;                   /* no stop test before this many
+                                        samples (>= 2; values below 2 mean 2) */
   int max_samples;
   const int *fixed_samples;          /* HOST [levels] exact counts, or NULL  */
   uint64_t seed;
@@ -282,11 +301,22 @@ typedef struct {
   double lvl_mean[MGM_MAX_LEVELS][2];
   double lvl_lr[MGM_MAX_LEVELS][2];    /* Hutch++ low-rank parts              */
   double lvl_var[MGM_MAX_LEVELS];
-  double lvl_cost[MGM_MAX_LEVELS];
+  double lvl_cost[MGM_MAX_LEVELS];     /* C_l used by the last stop test      */
   int lvl_samples[MGM_MAX_LEVELS];
   int64_t lvl_solves[MGM_MAX_LEVELS];  /* solves on D_l issued (incl. discarded batch tail) */
   int64_t lvl_iters[MGM_MAX_LEVELS];   /* FGMRES iterations on D_l            */
+  double lvl_lr_work[MGM_MAX_LEVELS];  /* Sec. 4 cost model of difference l's
+                                          Hutch++ phase (k sweeps and the
+                                          low-rank round)                   */
+  double lvl_work[MGM_MAX_LEVELS];     /* lvl_lr_work + the costs of the
+                                          samples kept (whatever `cost`)    */
   double *sample_dump;                 /* HOST [nstoch][max_dump][2] or NULL  */
+  double *cost_dump;                   /* HOST [nstoch][max_dump] or NULL:
+                                          each kept sample's Sec. 4 cost     */
+  int *iter_dump;                      /* HOST [nstoch][max_dump][2] or NULL:
+                                          FGMRES iterations of each kept
+                                          sample's solves on D_l, D_{l+1}
+                                          (0 where a level has no such solve) */
   int max_dump;
 } mgm_trace_result;
 

@@ -144,12 +144,15 @@ def setup_hierarchy(theta: np.ndarray, m0: float, blocks, ntv, seed: int,
     return Hierarchy(levels, Ps, Pbs, Vs)
 
 
-def coarsest_trace(lev: Level) -> complex:
-    """tr(D_L^{-1}) computed directly (Sec. 3.1; Alg. 2, coarsest level)."""
-    if lev.n <= 8192:
+def coarsest_trace(lev: Level, dense_max: int = 8192, blk: int = 512) -> complex:
+    """tr(D_L^{-1}) computed directly (Sec. 3.1; Alg. 2, coarsest level).
+
+    Up to ``dense_max`` rows by a dense inverse; above, by sparse-LU solves
+    against blocks of ``blk`` identity columns, summing the diagonal entries
+    of D^{-1} they produce."""
+    if lev.n <= dense_max:
         return complex(np.trace(np.linalg.inv(lev.D.toarray())))
     total = 0.0 + 0.0j
-    blk = 512
     for j0 in range(0, lev.n, blk):
         j1 = min(lev.n, j0 + blk)
         E = np.zeros((lev.n, j1 - j0), dtype=np.complex128)

@@ -11,7 +11,7 @@ All four share one control loop, which is Alg. 2's stochastic part; with a
 single stochastic level its stopping rule reduces to Alg. 1's
 V/s <= (eps tau)^2, so Alg. 1 and the Hutch++ remainder use it too.
 
-Readings of the paper taken here (each also listed in the design notes):
+Readings of the paper taken here:
 
 * Level operators.  Reduced form (Sec. 3.1, eq. mlmc_dec_trace_reduced, which
   Alg. 2's remarks allow): A_l = D_l^{-1} - P_l D_{l+1}^{-1} P_l^H on vectors
@@ -36,10 +36,15 @@ Readings of the paper taken here (each also listed in the design notes):
   uniform targets: rho_l^2 = (eps |tau|)^2 / (L-1)  (Sec. 3, eqs.
   accuracy_opt / optimal_variance).  If every sqrt(C_j V_j) is 0 the weights
   fall back to uniform.
-* Cost per sample C_{s,l}: a fixed per-level number.  The default model is
-  nnz(D_l) + nnz(D_{l+1}) + 2 n_l d_l with nnz(D_0) = 9 n_0 and 5 M n_l for a
-  coarse level of M dofs per site -- arithmetic proportional to non-zeros, as
-  the paper's cost model (Sec. 4), but independent of iteration counts.
+* Cost per sample C_{s,l} (Alg. 2; the cost model of Sec. 4), three modes:
+  ``flops`` -- the paper's model: the arithmetic of every matrix-vector
+  product of the sample (``oracle.cost``), which depends on the iteration
+  counts of its two solves; the oracle solves exactly, so these per-sample
+  costs are given (``sample_costs``) and C_l is their running mean, as in
+  Alg. 2.  ``static`` -- one deterministic number per level, nnz(D_l) +
+  nnz(D_{l+1}) + 2 n_l d_l (structural non-zeros as in ``oracle.cost``),
+  i.e. one matrix-vector product per solve.  ``fixed`` -- given per-level
+  constants.
 
 Parity: pinned by tests (unbiasedness, the Rademacher / Z4 single-sample
 variance formulas of Sec. 2, the 1/N vs 1/N^2 slopes, telescoping, the
@@ -52,6 +57,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
+from . import cost as cmodel
 from . import rng
 from .mg import Hierarchy, coarsest_trace
 
@@ -65,7 +71,9 @@ class TraceParams:
     k_power: int = 2
     noise: str = rng.Z2Z2
     targets: str = "optimal"           # optimal | uniform
-    fixed_cost: Optional[list] = None  # per stochastic level; None -> nnz model
+    cost: str = "static"               # static | fixed | flops
+    fixed_cost: Optional[list] = None  # per stochastic level (implies cost="fixed")
+    sample_costs: Optional[list] = None  # flops mode: C_{s,l} per level, per sample index
     min_samples: int = 2
     max_samples: int = 1_000_000
     fixed_samples: Optional[list] = None   # replay mode: exact sample counts
@@ -83,6 +91,8 @@ class StochLevel:
     tau_lr: complex = 0.0
     samples: list = field(default_factory=list)
     active: bool = True
+    sample_costs: Optional[list] = None   # given C_{s,l} (flops mode)
+    cost_sum: float = 0.0
 
     @property
     def s(self) -> int:
@@ -98,10 +108,12 @@ class StochLevel:
         return float(np.sum(np.abs(t - t.mean()) ** 2) / (len(t) - 1))
 
 
-def _cost_model(hier: Hierarchy, l: int, n: int, d: int, L: int) -> float:
+def static_cost(hier: Hierarchy, l: int, n: int, d: int, L: int) -> float:
+    """nnz(D_l) + nnz(D_{l+1}) + 2 n d: one product with each operator of
+    the difference and the projection (structural non-zeros)."""
     def nnz(j):
         lev = hier.levels[j]
-        return 9 * lev.n if j == 0 else 5 * lev.M * lev.n
+        return cmodel.nnz_D(cmodel.LevelShape(lev.Nx, lev.Nt, lev.M), j == 0)
     c = nnz(l) + 2 * n * d
     if l + 1 < L:
         c += nnz(l + 1)
@@ -171,12 +183,22 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
     ops, tau_exact = level_ops(hier, prm.variant, prm.form, prm.levels)
     nl = len(ops)
     use_lr = prm.variant in ("hutchpp", "mlmcpp")
+    mode = "fixed" if prm.fixed_cost is not None else prm.cost
+    if mode not in ("static", "fixed", "flops"):
+        raise ValueError(prm.cost)
+    if mode == "flops" and prm.sample_costs is None:
+        raise ValueError("cost='flops' needs the per-sample costs (sample_costs)")
     levels = []
     for l, (A, n) in enumerate(ops):
         d = prm.d[l] if use_lr else 0
-        cost = (prm.fixed_cost[l] if prm.fixed_cost is not None
-                else _cost_model(hier, l, n, d, prm.levels or hier.L))
-        levels.append(StochLevel(A, n, d, cost))
+        if mode == "fixed":
+            cost = float(prm.fixed_cost[l])
+        elif mode == "static":
+            cost = static_cost(hier, l, n, d, prm.levels or hier.L)
+        else:
+            cost = float("nan")   # C_l: the mean of the costs of the samples taken
+        levels.append(StochLevel(A, n, d, cost,
+                                 sample_costs=prm.sample_costs[l] if mode == "flops" else None))
 
     # deflation vectors and low-rank parts (Alg. 2, first loop)
     for l, lv in enumerate(levels):
@@ -191,6 +213,11 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
         for l, lv in enumerate(levels):
             if lv.active:
                 lv.samples.append(sample(lv, prm.noise, prm.seed, l, s - 1))
+                if lv.sample_costs is not None:
+                    if s - 1 >= len(lv.sample_costs):
+                        raise IndexError(f"no cost given for sample {s - 1} of level {l}")
+                    lv.cost_sum += lv.sample_costs[s - 1]
+                    lv.cost = lv.cost_sum / lv.s
         tau = sum(lv.mean() + lv.tau_lr for lv in levels) + tau_exact
         if prm.fixed_samples is not None:
             for l, lv in enumerate(levels):

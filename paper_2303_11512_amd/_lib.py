@@ -24,6 +24,7 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16": PREC_FP16}
 VARIANTS = {"hutchinson": 0, "hutchpp": 1, "mlmc": 2, "mlmcpp": 3}
 FORMS = {"reduced": 0, "full": 1}
 TARGETS = {"optimal": 0, "uniform": 1}
+COSTS = {"static": 0, "fixed": 1, "flops": 2}
 NOISES = {"rademacher": NOISE_RADEMACHER, "z2z2": NOISE_Z2Z2}
 
 
@@ -85,7 +86,7 @@ class TraceParams(C.Structure):
         ("k_power", C.c_int),
         ("noise", C.c_int),
         ("targets", C.c_int),
-        ("use_fixed_cost", C.c_int),
+        ("cost", C.c_int),
         ("fixed_cost", C.c_double * MAX_LEVELS),
         ("min_samples", C.c_int),
         ("max_samples", C.c_int),
@@ -109,7 +110,11 @@ class TraceResult(C.Structure):
         ("lvl_samples", C.c_int * MAX_LEVELS),
         ("lvl_solves", C.c_int64 * MAX_LEVELS),
         ("lvl_iters", C.c_int64 * MAX_LEVELS),
+        ("lvl_lr_work", C.c_double * MAX_LEVELS),
+        ("lvl_work", C.c_double * MAX_LEVELS),
         ("sample_dump", C.POINTER(C.c_double)),
+        ("cost_dump", C.POINTER(C.c_double)),
+        ("iter_dump", C.POINTER(C.c_int)),
         ("max_dump", C.c_int),
     ]
 
@@ -435,7 +440,7 @@ class Context:
                                               _P(_ptr(Q))), "orthonormalize")
 
     def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
-                       noise="z2z2", targets="optimal", fixed_cost=None, min_samples=2,
+                       noise="z2z2", targets="optimal", cost="static", fixed_cost=None, min_samples=2,
                        max_samples=0, fixed_samples=None, seed=1, batch=64, solve=None,
                        max_dump=0, concurrent=True) -> dict:
         p = TraceParams()
@@ -447,8 +452,8 @@ class Context:
         p.k_power = k_power
         p.noise = NOISES[noise]
         p.targets = TARGETS[targets]
+        p.cost = COSTS["fixed" if fixed_cost is not None else cost]
         if fixed_cost is not None:
-            p.use_fixed_cost = 1
             for i, v in enumerate(fixed_cost):
                 p.fixed_cost[i] = v
         p.min_samples = min_samples
@@ -462,10 +467,14 @@ class Context:
         p.solve = solve or solve_params()
         p.concurrent = int(bool(concurrent))
         r = TraceResult()
-        dump = None
+        dump = cdump = idump = None
         if max_dump > 0:
             dump = (C.c_double * (MAX_LEVELS * max_dump * 2))()
+            cdump = (C.c_double * (MAX_LEVELS * max_dump))()
+            idump = (C.c_int * (MAX_LEVELS * max_dump * 2))()
             r.sample_dump = C.cast(dump, C.POINTER(C.c_double))
+            r.cost_dump = C.cast(cdump, C.POINTER(C.c_double))
+            r.iter_dump = C.cast(idump, C.POINTER(C.c_int))
             r.max_dump = max_dump
         self._chk(self.lib.mgm_trace_estimate(self.h, gid, C.byref(p), C.byref(r)), "trace_estimate")
         ns = r.nstoch
@@ -479,6 +488,8 @@ class Context:
             level_samples=[r.lvl_samples[i] for i in range(ns)],
             solves=[r.lvl_solves[i] for i in range(MAX_LEVELS)],
             iters=[r.lvl_iters[i] for i in range(MAX_LEVELS)],
+            level_lr_work=[r.lvl_lr_work[i] for i in range(ns)],
+            level_work=[r.lvl_work[i] for i in range(ns)],
         )
         if dump is not None:
             arr = np.frombuffer(dump, dtype=np.float64).reshape(MAX_LEVELS, max_dump, 2)
@@ -487,4 +498,8 @@ class Context:
                  + 1j * arr[i, :min(max_dump, out["level_samples"][i]), 1]).copy()
                 for i in range(ns)
             ]
+            carr = np.frombuffer(cdump, dtype=np.float64).reshape(MAX_LEVELS, max_dump)
+            iarr = np.frombuffer(idump, dtype=np.int32).reshape(MAX_LEVELS, max_dump, 2)
+            out["sample_costs"] = [carr[i, :min(max_dump, out["level_samples"][i])].copy() for i in range(ns)]
+            out["sample_iters"] = [iarr[i, :min(max_dump, out["level_samples"][i])].copy() for i in range(ns)]
         return out

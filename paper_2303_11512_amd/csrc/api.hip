@@ -434,15 +434,18 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         flops = 8.0 * n * n * b;
         break;
       case MGM_KERNEL_CGS: {
+        // the projection coefficients of one Gram-Schmidt pass in FGMRES
+        // step 15: 16 distinct basis vectors per RHS in the solver's layout
+        // V[i][r][n] against w = y
         const int nv = 16;
-        c->scratch3.ensure(sizeof(cd) * (size_t)nrhs * (nv + 1) * reduce_chunks(n) + sizeof(cd) * nrhs * nv);
-        cd* out = c->scratch3.as<cd>();
+        const int64_t vs = (int64_t)nrhs * n;
+        c->scratch3.ensure(sizeof(cd) * ((size_t)nv * vs + (size_t)nrhs * (nv + 1) * reduce_chunks(n) +
+                                         (size_t)nrhs * nv));
+        cd* V = c->scratch3.as<cd>();
+        cd* out = V + nv * vs;
         cd* part = out + (int64_t)nrhs * nv;
-        // V_i of RHS r = x shifted by i elements (in bounds: i <= 15 < n)
-        require(n > 16, "level too small for the CGS probe");
-        launch = [=] {
-          launch_dot_multi_ld<double>(s, x, 1, n, nv, y, n - nv, nrhs, out, nv, 0, nullptr, part);
-        };
+        launch_noise<double>(s, V, n, nrhs * nv, MGM_NOISE_Z2Z2, 13, 0, 0, 0);
+        launch = [=] { launch_dot_multi_ld<double>(s, V, vs, n, nv, y, n, nrhs, out, nv, 0, nullptr, part); };
         bytes = 16.0 * (nv + 1) * n * b;
         flops = 8.0 * nv * n * b;
         break;

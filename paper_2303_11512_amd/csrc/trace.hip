@@ -39,6 +39,10 @@ struct StochLevel {
   double cost = 0;
   zc tau_lr = 0;
   std::vector<zc> samples;
+  std::vector<double> costs;                // C_{s,l} of each sample (cost model)
+  std::vector<std::array<int, 2>> its;      // FGMRES iterations of its two solves
+  double cost_sum = 0;
+  double lr_cost = 0;                       // cost model work of the Hutch++ phase
   bool active = true;
   DevBuf* Q = nullptr; // [d][n], owned by the field's estimator workspace
   int s() const { return (int)samples.size(); }
@@ -56,6 +60,14 @@ struct StochLevel {
     return acc / (double)(samples.size() - 1);
   }
 };
+
+// Evaluated samples of one level difference in one batch, in index order.
+struct Batch {
+  std::vector<zc> vals;
+  std::vector<double> cost;
+  std::vector<std::array<int, 2>> its;
+};
+using Its = std::vector<std::array<int, 2>>;  // per vector: iterations on D_l and D_{l+1}
 
 struct Estimator {
   mgm_ctx* c;
@@ -75,31 +87,87 @@ struct Estimator {
     L = g.mlmc_levels;
     full = p.form == MGM_FORM_FULL;
     hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
+    cost_init();
+  }
+
+  // ---- the cost model of Sec. 4: complex multiply-adds of every
+  // matrix-vector product a sample performs.  Operators count their
+  // structural non-zeros (9 per fine row, 5 M^2 per coarse site), R and P
+  // n_j ntv_j each, a SAP cycle the residual rows of both colours plus one
+  // K x K block-inverse product per block, a dense inverse n^2; an FGMRES
+  // iteration one preconditioner and one operator product, a restart cycle
+  // two residuals; the projection 2 n d.  Vector work (Gram-Schmidt, dot
+  // products) is not counted.  Solves on a level with a dense inverse are
+  // one dense product and the residual check.
+  std::vector<double> c_nnzD, c_nnzP, c_prec;
+  void cost_init() {
+    const int Ls = (int)g.levels.size();
+    c_nnzD.assign(Ls, 0.0);
+    c_nnzP.assign(Ls, 0.0);
+    c_prec.assign(Ls, 0.0);
+    for (int j = 0; j < Ls; ++j) {
+      const Level& Lj = *g.levels[j];
+      c_nnzD[j] = j == 0 ? 9.0 * Lj.n : 5.0 * Lj.M * Lj.M * (double)Lj.sites;
+      c_nnzP[j] = Lj.has_coarse ? (double)Lj.n * Lj.ntv : 0.0;
+    }
+    for (int j = Ls - 1; j >= 0; --j) {
+      const Level& Lj = *g.levels[j];
+      if (Lj.is_coarsest || !Lj.has_coarse) {
+        c_prec[j] = (double)Lj.n * Lj.n;
+        continue;
+      }
+      const Level& C = *g.levels[j + 1];
+      const double coarse = C.is_coarsest ? (double)C.n * C.n
+                            : C.inner_iters <= 0 ? c_prec[j + 1]
+                                                 : C.inner_iters * (c_prec[j + 1] + c_nnzD[j + 1]);
+      const double sap = c_nnzD[j] + (double)Lj.nblk * Lj.K * Lj.K;
+      c_prec[j] = 2.0 * c_nnzP[j] + coarse + Lj.sap_cycles * sap;
+    }
+  }
+  double solve_cost(int j, int its) const {
+    const Level& Lj = *g.levels[j];
+    if (Lj.has_dense) return (double)Lj.n * Lj.n + c_nnzD[j];
+    const int m = std::max(1, p.solve.restart);
+    const int cycles = std::max(1, (its + m - 1) / m);
+    return its * (c_nnzD[j] + c_prec[j]) + 2.0 * cycles * c_nnzD[j];
+  }
+  // A_l applied to one vector whose solves took (its[0], its[1]) iterations
+  double apply_cost(int l, const std::array<int, 2>& its) const {
+    if (hutch) return solve_cost(0, its[0]);
+    if (!full) return 2.0 * c_nnzP[l] + solve_cost(l, its[0]) + solve_cost(l + 1, its[1]);
+    auto walk = [&](int j) {
+      double w = 0;
+      for (int q = 0; q < j; ++q) w += 2.0 * c_nnzP[q];
+      return w;
+    };
+    return walk(l) + solve_cost(l, its[0]) + walk(l + 1) + solve_cost(l + 1, its[1]);
   }
 
   // solve on level l through the view cv (this thread's, or the worker's on
-  // the field's second stream); solve and iteration counts go to cnt[l]
-  void solve_on(mgm_ctx* cv, int l, int k, const cd* b, cd* x, std::vector<std::array<int64_t, 2>>& cnt) {
-    std::vector<int> its(k);
-    const int st = solve_chunked(cv, g, l, k, b, x, p.solve, its.data(), nullptr);
+  // the field's second stream); solve and iteration counts go to cnt[l], the
+  // iterations of each right-hand side to its_out
+  void solve_on(mgm_ctx* cv, int l, int k, const cd* b, cd* x, std::vector<std::array<int64_t, 2>>& cnt,
+                std::vector<int>& its_out) {
+    its_out.assign(k, 0);
+    const int st = solve_chunked(cv, g, l, k, b, x, p.solve, its_out.data(), nullptr);
     if (st != MGM_OK) throw Error(st, "solve on level " + std::to_string(l) + " did not converge");
     cnt[l][0] += k;
-    for (int v : its) cnt[l][1] += v;
+    for (int v : its_out) cnt[l][1] += v;
   }
-  void solve(int l, int k, const cd* b, cd* x) {
+  std::vector<int> solve(int l, int k, const cd* b, cd* x) {
     std::vector<std::array<int64_t, 2>> cnt(MGM_MAX_LEVELS, {0, 0});
-    solve_on(c, l, k, b, x, cnt);
+    std::vector<int> its;
+    solve_on(c, l, k, b, x, cnt, its);
     res.lvl_solves[l] += (int)cnt[l][0];
     res.lvl_iters[l] += (int)cnt[l][1];
+    return its;
   }
 
-  // lift(j, X) = Ph_j D_j^{-1} Ph_j^H X for fine vectors X (full form)
-  void lift(int j, int k, const cd* X, cd* out) {
+  // lift(j, X) = Ph_j D_j^{-1} Ph_j^H X for fine vectors X (full form);
+  // returns the iterations of its solve per vector
+  std::vector<int> lift(int j, int k, const cd* X, cd* out) {
     hipStream_t s = c->stream;
-    if (j == 0) {
-      solve(0, k, X, out);
-      return;
-    }
+    if (j == 0) return solve(0, k, X, out);
     // restrict down to level j, ping-ponging between t3 and t4
     std::vector<int64_t> nn(L);
     for (int q = 0; q < L; ++q) nn[q] = g.levels[q]->n;
@@ -117,7 +185,7 @@ struct Estimator {
       src = bufs[cur];
       cur ^= 1;
     }
-    solve(j, k, src, bufs[cur]);
+    std::vector<int> its = solve(j, k, src, bufs[cur]);
     src = bufs[cur];
     cur ^= 1;
     for (int q = j - 1; q >= 0; --q) {
@@ -128,22 +196,27 @@ struct Estimator {
       src = dst;
       cur ^= 1;
     }
+    return its;
   }
 
   // Y = A_l X for k vectors of the level difference sl: Hutchinson variants
   // (A = D^{-1}) and the full form on fine vectors
-  void applyA(const StochLevel& sl, int k, const cd* X, cd* Y) {
+  Its applyA(const StochLevel& sl, int k, const cd* X, cd* Y) {
     hipStream_t s = c->stream;
     const int l = sl.level;
+    Its its(k, {0, 0});
     if (hutch) {
-      solve(0, k, X, Y);
-      return;
+      const std::vector<int> a = solve(0, k, X, Y);
+      for (int v = 0; v < k; ++v) its[v][0] = a[v];
+      return its;
     }
     const int64_t n0 = g.levels[0]->n;
     t1.ensure(sizeof(cd) * (size_t)k * n0);
-    lift(l, k, X, Y);
-    lift(l + 1, k, X, t1.as<cd>());
+    const std::vector<int> a = lift(l, k, X, Y);
+    const std::vector<int> b = lift(l + 1, k, X, t1.as<cd>());
     launch_axpby<double>(s, 1.0, Y, -1.0, t1.as<cd>(), Y, n0, k, nullptr);
+    for (int v = 0; v < k; ++v) its[v] = {a[v], b[v]};
+    return its;
   }
 
   // Y = A_i X for several blocks of vectors, each of one level difference i
@@ -158,9 +231,11 @@ struct Estimator {
     cd* Y;
   };
   static constexpr int kSegs = 4;  // most blocks one level's solve gathers
-  void applyA_levels(const std::vector<StochLevel>& lv, const std::vector<Item>& items) {
+  // its[q]: per vector of block q, the iterations of its two solves
+  void applyA_levels(const std::vector<StochLevel>& lv, const std::vector<Item>& items, std::vector<Its>& its) {
+    its.assign(items.size(), Its());
     if (hutch || full) {
-      for (const Item& it : items) applyA(lv[it.i], it.k, it.X, it.Y);
+      for (size_t q = 0; q < items.size(); ++q) its[q] = applyA(lv[items[q].i], items[q].k, items[q].X, items[q].Y);
       return;
     }
     hipStream_t s = c->stream;
@@ -207,11 +282,14 @@ struct Estimator {
       }
       src[j] = in.as<cd>();
     }
-    solve_levels(total, src);
+    std::vector<std::vector<int>> lits(L);
+    solve_levels(total, src, lits);
     t3.ensure(sizeof(cd) * (size_t)kmax * g.levels[0]->n);
     for (int q = 0; q < ni; ++q) {
       const Item& it = items[q];
       const int l = lv[it.i].level;
+      its[q].resize(it.k);
+      for (int v = 0; v < it.k; ++v) its[q][v] = {lits[l][own_off[q] + v], lits[l + 1][crs_off[q] + v]};
       Level& F = *g.levels[l];
       Level& C = *g.levels[l + 1];
       const cd* fine = g.est.lout[l].as<cd>() + (int64_t)own_off[q] * F.n;
@@ -237,14 +315,15 @@ struct Estimator {
   // the field's stream, the others one after the other on the field's second
   // stream from a worker thread with its own workspace set, so the
   // latency-bound coarse-level kernels overlap the fine level's.
-  void solve_levels(const std::vector<int>& total, const std::vector<const cd*>& src) {
+  void solve_levels(const std::vector<int>& total, const std::vector<const cd*>& src,
+                    std::vector<std::vector<int>>& lits) {
     std::vector<int> todo;
     for (int j = 0; j < L; ++j)
       if (total[j] > 0) todo.push_back(j);
     std::vector<std::array<int64_t, 2>> cnt(MGM_MAX_LEVELS, {0, 0}), wcnt(MGM_MAX_LEVELS, {0, 0});
     auto out = [&](int j) { return g.est.lout[j].as<cd>(); };
     if (todo.size() < 2 || !p.concurrent) {
-      for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt);
+      for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt, lits[j]);
     } else {
       if (!g.stream2) {
         HIPCHK(hipStreamCreateWithFlags(&g.stream2, hipStreamNonBlocking));
@@ -263,7 +342,8 @@ struct Estimator {
         w.wslot = 1;
         try {
           HIPCHK(hipSetDevice(c->device));
-          for (size_t q = 1; q < todo.size(); ++q) solve_on(&w, todo[q], total[todo[q]], src[todo[q]], out(todo[q]), wcnt);
+          for (size_t q = 1; q < todo.size(); ++q)
+            solve_on(&w, todo[q], total[todo[q]], src[todo[q]], out(todo[q]), wcnt, lits[todo[q]]);
         } catch (const Error& e) {
           wst = e.code;
           wmsg = e.what();
@@ -275,7 +355,7 @@ struct Estimator {
       int st = MGM_OK;
       std::string msg;
       try {
-        solve_on(c, todo[0], total[todo[0]], src[todo[0]], out(todo[0]), cnt);
+        solve_on(c, todo[0], total[todo[0]], src[todo[0]], out(todo[0]), cnt, lits[todo[0]]);
       } catch (const Error& e) {
         st = e.code;
         msg = e.what();
@@ -314,8 +394,12 @@ struct Estimator {
   // stochastic batch (A zeta does not depend on Q; only the projection of
   // zeta, applied afterwards, does): first[i] samples of difference i,
   // returned in first_vals.
-  void low_rank_all(std::vector<StochLevel>& lv, const std::vector<int>& first,
-                    std::vector<std::vector<zc>>& first_vals) {
+  void add_lr_cost(std::vector<StochLevel>& lv, const std::vector<Item>& items, const std::vector<Its>& its,
+                   size_t nitems) {
+    for (size_t q = 0; q < nitems; ++q)
+      for (const auto& v : its[q]) lv[items[q].i].lr_cost += apply_cost(lv[items[q].i].level, v);
+  }
+  void low_rank_all(std::vector<StochLevel>& lv, const std::vector<int>& first, std::vector<Batch>& first_vals) {
     std::vector<Item> items;
     for (int i = 0; i < (int)lv.size(); ++i) {
       StochLevel& sl = lv[i];
@@ -331,8 +415,10 @@ struct Estimator {
       sample_batches(lv, first, first_vals);
       return;
     }
+    std::vector<Its> its;
     for (int it = 0; it < std::max(1, p.k_power); ++it) {
-      applyA_levels(lv, items);
+      applyA_levels(lv, items, its);
+      add_lr_cost(lv, items, its, items.size());
       for (Item& x : items) {
         orthonormalize(c, lv[x.i].n, x.k, x.Y, lv[x.i].Q->as<cd>());
         x.X = lv[x.i].Q->as<cd>();
@@ -340,7 +426,8 @@ struct Estimator {
     }
     const size_t nlr = items.size();
     sample_start(lv, first, items);
-    applyA_levels(lv, items);
+    applyA_levels(lv, items, its);
+    add_lr_cost(lv, items, its, nlr);
     for (size_t q = 0; q < nlr; ++q) {
       const Item& x = items[q];
       std::vector<zc> v;
@@ -349,7 +436,8 @@ struct Estimator {
       for (const zc& y : v) acc += y;
       lv[x.i].tau_lr = acc;
     }
-    sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()), first_vals);
+    sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()),
+                  std::vector<Its>(its.begin() + nlr, its.end()), first_vals);
   }
 
   // noise zeta for samples s .. s+b[i]-1 of every difference i with b[i] > 0
@@ -368,10 +456,11 @@ struct Estimator {
 
   // tau_{s,l} = z^H (A zeta) with z = zeta - Q (Q^H zeta), for the blocks
   // sample_start made (X = zeta, Y = A zeta)
-  void sample_finish(std::vector<StochLevel>& lv, const std::vector<Item>& items,
-                     std::vector<std::vector<zc>>& out) {
+  void sample_finish(std::vector<StochLevel>& lv, const std::vector<Item>& items, const std::vector<Its>& its,
+                     std::vector<Batch>& out) {
     hipStream_t s = c->stream;
-    for (const Item& it : items) {
+    for (size_t q = 0; q < items.size(); ++q) {
+      const Item& it = items[q];
       StochLevel& sl = lv[it.i];
       const int64_t n = sl.n;
       cd* Z = g.est.Z[it.i].as<cd>();
@@ -384,16 +473,20 @@ struct Estimator {
         launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z, n, it.k,
                                     nullptr, nullptr, nullptr);
       }
-      dots_host(Z, it.Y, n, it.k, out[it.i]);
+      Batch& bt = out[it.i];
+      dots_host(Z, it.Y, n, it.k, bt.vals);
+      bt.its = its[q];
+      bt.cost.resize(it.k);
+      for (int v = 0; v < it.k; ++v) bt.cost[v] = apply_cost(sl.level, its[q][v]) + 2.0 * (double)n * sl.d;
     }
   }
 
-  void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b,
-                      std::vector<std::vector<zc>>& out) {
+  void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Batch>& out) {
     std::vector<Item> items;
+    std::vector<Its> its;
     sample_start(lv, b, items);
-    applyA_levels(lv, items);
-    sample_finish(lv, items, out);
+    applyA_levels(lv, items, its);
+    sample_finish(lv, items, its, out);
   }
 
   std::vector<double> weights(const std::vector<StochLevel>& lv) {
@@ -423,7 +516,7 @@ struct Estimator {
     int common = p.batch;
     if (!p.fixed_samples) {
       if (s < 2) {
-        common = std::max(minS, p.batch / 2);
+        common = std::min(p.batch, std::max(minS, p.batch / 2));
       } else {
         const std::vector<double> w = weights(lv);
         double need = 0;
@@ -446,15 +539,12 @@ struct Estimator {
     return nb;
   }
 
-  double nnz_model(int j) const {
-    const Level& Lj = *g.levels[j];
-    return j == 0 ? 9.0 * Lj.n : 5.0 * Lj.M * Lj.n;
-  }
-
   int run() {
     require(g.mg_ready, "trace_estimate needs setup_mg first", MGM_ESTATE);
     require(p.eps > 0 || p.fixed_samples, "eps must be positive");
     require(p.batch >= 1, "batch must be >= 1");
+    require(p.cost == MGM_COST_STATIC || p.cost == MGM_COST_FIXED || p.cost == MGM_COST_FLOPS,
+            "unknown cost model");
     const int nst = hutch ? 1 : L - 1;
     require(nst >= 1, "MLMC variants need at least two levels");
     const bool lr = p.variant == MGM_VARIANT_HUTCHPP || p.variant == MGM_VARIANT_MLMCPP;
@@ -466,24 +556,27 @@ struct Estimator {
       sl.n = (hutch || full) ? g.levels[0]->n : g.levels[i]->n;
       sl.d = lr ? p.d[i] : 0;
       require(sl.d >= 0 && sl.d <= 64, "d must be in [0, 64]");
-      if (p.use_fixed_cost) {
+      if (p.cost == MGM_COST_FIXED) {
         sl.cost = p.fixed_cost[i];
+      } else if (p.cost == MGM_COST_STATIC) {
+        sl.cost = c_nnzD[i] + 2.0 * sl.n * sl.d;
+        if (i + 1 < L) sl.cost += c_nnzD[i + 1];
       } else {
-        sl.cost = nnz_model(i) + 2.0 * sl.n * sl.d;
-        if (i + 1 < L) sl.cost += nnz_model(i + 1);
+        sl.cost = std::nan("");  // C_l: the mean cost of the samples taken
       }
     }
     const zc tau_exact = hutch ? zc(0) : zc(g.trL[0], g.trL[1]);
+    const int minS = std::max(2, p.min_samples);
+    // a batch never exceeds p.batch samples per level (batch_sizes)
     kmax = std::max(1, p.batch);
     for (int i = 0; i < nst; ++i) kmax = std::max(kmax, lv[i].d);
     // every reduction workspace at its largest size up front (no reallocation later)
     part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
-    const int minS = std::max(2, p.min_samples);
     const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
     zc tau = 0;
     int s = 0;
     // the first stochastic batch rides with the last low-rank round
-    std::vector<std::vector<zc>> pre(nst);
+    std::vector<Batch> pre(nst);
     bool have_pre = false;
     if (lr) {
       const std::vector<int> nb = batch_sizes(lv, s, tau, maxS);
@@ -494,7 +587,7 @@ struct Estimator {
       bool any = false;
       for (auto& sl : lv) any = any || sl.active;
       if (!any) break;
-      std::vector<std::vector<zc>> vals(nst);
+      std::vector<Batch> vals(nst);
       if (have_pre) {
         vals.swap(pre);
         have_pre = false;
@@ -503,15 +596,22 @@ struct Estimator {
       }
       // replay Alg. 2 sample by sample; stop where an active level has no
       // evaluated sample left (levels advance in lockstep)
-      for (int t = 0; t < p.batch; ++t) {
+      for (int t = 0;; ++t) {
         bool any_active = false, missing = false;
         for (int i = 0; i < nst; ++i) {
           any_active = any_active || lv[i].active;
-          if (lv[i].active && t >= (int)vals[i].size()) missing = true;
+          if (lv[i].active && t >= (int)vals[i].vals.size()) missing = true;
         }
         if (!any_active || missing) break;
-        for (int i = 0; i < nst; ++i)
-          if (lv[i].active) lv[i].samples.push_back(vals[i][t]);
+        for (int i = 0; i < nst; ++i) {
+          StochLevel& sl = lv[i];
+          if (!sl.active) continue;
+          sl.samples.push_back(vals[i].vals[t]);
+          sl.costs.push_back(vals[i].cost[t]);
+          sl.its.push_back(vals[i].its[t]);
+          sl.cost_sum += vals[i].cost[t];
+          if (p.cost == MGM_COST_FLOPS) sl.cost = sl.cost_sum / sl.s();
+        }
         ++s;
         tau = tau_exact;
         for (auto& sl : lv) tau += sl.mean() + sl.tau_lr;
@@ -552,10 +652,19 @@ struct Estimator {
       res.lvl_var[i] = lv[i].var();
       res.lvl_cost[i] = lv[i].cost;
       res.lvl_samples[i] = lv[i].s();
-      if (res.sample_dump && res.max_dump > 0) {
-        for (int k = 0; k < std::min(res.max_dump, lv[i].s()); ++k) {
-          res.sample_dump[((int64_t)i * res.max_dump + k) * 2] = lv[i].samples[k].real();
-          res.sample_dump[((int64_t)i * res.max_dump + k) * 2 + 1] = lv[i].samples[k].imag();
+      res.lvl_lr_work[i] = lv[i].lr_cost;
+      res.lvl_work[i] = lv[i].lr_cost + lv[i].cost_sum;
+      const int nd = res.max_dump > 0 ? std::min(res.max_dump, lv[i].s()) : 0;
+      for (int k = 0; k < nd; ++k) {
+        const int64_t at = (int64_t)i * res.max_dump + k;
+        if (res.sample_dump) {
+          res.sample_dump[at * 2] = lv[i].samples[k].real();
+          res.sample_dump[at * 2 + 1] = lv[i].samples[k].imag();
+        }
+        if (res.cost_dump) res.cost_dump[at] = lv[i].costs[k];
+        if (res.iter_dump) {
+          res.iter_dump[at * 2] = lv[i].its[k][0];
+          res.iter_dump[at * 2 + 1] = lv[i].its[k][1];
         }
       }
     }
@@ -570,6 +679,8 @@ int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_re
     r.lvl_solves[i] = 0;
     r.lvl_iters[i] = 0;
     r.lvl_samples[i] = 0;
+    r.lvl_lr_work[i] = 0;
+    r.lvl_work[i] = 0;
   }
   Estimator e(c, g, p, r);
   return e.run();

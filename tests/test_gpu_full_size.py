@@ -119,14 +119,64 @@ def test_full_size_mixed_precision_solves_512(full512):
         assert d < 1e-6
 
 
-def test_full_size_trace_replay_128(full128):
+@pytest.fixture(scope="module")
+def oracle128():
+    from oracle import mg as omg
+    cfg = WORKLOADS["schwinger128"]
+    log("schwinger128: oracle hierarchy")
+    return omg.setup_hierarchy(gauge_for(cfg), cfg["m0"], cfg["blocks"], cfg["ntv"],
+                               mg_setup_kwargs(cfg)["seed"])
+
+
+def test_bench_configuration_parity_128(full128, oracle128):
+    """The timed step exactly as bench.py runs it: adaptive MG-MLMC++ (Alg. 2,
+    reduced form, optimal targets weighed by the Sec. 4 cost model, at least
+    16 samples per level), FGMRES(32) to 1e-10, FP16-block preconditioner,
+    batch 64, 128^2.  The oracle solves exactly and replays the GPU's
+    per-sample costs, which it first recomputes from the GPU's iteration
+    counts with its own cost model: the sample counts are equal, the
+    estimate and every kept sample agree to 1e-8 relative."""
+    from bench import BATCH, SOLVE, method_kwargs
+    from oracle import cost as ocost
+    from oracle import trace as otr
+    from paper_2303_11512_amd import solve_params
+    ctx, gid, D = full128
+    cfg = WORKLOADS["schwinger128"]
+    mk = mg_setup_kwargs(cfg)
+    kw = method_kwargs(cfg, 7)
+    log("schwinger128: GPU estimate in the bench configuration")
+    got = ctx.trace_estimate(gid, solve=solve_params(**SOLVE), batch=BATCH, max_dump=4096, **kw)
+    shape = ocost.shape_from_blocks(cfg["Lx"], cfg["Lt"], mk["blocks"], mk["ntv"], mk["sap_block"],
+                                    [max(1, v) for v in mk["sap_cycles"]], inner_iters=mk["inner_iters"],
+                                    mlmc_levels=mk["mlmc_levels"], restart=SOLVE["restart"])
+    costs = []
+    for l, its in enumerate(got["sample_iters"]):
+        want_c = [ocost.sample(shape, l, int(a), int(b), kw["d"][l]) for a, b in its]
+        assert np.array_equal(np.asarray(got["sample_costs"][l]), np.asarray(want_c, dtype=float)), l
+        costs.append(want_c)
+    log(f"  GPU samples {got['level_samples']}, C_l {got['level_cost']}; oracle estimate (replayed costs)")
+    want = otr.estimate(oracle128, otr.TraceParams(**kw, sample_costs=costs))
+    scale = abs(want["tau"])
+    log(f"  tau GPU {got['tau']:.10f} oracle {want['tau']:.10f}, "
+        f"rel. difference {abs(got['tau'] - want['tau']) / scale:.2e}")
+    assert got["level_samples"] == want["level_samples"]
+    assert min(got["level_samples"]) >= kw["min_samples"]
+    assert abs(got["tau"] - want["tau"]) < 1e-8 * scale
+    for l in range(len(want["level_samples"])):
+        assert abs(got["level_lr"][l] - want["level_lr"][l]) < 1e-8 * scale, l
+        ws, gs = np.array(want["samples"][l]), np.asarray(got["samples"][l])
+        sc = max(np.max(np.abs(ws)), scale / len(ws))
+        log(f"  level {l}: max sample difference / scale {np.max(np.abs(gs - ws)) / sc:.2e}")
+        assert np.max(np.abs(gs - ws)) < 1e-8 * sc, l
+
+
+def test_full_size_trace_replay_128(full128, oracle128):
     """MG-MLMC++ (Alg. 2, reduced form) on the 128^2 workload in the timed
     step's hierarchy, FP16-block preconditioner and batch of 64, replayed with
     8 samples per level difference (Hutch++ with 32 vectors and two power
     steps first): the estimate, the low-rank parts and every sample match the
     oracle's on identical seeds to 1e-8 relative.  Solves are taken to 1e-12
     so that solver error stays far below that."""
-    from oracle import mg as omg
     from oracle import trace as otr
     from paper_2303_11512_amd import solve_params
     ctx, gid, D = full128
@@ -136,10 +186,8 @@ def test_full_size_trace_replay_128(full128):
     log("schwinger128: GPU estimate (replay, 8 samples per level)")
     got = ctx.trace_estimate(gid, solve=solve_params(tol=1e-12, restart=32, max_restarts=50), batch=64,
                              max_dump=4096, **kw)
-    log("schwinger128: oracle hierarchy and estimate")
-    hier = omg.setup_hierarchy(gauge_for(cfg), cfg["m0"], cfg["blocks"], cfg["ntv"],
-                               mg_setup_kwargs(cfg)["seed"])
-    want = otr.estimate(hier, otr.TraceParams(**kw))
+    log("schwinger128: oracle estimate")
+    want = otr.estimate(oracle128, otr.TraceParams(**kw))
     scale = abs(want["tau"])
     log(f"  tau GPU {got['tau']:.10f} oracle {want['tau']:.10f}, "
         f"rel. difference {abs(got['tau'] - want['tau']) / scale:.2e}")
