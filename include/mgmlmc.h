@@ -232,6 +232,18 @@ int mgm_noise(mgm_ctx *ctx, int kind, uint64_t seed, int purpose, int level, int
  * real positive diagonal of R (CholQR2); Q written to DEVICE [d][n]. */
 int mgm_orthonormalize(mgm_ctx *ctx, int64_t n, int d, const void *Y, void *Q);
 
+/* orthonormalize_noalloc -- the same Q = qr+(Y) as mgm_orthonormalize, for
+ * callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. while a HIP graph is being captured, or a serving loop
+ * with a fixed memory budget).  The call allocates nothing: its workspace is
+ * one static device array of about 25 MB that each device using the library
+ * holds until the process ends.  Limits: 1 <= d <= 64, d <= n, n * d <= 2^20
+ * (MGM_EINVAL beyond).  Every call on a device shares that array, so calls
+ * that overlap on one device (several host threads or streams) race; calls
+ * in order on one stream are safe.  Synchronises the stream, like
+ * mgm_orthonormalize. */
+int mgm_orthonormalize_noalloc(mgm_ctx *ctx, int64_t n, int d, const void *Y, void *Q);
+
 /* ---------------------------------------------------------------------------
  * trace_estimate -- tr(D^{-1}) by
  *   MGM_VARIANT_HUTCH    Alg. 1 (plain Hutchinson) on D^{-1};

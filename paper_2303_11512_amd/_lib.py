@@ -141,6 +141,7 @@ SIGNATURES = {
     "mgm_noise": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int,
                             _P]),
     "mgm_orthonormalize": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
+    "mgm_orthonormalize_noalloc": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
     "mgm_trace_estimate": (C.c_int, [_P, C.c_int, C.POINTER(TraceParams), C.POINTER(TraceResult)]),
     "mgm_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -438,6 +439,12 @@ class Context:
     def orthonormalize(self, Y, Q):
         self._chk(self.lib.mgm_orthonormalize(self.h, Y.shape[1], Y.shape[0], _P(_ptr(Y)),
                                               _P(_ptr(Q))), "orthonormalize")
+
+    def orthonormalize_noalloc(self, Y, Q):
+        """As orthonormalize, in the library's static workspace (no device
+        allocation; n * d <= 2^20)."""
+        self._chk(self.lib.mgm_orthonormalize_noalloc(self.h, Y.shape[1], Y.shape[0], _P(_ptr(Y)),
+                                                      _P(_ptr(Q))), "orthonormalize_noalloc")
 
     def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
                        noise="z2z2", targets="optimal", cost="static", fixed_cost=None, min_samples=2,

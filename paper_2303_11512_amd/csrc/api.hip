@@ -3,6 +3,7 @@
 // errors into status codes; nothing here aborts the process.
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <thread>
 
 #include "internal.h"
@@ -34,6 +35,45 @@ int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 }  // namespace mgm
 
 namespace {
+
+// ---------------------------------------------------------------- no-allocation workspace
+// Device memory of mgm_orthonormalize_noalloc: the CholQR workspace of a
+// d x n block with n d <= kNoAllocND -- the temporary Q (n d), the Gram
+// partials (ceil(n / 128) d^2 <= n d 64 / 128 + 64^2 for d <= 64), the Gram
+// matrix / R^{-1} (64^2) and the failure flag -- in one static array
+// that every device holds from the library's load until the process ends.
+// Host code never uses the array's name as an address: its per-device
+// address comes from hipGetSymbolAddress (resolved by mgm_create with the
+// device current) and only that address reaches kernels.
+constexpr int64_t kNoAllocND = int64_t(1) << 20;                  // complex elements of Q
+constexpr int64_t kNoAllocPart = kNoAllocND / 128 * 64 + 64 * 64;  // Gram partials
+constexpr int64_t kNoAllocG = 64 * 64;
+constexpr int64_t kNoAllocCx = kNoAllocND + kNoAllocPart + kNoAllocG + 16;  // + the flag
+__device__ __align__(256) cd scratch[kNoAllocCx];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+cd* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// the array's address on `device` (must be the current device); once per device
+cd* resolve_scratch(int device) {
+  require(device >= 0 && device < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(ptr != nullptr, "no device address for the no-allocation workspace", MGM_EHIP);
+    g_scratch_ptr[device] = static_cast<cd*>(ptr);
+  }
+  return g_scratch_ptr[device];
+}
+
+cd* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  require(device >= 0 && device < kMaxDevices && g_scratch_ptr[device],
+          "no-allocation workspace not resolved on this device", MGM_ESTATE);
+  return g_scratch_ptr[device];
+}
 
 template <class F>
 int guarded(mgm_ctx* c, F&& f) {
@@ -122,6 +162,11 @@ int mgm_create(mgm_ctx** out, int device, void* stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MGM_EHIP;
   if (hipSetDevice(device) != hipSuccess) return MGM_EHIP;
+  try {
+    resolve_scratch(device);
+  } catch (const Error& e) {
+    return e.code;
+  }
   mgm_ctx* c = new mgm_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
@@ -331,6 +376,23 @@ int mgm_orthonormalize(mgm_ctx* c, int64_t n, int d, const void* Y, void* Q) {
   return guarded(c, [&] {
     require(Y && Q && Y != Q, "bad arguments");
     orthonormalize(c, n, d, static_cast<const cd*>(Y), static_cast<cd*>(Q));
+    return MGM_OK;
+  });
+}
+
+int mgm_orthonormalize_noalloc(mgm_ctx* c, int64_t n, int d, const void* Y, void* Q) {
+  return guarded(c, [&] {
+    require(Y && Q && Y != Q, "bad arguments");
+    require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
+    require(n <= kNoAllocND / d, "orthonormalize_noalloc: n * d exceeds 2^20 complex elements");
+    const int64_t np = gram_partials(n) * d * d;
+    require(np <= kNoAllocPart, "orthonormalize_noalloc: Gram partials exceed the workspace");
+    cd* base = scratch_of(c->device);
+    cd* tmp = base;
+    cd* part = base + kNoAllocND;
+    cd* G = part + kNoAllocPart;
+    int* fail = reinterpret_cast<int*>(G + kNoAllocG);
+    orthonormalize_ws(c->stream, n, d, static_cast<const cd*>(Y), static_cast<cd*>(Q), tmp, G, part, fail);
     return MGM_OK;
   });
 }

@@ -682,6 +682,17 @@ void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partia
 
 int64_t gram_partials(int64_t n) { return (n + GCH - 1) / GCH; }
 
+__global__ void k_fill_int(int* __restrict__ p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+void launch_fill_int(hipStream_t s, int* p, int count, int v) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((count + NT - 1) / NT), dim3(NT), 0, s, p, count, v);
+  KCHK();
+}
+
 void launch_cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev) {
   require(d >= 1 && d <= 64, "orthonormalize: 1 <= d <= 64");
   hipLaunchKernelGGL(k_cholesky_rinv, dim3(1), dim3(NT), 0, s, G, d, shift, fail_dev);

@@ -294,6 +294,8 @@ template <class T>
 void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
                         T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr);
 void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial);
+// p[0..count) = v (a kernel, so that captured graphs hold no memset node)
+void launch_fill_int(hipStream_t s, int* p, int count, int v);
 // G + shift tr(G) I = R^H R; G <- R^{-1}; *fail_dev |= 1 if not positive definite
 void launch_cholesky_rinv(hipStream_t s, cd* G, int d, double shift, int* fail_dev);
 // number of Gram partials launch_gram writes (each d x d)
@@ -478,6 +480,8 @@ int solve_chunked(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                   const mgm_solve_params& sp, int* iters, double* relres);
 void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p);
 void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q);
+void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
+                       int* fail);
 int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r);
 // learned initial guess (cnn.hip)
 void cnn_check_lattice(const Gauge& g);

@@ -418,27 +418,21 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 
 // Q = qr+(Y): shifted CholQR followed by two plain CholQR passes.  The
 // product of the three triangular factors has a positive diagonal, so Q is
-// the unique thin-QR factor with positive real diag(R).
-void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
-  hipStream_t s = c->stream;
+// the unique thin-QR factor with positive real diag(R).  Workspace: tmp
+// [d][n], G [d][d], part [gram_partials(n)][d][d], fail (one int).
+void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
+                       int* fail) {
   require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
-  c->qr_tmp.ensure(sizeof(cd) * (size_t)d * n);
-  c->qr_G.ensure(sizeof(cd) * d * d);
-  c->qr_part.ensure(sizeof(cd) * (size_t)d * d * gram_partials(n));
-  c->qr_fail.ensure(sizeof(int));
-  cd* tmp = c->qr_tmp.as<cd>();
-  cd* G = c->qr_G.as<cd>();
-  int* fail = c->qr_fail.as<int>();
-  HIPCHK(hipMemsetAsync(fail, 0, sizeof(int), s));
-  // pass 0: Y -> Q (shifted Gram), pass 1: Q -> tmp, pass 2: tmp -> Q
   require(Y != Q, "orthonormalize: Y and Q must not overlap");
+  launch_fill_int(s, fail, 1, 0);
+  // pass 0: Y -> Q (shifted Gram), pass 1: Q -> tmp, pass 2: tmp -> Q
   const double shifts[3] = {1e-14, 0.0, 0.0};
   const cd* srcs[3] = {Y, Q, tmp};
   cd* dsts[3] = {Q, tmp, Q};
   for (int pass = 0; pass < 3; ++pass) {
     const cd* src = srcs[pass];
     cd* dst = dsts[pass];
-    launch_gram(s, src, n, d, G, c->qr_part.as<cd>());
+    launch_gram(s, src, n, d, G, part);
     launch_cholesky_rinv(s, G, d, shifts[pass], fail);
     launch_right_tri(s, src, G, n, d, dst);
   }
@@ -446,6 +440,16 @@ void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
   HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (hfail) throw Error(MGM_ENONFINITE, "CholQR: Gram matrix not positive definite (rank-deficient block)");
+}
+
+void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q) {
+  require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
+  c->qr_tmp.ensure(sizeof(cd) * (size_t)d * n);
+  c->qr_G.ensure(sizeof(cd) * d * d);
+  c->qr_part.ensure(sizeof(cd) * (size_t)d * d * gram_partials(n));
+  c->qr_fail.ensure(sizeof(int));
+  orthonormalize_ws(c->stream, n, d, Y, Q, c->qr_tmp.as<cd>(), c->qr_G.as<cd>(), c->qr_part.as<cd>(),
+                    c->qr_fail.as<int>());
 }
 
 // ------------------------------------------------------------------ setup
