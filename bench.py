@@ -93,14 +93,18 @@ TRAFFIC_SUMMARY = {p: os.path.join(ROOT, "profiles", f"{KERNEL_NAME[p].replace('
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_11512_amd", "csrc", "ops.hip")
 
 
-def measured_traffic(precision):
-    """HBM bytes per launch of the dominant kernel from its committed counter
-    summary; None when there is none or the kernel source has changed since
-    the counters were taken."""
+STENCIL512_SUMMARY = os.path.join(ROOT, "profiles", "k_wilson_strip_schwinger512_traffic.txt")
+
+
+def measured_traffic(precision=None, path=None):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (the dominant kernel of the step for `precision`, or the file `path`);
+    None when there is none or the kernel source has changed since the
+    counters were taken."""
     import hashlib
     try:
         fields = {}
-        with open(TRAFFIC_SUMMARY[precision]) as f:
+        with open(path or TRAFFIC_SUMMARY[precision]) as f:
             for ln in f:
                 if ":" in ln and not ln.startswith((" ", "#")):
                     k, v = ln.split(":", 1)
@@ -340,6 +344,13 @@ def run_mixed(args):
     th = gauge_for(cfg)
     ctx = Context(0)
     gid = ctx.set_gauge(torch.from_numpy(links_from_theta(th)).to("cuda"), cfg["m0"], True)
+    if args.roofline_only:
+        # counter runs: the fine stencil and the copy kernel at 512^2, 64 RHS
+        # (no multigrid needed)
+        out = {k: ctx.time_kernel(gid, k, 0, KERNEL_RHS, reps=5) for k in ("stencil", "copy")}
+        print(json.dumps(out))
+        ctx.close()
+        return
     kw = mg_setup_kwargs(cfg)
     t0 = time.perf_counter()
     ctx.setup_mg(gid, mg_params(**kw))
@@ -377,9 +388,13 @@ def run_mixed(args):
     ctx.set_precision(gid, "fp64")
     st = ctx.time_kernel(gid, "stencil", 0, KERNEL_RHS)
     ach = st["bytes"] / (st["us"] * 1e-6) / 1e9
+    cp = ctx.time_kernel(gid, "copy", 0, KERNEL_RHS)
+    copy_gbs = cp["bytes"] / (cp["us"] * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": f"fine stencil, FP64, 512x512, {KERNEL_RHS} RHS",
-            "launch_us": st["us"], "alg_bytes": st["bytes"]}
+            "traffic": measured_traffic(path=STENCIL512_SUMMARY),
+            "kernel": f"fine stencil, FP64, 512x512, {KERNEL_RHS} RHS",
+            "launch_us": st["us"], "alg_bytes": st["bytes"],
+            "copy_GBs": copy_gbs, "frac_of_copy": ach / copy_gbs}
     print(f"# stencil 512^2: {st['us']:.1f} us, {ach:.0f} GB/s", file=sys.stderr, flush=True)
     xn = torch.linalg.norm(res["fp64"]["x"])
     tau64 = res["fp64"]["tau"]

@@ -55,6 +55,7 @@ extern "C" {
 #define MGM_PURPOSE_SKETCH 2
 #define MGM_PURPOSE_SAMPLE 3
 #define MGM_PURPOSE_TRAIN 4   /* right-hand sides of the network's training pairs */
+#define MGM_PURPOSE_DEFLATE 5 /* start block of the deflation subspace iteration */
 
 /* precision of the multigrid preconditioner (the outer FGMRES, its residuals,
  * orthogonalisation and every trace sum are always FP64):
@@ -249,7 +250,19 @@ int mgm_orthonormalize_noalloc(mgm_ctx *ctx, int64_t n, int d, const void *Y, vo
  *   MGM_VARIANT_HUTCH    Alg. 1 (plain Hutchinson) on D^{-1};
  *   MGM_VARIANT_HUTCHPP  Hutch++ (Sec. 2.4) on D^{-1};
  *   MGM_VARIANT_MLMC     MG-MLMC (Sec. 3.1), i.e. Alg. 2 with d_l = 0;
- *   MGM_VARIANT_MLMCPP   MG-MLMC++ (Alg. 2).
+ *   MGM_VARIANT_MLMCPP   MG-MLMC++ (Alg. 2);
+ *   MGM_VARIANT_DEFLATED deflated Hutchinson (Sec. 2.2, the reference method
+ *                        of Sec. 4): Pi = Q Q^H with Q (n x d[0]) from k_power
+ *                        sweeps of block subspace iteration
+ *                        Q <- qr(D^{-1} gamma5 D^{-1} gamma5 Q) (noise purpose
+ *                        DEFLATE at the start), which converges to the right
+ *                        singular vectors of D of the d[0] smallest singular
+ *                        values (D^{-H} = gamma5 D^{-1} gamma5 for this
+ *                        operator); tr(Pi D^{-1}) = tr(Q^H D^{-1} Q) from d[0]
+ *                        solves (exact for any orthonormal Q, Sec. 2.3) and
+ *                        Hutchinson on (I - Pi) D^{-1}.  The exact-deflation
+ *                        value sum u_i^H v_i / sigma_i of the Ritz triplets of
+ *                        D on span(Q) is reported next to it (defl_ritz).
  * Level differences use the reduced form (eq. mlmc_dec_trace_reduced) or the
  * full form with accumulated prolongations (eq. mlmc_decomp_trace).  Samples
  * are drawn `batch` at a time per active level and Alg. 2's stopping rule is
@@ -262,10 +275,13 @@ int mgm_orthonormalize_noalloc(mgm_ctx *ctx, int64_t n, int d, const void *Y, vo
 #define MGM_VARIANT_HUTCHPP 1
 #define MGM_VARIANT_MLMC 2
 #define MGM_VARIANT_MLMCPP 3
+#define MGM_VARIANT_DEFLATED 4
 #define MGM_FORM_REDUCED 0
 #define MGM_FORM_FULL 1
 #define MGM_TARGETS_OPTIMAL 0
 #define MGM_TARGETS_UNIFORM 1
+#define MGM_PROJ_ONE_SIDED 0
+#define MGM_PROJ_TWO_SIDED 1
 /* cost C_{s,l} of a stochastic sample (Alg. 2), which weighs the optimal
  * target variances (Sec. 3, eq. optimal_variance):
  *   STATIC  one number per level: nnz(D_l) + nnz(D_{l+1}) + 2 n_l d_l;
@@ -301,6 +317,12 @@ typedef struct {
   uint64_t seed;
   int batch;                         /* samples per level per GPU batch      */
   mgm_solve_params solve;
+  int projection;                    /* MGM_PROJ_ONE_SIDED: tau_s =
+                                        z^H (A zeta) as Alg. 2 prints;
+                                        MGM_PROJ_TWO_SIDED: tau_s = z^H (A z),
+                                        Hutchinson on (I - QQ^H) A (I - QQ^H):
+                                        same mean, another variance; its
+                                        samples are solved after Q is final */
   int concurrent;                    /* 1: a phase's solves on different
                                         levels run at once on two streams of
                                         the field (same results as 0)       */
@@ -325,6 +347,12 @@ typedef struct {
   double *sample_dump;                 /* HOST [nstoch][max_dump][2] or NULL  */
   double *cost_dump;                   /* HOST [nstoch][max_dump] or NULL:
                                           each kept sample's Sec. 4 cost     */
+  double defl_ritz[2];                 /* deflated variant: sum u_i^H v_i /
+                                          sigma_i over the Ritz singular
+                                          triplets of D on span(Q)           */
+  double *sigma_dump;                  /* deflated variant: HOST [d[0]] or
+                                          NULL, those Ritz singular values
+                                          ascending                         */
   int *iter_dump;                      /* HOST [nstoch][max_dump][2] or NULL:
                                           FGMRES iterations of each kept
                                           sample's solves on D_l, D_{l+1}

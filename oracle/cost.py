@@ -149,7 +149,7 @@ def sample(sh: SolverShape, l: int, its_fine: int, its_coarse: int, d: int, form
            variant: str = "mlmcpp") -> int:
     """C_{s,l}: the projection and the level-difference application of one
     stochastic sample (Alg. 2, the projected vector and the sample value)."""
-    if variant in ("hutchinson", "hutchpp"):
+    if variant in ("hutchinson", "hutchpp", "deflated"):
         return solve(sh, 0, its_fine) + 2 * sh.levels[0].n * d
     if form == "reduced":
         lev = sh.levels[l]

@@ -39,6 +39,7 @@ _C2 = np.uint64(0x94D049BB133111EB)
 PURPOSE_SETUP = 1    # multigrid test vectors
 PURPOSE_SKETCH = 2   # Hutch++ block power iteration start vectors S_l
 PURPOSE_SAMPLE = 3   # stochastic samples zeta_s
+PURPOSE_DEFLATE = 5  # start block of the deflation subspace iteration
 
 RADEMACHER = "rademacher"
 Z2Z2 = "z2z2"

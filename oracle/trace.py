@@ -6,6 +6,10 @@
                   d solves, Hutchinson on the projected remainder.
 * ``mlmc``        MG-MLMC (Sec. 3.1): Alg. 2 with d_l = 0.
 * ``mlmcpp``      MG-MLMC++ (Alg. 2).
+* ``deflated``    deflated Hutchinson (Sec. 2.2, the reference method of
+                  Sec. 4): the deflation basis from subspace iteration on
+                  D^{-1} D^{-H} (``oracle.deflation``), tr(Q^H D^{-1} Q) from
+                  d solves, Hutchinson on the projected remainder.
 
 All four share one control loop, which is Alg. 2's stochastic part; with a
 single stochastic level its stopping rule reduces to Alg. 1's
@@ -25,7 +29,8 @@ Readings of the paper taken here:
   solves per level.
 * Eq. hutchpp_decomp is read as D^{-1} = (I - QQ^H) D^{-1} + QQ^H D^{-1}.
 * Samples are one-sided as printed: z = zeta - Q (Q^H zeta),
-  tau_s = z^H (A_l zeta).
+  tau_s = z^H (A_l zeta); the two-sided z^H (A_l z) is an option (same mean,
+  different variance).
 * tau is complex; the accuracy tests use |tau|, the variance uses
   |tau_i - mean|^2 (Alg. 1 / Alg. 2 as printed).  No stop test before
   ``min_samples`` (>= 2) samples, since V has a 1/(s-1) factor.
@@ -58,6 +63,7 @@ from typing import Callable, Optional
 import numpy as np
 
 from . import cost as cmodel
+from . import deflation
 from . import rng
 from .mg import Hierarchy, coarsest_trace
 
@@ -79,6 +85,7 @@ class TraceParams:
     fixed_samples: Optional[list] = None   # replay mode: exact sample counts
     seed: int = 1
     levels: int = 0                    # hierarchy levels used by the MLMC variants (0 = all)
+    projection: str = "one-sided"      # one-sided (Alg. 2 as printed) | two-sided
 
 
 @dataclass
@@ -126,7 +133,7 @@ def level_ops(hier: Hierarchy, variant: str, form: str, levels: int = 0):
     ``levels`` < hier.L closes the telescoping sum at level ``levels - 1``:
     the coarser levels of the hierarchy then only serve the solver."""
     L = levels if levels else hier.L
-    if variant in ("hutchinson", "hutchpp"):
+    if variant in ("hutchinson", "hutchpp", "deflated"):
         lev0 = hier.levels[0]
         return [(lev0.solve, lev0.n)], 0.0
     if L < 2:
@@ -171,18 +178,21 @@ def low_rank(A, n: int, d: int, k: int, noise: str, seed: int, level: int):
     return Q, tau_lr
 
 
-def sample(lvl: StochLevel, noise: str, seed: int, level: int, index: int) -> complex:
-    """tau_{s,l} = z^H (A_l zeta), z = zeta - Q (Q^H zeta)  (Alg. 2 lines 12-13)."""
+def sample(lvl: StochLevel, noise: str, seed: int, level: int, index: int, two_sided: bool = False) -> complex:
+    """tau_{s,l} = z^H (A_l zeta), z = zeta - Q (Q^H zeta): Alg. 2's projected
+    vector and sample value, one-sided as printed.  ``two_sided``:
+    tau_{s,l} = z^H (A_l z), Hutchinson on (I - QQ^H) A_l (I - QQ^H), which
+    has the same mean tr((I - QQ^H) A_l) and another variance."""
     zeta = rng.noise_vector(noise, seed, rng.PURPOSE_SAMPLE, level, index, lvl.n)
     z = zeta if lvl.Q is None else zeta - lvl.Q @ (lvl.Q.conj().T @ zeta)
-    x = lvl.apply(zeta[:, None])[:, 0]
+    x = lvl.apply((z if two_sided else zeta)[:, None])[:, 0]
     return complex(np.vdot(z, x))
 
 
 def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
     ops, tau_exact = level_ops(hier, prm.variant, prm.form, prm.levels)
     nl = len(ops)
-    use_lr = prm.variant in ("hutchpp", "mlmcpp")
+    use_lr = prm.variant in ("hutchpp", "mlmcpp", "deflated")
     mode = "fixed" if prm.fixed_cost is not None else prm.cost
     if mode not in ("static", "fixed", "flops"):
         raise ValueError(prm.cost)
@@ -202,7 +212,11 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
 
     # deflation vectors and low-rank parts (Alg. 2, first loop)
     for l, lv in enumerate(levels):
-        if lv.d > 0:
+        if lv.d > 0 and prm.variant == "deflated":
+            g5 = hier.levels[0].chirality().astype(np.complex128)
+            lv.Q = deflation.subspace_basis(lv.apply, g5, lv.n, lv.d, max(1, prm.k_power), prm.noise, prm.seed)
+            lv.tau_lr = complex(np.trace(lv.Q.conj().T @ lv.apply(lv.Q)))
+        elif lv.d > 0:
             lv.Q, lv.tau_lr = low_rank(lv.apply, lv.n, lv.d, prm.k_power, prm.noise, prm.seed, l)
 
     # stochastic part (Alg. 2, second loop)
@@ -212,7 +226,8 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
         s += 1
         for l, lv in enumerate(levels):
             if lv.active:
-                lv.samples.append(sample(lv, prm.noise, prm.seed, l, s - 1))
+                lv.samples.append(sample(lv, prm.noise, prm.seed, l, s - 1,
+                                         two_sided=prm.projection == "two-sided"))
                 if lv.sample_costs is not None:
                     if s - 1 >= len(lv.sample_costs):
                         raise IndexError(f"no cost given for sample {s - 1} of level {l}")

@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(HERE, "libmgmlmc.so")
 MAX_LEVELS = 6
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 NOISE_RADEMACHER, NOISE_Z2Z2 = 0, 1
-PURPOSE_SETUP, PURPOSE_SKETCH, PURPOSE_SAMPLE, PURPOSE_TRAIN = 1, 2, 3, 4
+PURPOSE_SETUP, PURPOSE_SKETCH, PURPOSE_SAMPLE, PURPOSE_TRAIN, PURPOSE_DEFLATE = 1, 2, 3, 4, 5
 PREC_FP64, PREC_FP32, PREC_FP16 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16": PREC_FP16}
-VARIANTS = {"hutchinson": 0, "hutchpp": 1, "mlmc": 2, "mlmcpp": 3}
+VARIANTS = {"hutchinson": 0, "hutchpp": 1, "mlmc": 2, "mlmcpp": 3, "deflated": 4}
 FORMS = {"reduced": 0, "full": 1}
 TARGETS = {"optimal": 0, "uniform": 1}
 COSTS = {"static": 0, "fixed": 1, "flops": 2}
@@ -94,6 +94,7 @@ class TraceParams(C.Structure):
         ("seed", C.c_uint64),
         ("batch", C.c_int),
         ("solve", SolveParams),
+        ("projection", C.c_int),
         ("concurrent", C.c_int),
     ]
 
@@ -114,6 +115,8 @@ class TraceResult(C.Structure):
         ("lvl_work", C.c_double * MAX_LEVELS),
         ("sample_dump", C.POINTER(C.c_double)),
         ("cost_dump", C.POINTER(C.c_double)),
+        ("defl_ritz", C.c_double * 2),
+        ("sigma_dump", C.POINTER(C.c_double)),
         ("iter_dump", C.POINTER(C.c_int)),
         ("max_dump", C.c_int),
     ]
@@ -449,7 +452,7 @@ class Context:
     def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
                        noise="z2z2", targets="optimal", cost="static", fixed_cost=None, min_samples=2,
                        max_samples=0, fixed_samples=None, seed=1, batch=64, solve=None,
-                       max_dump=0, concurrent=True) -> dict:
+                       max_dump=0, concurrent=True, projection="one-sided") -> dict:
         p = TraceParams()
         p.variant = VARIANTS[variant]
         p.form = FORMS[form]
@@ -473,7 +476,12 @@ class Context:
         p.batch = batch
         p.solve = solve or solve_params()
         p.concurrent = int(bool(concurrent))
+        p.projection = {"one-sided": 0, "two-sided": 1}[projection]
         r = TraceResult()
+        sig = None
+        if variant == "deflated" and len(d) > 0 and d[0] > 0:
+            sig = (C.c_double * d[0])()
+            r.sigma_dump = C.cast(sig, C.POINTER(C.c_double))
         dump = cdump = idump = None
         if max_dump > 0:
             dump = (C.c_double * (MAX_LEVELS * max_dump * 2))()
@@ -498,6 +506,9 @@ class Context:
             level_lr_work=[r.lvl_lr_work[i] for i in range(ns)],
             level_work=[r.lvl_work[i] for i in range(ns)],
         )
+        if sig is not None:
+            out["defl_ritz"] = complex(r.defl_ritz[0], r.defl_ritz[1])
+            out["sigma"] = np.array(sig[:])
         if dump is not None:
             arr = np.frombuffer(dump, dtype=np.float64).reshape(MAX_LEVELS, max_dump, 2)
             out["samples"] = [

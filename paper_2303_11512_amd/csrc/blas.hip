@@ -682,6 +682,20 @@ void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partia
 
 int64_t gram_partials(int64_t n) { return (n + GCH - 1) / GCH; }
 
+// out = gamma5 in on the fine level: the spin-1 component (odd dof) negated
+__global__ void __launch_bounds__(NT) k_gamma5(const cd* __restrict__ in, cd* __restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= count) return;
+  const cd v = in[i];
+  out[i] = (i & 1) ? mk(-v.re, -v.im) : v;
+}
+
+void launch_gamma5(hipStream_t s, const cd* in, cd* out, int64_t count) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_gamma5, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, s, in, out, count);
+  KCHK();
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int count, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;

@@ -294,6 +294,9 @@ template <class T>
 void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
                         T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr);
 void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial);
+// out = gamma5 in for `count` complex numbers of fine-level vectors (even
+// length n, so the dof parity is the spin)
+void launch_gamma5(hipStream_t s, const cd* in, cd* out, int64_t count);
 // p[0..count) = v (a kernel, so that captured graphs hold no memset node)
 void launch_fill_int(hipStream_t s, int* p, int count, int v);
 // G + shift tr(G) I = R^H R; G <- R^{-1}; *fail_dev |= 1 if not positive definite

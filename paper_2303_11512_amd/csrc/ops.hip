@@ -108,8 +108,11 @@ __device__ __forceinline__ void wilson_site(T diag, cx<T> o0, cx<T> o1, cx<T> e0
 // stores keep it from displacing the input's halo rows in L2.
 template <class T>
 __device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
-  __builtin_nontemporal_store(v.re, &p->re);
-  __builtin_nontemporal_store(v.im, &p->im);
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.re;
+  w.y = v.im;
+  __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
 }
 
 // Thread per site, for any lattice.  The (tile, RHS) grid is renumbered as a
@@ -166,9 +169,11 @@ __global__ void __launch_bounds__(NT) k_wilson_strip(const cx<T>* __restrict__ U
   __shared__ cx<T> sx[2][2][NT * SPT];
   __shared__ cx<T> su[2][NT * SPT];
   const int64_t G = gridDim.x;
-  const int64_t Lg = xcd_tile(blockIdx.x + G * blockIdx.y, G * gridDim.y);
-  const int r = (int)(Lg / G);
-  const int strip = (int)(Lg % G);
+  const int64_t NR = gridDim.y;
+  const int64_t Lg = xcd_tile(blockIdx.x + G * blockIdx.y, G * NR);
+  // RHS fastest: the strips an XCD holds at once share rows of the links
+  const int r = (int)(Lg % NR);
+  const int strip = (int)(Lg / NR);
   if (active && !active[r]) return;
   const int64_t V = (int64_t)Lx * Lt;
   const int BD = blockDim.x;

@@ -16,6 +16,7 @@
 // go into one solve per level: a coarse level is small enough that its
 // kernels cost nearly the same for 32 or 64 right-hand sides, and each
 // right-hand side still has its own Krylov space and stopping test.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <complex>
@@ -77,6 +78,8 @@ struct Estimator {
   int L;                 // number of levels of the hierarchy
   bool full;             // full (hatted) form
   bool hutch;            // single-level variants on D^{-1}
+  bool deflated;         // deflated Hutchinson (subspace-iteration basis)
+  bool two_sided;        // samples z^H A z instead of z^H A zeta
   int kmax = 1;          // most vectors one difference hands to a solve
   // workspaces of the field (scratch vectors, dot products)
   DevBuf &t1, &t3, &t4, &dots, &part;
@@ -86,7 +89,10 @@ struct Estimator {
         dots(g_.est.dots), part(g_.est.part) {
     L = g.mlmc_levels;
     full = p.form == MGM_FORM_FULL;
-    hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP;
+    hutch = p.variant == MGM_VARIANT_HUTCH || p.variant == MGM_VARIANT_HUTCHPP ||
+            p.variant == MGM_VARIANT_DEFLATED;
+    deflated = p.variant == MGM_VARIANT_DEFLATED;
+    two_sided = p.projection == MGM_PROJ_TWO_SIDED;
     cost_init();
   }
 
@@ -416,6 +422,10 @@ struct Estimator {
       return;
     }
     std::vector<Its> its;
+    if (deflated) {
+      deflation_basis(lv[0]);
+      items[0].X = lv[0].Q->as<cd>();
+    } else {
     for (int it = 0; it < std::max(1, p.k_power); ++it) {
       applyA_levels(lv, items, its);
       add_lr_cost(lv, items, its, items.size());
@@ -424,8 +434,11 @@ struct Estimator {
         x.X = lv[x.i].Q->as<cd>();
       }
     }
+    }
     const size_t nlr = items.size();
-    sample_start(lv, first, items);
+    // A zeta does not depend on Q, so the first batch of one-sided samples
+    // rides with the last round; two-sided samples need the final Q first
+    if (!two_sided) sample_start(lv, first, items);
     applyA_levels(lv, items, its);
     add_lr_cost(lv, items, its, nlr);
     for (size_t q = 0; q < nlr; ++q) {
@@ -436,8 +449,148 @@ struct Estimator {
       for (const zc& y : v) acc += y;
       lv[x.i].tau_lr = acc;
     }
-    sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()),
-                  std::vector<Its>(its.begin() + nlr, its.end()), first_vals);
+    if (two_sided) {
+      sample_batches(lv, first, first_vals);
+    } else {
+      sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()),
+                    std::vector<Its>(its.begin() + nlr, its.end()), first_vals);
+    }
+    if (deflated) ritz_triplets(lv[0]);
+  }
+
+  // Deflation basis (Sec. 2.2): k_power sweeps of block subspace iteration
+  // Q <- qr(D^{-1} gamma5 D^{-1} gamma5 Q) from noise of purpose DEFLATE; it
+  // converges to the right singular vectors of D of the smallest singular
+  // values, since D^{-1} D^{-H} = D^{-1} gamma5 D^{-1} gamma5 here.
+  void deflation_basis(StochLevel& sl) {
+    hipStream_t s = c->stream;
+    const int d = sl.d;
+    const int64_t n = sl.n;
+    cd* S = g.est.S[0].as<cd>();
+    cd* Y = g.est.Y[0].as<cd>();
+    t1.ensure(sizeof(cd) * (size_t)d * n);
+    cd* T = t1.as<cd>();
+    launch_noise<double>(s, S, n, d, p.noise, p.seed, MGM_PURPOSE_DEFLATE, 0, 0);
+    const cd* X = S;
+    for (int it = 0; it < std::max(1, p.k_power); ++it) {
+      launch_gamma5(s, X, Y, (int64_t)d * n);
+      for (int v : solve(0, d, Y, T)) sl.lr_cost += solve_cost(0, v);
+      launch_gamma5(s, T, Y, (int64_t)d * n);
+      for (int v : solve(0, d, Y, T)) sl.lr_cost += solve_cost(0, v);
+      orthonormalize(c, n, d, T, sl.Q->as<cd>());
+      X = sl.Q->as<cd>();
+    }
+  }
+
+  // Ritz singular triplets of D on span(Q): W = D Q, G = W^H W, C = W^H Q;
+  // sum_i u_i^H v_i / sigma_i = tr(G^{-1} C) (with G = Y diag(sigma^2) Y^H,
+  // v_i = Q y_i, u_i = W y_i / sigma_i) and sigma = sqrt(eig(G)).
+  void ritz_triplets(StochLevel& sl) {
+    hipStream_t s = c->stream;
+    const int d = sl.d;
+    const int64_t n = sl.n;
+    cd* W = g.est.S[0].as<cd>();  // free after the subspace iteration
+    apply_level(c, g, 0, d, sl.Q->as<cd>(), W);
+    dots.ensure(sizeof(cd) * 2 * (size_t)d * d);
+    cd* Gd = dots.as<cd>();
+    cd* Cd = Gd + (int64_t)d * d;
+    launch_dot_multi_ld<double>(s, W, n, 0, d, W, n, d, Gd, d, 0, nullptr, part.as<cd>());
+    launch_dot_multi_ld<double>(s, W, n, 0, d, sl.Q->as<cd>(), n, d, Cd, d, 0, nullptr, part.as<cd>());
+    std::vector<cd> h(2 * (size_t)d * d);
+    HIPCHK(hipMemcpyAsync(h.data(), Gd, sizeof(cd) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // out[r * d + i] = (W_i)^H X_r, i.e. G[i][r] and C[i][r]
+    std::vector<zc> G((size_t)d * d), Cm((size_t)d * d);
+    for (int r = 0; r < d; ++r)
+      for (int i = 0; i < d; ++i) {
+        G[(size_t)i * d + r] = zc(h[(size_t)r * d + i].re, h[(size_t)r * d + i].im);
+        Cm[(size_t)i * d + r] = zc(h[(size_t)d * d + (size_t)r * d + i].re, h[(size_t)d * d + (size_t)r * d + i].im);
+      }
+    // Cholesky G = L L^H, then tr(G^{-1} C) = sum_j (L^{-H} L^{-1} C)_jj
+    std::vector<zc> Lc = G;
+    for (int j = 0; j < d; ++j) {
+      double dj = Lc[(size_t)j * d + j].real();
+      for (int k = 0; k < j; ++k) dj -= std::norm(Lc[(size_t)j * d + k]);
+      require(dj > 0, "deflation: D Q is rank-deficient", MGM_ENONFINITE);
+      dj = std::sqrt(dj);
+      Lc[(size_t)j * d + j] = dj;
+      for (int i = j + 1; i < d; ++i) {
+        zc v = Lc[(size_t)i * d + j];
+        for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * d + k] * std::conj(Lc[(size_t)j * d + k]);
+        Lc[(size_t)i * d + j] = v / dj;
+      }
+    }
+    zc tr = 0;
+    std::vector<zc> col(d);
+    for (int r = 0; r < d; ++r) {
+      for (int i = 0; i < d; ++i) col[i] = Cm[(size_t)i * d + r];
+      for (int i = 0; i < d; ++i) {  // L y = c
+        zc v = col[i];
+        for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * d + k] * col[k];
+        col[i] = v / Lc[(size_t)i * d + i];
+      }
+      for (int i = d - 1; i >= 0; --i) {  // L^H x = y
+        zc v = col[i];
+        for (int k = i + 1; k < d; ++k) v -= std::conj(Lc[(size_t)k * d + i]) * col[k];
+        col[i] = v / Lc[(size_t)i * d + i];
+      }
+      tr += col[r];
+    }
+    res.defl_ritz[0] = tr.real();
+    res.defl_ritz[1] = tr.imag();
+    if (res.sigma_dump) {
+      const std::vector<double> lam = hermitian_eigenvalues(G, d);
+      for (int i = 0; i < d; ++i) res.sigma_dump[i] = std::sqrt(std::max(0.0, lam[i]));
+    }
+  }
+
+  // eigenvalues (ascending) of the Hermitian d x d matrix A by cyclic Jacobi
+  // on its real symmetric embedding [[Re A, -Im A], [Im A, Re A]], whose
+  // eigenvalues are those of A, each twice
+  static std::vector<double> hermitian_eigenvalues(const std::vector<zc>& A, int d) {
+    const int m = 2 * d;
+    std::vector<double> B((size_t)m * m);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        const zc a = A[(size_t)i * d + j];
+        B[(size_t)i * m + j] = a.real();
+        B[(size_t)(i + d) * m + j + d] = a.real();
+        B[(size_t)i * m + j + d] = -a.imag();
+        B[(size_t)(i + d) * m + j] = a.imag();
+      }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0, tot = 0;
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          tot += B[(size_t)i * m + j] * B[(size_t)i * m + j];
+          if (i != j) off += B[(size_t)i * m + j] * B[(size_t)i * m + j];
+        }
+      if (off <= 1e-30 * tot) break;
+      for (int pp = 0; pp < m; ++pp)
+        for (int q = pp + 1; q < m; ++q) {
+          const double apq = B[(size_t)pp * m + q];
+          if (apq == 0.0) continue;
+          const double th = (B[(size_t)q * m + q] - B[(size_t)pp * m + pp]) / (2.0 * apq);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+          const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+          for (int k = 0; k < m; ++k) {  // columns pp, q
+            const double bkp = B[(size_t)k * m + pp], bkq = B[(size_t)k * m + q];
+            B[(size_t)k * m + pp] = cs * bkp - sn * bkq;
+            B[(size_t)k * m + q] = sn * bkp + cs * bkq;
+          }
+          for (int k = 0; k < m; ++k) {  // rows pp, q
+            const double bpk = B[(size_t)pp * m + k], bqk = B[(size_t)q * m + k];
+            B[(size_t)pp * m + k] = cs * bpk - sn * bqk;
+            B[(size_t)q * m + k] = sn * bpk + cs * bqk;
+          }
+        }
+    }
+    std::vector<double> ev(m);
+    for (int i = 0; i < m; ++i) ev[i] = B[(size_t)i * m + i];
+    std::sort(ev.begin(), ev.end());
+    std::vector<double> out(d);
+    for (int i = 0; i < d; ++i) out[i] = 0.5 * (ev[2 * i] + ev[2 * i + 1]);
+    return out;
   }
 
   // noise zeta for samples s .. s+b[i]-1 of every difference i with b[i] > 0
@@ -450,6 +603,7 @@ struct Estimator {
       g.est.X[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
       launch_noise<double>(c->stream, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed, MGM_PURPOSE_SAMPLE, i,
                            sl.s());
+      if (two_sided) project(sl, i, b[i]);
       items.push_back({i, b[i], g.est.Z[i].as<cd>(), g.est.X[i].as<cd>()});
     }
   }
@@ -458,27 +612,32 @@ struct Estimator {
   // sample_start made (X = zeta, Y = A zeta)
   void sample_finish(std::vector<StochLevel>& lv, const std::vector<Item>& items, const std::vector<Its>& its,
                      std::vector<Batch>& out) {
-    hipStream_t s = c->stream;
     for (size_t q = 0; q < items.size(); ++q) {
       const Item& it = items[q];
       StochLevel& sl = lv[it.i];
       const int64_t n = sl.n;
       cd* Z = g.est.Z[it.i].as<cd>();
-      if (sl.d > 0) {
-        DevBuf& C = g.est.C[it.i];
-        C.ensure(sizeof(cd) * (size_t)kmax * sl.d);
-        part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
-        launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z, n, it.k, C.as<cd>(), sl.d, 0, nullptr,
-                                    part.as<cd>());
-        launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z, n, it.k,
-                                    nullptr, nullptr, nullptr);
-      }
+      if (!two_sided) project(sl, it.i, it.k);  // (two-sided: done before the solve)
       Batch& bt = out[it.i];
       dots_host(Z, it.Y, n, it.k, bt.vals);
       bt.its = its[q];
       bt.cost.resize(it.k);
       for (int v = 0; v < it.k; ++v) bt.cost[v] = apply_cost(sl.level, its[q][v]) + 2.0 * (double)n * sl.d;
     }
+  }
+
+  // z = zeta - Q (Q^H zeta) in place for the k noise vectors of difference i
+  void project(StochLevel& sl, int i, int k) {
+    if (sl.d <= 0) return;
+    hipStream_t s = c->stream;
+    const int64_t n = sl.n;
+    cd* Z = g.est.Z[i].as<cd>();
+    DevBuf& C = g.est.C[i];
+    C.ensure(sizeof(cd) * (size_t)kmax * sl.d);
+    part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
+    launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z, n, k, C.as<cd>(), sl.d, 0, nullptr, part.as<cd>());
+    launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z, n, k, nullptr, nullptr,
+                                nullptr);
   }
 
   void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Batch>& out) {
@@ -545,9 +704,11 @@ struct Estimator {
     require(p.batch >= 1, "batch must be >= 1");
     require(p.cost == MGM_COST_STATIC || p.cost == MGM_COST_FIXED || p.cost == MGM_COST_FLOPS,
             "unknown cost model");
+    require(p.projection == MGM_PROJ_ONE_SIDED || p.projection == MGM_PROJ_TWO_SIDED, "unknown projection");
     const int nst = hutch ? 1 : L - 1;
     require(nst >= 1, "MLMC variants need at least two levels");
-    const bool lr = p.variant == MGM_VARIANT_HUTCHPP || p.variant == MGM_VARIANT_MLMCPP;
+    const bool lr = p.variant == MGM_VARIANT_HUTCHPP || p.variant == MGM_VARIANT_MLMCPP || deflated;
+    require(!deflated || (p.d[0] >= 1 && p.d[0] <= 64), "deflated variant: d[0] must be in [1, 64]");
     std::vector<StochLevel> lv(nst);
     for (int i = 0; i < nst; ++i) {
       StochLevel& sl = lv[i];
@@ -675,6 +836,7 @@ struct Estimator {
 }  // namespace
 
 int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r) {
+  r.defl_ritz[0] = r.defl_ritz[1] = 0;
   for (int i = 0; i < MGM_MAX_LEVELS; ++i) {
     r.lvl_solves[i] = 0;
     r.lvl_iters[i] = 0;

@@ -248,3 +248,26 @@ def test_mixed_precision_cut_of_the_512_workload(ctx, precision):
     got = _gpu(ctx, gid, batch=16, **kw)
     want = otr.estimate(hier, otr.TraceParams(**kw))
     _cmp(got, want)
+
+
+@pytest.mark.parametrize("variant,batch,fixed", [("hutchpp", 16, [25]), ("hutchpp", 8, None),
+                                                 ("mlmcpp", 32, None)])
+def test_two_sided_projection_parity(ctx, s16, s32, variant, batch, fixed):
+    """tau_s = z^H (A z) (the samples are projected before their solves, so
+    they do not ride with the last Hutch++ round): parity with the oracle on
+    identical seeds, replay and adaptive."""
+    if variant == "hutchpp":
+        cfg, rec, gid, hier = s16
+        kw = dict(variant="hutchpp", eps=1e-2, d=[8], k_power=2, noise="rademacher", seed=13)
+    else:
+        rec, gid, hier = s32
+        kw = dict(variant="mlmcpp", eps=2e-2, d=[8, 8], k_power=2, noise="z2z2", seed=23)
+    if fixed:
+        kw["fixed_samples"] = fixed
+    log(f"two-sided {variant} batch {batch} fixed {fixed}")
+    got = _gpu(ctx, gid, batch=batch, projection="two-sided", **kw)
+    want = otr.estimate(hier, otr.TraceParams(projection="two-sided", **kw))
+    _cmp(got, want)
+    # and the one-sided samples of the same seeds differ (another estimator)
+    one = _gpu(ctx, gid, batch=batch, **kw)
+    assert np.max(np.abs(np.asarray(one["samples"][0])[:5] - np.asarray(got["samples"][0])[:5])) > 1e-6 * abs(got["tau"])

@@ -166,3 +166,28 @@ def test_optimal_vs_uniform_targets_weights():
     lv[1].cost = 4.0
     w = tr._target_weights(lv, "optimal")
     assert np.allclose(w, [np.sqrt(8) / (np.sqrt(8) + np.sqrt(32)), np.sqrt(32) / (np.sqrt(8) + np.sqrt(32))])
+
+
+def test_two_sided_projection_mean_and_variance(small):
+    # one-sided z^H A zeta samples (I - QQ^H) A, two-sided z^H A z samples
+    # (I - QQ^H) A (I - QQ^H): both have mean tr((I - QQ^H) A); their Z2xZ2
+    # variances are ||offdiag(M)||_F^2 of the respective M (Sec. 2)
+    h, A = small
+    n = A.shape[0]
+    Q, _ = tr.low_rank(lambda X: A @ X, n, 5, 2, rng.Z2Z2, 5, 0)
+    P = np.eye(n) - Q @ Q.conj().T
+    N = 30000
+    off = lambda M: M - np.diag(np.diag(M))
+    for two, M in ((False, P @ A), (True, P @ A @ P)):
+        lvl = tr.StochLevel(lambda X: A @ X, n, 5, 1.0, Q=Q)
+        assert abs(tr.sample(lvl, rng.Z2Z2, 7, 0, 3, two_sided=two)
+                   - (lambda z: np.vdot(P @ z, A @ ((P @ z) if two else z)))(
+                       rng.noise_vector(rng.Z2Z2, 7, rng.PURPOSE_SAMPLE, 0, 3, n))) < 1e-12
+        Z = rng.noise_block(rng.Z2Z2, 9, rng.PURPOSE_SAMPLE, 0, 0, N, n)
+        t = np.einsum("ij,ij->j", Z.conj(), M @ Z)
+        s2 = np.linalg.norm(off(M)) ** 2
+        assert abs(t.mean() - np.trace(P @ A)) < 4.5 * np.sqrt(s2 / N)
+        assert abs(np.sum(np.abs(t - t.mean()) ** 2) / (N - 1) / s2 - 1) < 0.05
+    # same mean, different variances (the test can tell the two forms apart)
+    assert abs(np.trace(P @ A) - np.trace(P @ A @ P)) < 1e-12 * abs(np.trace(A))
+    assert abs(np.linalg.norm(off(P @ A)) / np.linalg.norm(off(P @ A @ P)) - 1) > 0.02
