@@ -508,6 +508,95 @@ def run_cnn(args):
     ctx.close()
 
 
+def run_scan(args):
+    """Parameter scan on the 128^2 field (the shapes of the paper's Fig. 2 and
+    Fig. 1): for each Wilson mass of `--masses` (the workload's -0.10 and
+    values closer to the critical mass, i.e. worse conditioned, as the paper's
+    five masses), MG-MLMC (d = 0) and MG-MLMC++ over the number of deflation
+    vectors d (the same on every level difference) and block power sweeps k,
+    optimal and uniform target variances, and deflated Hutchinson.  Per point:
+    the Sec. 4 cost-model work per level difference (MFlop, 8 real flops per
+    complex multiply-add), the sample counts and the GPU time per estimate,
+    averaged over `--steps` seeds."""
+    import torch
+    from lattice_inputs import WORKLOADS, gauge_for, links_from_theta
+    from paper_2303_11512_amd import Context, MGMError, mg_params, solve_params
+    cfg = dict(WORKLOADS["schwinger128"], name="schwinger128")
+    ctx = Context(0)
+    links = torch.from_numpy(links_from_theta(gauge_for(cfg))).to("cuda")
+    sp = solve_params(**SOLVE)
+    rows = []
+    masses = [float(m) for m in args.masses.split(",")]
+    for m0 in masses:
+        gid = ctx.set_gauge(links, m0, True)
+        try:
+            ctx.setup_mg(gid, mg_params(**mg_setup_kwargs(cfg), precision=args.precision))
+        except MGMError as e:
+            print(f"# m0 {m0}: multigrid setup failed ({e}); mass skipped", file=sys.stderr, flush=True)
+            ctx.free_gauge(gid)
+            continue
+
+        def point(label, **kw):
+            base = dict(method_kwargs(cfg, 0), batch=BATCH)
+            base.update(kw)
+            try:
+                ctx.trace_estimate(gid, solve=sp, **dict(base, seed=cfg["trace_seed"] + 900))  # warm-up
+                torch.cuda.synchronize()
+                outs = []
+                t0 = time.perf_counter()
+                for k in range(args.steps):
+                    outs.append(ctx.trace_estimate(gid, solve=sp, **dict(base, seed=cfg["trace_seed"] + k)))
+                torch.cuda.synchronize()
+            except MGMError as e:
+                print(f"# m0 {m0} {label}: failed ({e})", file=sys.stderr, flush=True)
+                return None
+            dt = (time.perf_counter() - t0) / args.steps
+            nl = len(outs[0]["level_samples"])
+            row = {"m0": m0, "label": label, "ms_per_estimate": dt * 1e3,
+                   "d_chosen": [float(np.mean([o["level_d"][l] for o in outs])) for l in range(len(outs[0]["level_d"]))],
+                   "samples": [float(np.mean([o["level_samples"][l] for o in outs])) for l in range(nl)],
+                   "mflop": [float(np.mean([o["level_work"][l] for o in outs])) * 8e-6 for l in range(nl)],
+                   "mflop_lowrank": [float(np.mean([o["level_lr_work"][l] for o in outs])) * 8e-6 for l in range(nl)],
+                   "iters_per_solve": [round(sum(o["iters"][l] for o in outs) / max(1, sum(o["solves"][l] for o in outs)), 2)
+                                       for l in range(2)],
+                   "tau_mean": float(np.mean([o["tau"].real for o in outs]))}
+            row["mflop_total"] = sum(row["mflop"])
+            rows.append(row)
+            print(f"# m0 {m0} {label}: {dt * 1e3:.1f} ms, samples {[round(v, 1) for v in row['samples']]}, "
+                  f"MFlop {row['mflop_total']:.0f}, iters {row['iters_per_solve']}", file=sys.stderr, flush=True)
+            return row
+
+        pts = [point("mlmc optimal", variant="mlmc", d=[0, 0]), point("mlmc uniform", variant="mlmc", d=[0, 0],
+                                                                      targets="uniform")]
+        for kp in (1, 2):
+            for d in (8, 32, 64):
+                pts.append(point(f"mlmcpp d={d} k={kp} optimal", d=[d, d], k_power=kp))
+        pp = [r for r in pts[2:] if r]
+        if pp:
+            best = min(pp, key=lambda r: r["mflop_total"])
+            bd = int(best["label"].split("d=")[1].split()[0])
+            bk = int(best["label"].split("k=")[1].split()[0])
+            point(f"mlmcpp d={bd} k={bk} uniform", d=[bd, bd], k_power=bk, targets="uniform")
+        for kp in (1, 2):
+            point(f"mlmcpp adaptive d (from 4, <= 64, 16 pilots) k={kp} optimal", d=[4, 4], k_power=kp, d_max=64,
+                  pilot=16)
+        for d in (32, 64):
+            point(f"deflated hutchinson k={d} (3 sweeps)", variant="deflated", d=[d], k_power=3)
+        ctx.free_gauge(gid)
+    ref = [r for r in rows if r["m0"] == masses[0] and r["label"].startswith("mlmcpp d=32 k=2 optimal")]
+    print(json.dumps({
+        "metric": "Sec. 4 cost-model MFlop and GPU time per trace estimate at 1e-3 (parameter scan)",
+        "value": ref[0]["mflop_total"] if ref else None, "unit": "MFlop (MG-MLMC++ d=32 k=2, first mass)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ref[0]["ms_per_estimate"] if ref else None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+f16",
+        "data": "synthetic",
+        "config": {"workload": f"scan128: {cfg['Lx']}x{cfg['Lt']} Schwinger field of the 128^2 workload (beta "
+                               f"{cfg['beta']}), masses {masses}, 3-level MG, {cfg['noise']} noise, eps {cfg['eps']}, "
+                               f"preconditioner {args.precision}", "points": rows},
+        "roofline": None, "cpu_baseline": None}))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +617,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=1000, help="cnn workload: pairs per training field")
     ap.add_argument("--epochs", type=int, default=4, help="cnn workload: training epochs")
     ap.add_argument("--eval-fields", type=int, default=4, help="cnn workload: unseen fields per size")
+    ap.add_argument("--masses", default="-0.10,-0.12,-0.13,-0.14",
+                    help="scan128 workload: Wilson masses of the scan")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -540,6 +631,9 @@ def main():
         return
     if args.workload == "mixed512":
         run_mixed(args)
+        return
+    if args.workload == "scan128":
+        run_scan(args)
         return
 
     import torch

@@ -56,6 +56,7 @@ extern "C" {
 #define MGM_PURPOSE_SAMPLE 3
 #define MGM_PURPOSE_TRAIN 4   /* right-hand sides of the network's training pairs */
 #define MGM_PURPOSE_DEFLATE 5 /* start block of the deflation subspace iteration */
+#define MGM_PURPOSE_PILOT 6   /* pilot samples of the adaptive choice of d_l */
 
 /* precision of the multigrid preconditioner (the outer FGMRES, its residuals,
  * orthogonalisation and every trace sum are always FP64):
@@ -317,6 +318,20 @@ typedef struct {
   uint64_t seed;
   int batch;                         /* samples per level per GPU batch      */
   mgm_solve_params solve;
+  int d_max;                         /* > 0 (HUTCHPP, MLMCPP): adaptive d_l.
+                                        Candidates d[l], 2 d[l], ... <= d_max
+                                        (<= 64); per candidate the Hutch++
+                                        basis, tau_lr and `pilot` pilot
+                                        samples (noise purpose PILOT, then
+                                        discarded) predict the level's cost
+                                        T(d) = W_lr(d) + V(d) C(d) / rho^2,
+                                        rho^2 = (eps |tau0|)^2 / (levels),
+                                        tau0 from the first candidates; the
+                                        doubling stops when T stops falling
+                                        and the best candidate's basis is
+                                        used.  The choice of d is left open
+                                        by the paper (Sec. 5).  0: fixed d. */
+  int pilot;                         /* pilot samples per candidate (>= 2)  */
   int projection;                    /* MGM_PROJ_ONE_SIDED: tau_s =
                                         z^H (A zeta) as Alg. 2 prints;
                                         MGM_PROJ_TWO_SIDED: tau_s = z^H (A z),
@@ -347,6 +362,8 @@ typedef struct {
   double *sample_dump;                 /* HOST [nstoch][max_dump][2] or NULL  */
   double *cost_dump;                   /* HOST [nstoch][max_dump] or NULL:
                                           each kept sample's Sec. 4 cost     */
+  int lvl_d[MGM_MAX_LEVELS];           /* Hutch++ vectors used per level
+                                          difference (the adaptive choice)  */
   double defl_ritz[2];                 /* deflated variant: sum u_i^H v_i /
                                           sigma_i over the Ritz singular
                                           triplets of D on span(Q)           */

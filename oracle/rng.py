@@ -40,6 +40,7 @@ PURPOSE_SETUP = 1    # multigrid test vectors
 PURPOSE_SKETCH = 2   # Hutch++ block power iteration start vectors S_l
 PURPOSE_SAMPLE = 3   # stochastic samples zeta_s
 PURPOSE_DEFLATE = 5  # start block of the deflation subspace iteration
+PURPOSE_PILOT = 6    # pilot samples of the adaptive choice of d_l (discarded)
 
 RADEMACHER = "rademacher"
 Z2Z2 = "z2z2"

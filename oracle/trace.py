@@ -86,6 +86,8 @@ class TraceParams:
     seed: int = 1
     levels: int = 0                    # hierarchy levels used by the MLMC variants (0 = all)
     projection: str = "one-sided"      # one-sided (Alg. 2 as printed) | two-sided
+    d_max: int = 0                     # > 0: adaptive d_l, candidates d[l] * 2^j <= d_max
+    pilot: int = 16                    # pilot samples per candidate (adaptive d_l)
 
 
 @dataclass
@@ -211,8 +213,13 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
                                  sample_costs=prm.sample_costs[l] if mode == "flops" else None))
 
     # deflation vectors and low-rank parts (Alg. 2, first loop)
+    chosen = None
+    if use_lr and prm.d_max > 0 and prm.variant in ("hutchpp", "mlmcpp"):
+        chosen = _adaptive_d(hier, levels, prm, tau_exact, mode)
     for l, lv in enumerate(levels):
-        if lv.d > 0 and prm.variant == "deflated":
+        if chosen is not None:
+            pass  # Q and tau_lr set by the adaptive choice
+        elif lv.d > 0 and prm.variant == "deflated":
             g5 = hier.levels[0].chirality().astype(np.complex128)
             lv.Q = deflation.subspace_basis(lv.apply, g5, lv.n, lv.d, max(1, prm.k_power), prm.noise, prm.seed)
             lv.tau_lr = complex(np.trace(lv.Q.conj().T @ lv.apply(lv.Q)))
@@ -255,6 +262,7 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
     return dict(
         tau=complex(tau),
         tau_exact=complex(tau_exact),
+        level_d=[lv.d for lv in levels],
         level_mean=[lv.mean() for lv in levels],
         level_lr=[lv.tau_lr for lv in levels],
         level_var=[lv.var() for lv in levels],
@@ -263,6 +271,65 @@ def estimate(hier: Hierarchy, prm: TraceParams) -> dict:
         samples=[list(lv.samples) for lv in levels],
         Q=[lv.Q for lv in levels],
     )
+
+
+def _adaptive_d(hier: Hierarchy, levels: list, prm: TraceParams, tau_exact, mode: str) -> list:
+    """Adaptive number of deflation vectors per level difference (the choice
+    of d_l is left open by the paper, Sec. 5; adaptive Hutch++ is cited in
+    Sec. 2.4).  Candidates d = d_l, 2 d_l, 4 d_l, ... <= d_max.  For each,
+    the block power iteration gives Q_d and tau_lr(d); ``pilot`` samples of
+    the projected remainder (noise purpose PILOT, the same vectors for every
+    candidate, discarded afterwards) give its variance V(d); the predicted
+    cost of the level is T(d) = W_lr(d) + V(d) C(d) / rho^2 with the
+    per-sample cost C(d), the low-rank work W_lr(d) = (k+1) d C_A (C_A: one
+    application of A_l) and rho^2 = (eps |tau0|)^2 / (number of differences),
+    tau0 the estimate from the first candidates' pilot means.  The doubling
+    stops at the first candidate that does not lower T; the best Q and
+    tau_lr are kept.  Costs: the static or fixed model (the flops model needs
+    the GPU's iteration counts).  Parity unpinned with respect to the paper:
+    this rule is a reading of "how to choose d" left open there; it is
+    pinned only by its own definition and the d = n special case."""
+    if mode == "flops":
+        raise ValueError("adaptive d_l in the oracle needs cost='static' or 'fixed'")
+    L = prm.levels or hier.L
+    nl = len(levels)
+    kp = max(1, prm.k_power)
+
+    def cost_apply(l, lv):
+        return float(prm.fixed_cost[l]) if mode == "fixed" else static_cost(hier, l, lv.n, 0, L)
+
+    def candidate(l, lv, d):
+        Q, tau_lr = low_rank(lv.apply, lv.n, d, prm.k_power, prm.noise, prm.seed, l)
+        Z = rng.noise_block(prm.noise, prm.seed, rng.PURPOSE_PILOT, l, 0, prm.pilot, lv.n)
+        two = prm.projection == "two-sided"
+        Zp = Z - Q @ (Q.conj().T @ Z)
+        X = lv.apply(Zp if two else Z)
+        t = np.einsum("ij,ij->j", Zp.conj(), X)
+        V = float(np.sum(np.abs(t - t.mean()) ** 2) / (len(t) - 1))
+        ca = cost_apply(l, lv)
+        return dict(d=d, Q=Q, tau_lr=tau_lr, V=V, mean=complex(t.mean()),
+                    C=ca + (0.0 if mode == "fixed" else 2.0 * lv.n * d), W=(kp + 1) * d * ca)
+
+    cur = [candidate(l, lv, lv.d) for l, lv in enumerate(levels)]
+    tau0 = tau_exact + sum(c["mean"] + c["tau_lr"] for c in cur)
+    rho2 = (prm.eps * abs(tau0)) ** 2 / nl
+    T = lambda c: c["W"] + c["V"] * c["C"] / rho2
+    chosen = []
+    for l, lv in enumerate(levels):
+        best = cur[l]
+        d = best["d"]
+        while 2 * d <= prm.d_max:
+            d *= 2
+            trial = candidate(l, lv, d)
+            if T(trial) < T(best):
+                best = trial
+            else:
+                break
+        lv.d, lv.Q, lv.tau_lr = best["d"], best["Q"], best["tau_lr"]
+        if mode != "fixed":
+            lv.cost = static_cost(hier, l, lv.n, lv.d, L)
+        chosen.append(best["d"])
+    return chosen
 
 
 def _target_weights(levels, targets: str) -> list:

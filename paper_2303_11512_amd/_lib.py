@@ -94,6 +94,8 @@ class TraceParams(C.Structure):
         ("seed", C.c_uint64),
         ("batch", C.c_int),
         ("solve", SolveParams),
+        ("d_max", C.c_int),
+        ("pilot", C.c_int),
         ("projection", C.c_int),
         ("concurrent", C.c_int),
     ]
@@ -115,6 +117,7 @@ class TraceResult(C.Structure):
         ("lvl_work", C.c_double * MAX_LEVELS),
         ("sample_dump", C.POINTER(C.c_double)),
         ("cost_dump", C.POINTER(C.c_double)),
+        ("lvl_d", C.c_int * MAX_LEVELS),
         ("defl_ritz", C.c_double * 2),
         ("sigma_dump", C.POINTER(C.c_double)),
         ("iter_dump", C.POINTER(C.c_int)),
@@ -452,7 +455,7 @@ class Context:
     def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
                        noise="z2z2", targets="optimal", cost="static", fixed_cost=None, min_samples=2,
                        max_samples=0, fixed_samples=None, seed=1, batch=64, solve=None,
-                       max_dump=0, concurrent=True, projection="one-sided") -> dict:
+                       max_dump=0, concurrent=True, projection="one-sided", d_max=0, pilot=16) -> dict:
         p = TraceParams()
         p.variant = VARIANTS[variant]
         p.form = FORMS[form]
@@ -477,6 +480,8 @@ class Context:
         p.solve = solve or solve_params()
         p.concurrent = int(bool(concurrent))
         p.projection = {"one-sided": 0, "two-sided": 1}[projection]
+        p.d_max = d_max
+        p.pilot = pilot
         r = TraceResult()
         sig = None
         if variant == "deflated" and len(d) > 0 and d[0] > 0:
@@ -503,6 +508,7 @@ class Context:
             level_samples=[r.lvl_samples[i] for i in range(ns)],
             solves=[r.lvl_solves[i] for i in range(MAX_LEVELS)],
             iters=[r.lvl_iters[i] for i in range(MAX_LEVELS)],
+            level_d=[r.lvl_d[i] for i in range(ns)],
             level_lr_work=[r.lvl_lr_work[i] for i in range(ns)],
             level_work=[r.lvl_work[i] for i in range(ns)],
         )

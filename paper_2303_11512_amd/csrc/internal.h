@@ -411,6 +411,7 @@ struct EstWork {
   // per level difference: Hutch++ sketch S, its image Y and basis Q; sample
   // noise Z, its image X and projection coefficients C
   DevBuf S[MGM_MAX_LEVELS], Y[MGM_MAX_LEVELS], Q[MGM_MAX_LEVELS];
+  DevBuf Q2[MGM_MAX_LEVELS];  // second basis: the trial of the adaptive choice of d
   DevBuf Z[MGM_MAX_LEVELS], X[MGM_MAX_LEVELS], C[MGM_MAX_LEVELS];
   // per operator level: the merged right-hand sides of one solve and its solutions
   DevBuf lin[MGM_MAX_LEVELS], lout[MGM_MAX_LEVELS];

@@ -458,6 +458,153 @@ struct Estimator {
     if (deflated) ritz_triplets(lv[0]);
   }
 
+  // ---- adaptive number of Hutch++ vectors per level difference (the
+  // choice of d is left open by the paper, Sec. 5).  Candidates d, 2d, ...
+  // <= d_max; for each: the block power iteration's basis (into the level's
+  // spare basis buffer), tau_lr, and `pilot` samples of the projected
+  // remainder (noise purpose PILOT, the same vectors for every candidate,
+  // discarded afterwards) give the variance V(d) and per-sample cost C(d);
+  // the level's predicted cost is T(d) = W_lr(d) + V(d) C(d) / rho^2 with
+  // rho^2 = (eps |tau0|)^2 / (levels), tau0 from the first candidates.  The
+  // doubling stops at the first candidate that does not lower T.  W_lr and
+  // C come from the cost model in use (static/fixed: (k+1) d C_A and C_A +
+  // 2 n d; flops: as counted).
+  struct Cand {
+    int d = 0;
+    int buf = 0;  // 0: est.Q[i], 1: est.Q2[i]
+    zc tau_lr = 0, mean = 0;
+    double V = 0, C = 0, W = 0;
+  };
+  // C_A of the static or fixed model: one application of A_l (as the static
+  // per-sample cost, without the projection)
+  double apply_static(int i, const StochLevel&) const {
+    if (p.cost == MGM_COST_FIXED) return p.fixed_cost[i];
+    return c_nnzD[i] + (i + 1 < L ? c_nnzD[i + 1] : 0.0);
+  }
+  void candidates(std::vector<StochLevel>& lv, const std::vector<int>& which, const std::vector<int>& dd,
+                  const std::vector<int>& buf, std::vector<Cand>& out) {
+    std::vector<Item> items;
+    std::vector<double> w0(lv.size(), 0.0);
+    for (int i : which) {
+      StochLevel& sl = lv[i];
+      DevBuf& Qb = buf[i] ? g.est.Q2[i] : g.est.Q[i];
+      const size_t bytes = sizeof(cd) * (size_t)dd[i] * sl.n;
+      g.est.S[i].ensure(sizeof(cd) * (size_t)p.d_max * sl.n);
+      g.est.Y[i].ensure(sizeof(cd) * (size_t)p.d_max * sl.n);
+      Qb.ensure(bytes);
+      launch_noise<double>(c->stream, g.est.S[i].as<cd>(), sl.n, dd[i], p.noise, p.seed, MGM_PURPOSE_SKETCH, i, 0);
+      items.push_back({i, dd[i], g.est.S[i].as<cd>(), g.est.Y[i].as<cd>()});
+      w0[i] = sl.lr_cost;
+    }
+    std::vector<Its> its;
+    for (int it = 0; it < std::max(1, p.k_power); ++it) {
+      applyA_levels(lv, items, its);
+      add_lr_cost(lv, items, its, items.size());
+      for (Item& x : items) {
+        DevBuf& Qb = buf[x.i] ? g.est.Q2[x.i] : g.est.Q[x.i];
+        orthonormalize(c, lv[x.i].n, x.k, x.Y, Qb.as<cd>());
+        x.X = Qb.as<cd>();
+      }
+    }
+    applyA_levels(lv, items, its);
+    add_lr_cost(lv, items, its, items.size());
+    for (const Item& x : items) {
+      std::vector<zc> v;
+      dots_host(x.X, x.Y, lv[x.i].n, x.k, v);
+      Cand& cd_ = out[x.i];
+      cd_ = Cand();
+      cd_.d = x.k;
+      cd_.buf = buf[x.i];
+      for (const zc& y : v) cd_.tau_lr += y;
+    }
+    // pilot samples with each level's trial basis
+    std::vector<int> nb(lv.size(), 0);
+    std::vector<DevBuf*> saveQ(lv.size());
+    std::vector<int> saved(lv.size());
+    for (int i : which) {
+      nb[i] = p.pilot;
+      saveQ[i] = lv[i].Q;
+      saved[i] = lv[i].d;
+      lv[i].Q = buf[i] ? &g.est.Q2[i] : &g.est.Q[i];
+      lv[i].d = dd[i];
+    }
+    std::vector<Item> pit;
+    sample_start(lv, nb, pit, true);
+    applyA_levels(lv, pit, its);
+    std::vector<Batch> pv(lv.size());
+    sample_finish(lv, pit, its, pv);
+    for (int i : which) {
+      StochLevel& sl = lv[i];
+      Cand& cd_ = out[i];
+      const std::vector<zc>& t = pv[i].vals;
+      zc mu = 0;
+      for (const zc& y : t) mu += y;
+      mu /= (double)t.size();
+      double V = 0;
+      for (const zc& y : t) V += std::norm(y - mu);
+      cd_.V = V / (double)(t.size() - 1);
+      cd_.mean = mu;
+      double cs = 0;
+      for (double x : pv[i].cost) cs += x;
+      sl.lr_cost += cs;  // the pilot work is planning overhead of the Hutch++ phase
+      if (p.cost == MGM_COST_FLOPS) {
+        cd_.C = cs / (double)t.size();
+        cd_.W = sl.lr_cost - cs - w0[i];
+      } else {
+        const double ca = apply_static(i, sl);
+        cd_.C = p.cost == MGM_COST_FIXED ? ca : ca + 2.0 * (double)sl.n * dd[i];
+        cd_.W = (std::max(1, p.k_power) + 1.0) * dd[i] * ca;
+      }
+      sl.Q = saveQ[i];
+      sl.d = saved[i];
+    }
+  }
+  void low_rank_adaptive(std::vector<StochLevel>& lv) {
+    const int nl = (int)lv.size();
+    require(p.pilot >= 2, "adaptive d: pilot must be >= 2");
+    require(p.d_max <= 64, "adaptive d: d_max must be <= 64");
+    std::vector<int> which, dd(nl), buf(nl, 0);
+    std::vector<Cand> best(nl), trial(nl);
+    for (int i = 0; i < nl; ++i) {
+      require(lv[i].d >= 1 && lv[i].d <= p.d_max, "adaptive d: need 1 <= d[l] <= d_max");
+      which.push_back(i);
+      dd[i] = lv[i].d;
+    }
+    candidates(lv, which, dd, buf, best);
+    zc tau0 = hutch ? zc(0) : zc(g.trL[0], g.trL[1]);
+    for (int i = 0; i < nl; ++i) tau0 += best[i].mean + best[i].tau_lr;
+    const double rho2 = (p.eps * std::abs(tau0)) * (p.eps * std::abs(tau0)) / nl;
+    auto T = [&](const Cand& x) { return x.W + x.V * x.C / rho2; };
+    std::vector<char> growing(nl);
+    for (int i = 0; i < nl; ++i) growing[i] = 2 * best[i].d <= p.d_max;
+    while (true) {
+      which.clear();
+      for (int i = 0; i < nl; ++i)
+        if (growing[i]) {
+          which.push_back(i);
+          dd[i] = 2 * best[i].d;
+          buf[i] = 1 - best[i].buf;  // the trial goes into the other buffer
+        }
+      if (which.empty()) break;
+      candidates(lv, which, dd, buf, trial);
+      for (int i : which) {
+        if (T(trial[i]) < T(best[i])) {
+          best[i] = trial[i];
+          growing[i] = 2 * best[i].d <= p.d_max;
+        } else {
+          growing[i] = 0;
+        }
+      }
+    }
+    for (int i = 0; i < nl; ++i) {
+      StochLevel& sl = lv[i];
+      sl.d = best[i].d;
+      sl.Q = best[i].buf ? &g.est.Q2[i] : &g.est.Q[i];
+      sl.tau_lr = best[i].tau_lr;
+      if (p.cost == MGM_COST_STATIC) sl.cost = apply_static(i, sl) + 2.0 * (double)sl.n * sl.d;
+    }
+  }
+
   // Deflation basis (Sec. 2.2): k_power sweeps of block subspace iteration
   // Q <- qr(D^{-1} gamma5 D^{-1} gamma5 Q) from noise of purpose DEFLATE; it
   // converges to the right singular vectors of D of the smallest singular
@@ -595,14 +742,17 @@ struct Estimator {
 
   // noise zeta for samples s .. s+b[i]-1 of every difference i with b[i] > 0
   // (s = samples taken so far); appends the blocks Y = A zeta to `items`
-  void sample_start(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Item>& items) {
+  void sample_start(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Item>& items,
+                    bool pilot = false) {
     for (int i = 0; i < (int)lv.size(); ++i) {
       if (b[i] <= 0) continue;
       StochLevel& sl = lv[i];
       g.est.Z[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
       g.est.X[i].ensure(sizeof(cd) * (size_t)kmax * sl.n);
-      launch_noise<double>(c->stream, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed, MGM_PURPOSE_SAMPLE, i,
-                           sl.s());
+      // stochastic samples continue their stream; pilot samples are the
+      // same PILOT vectors 0 .. b-1 for every candidate
+      launch_noise<double>(c->stream, g.est.Z[i].as<cd>(), sl.n, b[i], p.noise, p.seed,
+                           pilot ? MGM_PURPOSE_PILOT : MGM_PURPOSE_SAMPLE, i, pilot ? 0 : sl.s());
       if (two_sided) project(sl, i, b[i]);
       items.push_back({i, b[i], g.est.Z[i].as<cd>(), g.est.X[i].as<cd>()});
     }
@@ -708,6 +858,7 @@ struct Estimator {
     const int nst = hutch ? 1 : L - 1;
     require(nst >= 1, "MLMC variants need at least two levels");
     const bool lr = p.variant == MGM_VARIANT_HUTCHPP || p.variant == MGM_VARIANT_MLMCPP || deflated;
+    const bool adaptive = p.d_max > 0 && (p.variant == MGM_VARIANT_HUTCHPP || p.variant == MGM_VARIANT_MLMCPP);
     require(!deflated || (p.d[0] >= 1 && p.d[0] <= 64), "deflated variant: d[0] must be in [1, 64]");
     std::vector<StochLevel> lv(nst);
     for (int i = 0; i < nst; ++i) {
@@ -731,6 +882,7 @@ struct Estimator {
     // a batch never exceeds p.batch samples per level (batch_sizes)
     kmax = std::max(1, p.batch);
     for (int i = 0; i < nst; ++i) kmax = std::max(kmax, lv[i].d);
+    if (adaptive) kmax = std::max(kmax, std::max(p.d_max, p.pilot));
     // every reduction workspace at its largest size up front (no reallocation later)
     part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
     const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
@@ -739,7 +891,9 @@ struct Estimator {
     // the first stochastic batch rides with the last low-rank round
     std::vector<Batch> pre(nst);
     bool have_pre = false;
-    if (lr) {
+    if (lr && adaptive) {
+      low_rank_adaptive(lv);
+    } else if (lr) {
       const std::vector<int> nb = batch_sizes(lv, s, tau, maxS);
       low_rank_all(lv, nb, pre);
       have_pre = true;
@@ -813,6 +967,7 @@ struct Estimator {
       res.lvl_var[i] = lv[i].var();
       res.lvl_cost[i] = lv[i].cost;
       res.lvl_samples[i] = lv[i].s();
+      res.lvl_d[i] = lv[i].d;
       res.lvl_lr_work[i] = lv[i].lr_cost;
       res.lvl_work[i] = lv[i].lr_cost + lv[i].cost_sum;
       const int nd = res.max_dump > 0 ? std::min(res.max_dump, lv[i].s()) : 0;
@@ -843,6 +998,7 @@ int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_re
     r.lvl_samples[i] = 0;
     r.lvl_lr_work[i] = 0;
     r.lvl_work[i] = 0;
+    r.lvl_d[i] = 0;
   }
   Estimator e(c, g, p, r);
   return e.run();

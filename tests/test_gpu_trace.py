@@ -271,3 +271,24 @@ def test_two_sided_projection_parity(ctx, s16, s32, variant, batch, fixed):
     # and the one-sided samples of the same seeds differ (another estimator)
     one = _gpu(ctx, gid, batch=batch, **kw)
     assert np.max(np.abs(np.asarray(one["samples"][0])[:5] - np.asarray(got["samples"][0])[:5])) > 1e-6 * abs(got["tau"])
+
+
+@pytest.mark.parametrize("case", ["hutchpp", "mlmcpp", "mlmcpp-fixed"])
+def test_adaptive_d_parity(ctx, s16, s32, case):
+    """Adaptive number of Hutch++ vectors per level difference: the same
+    candidates, pilot variances and choices as the oracle's (static or fixed
+    cost model), then Alg. 2 with the chosen bases."""
+    if case == "hutchpp":
+        cfg, rec, gid, hier = s16
+        kw = dict(variant="hutchpp", eps=1e-2, d=[2], k_power=2, noise="rademacher", seed=17, d_max=32, pilot=16)
+    else:
+        rec, gid, hier = s32
+        kw = dict(variant="mlmcpp", eps=2e-2, d=[2, 4], k_power=1, noise="z2z2", seed=29, d_max=64, pilot=24)
+        if case == "mlmcpp-fixed":
+            kw.update(fixed_cost=[5.0, 1.0], cost="fixed")
+    log(f"adaptive d {case}")
+    got = _gpu(ctx, gid, batch=16, **kw)
+    want = otr.estimate(hier, otr.TraceParams(**kw))
+    log(f"  chosen d GPU {got['level_d']} oracle {want['level_d']}")
+    assert got["level_d"] == want["level_d"]
+    _cmp(got, want)

@@ -191,3 +191,50 @@ def test_two_sided_projection_mean_and_variance(small):
     # same mean, different variances (the test can tell the two forms apart)
     assert abs(np.trace(P @ A) - np.trace(P @ A @ P)) < 1e-12 * abs(np.trace(A))
     assert abs(np.linalg.norm(off(P @ A)) / np.linalg.norm(off(P @ A @ P)) - 1) > 0.02
+
+
+def test_adaptive_d_choice_rule():
+    # the adaptive choice of d_l: the pilot variance and the low-rank work of
+    # each candidate, recomputed here from their definitions, decide; the
+    # chosen candidate minimises T(d) = W(d) + V(d) C(d) / rho^2 along the
+    # doubling path up to where T first rises, and the estimate uses its Q
+    th = metropolis_u1(8, 8, 3.0, 40, 81)
+    h = mg.setup_hierarchy(th, -0.02, blocks=[(2, 2)], ntv=[2], seed=4)
+    A = np.linalg.inv(h.levels[0].D.toarray())
+    P = h.P[0].toarray()
+    A = A - P @ np.linalg.inv(h.levels[1].D.toarray()) @ P.conj().T
+    n = A.shape[0]
+    prm = dict(variant="mlmcpp", eps=1e-2, d=[2], k_power=2, noise=rng.Z2Z2, seed=3, d_max=64, pilot=24,
+               fixed_samples=[8])
+    out = tr.estimate(h, tr.TraceParams(**prm))
+    ca = tr.static_cost(h, 0, n, 0, 2)
+
+    def T_of(d, rho2):
+        Q, tlr = tr.low_rank(lambda X: A @ X, n, d, 2, rng.Z2Z2, 3, 0)
+        Z = rng.noise_block(rng.Z2Z2, 3, rng.PURPOSE_PILOT, 0, 0, 24, n)
+        t = np.einsum("ij,ij->j", (Z - Q @ (Q.conj().T @ Z)).conj(), A @ Z)
+        V = np.sum(np.abs(t - t.mean()) ** 2) / 23
+        return 3 * d * ca + V * (ca + 2 * n * d) / rho2, t.mean(), tlr, Q
+
+    _, m0, lr0, _ = T_of(2, 1.0)
+    tau0 = out["tau_exact"] + m0 + lr0
+    rho2 = (1e-2 * abs(tau0)) ** 2
+    path = [2]
+    Ts = [T_of(2, rho2)[0]]
+    while path[-1] * 2 <= 64:
+        path.append(path[-1] * 2)
+        Ts.append(T_of(path[-1], rho2)[0])
+        if Ts[-1] >= Ts[-2]:
+            break
+    best = path[int(np.argmin(Ts))]
+    assert out["level_d"] == [best]
+    Qb = T_of(best, rho2)[3]
+    assert np.allclose(out["Q"][0] @ out["Q"][0].conj().T, Qb @ Qb.conj().T, atol=1e-10)
+    # larger d only ever lowers the pilot variance here, down to 0 at d = n
+    Vs = []
+    for d in (2, 8, 32, n):
+        Q, _ = tr.low_rank(lambda X: A @ X, n, d, 2, rng.Z2Z2, 3, 0)
+        Z = rng.noise_block(rng.Z2Z2, 3, rng.PURPOSE_PILOT, 0, 0, 24, n)
+        t = np.einsum("ij,ij->j", (Z - Q @ (Q.conj().T @ Z)).conj(), A @ Z)
+        Vs.append(np.sum(np.abs(t - t.mean()) ** 2) / 23)
+    assert Vs[-1] < 1e-20 * Vs[0] and Vs[2] < Vs[0]
