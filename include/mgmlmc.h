@@ -187,9 +187,14 @@ typedef struct {
   int max_restarts;
   int rhs_block;     /* RHS solved together (0 = all, -1 = the autotuned
                         width of the level, all if none) */
-  int use_cnn;       /* level 0 only: start from the learned guess
-                        (mgm_cnn_*) instead of x0 = 0 */
+  int use_cnn;       /* level 0 only, flags (mgm_cnn_*): MGM_CNN_GUESS
+                        starts from the learned guess instead of x0 = 0;
+                        MGM_CNN_STAGE puts the network in front of the
+                        multigrid cycle in every preconditioner call */
 } mgm_solve_params;
+
+#define MGM_CNN_GUESS 1
+#define MGM_CNN_STAGE 2
 
 typedef struct {
   int *iters;        /* HOST [nrhs] or NULL */
@@ -399,6 +404,8 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
  *   MGM_KERNEL_SAP_LOW  one SAP colour sweep of the low-precision cycle at the
  *                       field's current precision (FP32 vectors; FP16 blocks on
  *                       16-dof levels in FP16 mode)
+ *   MGM_KERNEL_CONV_H   the same hidden convolution with FP16 weights and
+ *                       activations (FP16 matrix cores, FP32 accumulation)
  * ------------------------------------------------------------------------- */
 #define MGM_KERNEL_STENCIL 0
 #define MGM_KERNEL_SAP 1
@@ -407,6 +414,7 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
 #define MGM_KERNEL_COPY 4
 #define MGM_KERNEL_CONV 5
 #define MGM_KERNEL_SAP_LOW 6
+#define MGM_KERNEL_CONV_H 7
 
 int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
                     double *us_out, double *bytes_out, double *flops_out);
@@ -431,6 +439,15 @@ int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, i
  * x0 = alpha_r f(b_r), alpha_r = <D f(b_r), b_r> / ||D f(b_r)||^2 per RHS (the
  * minimal residual along f(b_r), so ||b - D x0|| <= ||b||); a zero or
  * non-finite alpha_r gives x0 = 0, i.e. plain multigrid.
+ *
+ * With MGM_CNN_STAGE the network is the first stage of the level-0
+ * preconditioner of the (flexible) outer FGMRES: for an Arnoldi vector v_r
+ * (unit norm) z_r = x_r + M(v_r - D x_r) with M the multigrid cycle and
+ * x_r = alpha_r f(sqrt(n0) v_r), alpha_r the minimal residual factor as
+ * above (sqrt(n0) scales v_r to the size of a Z2 x Z2 vector, the network's
+ * training input).  A zero or non-finite alpha_r gives z_r = M v_r, i.e.
+ * multigrid alone.  Each iteration then costs one network evaluation and
+ * one extra application of D on top of the cycle.
  * ------------------------------------------------------------------------- */
 #define MGM_CNN_NPARAMS 20836
 

@@ -173,7 +173,7 @@ class Job(C.Structure):
     _fields_ = [("gauge_id", C.c_int), ("level", C.c_int), ("nrhs", C.c_int),
                 ("b", C.c_void_p), ("x", C.c_void_p)]
 
-KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4, "conv": 5, "sap_low": 6}
+KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4, "conv": 5, "sap_low": 6, "conv_h": 7}
 
 _lib = None
 
@@ -241,8 +241,15 @@ def mg_params(nlevels, blocks, ntv, sap_block=None, sap_cycles=None, inner_iters
     return p
 
 
+CNN_USES = {False: 0, None: 0, True: 1, 2: 2, 3: 3, "guess": 1, "stage": 2, "both": 3}
+
+
 def solve_params(tol=1e-10, restart=16, max_restarts=50, rhs_block=0, use_cnn=False) -> SolveParams:
-    return SolveParams(tol, restart, max_restarts, rhs_block, int(bool(use_cnn)))
+    """use_cnn: False, True / "guess" (learned initial guess), "stage" (learned
+    first stage of every level-0 preconditioner call) or "both"."""
+    if use_cnn not in CNN_USES:
+        raise ValueError(f"use_cnn must be one of {list(CNN_USES)}")
+    return SolveParams(tol, restart, max_restarts, rhs_block, CNN_USES[use_cnn])
 
 
 def adam_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> AdamParams:

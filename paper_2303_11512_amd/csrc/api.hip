@@ -531,6 +531,21 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         flops = 2.0 * V * b * 32 * 288;
         break;
       }
+      case MGM_KERNEL_CONV_H: {
+        require(level == 0, "the network runs on level 0");
+        cnn_check_lattice(g);
+        const Cnn* net = &cnn_of(c);
+        const int64_t V = (int64_t)g.Lx * g.Lt;
+        g.cnn.h[0].ensure(sizeof(_Float16) * V * 32 * nrhs);
+        g.cnn.h[1].ensure(sizeof(_Float16) * V * 32 * nrhs);
+        const _Float16* in = g.cnn.h[0].as<_Float16>();
+        _Float16* out = g.cnn.h[1].as<_Float16>();
+        HIPCHK(hipMemsetAsync(g.cnn.h[0].p, 0, sizeof(_Float16) * V * 32 * nrhs, s));
+        launch = [=, &g] { cnn_time_conv_h(s, *net, g, nrhs, in, out); };
+        bytes = 2.0 * V * b * 64 + 2.0 * 32 * 288 + 4.0 * 32;
+        flops = 2.0 * V * b * 32 * 288;
+        break;
+      }
       default:
         throw Error(MGM_EINVAL, "unknown kernel kind");
     }
@@ -689,7 +704,14 @@ int mgm_cnn_set_params(mgm_ctx* c, const float* theta) {
 int mgm_cnn_set_precision(mgm_ctx* c, int precision) {
   return guarded(c, [&] {
     require(precision == MGM_PREC_FP32 || precision == MGM_PREC_FP16, "network precision must be FP32 or FP16");
-    cnn_of(c).half = precision == MGM_PREC_FP16;
+    Cnn& net = cnn_of(c);
+    const bool half = precision == MGM_PREC_FP16;
+    if (net.half != half) {
+      net.half = half;
+      // captured solver steps with the learned stage hold the other
+      // precision's kernels: retire every captured graph
+      g_alloc_epoch.fetch_add(1);
+    }
     return MGM_OK;
   });
 }

@@ -135,20 +135,29 @@ __global__ void __launch_bounds__(CNT) k_conv(const float* __restrict__ in, int 
   }
 }
 
-// The same convolution with FP16 activations and weights on the 16x16x16
-// FP16 matrix cores (FP32 accumulation; bias, tanh and the output rounding in
-// FP32 -> FP16).  Lane l supplies A[l%16][4(l/16) + j] and B[4(l/16) + j][l%16];
-// element v of its result is D[4(l/16) + v][l%16].  K index k = tap * CIN + ch
-// in chunks of 16 (padded with zeros past 9 * CIN).
+// The same convolution with FP16 activations and weights on the FP16 matrix
+// cores (FP32 accumulation; bias, tanh and the output rounding in FP32 ->
+// FP16).  K index k = tap * CIN + ch in chunks of 16 or 32 (padded with zeros
+// past 9 * CIN).
 typedef _Float16 hv4 __attribute__((ext_vector_type(4)));
 
-template <int C>
+typedef _Float16 hv8 __attribute__((ext_vector_type(8)));
+
+// words of W halves (4: 8 bytes, 8: 16 bytes)
+template <int W> struct HWord;
+template <> struct HWord<4> { typedef hv4 T; };
+template <> struct HWord<8> { typedef hv8 T; };
+
+// Halo tile into LDS with site stride S (halves), in words of W channels.
+template <int C, int S, int W>
 __device__ __forceinline__ void load_tile_h(const _Float16* __restrict__ in, int Lx, int Lt, int anti, int b,
                                             int t0, int x0, _Float16* xs) {
-  constexpr int S = C + 4;  // site stride in LDS (halves): 8-byte aligned rows of 4
+  typedef typename HWord<W>::T word;
+  constexpr int CQ = C / W;  // words per site
+  static_assert(C % W == 0 && S % W == 0, "channels in whole words");
   const _Float16* base = in + (int64_t)b * Lx * Lt * C;
-  for (int e = threadIdx.x; e < HE * HE * C; e += CNT) {
-    const int site = e / C, ch = e - site * C;
+  for (int e = threadIdx.x; e < HE * HE * CQ; e += CNT) {
+    const int site = e / CQ, w = e - site * CQ;
     const int r = site / HE, cc = site - r * HE;
     int t = t0 + r - 1, x = x0 + cc - 1;
     bool neg = false;
@@ -163,60 +172,91 @@ __device__ __forceinline__ void load_tile_h(const _Float16* __restrict__ in, int
       x += Lx;
     else if (x >= Lx)
       x -= Lx;
-    const _Float16 v = base[((int64_t)t * Lx + x) * C + ch];
-    xs[site * S + ch] = neg ? (_Float16)(-v) : v;
+    word v = *reinterpret_cast<const word*>(base + ((int64_t)t * Lx + x) * C + W * w);
+    if (neg) v = -v;
+    *reinterpret_cast<word*>(xs + site * S + W * w) = v;
   }
 }
 
+// FP16 matrix-core step on words of W halves: 16x16x16 (W = 4) or the
+// 16x16x32 shape of gfx950 (W = 8).  Lane l supplies the K slots
+// W (l/16) .. W (l/16) + W - 1 of row l%16 of A and of column l%16 of B; the
+// hardware pairs equal slots of A and B, so the product sums over all K
+// whatever order it takes them in.  Result element v: D[4(l/16) + v][l%16].
+template <int W>
+__device__ __forceinline__ f4 hmma_w(typename HWord<W>::T a, typename HWord<W>::T b, f4 c) {
+  if constexpr (W == 8)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// Global traffic in words: the halo tile and the weights are loaded as words
+// of W halves (W = 8 when CIN is a multiple of 8: then the 16x16x32 shape),
+// and the 16 x 16 x COUT output tile is transposed through LDS (reusing the
+// tile's space) so that it is stored as contiguous 8-byte words.
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(CNT) k_conv_h(const _Float16* __restrict__ in, int Lx, int Lt, int anti,
                                                 const _Float16* __restrict__ wp, const float* __restrict__ bias,
                                                 _Float16* __restrict__ out) {
+  constexpr int W = CIN % 8 == 0 ? 8 : 4;  // K slots per lane
+  typedef typename HWord<W>::T word;
+  constexpr int KW = 4 * W;                // K per matrix-core step
   constexpr int K = 9 * CIN;
-  constexpr int KC = (K + 15) / 16;  // 16-wide K chunks
-  constexpr int KS = KC * 16 + 4;    // LDS row stride of the weights (halves)
-  constexpr int S = CIN + 4;
+  constexpr int KC = (K + KW - 1) / KW;    // K chunks (zero-padded past K)
+  constexpr int KS = KC * KW + W;          // LDS row stride of the weights (halves)
+  constexpr int S = CIN + W;               // LDS site stride of the tile
   constexpr int NB = (COUT + 15) / 16;
-  __shared__ __attribute__((aligned(16))) _Float16 xs[HE * HE * S];
-  __shared__ __attribute__((aligned(16))) _Float16 ws[COUT * KS];
+  constexpr int OS = COUT + 4;             // LDS site stride of the output tile
+  constexpr int XN = HE * HE * S, WN = COUT * KS, ON = TE * TE * OS;
+  constexpr int SM = XN + WN > ON ? XN + WN : ON;
+  static_assert(CIN % 4 == 0 && COUT % 4 == 0 && K % W == 0 && KS % W == 0 && S % W == 0 && XN % W == 0,
+                "whole LDS words");
+  __shared__ __attribute__((aligned(16))) _Float16 smem[SM];
+  _Float16* xs = smem;
+  _Float16* ws = smem + XN;
   const int x0 = blockIdx.x * TE, t0 = blockIdx.y * TE, b = blockIdx.z;
-  load_tile_h<CIN>(in, Lx, Lt, anti, b, t0, x0, xs);
-  for (int e = threadIdx.x; e < COUT * KC * 16; e += CNT) {
-    const int n = e / (KC * 16), k = e - n * KC * 16;
-    ws[n * KS + k] = k < K ? wp[n * K + k] : (_Float16)0;
+  load_tile_h<CIN, S, W>(in, Lx, Lt, anti, b, t0, x0, xs);
+  word zero;
+#pragma unroll
+  for (int j = 0; j < W; ++j) zero[j] = (_Float16)0;
+  constexpr int RW = KC * KW / W;  // words per weight row
+  for (int e = threadIdx.x; e < COUT * RW; e += CNT) {
+    const int n = e / RW, k = W * (e - n * RW);
+    // K is a multiple of W: a word is wholly inside or wholly past K
+    *reinterpret_cast<word*>(ws + n * KS + k) = k < K ? *reinterpret_cast<const word*>(wp + n * K + k) : zero;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
-  typedef float f4v __attribute__((ext_vector_type(4)));
-  f4v acc[4][NB];
+  f4 acc[4][NB];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f4{0.f, 0.f, 0.f, 0.f};
   for (int kc = 0; kc < KC; ++kc) {
-    const int k = kc * 16 + 4 * q;  // this lane's 4 consecutive K indices
-    hv4 bw[NB];
+    const int k = kc * KW + W * q;  // this lane's W consecutive K indices
+    // W consecutive K indices share one tap (CIN is a multiple of W), so the
+    // lane's A and B fragments are single LDS words
+    word bw[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int n = nb * 16 + i;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bw[nb][j] = n < COUT ? ws[n * KS + k + j] : (_Float16)0;
+      bw[nb] = n < COUT ? *reinterpret_cast<const word*>(ws + n * KS + k) : zero;
     }
     const bool inK = k < K;
     const int tap = inK ? k / CIN : 0, ch = inK ? k - tap * CIN : 0;
     const int dt = tap / 3, dx = tap - 3 * dt;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      hv4 a;
       const _Float16* xr = xs + ((wave * 4 + rr + dt) * HE + i + dx) * S + ch;
+      const word a = inK ? *reinterpret_cast<const word*>(xr) : zero;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = inK ? xr[j] : (_Float16)0;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[rr][nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bw[nb], acc[rr][nb], 0, 0, 0);
+      for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = hmma_w<W>(a, bw[nb], acc[rr][nb]);
     }
   }
+  __syncthreads();  // every wave is done with the tile and weights: reuse smem
+  _Float16* os = smem;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int n = nb * 16 + i;
@@ -224,14 +264,21 @@ __global__ void __launch_bounds__(CNT) k_conv_h(const _Float16* __restrict__ in,
     const float bn = bias[n];
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      const int64_t row = ((int64_t)b * Lt + t0 + wave * 4 + rr) * Lx + x0 + 4 * q;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         float z = acc[rr][nb][v] + bn;
         if (EPI == EPI_TANH) z = tanhf(z);
-        out[(row + v) * COUT + n] = (_Float16)z;
+        os[((wave * 4 + rr) * TE + 4 * q + v) * OS + n] = (_Float16)z;
       }
     }
+  }
+  __syncthreads();
+  constexpr int OQ = COUT / 4;
+  for (int e = threadIdx.x; e < TE * TE * OQ; e += CNT) {
+    const int site = e / OQ, w4 = e - site * OQ;
+    const int row = site / TE, col = site - row * TE;
+    const int64_t o = (((int64_t)b * Lt + t0 + row) * Lx + x0 + col) * COUT + 4 * w4;
+    *reinterpret_cast<hv4*>(out + o) = *reinterpret_cast<const hv4*>(os + site * OS + 4 * w4);
   }
 }
 
@@ -473,6 +520,51 @@ __global__ void __launch_bounds__(CNT) k_mr_apply(const double* __restrict__ par
   }
 }
 
+// Learned stage: x = alpha_r y and res = b - alpha_r u per RHS, alpha_r as in
+// k_mr_apply; an unusable alpha_r gives x = 0 and res = b (multigrid alone).
+// res may alias u (element-wise read before write).
+__global__ void __launch_bounds__(CNT) k_mr_apply_res(const double* __restrict__ part, int nch, int64_t n,
+                                                      cd* __restrict__ x, const cd* u, const cd* __restrict__ b,
+                                                      cd* res) {
+  const int r = blockIdx.y;
+  double sr = 0.0, si = 0.0, sd = 0.0;
+  for (int c = 0; c < nch; ++c) {
+    const double* p = part + ((int64_t)r * nch + c) * 3;
+    sr += p[0];
+    si += p[1];
+    sd += p[2];
+  }
+  const double ar = sr / sd, ai = si / sd;
+  const bool ok = sd > 0.0 && isfinite(ar) && isfinite(ai) && (ar != 0.0 || ai != 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * CNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * CNT) {
+    const int64_t o = r * n + e;
+    const cd y = x[o], ue = u[o], be = b[o];
+    // the fallback never multiplies: y and u may hold NaN
+    x[o] = ok ? cd{ar * y.re - ai * y.im, ar * y.im + ai * y.re} : cd{0.0, 0.0};
+    res[o] = ok ? cd{be.re - (ar * ue.re - ai * ue.im), be.im - (ar * ue.im + ai * ue.re)} : be;
+  }
+}
+
+// z += x for the active RHS
+__global__ void __launch_bounds__(CNT) k_stage_add(cd* __restrict__ z, const cd* __restrict__ x, int64_t n,
+                                                   const int* __restrict__ act) {
+  const int r = blockIdx.y;
+  if (act && !act[r]) return;
+  for (int64_t e = (int64_t)blockIdx.x * CNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * CNT) {
+    const cd a = z[r * n + e], v = x[r * n + e];
+    z[r * n + e] = cd{a.re + v.re, a.im + v.im};
+  }
+}
+
+// in * s
+__global__ void __launch_bounds__(CNT) k_scale_copy(const cd* __restrict__ in, double s, int64_t cnt,
+                                                    cd* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * CNT + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * CNT) {
+    const cd v = in[e];
+    out[e] = cd{s * v.re, s * v.im};
+  }
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + CNT - 1) / CNT); }
 
 constexpr int WIDTH[5] = {4, 32, 32, 32, 4};
@@ -544,6 +636,14 @@ void cnn_time_conv(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const 
   const dim3 grid(g.Lx / TE, g.Lt / TE, nb);
   hipLaunchKernelGGL((k_conv<32, 32, EPI_TANH>), grid, dim3(CNT), 0, s, in, g.Lx, g.Lt, g.anti,
                      net.wf[1].as<float>(), net.bias(1), nullptr, out);
+  KCHK();
+}
+
+void cnn_time_conv_h(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const _Float16* in,
+                     _Float16* out) {
+  const dim3 grid(g.Lx / TE, g.Lt / TE, nb);
+  hipLaunchKernelGGL((k_conv_h<32, 32, EPI_TANH>), grid, dim3(CNT), 0, s, in, g.Lx, g.Lt, g.anti,
+                     net.wh[1].as<_Float16>(), net.bias(1), out);
   KCHK();
 }
 
@@ -706,6 +806,37 @@ void cnn_initial_guess(mgm_ctx* c, Gauge& g, int nrhs, const cd* b, cd* x, cd* u
   g.cnn.mr.ensure(sizeof(double) * 3 * nrhs * nch);
   hipLaunchKernelGGL(k_mr_partial, dim3(nch, nrhs), dim3(CNT), 0, s, u, b, n, g.cnn.mr.as<double>());
   hipLaunchKernelGGL(k_mr_apply, dim3(nch, nrhs), dim3(CNT), 0, s, g.cnn.mr.as<double>(), nch, n, x);
+  KCHK();
+}
+
+// Learned first stage of the level-0 preconditioner of the flexible outer
+// FGMRES: z = x1 + M(v - D x1) with M the multigrid cycle and
+// x1 = alpha_r f(sqrt(n) v_r), alpha_r minimising ||v_r - alpha D f(.)|| (the
+// Arnoldi vectors have unit norm; the factor sqrt(n) gives the network inputs
+// of the size of its Z2 x Z2 training right-hand sides).  A zero or
+// non-finite alpha_r leaves z = M v (multigrid fallback).  The error of z is
+// (I - M D) applied to the error of x1.  No host synchronisation.
+void cnn_precondition(mgm_ctx* c, Gauge& g, int nrhs, const cd* v, cd* z, const int* act) {
+  hipStream_t s = c->stream;
+  require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)");
+  const int64_t n = g.levels[0]->n, cnt = (int64_t)nrhs * n;
+  CnnWork& w = g.cnn;
+  w.st_x.ensure(sizeof(cd) * cnt);
+  w.st_u.ensure(sizeof(cd) * cnt);
+  cd* x1 = w.st_x.as<cd>();
+  cd* u = w.st_u.as<cd>();
+  const unsigned gb = (unsigned)std::min<int64_t>(blocks_for(cnt), 8192);
+  hipLaunchKernelGGL(k_scale_copy, dim3(gb), dim3(CNT), 0, s, v, std::sqrt((double)n), cnt, u);
+  cnn_apply(s, *c->cnn, g, nrhs, u, x1, w);
+  apply_level(c, g, 0, nrhs, x1, u);
+  const int nch = (int)std::min<int64_t>(64, (n + CNT - 1) / CNT);
+  w.mr.ensure(sizeof(double) * 3 * nrhs * nch);
+  hipLaunchKernelGGL(k_mr_partial, dim3(nch, nrhs), dim3(CNT), 0, s, u, v, n, w.mr.as<double>());
+  hipLaunchKernelGGL(k_mr_apply_res, dim3(nch, nrhs), dim3(CNT), 0, s, w.mr.as<double>(), nch, n, x1, u, v, u);
+  KCHK();
+  precondition_d(c, g, 0, nrhs, u, z, act);
+  const unsigned ga = (unsigned)std::min<int64_t>(blocks_for(n), 1024);
+  hipLaunchKernelGGL(k_stage_add, dim3(ga, nrhs), dim3(CNT), 0, s, z, x1, n, act);
   KCHK();
 }
 

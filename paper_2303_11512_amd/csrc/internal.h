@@ -402,6 +402,7 @@ struct CnnWork {
   DevBuf x0, y, gy, a[3], g[2], part, lpart, mr;
   DevBuf hx0, hy, h[2];  // FP16 inference buffers
   DevBuf pairs_b, pairs_x, batch_b, batch_x, idx;
+  DevBuf st_x, st_u;  // learned preconditioner stage: x1 and D x1 / residual
 };
 
 // Trace-estimator workspaces, kept with the field so that repeated estimates
@@ -499,5 +500,8 @@ void cnn_to_channels(hipStream_t s, const cd* in, int64_t ndof, float* out);
 void cnn_from_channels(hipStream_t s, const float* in, int64_t ndof, cd* out);
 void cnn_apply(hipStream_t s, const Cnn& net, const Gauge& g, int nrhs, const cd* b, cd* y, CnnWork& w);
 void cnn_initial_guess(mgm_ctx* c, Gauge& g, int nrhs, const cd* b, cd* x, cd* u);
+void cnn_precondition(mgm_ctx* c, Gauge& g, int nrhs, const cd* v, cd* z, const int* act);
 void cnn_time_conv(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const float* in, float* out);
+void cnn_time_conv_h(hipStream_t s, const Cnn& net, const Gauge& g, int nb, const _Float16* in,
+                     _Float16* out);
 }  // namespace mgm

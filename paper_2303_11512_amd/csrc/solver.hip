@@ -333,7 +333,11 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 
   launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p);
   launch_done_from_norm<double>(s, bnorm, nrhs, done);  // zero right-hand sides are solved
-  if (sp.use_cnn && l == 0 && !L.has_dense)
+  require(sp.use_cnn >= 0 && sp.use_cnn <= (MGM_CNN_GUESS | MGM_CNN_STAGE), "use_cnn: unknown flags");
+  const bool learned = l == 0 && !L.has_dense;
+  const bool stage = learned && (sp.use_cnn & MGM_CNN_STAGE);
+  if (stage) require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
+  if (learned && (sp.use_cnn & MGM_CNN_GUESS))
     cnn_initial_guess(c, g, nrhs, b, x, w);
   else
     launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
@@ -351,14 +355,16 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
       launch_scale<double>(s, w, beta, n, nrhs, V, act);
       for (int j = 0; j < m; ++j) {
         // the whole step is one graph: key level field (m + 1) * 1000 + l
-        // tells it from the preconditioner's own graphs and from other
-        // restart lengths; the step index is in the V / Z addresses
+        // (+ 500 with the learned stage) tells it from the preconditioner's
+        // own graphs, from other restart lengths and from the plain step;
+        // the step index is in the V / Z addresses
         const int64_t vs = (int64_t)nrhs * n;
-        const GraphKey key{(m + 1) * 1000 + l, nrhs, (const void*)(V + j * vs), (void*)(Z + j * vs), act,
-                           g.prm.precision};
+        const GraphKey key{(m + 1) * 1000 + l + (stage ? 500 : 0), nrhs, (const void*)(V + j * vs),
+                           (void*)(Z + j * vs), act, g.prm.precision};
         run_graph(c, g, key, [&] {
           arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
-            precondition_d(c, g, l, nrhs, v, z, a);
+            if (stage) cnn_precondition(c, g, nrhs, v, z, a);
+            else precondition_d(c, g, l, nrhs, v, z, a);
           });
         });
         const int slot = j % PinnedFlags::kDepth;

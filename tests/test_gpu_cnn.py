@@ -235,6 +235,119 @@ def test_broken_network_falls_back_to_plain_multigrid(ctx, trained):
         ctx.cnn_set_params(good)
 
 
+@pytest.mark.parametrize("use,precision", [("stage", "fp32"), ("stage", "fp16"), ("both", "fp16")])
+def test_solves_with_the_learned_stage_meet_the_tolerance(ctx, trained, use, precision):
+    """The network as the first stage of every level-0 preconditioner call
+    (flexible FGMRES): the true FP64 residual still meets the tolerance."""
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    D = dirac.wilson_dirac(rec.theta, rec.m0)
+    n = D.shape[0]
+    b = rhs_vectors(n, 12, 906)
+    ctx.cnn_set_precision(precision)
+    try:
+        x = empty(12, n)
+        log(f"stage solve use={use} precision={precision}")
+        _, its, rel = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=16, use_cnn=use))
+        _, its0, _ = ctx.solve_batch(gid, 0, to_dev(b), empty(12, n), solve_params(tol=1e-10, restart=16))
+    finally:
+        ctx.cnn_set_precision("fp32")
+    xh = to_host(x)
+    res = np.linalg.norm(b - (D @ xh.T).T, axis=1) / np.linalg.norm(b, axis=1)
+    assert np.all(res <= 1e-10), res
+    assert np.all(rel <= 1e-10)
+    log(f"  iterations plain {np.mean(its0):.2f}, {use} {np.mean(its):.2f}")
+
+
+def test_learned_stage_is_network_then_multigrid(ctx, trained):
+    """One FGMRES step (restart 1, no restart) with the learned stage returns
+    x = gamma z, z = x1 + M(v - D x1), x1 = alpha f(sqrt(n) v), v = b / ||b||,
+    alpha and gamma the minimal-residual factors.  Built here from the
+    network's own output (whose parity with the oracle network is tested
+    above), the oracle's D and the multigrid preconditioner entry M.
+    b = +-1 +-i has ||b|| = 64 at n = 2048, so v and sqrt(n) v carry the same
+    bits on both sides and the network sees identical input."""
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    D = dirac.wilson_dirac(rec.theta, rec.m0)
+    n = D.shape[0]
+    assert n == 2048
+    rng = np.random.default_rng(907)
+    nb = 3
+    b = rng.choice([-1.0, 1.0], (nb, n)) + 1j * rng.choice([-1.0, 1.0], (nb, n))
+    x = empty(nb, n)
+    log("stage: one FGMRES step against its parts")
+    st, _, _ = ctx.solve_batch(gid, 0, to_dev(b), x,
+                               solve_params(tol=1e-14, restart=1, max_restarts=0, use_cnn="stage"), check=False)
+    assert st in (0, -5)  # MGM_OK or MGM_ENOTCONV (one step does not converge)
+    v = b / 64.0
+    f = empty(nb, n)
+    ctx.cnn_apply(gid, to_dev(np.sqrt(float(n)) * v), f)
+    f = to_host(f)
+    u = (D @ f.T).T
+    alpha = np.array([np.vdot(u[r], v[r]) / np.vdot(u[r], u[r]) for r in range(nb)])
+    x1 = alpha[:, None] * f
+    r1 = v - alpha[:, None] * u
+    mr = empty(nb, n)
+    ctx.precondition(gid, 0, to_dev(r1), mr)
+    z = x1 + to_host(mr)
+    w = (D @ z.T).T
+    gamma = np.array([np.vdot(w[r], b[r]) / np.vdot(w[r], w[r]) for r in range(nb)])
+    want = gamma[:, None] * z
+    got = to_host(x)
+    err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+    log(f"  rel. error {err}")
+    assert np.all(err < 1e-9), err
+    # the stage did something: its first step differs from multigrid alone
+    mv = empty(nb, n)
+    ctx.precondition(gid, 0, to_dev(v), mv)
+    assert np.linalg.norm(z - to_host(mv)) > 1e-3 * np.linalg.norm(z)
+
+
+def test_broken_network_stage_is_plain_multigrid(ctx, trained):
+    """A NaN network gives no usable alpha: every stage call returns M v and
+    the solve is the plain one, bit for bit."""
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    good = ctx.cnn_get_params()
+    n = 2 * 32 * 32
+    b = to_dev(rhs_vectors(n, 6, 908))
+    x0 = empty(6, n)
+    ctx.solve_batch(gid, 0, b, x0, solve_params(tol=1e-10, restart=16))
+    try:
+        bad = good.copy()
+        bad[::5] = np.nan
+        ctx.cnn_set_params(bad)
+        x1 = empty(6, n)
+        ctx.solve_batch(gid, 0, b, x1, solve_params(tol=1e-10, restart=16, use_cnn="both"))
+        assert np.array_equal(to_host(x1), to_host(x0))
+    finally:
+        ctx.cnn_set_params(good)
+
+
+def test_network_precision_change_reaches_captured_solver_steps(ctx, trained):
+    """The stage runs inside captured Arnoldi steps; switching the network's
+    precision must switch the kernels those steps run (FP32, FP16, FP32,
+    FP16 on the same field: equal bits for equal precision, different bits
+    across precisions)."""
+    from paper_2303_11512_amd import solve_params
+    rec, gid, _ = trained
+    n = 2 * 32 * 32
+    b = to_dev(rhs_vectors(n, 4, 909))
+    out = []
+    try:
+        for prec in ("fp32", "fp16", "fp32", "fp16"):
+            ctx.cnn_set_precision(prec)
+            x = empty(4, n)
+            ctx.solve_batch(gid, 0, b, x, solve_params(tol=1e-10, restart=16, use_cnn="stage"))
+            out.append(to_host(x))
+    finally:
+        ctx.cnn_set_precision("fp32")
+    assert np.array_equal(out[0], out[2])
+    assert np.array_equal(out[1], out[3])
+    assert not np.array_equal(out[0], out[1])
+
+
 def test_lattice_must_tile_by_16(ctx):
     from paper_2303_11512_amd import MGMError
     gid, _ = _field(ctx, 24, 16, True, 14)
