@@ -685,7 +685,11 @@ def main():
     t0 = time.perf_counter()
     outs = []
     for k in range(args.steps):
+        # a named range per step, so that a profiler's kernel trace can be
+        # cut into steps (roctx; no cost without a profiler)
+        torch.cuda.nvtx.range_push(f"timed step {k}")
         outs.append(ctx.trace_estimate(gid, solve=sp, **trace_kwargs(cfg, k)))
+        torch.cuda.nvtx.range_pop()
         print(f"# step {k}: tau={outs[-1]['tau']:.6f} samples={outs[-1]['level_samples']}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
