@@ -439,11 +439,10 @@ __global__ void __launch_bounds__(NT) k_gram_partial(const cd* __restrict__ Y, i
 // G[e] = sum over chunks of partial[chunk][e]: a workgroup owns 8 consecutive
 // elements (one 128-byte row of every chunk), 32 threads per element stride
 // over the chunks, then the 32 sums are added in a fixed order.
-__global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ partial, int nch, int d,
+__global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ partial, int nch, int dd,
                                                     cd* __restrict__ G) {
   __shared__ cd sh[32][8];
   const int t = threadIdx.x, e8 = t & 7, c0 = t >> 3;
-  const int dd = d * d;
   const int e = blockIdx.x * 8 + e8;
   const int ec = e < dd ? e : 0;
   cd acc = mk(0.0, 0.0);
@@ -676,11 +675,108 @@ void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partia
   const unsigned nch = (unsigned)((n + GCH - 1) / GCH);
   hipLaunchKernelGGL(k_gram_partial, dim3(nch), dim3(NT), 0, s, Y, n, d, partial);
   KCHK();
-  hipLaunchKernelGGL(k_gram_reduce, dim3((d * d + 7) / 8), dim3(NT), 0, s, partial, (int)nch, d, G);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((d * d + 7) / 8), dim3(NT), 0, s, partial, (int)nch, d * d, G);
   KCHK();
 }
 
 int64_t gram_partials(int64_t n) { return (n + GCH - 1) / GCH; }
+
+
+// ------------------------------------------------------------------ Hutch++ projection
+// z = zeta - Q (Q^H zeta) for a block of k vectors as two FP64 matrix-core
+// products.  Q: d basis vectors [d][n]; Z: k vectors [k][n]; C: d x k
+// coefficients, C[i][r] = Q_i^H Z_r, stored at C[i * k + r].
+//
+// Coefficient partials: a workgroup owns PCH values of the element index e;
+// its waves take the 16 x 16 tiles (i-tile, r-tile) of C in turn and sum
+// conj(Q_i[e]) Z_r[e] over the chunk (M = i, N = r, K = e in steps of 4).
+constexpr int PCH = 256;
+__global__ void __launch_bounds__(NT) k_proj_partial(const cd* __restrict__ Q, int d, const cd* __restrict__ Z,
+                                                     int k, int64_t n, cd* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int nti = (d + 15) / 16, ntr = (k + 15) / 16;
+  const int64_t e0 = (int64_t)blockIdx.x * PCH;
+  for (int tile = wave; tile < nti * ntr; tile += 4) {
+    const int i0 = (tile / ntr) * 16, r0 = (tile % ntr) * 16;
+    const int i = i0 + l16, r = r0 + l16;
+    const cd* Qi = Q + (int64_t)(i < d ? i : 0) * n;
+    const cd* Zr = Z + (int64_t)(r < k ? r : 0) * n;
+    CAcc<double> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll 16
+    for (int kk = 0; kk < PCH; kk += 4) {
+      const int64_t e = e0 + kk + (lane >> 4);
+      const bool in = e < n;
+      const int64_t ec = in ? e : 0;
+      const cd a = ld_or0(Qi + ec, in && i < d);
+      const cd b = ld_or0(Zr + ec, in && r < k);
+      cmma(conj(a), b, acc);
+    }
+    // element v: row i0 + out_row(lane, v) of C, column r
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ii = i0 + MF<double>::out_row(lane, v);
+      if (ii < d && r < k) partial[((int64_t)blockIdx.x * d + ii) * k + r] = mk(acc.re[v], acc.im[v]);
+    }
+  }
+}
+
+// Z_r[e] -= sum_i Q_i[e] C[i][r]: a wave owns 16 values of e and every
+// r-tile (at most 4, k <= 64); M = r, N = e, K = i in steps of 4, so each Q
+// value is loaded once and serves all k vectors, and each Z value is read and
+// written once.
+__global__ void __launch_bounds__(NT) k_proj_update(const cd* __restrict__ Q, int d, const cd* __restrict__ C,
+                                                    int k, int64_t n, cd* __restrict__ Z) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (e0 >= n) return;
+  const int64_t e = e0 + l16;
+  const bool ein = e < n;
+  const int ntr = (k + 15) / 16;
+  CAcc<double> acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = CAcc<double>{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int i0 = 0; i0 < d; i0 += 4) {
+    const int i = i0 + q;  // B[i][e] = Q_i[e]; A[r][i] = C[i][r]
+    const cd b = ld_or0(Q + (int64_t)(i < d ? i : 0) * n + (ein ? e : 0), i < d && ein);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < ntr) {
+        const int r = t * 16 + l16;
+        const cd a = ld_or0(C + (int64_t)(i < d ? i : 0) * k + (r < k ? r : 0), i < d && r < k);
+        cmma(a, b, acc[t]);
+      }
+    }
+  }
+  // element v of tile t: vector r = 16 t + out_row(lane, v), element e
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= ntr) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = t * 16 + MF<double>::out_row(lane, v);
+      if (r < k && ein) {
+        cd* zp = Z + (int64_t)r * n + e;
+        const cd z = *zp;
+        *zp = mk(z.re - acc[t].re[v], z.im - acc[t].im[v]);
+      }
+    }
+  }
+}
+
+int64_t proj_partials(int64_t n) { return (n + PCH - 1) / PCH; }
+
+void launch_project(hipStream_t s, const cd* Q, int d, cd* Z, int k, int64_t n, cd* C, cd* partial) {
+  require(d >= 1 && d <= 64 && k >= 1 && k <= 64, "projection: 1 <= d, k <= 64");
+  const unsigned nch = (unsigned)proj_partials(n);
+  hipLaunchKernelGGL(k_proj_partial, dim3(nch), dim3(NT), 0, s, Q, d, Z, k, n, partial);
+  KCHK();
+  hipLaunchKernelGGL(k_gram_reduce, dim3((d * k + 7) / 8), dim3(NT), 0, s, partial, (int)nch, d * k, C);
+  KCHK();
+  hipLaunchKernelGGL(k_proj_update, dim3((unsigned)((n + 63) / 64)), dim3(NT), 0, s, Q, d, C, k, n, Z);
+  KCHK();
+}
 
 // out = gamma5 in on the fine level: the spin-1 component (odd dof) negated
 __global__ void __launch_bounds__(NT) k_gamma5(const cd* __restrict__ in, cd* __restrict__ out, int64_t count) {

@@ -306,6 +306,11 @@ int64_t gram_partials(int64_t n);
 void launch_local_qr(hipStream_t s, const cd* V, int64_t n, int Nx, int Nt, int M, int bx, int bt,
                      int ntv, cd* P);
 void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int d, cd* Q);
+// Z -= Q (Q^H Z) for k <= 64 vectors Z [k][n] and d <= 64 basis vectors
+// Q [d][n] on the FP64 matrix cores; C receives Q^H Z ([d][k]); partial
+// holds proj_partials(n) * d * k values.
+void launch_project(hipStream_t s, const cd* Q, int d, cd* Z, int k, int64_t n, cd* C, cd* partial);
+int64_t proj_partials(int64_t n);
 
 // ---------------------------------------------------------------- context
 template <class T>
@@ -414,6 +419,7 @@ struct EstWork {
   DevBuf S[MGM_MAX_LEVELS], Y[MGM_MAX_LEVELS], Q[MGM_MAX_LEVELS];
   DevBuf Q2[MGM_MAX_LEVELS];  // second basis: the trial of the adaptive choice of d
   DevBuf Z[MGM_MAX_LEVELS], X[MGM_MAX_LEVELS], C[MGM_MAX_LEVELS];
+  DevBuf ppart[MGM_MAX_LEVELS];  // partial coefficients of the projection
   // per operator level: the merged right-hand sides of one solve and its solutions
   DevBuf lin[MGM_MAX_LEVELS], lout[MGM_MAX_LEVELS];
 };

@@ -784,10 +784,12 @@ struct Estimator {
     cd* Z = g.est.Z[i].as<cd>();
     DevBuf& C = g.est.C[i];
     C.ensure(sizeof(cd) * (size_t)kmax * sl.d);
-    part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
-    launch_dot_multi_ld<double>(s, sl.Q->as<cd>(), n, 0, sl.d, Z, n, k, C.as<cd>(), sl.d, 0, nullptr, part.as<cd>());
-    launch_update_multi<double>(s, sl.Q->as<cd>(), n, 0, sl.d, C.as<cd>(), sl.d, -1.0, Z, n, k, nullptr, nullptr,
-                                nullptr);
+    DevBuf& pp = g.est.ppart[i];
+    pp.ensure(sizeof(cd) * (size_t)proj_partials(n) * sl.d * std::min(kmax, 64));
+    // blocks of at most 64 vectors (the matrix-core tiles of one launch)
+    for (int r0 = 0; r0 < k; r0 += 64)
+      launch_project(s, sl.Q->as<cd>(), sl.d, Z + (int64_t)r0 * n, std::min(64, k - r0), n, C.as<cd>(),
+                     pp.as<cd>());
   }
 
   void sample_batches(std::vector<StochLevel>& lv, const std::vector<int>& b, std::vector<Batch>& out) {
