@@ -153,6 +153,45 @@ def in_step_average(precision, alg_bytes):
         return None
 
 
+def ensemble_run(ctx, cfg, mgkw, args):
+    """Production mode for an ensemble: `--ensemble` gauge fields of the
+    workload (gauge seeds seed, seed + 1, ...), one estimate per field at once
+    through mgm_trace_jobs (each field on its own streams and host thread),
+    `--steps` rounds, same estimator settings as the timed step."""
+    import torch
+    from lattice_inputs import gauge_for, links_from_theta
+    from paper_2303_11512_amd import mg_params, solve_params
+    sp = solve_params(**SOLVE)
+    gids = []
+    for f in range(args.ensemble):
+        c = dict(cfg, gauge_seed=cfg["gauge_seed"] + f)
+        g = ctx.set_gauge(torch.from_numpy(links_from_theta(gauge_for(c))).to("cuda"), cfg["m0"], True)
+        ctx.setup_mg(g, mg_params(**mgkw, precision=args.precision))
+        gids.append(g)
+    ctx.trace_jobs([(g, dict(solve=sp, **trace_kwargs(cfg, 1000 + f))) for f, g in enumerate(gids)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rounds = [ctx.trace_jobs([(g, dict(solve=sp, **trace_kwargs(cfg, k))) for g in gids])
+              for k in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the same estimates one after the other (the first field alone is the
+    # headline's workload)
+    t1 = time.perf_counter()
+    seq = [[ctx.trace_estimate(g, solve=sp, **trace_kwargs(cfg, k)) for g in gids] for k in range(args.steps)]
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t1
+    same = all(a["tau"] == b["tau"] for r, q in zip(rounds, seq) for a, b in zip(r, q))
+    for g in gids:
+        ctx.free_gauge(g)
+    n = args.ensemble * args.steps
+    return {"what": f"{args.ensemble} fields of the workload (gauge seeds {cfg['gauge_seed']}.."
+                    f"{cfg['gauge_seed'] + args.ensemble - 1}), one estimate per field at once (mgm_trace_jobs)",
+            "estimates_per_s": n / dt, "sequential_estimates_per_s": n / dts,
+            "gain_over_sequential": dts / dt, "bitwise_equal_to_sequential": same,
+            "tau_per_field": [[o["tau"].real, o["tau"].imag] for o in rounds[0]]}
+
+
 def plain_fp64_run(ctx, th, cfg, mgkw, steps, ref):
     """Plain FP64 MG-FGMRES on the same GPU and seeds: FP64 preconditioner,
     no captured graphs, one stream, and Alg. 2's stochastic loop one sample
@@ -633,6 +672,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=1000, help="cnn workload: pairs per training field")
     ap.add_argument("--epochs", type=int, default=4, help="cnn workload: training epochs")
     ap.add_argument("--eval-fields", type=int, default=8, help="cnn workload: unseen fields per size")
+    ap.add_argument("--ensemble", type=int, default=3,
+                    help="fields estimated at once in the ensemble comparison (0 or 1: skip)")
     ap.add_argument("--masses", default="-0.10,-0.12,-0.13,-0.14",
                     help="scan128 workload: Wilson masses of the scan")
     args = ap.parse_args()
@@ -732,6 +773,11 @@ def main():
             unbatched = plain_fp64_run(ctx, th, cfg, mgkw, args.plain_steps, outs)
             print(f"# plain FP64 MG-FGMRES, one sample at a time: {unbatched}", file=sys.stderr, flush=True)
 
+    ensemble = None
+    if not args.no_compare and args.ensemble > 1:
+        ensemble = ensemble_run(ctx, cfg, mgkw, args)
+        print(f"# ensemble: {ensemble}", file=sys.stderr, flush=True)
+
     samples = [int(sum(o["level_samples"][l] for o in outs) / len(outs)) for l in range(len(outs[0]["level_samples"]))]
     cpu = None
     if not args.no_cpu:
@@ -766,6 +812,7 @@ def main():
                    "min_samples": MIN_SAMPLES, "cost_model": "flops (Sec. 4)", "estimates": spread,
                    "fp64_preconditioner_same_schedule": plain,
                    "plain_fp64_mg_fgmres": unbatched,
+                   "ensemble_concurrent": ensemble,
                    "solver_levels": mg_setup_kwargs(cfg)["nlevels"],
                    "iters_per_solve": [round(sum(o["iters"][l] for o in outs) / max(1, sum(o["solves"][l] for o in outs)), 2)
                                        for l in range(len(cfg["blocks"]) + 1)],

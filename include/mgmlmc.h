@@ -386,6 +386,18 @@ int mgm_trace_estimate(mgm_ctx *ctx, int gauge_id, const mgm_trace_params *prm,
                        mgm_trace_result *res);
 
 /* ---------------------------------------------------------------------------
+ * trace_jobs -- njobs independent estimates (Alg. 2 each) at once, e.g. one
+ * per gauge field of an ensemble: job j runs on field gauge_ids[j] with
+ * params[j] into results[j] (HOST arrays of njobs entries; the fields must be
+ * distinct).  Each job runs on its field's own streams from a host thread of
+ * its own, so the latency-bound kernels of the estimates overlap on the GPU.
+ * Each result is bit for bit that of a separate mgm_trace_estimate call.
+ * Returns the first failing job's status (its index in mgm_last_error).
+ * ------------------------------------------------------------------------- */
+int mgm_trace_jobs(mgm_ctx *ctx, int njobs, const int *gauge_ids, const mgm_trace_params *params,
+                   mgm_trace_result *results);
+
+/* ---------------------------------------------------------------------------
  * time_kernel -- measurement helper for rooflines: launches one kernel of the
  * path `reps` times back to back on the context stream (inputs: seeded noise
  * vectors allocated by the library) and returns, between two HIP events, the

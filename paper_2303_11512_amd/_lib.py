@@ -149,6 +149,8 @@ SIGNATURES = {
     "mgm_orthonormalize": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
     "mgm_orthonormalize_noalloc": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
     "mgm_trace_estimate": (C.c_int, [_P, C.c_int, C.POINTER(TraceParams), C.POINTER(TraceResult)]),
+    "mgm_trace_jobs": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(TraceParams),
+                                 C.POINTER(TraceResult)]),
     "mgm_time_kernel": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mgm_solve_jobs": (C.c_int, [_P, C.c_int, _P, C.POINTER(SolveParams), C.POINTER(C.c_int)]),
@@ -459,10 +461,13 @@ class Context:
         self._chk(self.lib.mgm_orthonormalize_noalloc(self.h, Y.shape[1], Y.shape[0], _P(_ptr(Y)),
                                                       _P(_ptr(Q))), "orthonormalize_noalloc")
 
-    def trace_estimate(self, gid, variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2,
-                       noise="z2z2", targets="optimal", cost="static", fixed_cost=None, min_samples=2,
-                       max_samples=0, fixed_samples=None, seed=1, batch=64, solve=None,
-                       max_dump=0, concurrent=True, projection="one-sided", d_max=0, pilot=16) -> dict:
+    @staticmethod
+    def _trace_in(variant="mlmcpp", form="reduced", eps=1e-2, d=(), k_power=2, noise="z2z2",
+                  targets="optimal", cost="static", fixed_cost=None, min_samples=2, max_samples=0,
+                  fixed_samples=None, seed=1, batch=64, solve=None, max_dump=0, concurrent=True,
+                  projection="one-sided", d_max=0, pilot=16):
+        """Parameter and result structs of one estimate plus the host buffers
+        they point to (kept alive by the caller until the call returns)."""
         p = TraceParams()
         p.variant = VARIANTS[variant]
         p.form = FORMS[form]
@@ -478,10 +483,10 @@ class Context:
                 p.fixed_cost[i] = v
         p.min_samples = min_samples
         p.max_samples = max_samples
-        fs = None
+        keep = {}
         if fixed_samples is not None:
-            fs = (C.c_int * len(fixed_samples))(*fixed_samples)
-            p.fixed_samples = C.cast(fs, C.POINTER(C.c_int))
+            keep["fs"] = (C.c_int * len(fixed_samples))(*fixed_samples)
+            p.fixed_samples = C.cast(keep["fs"], C.POINTER(C.c_int))
         p.seed = seed
         p.batch = batch
         p.solve = solve or solve_params()
@@ -490,20 +495,21 @@ class Context:
         p.d_max = d_max
         p.pilot = pilot
         r = TraceResult()
-        sig = None
         if variant == "deflated" and len(d) > 0 and d[0] > 0:
-            sig = (C.c_double * d[0])()
-            r.sigma_dump = C.cast(sig, C.POINTER(C.c_double))
-        dump = cdump = idump = None
+            keep["sig"] = (C.c_double * d[0])()
+            r.sigma_dump = C.cast(keep["sig"], C.POINTER(C.c_double))
         if max_dump > 0:
-            dump = (C.c_double * (MAX_LEVELS * max_dump * 2))()
-            cdump = (C.c_double * (MAX_LEVELS * max_dump))()
-            idump = (C.c_int * (MAX_LEVELS * max_dump * 2))()
-            r.sample_dump = C.cast(dump, C.POINTER(C.c_double))
-            r.cost_dump = C.cast(cdump, C.POINTER(C.c_double))
-            r.iter_dump = C.cast(idump, C.POINTER(C.c_int))
+            keep["dump"] = (C.c_double * (MAX_LEVELS * max_dump * 2))()
+            keep["cdump"] = (C.c_double * (MAX_LEVELS * max_dump))()
+            keep["idump"] = (C.c_int * (MAX_LEVELS * max_dump * 2))()
+            r.sample_dump = C.cast(keep["dump"], C.POINTER(C.c_double))
+            r.cost_dump = C.cast(keep["cdump"], C.POINTER(C.c_double))
+            r.iter_dump = C.cast(keep["idump"], C.POINTER(C.c_int))
             r.max_dump = max_dump
-        self._chk(self.lib.mgm_trace_estimate(self.h, gid, C.byref(p), C.byref(r)), "trace_estimate")
+        return p, r, keep
+
+    @staticmethod
+    def _trace_out(r, keep) -> dict:
         ns = r.nstoch
         out = dict(
             tau=complex(r.tau[0], r.tau[1]),
@@ -519,18 +525,36 @@ class Context:
             level_lr_work=[r.lvl_lr_work[i] for i in range(ns)],
             level_work=[r.lvl_work[i] for i in range(ns)],
         )
-        if sig is not None:
+        if "sig" in keep:
             out["defl_ritz"] = complex(r.defl_ritz[0], r.defl_ritz[1])
-            out["sigma"] = np.array(sig[:])
-        if dump is not None:
-            arr = np.frombuffer(dump, dtype=np.float64).reshape(MAX_LEVELS, max_dump, 2)
+            out["sigma"] = np.array(keep["sig"][:])
+        if "dump" in keep:
+            max_dump = r.max_dump
+            arr = np.frombuffer(keep["dump"], dtype=np.float64).reshape(MAX_LEVELS, max_dump, 2)
             out["samples"] = [
                 (arr[i, :min(max_dump, out["level_samples"][i]), 0]
                  + 1j * arr[i, :min(max_dump, out["level_samples"][i]), 1]).copy()
                 for i in range(ns)
             ]
-            carr = np.frombuffer(cdump, dtype=np.float64).reshape(MAX_LEVELS, max_dump)
-            iarr = np.frombuffer(idump, dtype=np.int32).reshape(MAX_LEVELS, max_dump, 2)
+            carr = np.frombuffer(keep["cdump"], dtype=np.float64).reshape(MAX_LEVELS, max_dump)
+            iarr = np.frombuffer(keep["idump"], dtype=np.int32).reshape(MAX_LEVELS, max_dump, 2)
             out["sample_costs"] = [carr[i, :min(max_dump, out["level_samples"][i])].copy() for i in range(ns)]
             out["sample_iters"] = [iarr[i, :min(max_dump, out["level_samples"][i])].copy() for i in range(ns)]
         return out
+
+    def trace_estimate(self, gid, **kw) -> dict:
+        """One MG-MLMC(++) estimate on field gid (keywords: see _trace_in)."""
+        p, r, keep = self._trace_in(**kw)
+        self._chk(self.lib.mgm_trace_estimate(self.h, gid, C.byref(p), C.byref(r)), "trace_estimate")
+        return self._trace_out(r, keep)
+
+    def trace_jobs(self, jobs) -> list:
+        """Independent estimates at once: jobs is a list of (gid, keywords),
+        one distinct field per job; returns one result dict per job."""
+        n = len(jobs)
+        ins = [self._trace_in(**kw) for _, kw in jobs]
+        gids = (C.c_int * max(1, n))(*[g for g, _ in jobs])
+        ps = (TraceParams * max(1, n))(*[p for p, _, _ in ins])
+        rs = (TraceResult * max(1, n))(*[r for _, r, _ in ins])
+        self._chk(self.lib.mgm_trace_jobs(self.h, n, gids, ps, rs), "trace_jobs")
+        return [self._trace_out(rs[j], ins[j][2]) for j in range(n)]

@@ -874,4 +874,57 @@ int mgm_trace_estimate(mgm_ctx* c, int gauge_id, const mgm_trace_params* prm,
   });
 }
 
+int mgm_trace_jobs(mgm_ctx* c, int njobs, const int* gauge_ids, const mgm_trace_params* prm,
+                   mgm_trace_result* res) {
+  return guarded(c, [&] {
+    require(njobs >= 0 && (njobs == 0 || (gauge_ids && prm && res)), "bad arguments");
+    std::vector<Gauge*> gs(njobs);
+    for (int j = 0; j < njobs; ++j) {
+      gs[j] = &gauge_of(c, gauge_ids[j]);
+      for (int q = 0; q < j; ++q) require(gs[q] != gs[j], "trace_jobs: every job needs a field of its own");
+    }
+    for (Gauge* g : gs) {
+      HIPCHK(hipEventRecord(g->ev_in, c->stream));
+      HIPCHK(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+      if (!g->view) g->view = std::make_shared<mgm_ctx>();
+      mgm_ctx& w = *g->view;  // the field's worker context: its stream, its workspaces
+      w.device = c->device;
+      w.stream = g->stream;
+      w.cnn = c->cnn;
+      w.wslot = 0;
+    }
+    std::vector<int> status(njobs, MGM_OK);
+    std::vector<std::string> msg(njobs);
+    std::vector<std::thread> workers;
+    for (int j = 0; j < njobs; ++j) {
+      workers.emplace_back([&, j] {
+        Gauge& g = *gs[j];
+        try {
+          HIPCHK(hipSetDevice(c->device));
+          status[j] = trace_estimate(g.view.get(), g, prm[j], res[j]);
+          HIPCHK(hipStreamSynchronize(g.stream));
+        } catch (const Error& e) {
+          status[j] = e.code;
+          msg[j] = e.what();
+        } catch (const std::exception& e) {
+          status[j] = MGM_EHIP;
+          msg[j] = e.what();
+        }
+      });
+    }
+    for (auto& t : workers) t.join();
+    for (Gauge* g : gs) {
+      HIPCHK(hipEventRecord(g->ev_out, g->stream));
+      HIPCHK(hipStreamWaitEvent(c->stream, g->ev_out, 0));
+    }
+    for (int j = 0; j < njobs; ++j)
+      if (status[j] != MGM_OK) {
+        if (!msg[j].empty()) throw Error(status[j], "job " + std::to_string(j) + ": " + msg[j]);
+        c->err = "job " + std::to_string(j) + " did not reach its target";
+        return status[j];
+      }
+    return MGM_OK;
+  });
+}
+
 }  // extern "C"

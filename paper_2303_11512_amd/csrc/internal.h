@@ -447,6 +447,9 @@ struct Gauge {
   CnnWork cnn;
   EstWork est;
   std::map<GraphKey, GraphEntry> graphs[2];  // per workspace set (one host thread each)
+  // the field's own worker context of mgm_trace_jobs, kept so that its
+  // workspaces (and the graphs that hold their addresses) are reused
+  std::shared_ptr<mgm_ctx> view;
   void clear_graphs() {
     for (auto& m : graphs) {
       for (auto& kv : m)

@@ -1702,10 +1702,9 @@ void launch_noise(hipStream_t s, cx<T>* out, int64_t n, int nrhs, int kind, uint
 template void launch_noise<double>(hipStream_t, cd*, int64_t, int, int, uint64_t, int, int, int64_t);
 template void launch_noise<float>(hipStream_t, cf*, int64_t, int, int, uint64_t, int, int, int64_t);
 
-// Workgroups of k_wilson_strip (128 threads, its LDS rows) the device keeps
-// resident at once, from the runtime's occupancy calculator; per device.
 // Workgroups of k_wilson_strip<T, *, SPT> with `threads` threads the whole
-// device holds at once (per device, cached).
+// device holds at once, from the runtime's occupancy calculator (per device,
+// cached).
 template <class T, int SPT>
 int64_t strip_capacity(int threads) {
   static std::atomic<int64_t> cap[64][5];

@@ -102,3 +102,36 @@ def test_free_gauge_releases_the_field(ctx):
         ctx.free_gauge(gid)
     gid2 = ctx.set_gauge(to_dev(np.exp(1j * th)), -0.05, True)
     assert gid2 != gid and ctx.level_info(gid2, 0)["n"] == 2 * 16 * 16
+
+
+def test_trace_jobs_match_separate_estimates(ctx, fields):
+    """mgm_trace_jobs: one estimate per field at once (different variants,
+    targets and seeds per job) gives, job by job, the bits of separate
+    mgm_trace_estimate calls; the estimates match the oracle's Alg. 2."""
+    from paper_2303_11512_amd import solve_params
+    sp = solve_params(tol=1e-12, restart=24)
+    kws = [dict(variant="mlmcpp", eps=3e-2, d=[4], k_power=1, noise="z2z2", seed=5, batch=16),
+           dict(variant="mlmc", eps=3e-2, noise="rademacher", seed=6, batch=8, targets="uniform"),
+           dict(variant="mlmcpp", eps=3e-2, d=[4, 4], k_power=2, noise="z2z2", seed=7, batch=16,
+                cost="flops")]
+    jobs = [(gid, dict(kw, solve=sp, max_dump=512)) for (_, gid, _), kw in zip(fields, kws)]
+    log("trace_jobs over 3 fields")
+    got = ctx.trace_jobs(jobs)
+    for k, ((rec, gid, hier), (_, kw)) in enumerate(zip(fields, jobs)):
+        alone = ctx.trace_estimate(gid, **kw)
+        assert got[k]["tau"] == alone["tau"], k
+        assert got[k]["level_samples"] == alone["level_samples"], k
+        for a, b in zip(got[k]["samples"], alone["samples"]):
+            assert np.array_equal(a, b), k
+        if kw.get("cost", "static") == "static":
+            want = otr.estimate(hier, otr.TraceParams(**{q: v for q, v in kw.items()
+                                                         if q not in ("solve", "max_dump", "batch")}))
+            assert got[k]["level_samples"] == want["level_samples"], k
+            assert abs(got[k]["tau"] - want["tau"]) < 1e-8 * abs(want["tau"]), k
+
+
+def test_trace_jobs_rejects_a_shared_field(ctx, fields):
+    from paper_2303_11512_amd import MGMError
+    gid = fields[0][1]
+    with pytest.raises(MGMError):
+        ctx.trace_jobs([(gid, dict(eps=1e-1)), (gid, dict(eps=1e-1))])
