@@ -357,6 +357,60 @@ __global__ void __launch_bounds__(NT) k_hcol(int j, int m, int nrhs, const cx<T>
   h[j + 1] = mk<T>(hn[r], 0);
 }
 
+// Hessenberg column j (as k_hcol) followed by the Givens update (as
+// k_givens) in one launch; host_flags (pinned host memory, or null) receives
+// every RHS's active flag after the step, so the host can poll it without a
+// copy.
+template <class T>
+__global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
+                                                    const cx<T>* __restrict__ c2, const T* __restrict__ hn,
+                                                    cx<T>* __restrict__ H, T* __restrict__ cs,
+                                                    cx<T>* __restrict__ sn, cx<T>* __restrict__ g,
+                                                    const T* __restrict__ thr, int* __restrict__ active,
+                                                    int* __restrict__ nit, int* __restrict__ host_flags) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs) return;
+  if (active[r]) {
+    cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
+    for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
+    h[j + 1] = mk<T>(hn[r], 0);
+    T* c = cs + (int64_t)r * m;
+    cx<T>* s = sn + (int64_t)r * m;
+    cx<T>* gr = g + (int64_t)r * (m + 1);
+    for (int i = 0; i < j; ++i) {
+      const cx<T> a = h[i], b = h[i + 1];
+      h[i] = c[i] * a + s[i] * b;
+      h[i + 1] = c[i] * b - conj(s[i]) * a;
+    }
+    const cx<T> a = h[j], b = h[j + 1];
+    const T na = sqrt(abs2(a)), nb = sqrt(abs2(b));
+    const T rho = sqrt(na * na + nb * nb);
+    T cj;
+    cx<T> sj;
+    if (na == (T)0) {
+      cj = 0;
+      sj = mk<T>(1, 0);
+      h[j] = b;
+    } else {
+      cj = na / rho;
+      const cx<T> ph = mk<T>(a.re / na, a.im / na);
+      sj = ph * conj(b);
+      sj = mk<T>(sj.re / rho, sj.im / rho);
+      h[j] = rho * ph;
+    }
+    h[j + 1] = mk<T>(0, 0);
+    c[j] = cj;
+    s[j] = sj;
+    const cx<T> gj = gr[j];
+    gr[j] = cj * gj;
+    gr[j + 1] = (T)-1 * (conj(sj) * gj);
+    nit[r] = j + 1;
+    const T res = sqrt(abs2(gr[j + 1]));
+    if (res <= thr[r] || nb == (T)0 || j + 1 == m) active[r] = 0;
+  }
+  if (host_flags) host_flags[r] = active[r];
+}
+
 // y = R^{-1} g with R the rotated (upper triangular) H of nit[r] steps
 template <class T>
 __global__ void __launch_bounds__(NT) k_backsolve(int m, int nrhs, const cx<T>* __restrict__ H,
@@ -641,6 +695,15 @@ void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>
 }
 
 template <class T>
+void launch_hcol_givens(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
+                        cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr, int* active, int* nit,
+                        int* host_flags) {
+  hipLaunchKernelGGL(k_hcol_givens<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, j, m, nrhs, c1, c2, hn, H,
+                     cs, sn, g, thr, active, nit, host_flags);
+  KCHK();
+}
+
+template <class T>
 void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
                  cx<T>* H, const int* active) {
   hipLaunchKernelGGL(k_hcol<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, j, m, nrhs, c1, c2, hn, H,
@@ -830,6 +893,9 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                 const int*);                                                      \
   template void launch_givens<T>(hipStream_t, int, int, int, cx<T>*, T*, cx<T>*, cx<T>*, const T*, \
                                  int*, int*);                                                     \
+  template void launch_hcol_givens<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,       \
+                                      const T*, cx<T>*, T*, cx<T>*, cx<T>*, const T*, int*, int*,    \
+                                      int*);                                                       \
   template void launch_backsolve<T>(hipStream_t, int, int, const cx<T>*, const cx<T>*, const int*, \
                                     cx<T>*);                                                      \
   template void launch_fgmres_init<T>(hipStream_t, int, const T*, const int*, const int*, T,       \

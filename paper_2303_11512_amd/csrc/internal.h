@@ -287,6 +287,12 @@ void launch_convert(hipStream_t s, const cx<TI>* in, cx<TO>* out, int64_t count)
 template <class T>
 void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g,
                    const T* thr, int* active, int* nit);
+// the Hessenberg column of step j and its Givens update in one launch;
+// host_flags (pinned, or null) receives the active flags after the step
+template <class T>
+void launch_hcol_givens(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
+                        cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr, int* active, int* nit,
+                        int* host_flags);
 template <class T>
 void launch_backsolve(hipStream_t s, int m, int nrhs, const cx<T>* H, const cx<T>* g,
                       const int* nit, cx<T>* y);
@@ -324,13 +330,14 @@ struct LevelData {
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 
-// Pinned host copies of per-RHS flags with kDepth completion events, so the
-// host can read step j's flags while the following steps are already queued.
+// Pinned host slots for per-RHS flags, written by the device, with kDepth
+// completion events, so the host can read step j's flags while the following
+// step is already queued.
 struct PinnedFlags {
-  static constexpr int kDepth = 3;
+  static constexpr int kDepth = 2;
   int* h = nullptr;
   int cap = 0;
-  hipEvent_t ev[kDepth] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[kDepth] = {};
   PinnedFlags() = default;
   PinnedFlags(const PinnedFlags&) = delete;
   PinnedFlags& operator=(const PinnedFlags&) = delete;
@@ -343,6 +350,7 @@ struct PinnedFlags {
     cap = 0;
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(int) * kDepth * (size_t)n, hipHostMallocDefault));
     cap = n;
+    g_alloc_epoch.fetch_add(1);  // captured steps hold the old address
   }
   ~PinnedFlags() {
     if (h) (void)hipHostFree(h);

@@ -146,7 +146,8 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
 // Hessenberg column, v_{j+1} = w/||w||, Givens update.
 template <class T, class PrecFn>
-void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec) {
+void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec,
+                  int* host_flags = nullptr) {
   hipStream_t s = c->stream;
   Level& L = *g.levels[l];
   const int64_t n = L.n;
@@ -165,11 +166,10 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   launch_update_multi<T>(s, V, vs, n, j + 1, c1, m + 1, (T)-1, w, n, nrhs, act, nullptr, nullptr);
   launch_dot_multi_ld<T>(s, V, vs, n, j + 1, w, n, nrhs, c2, m + 1, 0, act, part);
   launch_update_multi<T>(s, V, vs, n, j + 1, c2, m + 1, (T)-1, w, n, nrhs, act, hn, (T*)part);
-  launch_hcol<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), act);
   launch_scale<T>(s, w, hn, n, nrhs, V + (j + 1) * vs, act);
-  launch_givens<T>(s, j, m, nrhs, W.H.template as<cx<T>>(), W.cs.template as<T>(),
-                   W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
-                   W.nit.template as<int>());
+  launch_hcol_givens<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), W.cs.template as<T>(),
+                        W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
+                        W.nit.template as<int>(), host_flags);
 }
 
 // x = m steps of FGMRES from x0 = 0 on D_l x = b (no restart), a RHS stops
@@ -298,9 +298,10 @@ void precondition_graph(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* 
 
 // Outer FGMRES(m) in FP64.  Per RHS: stop on ||b - D x|| <= tol ||b|| (true
 // residual, checked at the end of every cycle).  Inside a cycle the host reads
-// the active flags of step j - 2 while steps j - 1 and j are already queued,
-// and ends the cycle once every RHS has converged (the extra steps are
-// no-ops: every kernel of a step skips inactive RHS).
+// the active flags of step j - 1 (written to pinned memory by that step's last
+// kernel) while step j is already queued, and ends the cycle once every RHS
+// has converged (the extra step is a no-op: every kernel of a step skips
+// inactive RHS).
 int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                 const mgm_solve_params& sp, int* iters_out, double* relres_out) {
   hipStream_t s = c->stream;
@@ -361,14 +362,18 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         const int64_t vs = (int64_t)nrhs * n;
         const GraphKey key{(m + 1) * 1000 + l + (stage ? 500 : 0), nrhs, (const void*)(V + j * vs),
                            (void*)(Z + j * vs), act, g.prm.precision};
-        run_graph(c, g, key, [&] {
-          arnoldi_step<double>(c, g, l, nrhs, j, m, W, [&](const cd* v, cd* z, const int* a) {
-            if (stage) cnn_precondition(c, g, nrhs, v, z, a);
-            else precondition_d(c, g, l, nrhs, v, z, a);
-          });
-        });
+        // the step's last kernel writes the active flags into pinned host
+        // slot j % kDepth (no copy); the event marks the step's end
         const int slot = j % PinnedFlags::kDepth;
-        HIPCHK(hipMemcpyAsync(W.flags.h + slot * nrhs, act, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+        run_graph(c, g, key, [&] {
+          arnoldi_step<double>(
+              c, g, l, nrhs, j, m, W,
+              [&](const cd* v, cd* z, const int* a) {
+                if (stage) cnn_precondition(c, g, nrhs, v, z, a);
+                else precondition_d(c, g, l, nrhs, v, z, a);
+              },
+              W.flags.h + slot * nrhs);
+        });
         HIPCHK(hipEventRecord(W.flags.ev[slot], s));
         if (j + 1 < PinnedFlags::kDepth) continue;
         const int prev = (j + 1) % PinnedFlags::kDepth;  // step j - (kDepth - 1)
