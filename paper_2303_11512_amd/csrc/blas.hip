@@ -231,6 +231,89 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
   }
 }
 
+// k_update_multi with the chunk reduction of the coefficients done in the
+// same launch: coef = sum over chunks of the Gram-Schmidt partials (layout
+// of k_dot_multi), added per coefficient exactly as k_reduce_chunks adds
+// them (lane l takes chunks l, l+64, ..., then the same shuffle tree), so the
+// result carries the same bits; the workgroups of chunk 0 also store the
+// coefficients to coef_out (row r at coef_out + r * ldc).
+template <class T, int EPT>
+__global__ void __launch_bounds__(NT) k_update_multi_r(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
+                                                       int nv, const cx<T>* __restrict__ dpart, int nchd,
+                                                       cx<T>* __restrict__ coef_out, int ldc, T sign,
+                                                       cx<T>* __restrict__ w, int64_t n, T* __restrict__ partial,
+                                                       const int* __restrict__ active) {
+  constexpr int CH = NT * EPT;
+  __shared__ cx<T> cs[64];
+  __shared__ T sh[8];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nv; i += NT / 64) {
+    const cx<T>* p = dpart + ((int64_t)r * nv + i) * nchd;
+    cx<T> acc = mk<T>(0, 0);
+    for (int c = lane; c < nchd; c += 64) acc = acc + p[c];
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) {
+      cs[i] = sign * acc;
+      if (blockIdx.x == 0) coef_out[(int64_t)r * ldc + i] = acc;
+    }
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
+  cx<T> acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    acc[e] = wr[k < n ? k : n - 1];  // past n: computed, never stored
+  }
+  constexpr int G = EPT >= 8 ? 2 : DG;
+  int i = 0;
+  for (; i + G <= nv; i += G) {
+    cx<T> vv[G][EPT];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const cx<T>* __restrict__ vi = Vr + (int64_t)(i + g) * sI;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = base + (int64_t)e * NT;
+        vv[g][e] = vi[k < n ? k : n - 1];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const cx<T> c = cs[i + g];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) cfma(acc[e], vv[g][e], c);
+    }
+  }
+  for (; i < nv; ++i) {
+    const cx<T>* __restrict__ vi = Vr + (int64_t)i * sI;
+    const cx<T> c = cs[i];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t k = base + (int64_t)e * NT;
+      cfma(acc[e], vi[k < n ? k : n - 1], c);
+    }
+  }
+  T nrm = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    if (k < n) {
+      wr[k] = acc[e];
+      nrm += abs2(acc[e]);
+    }
+  }
+  if (partial) {
+    nrm = block_sum_real(nrm, sh);
+    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = nrm;
+  }
+}
+
 template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w, int64_t n,
                                                      T* __restrict__ partial,
@@ -263,6 +346,34 @@ __global__ void __launch_bounds__(NT) k_norm_reduce(const T* __restrict__ partia
   for (int c = lane; c < nch; c += 64) acc += partial[(int64_t)r * nch + c];
   acc = wave_sum(acc);
   if (lane == 0) out[r] = sqrt(acc);
+}
+
+// v = w / ||w|| with ||w|| = sqrt(sum over chunks of the norm partials),
+// added as k_norm_reduce adds them (same bits); the workgroup with
+// blockIdx.x == 0 also stores ||w|| to den_out[r].
+template <class T>
+__global__ void __launch_bounds__(NT) k_scale_r(const cx<T>* __restrict__ w, const T* __restrict__ npart,
+                                                int nch, int64_t n, cx<T>* __restrict__ v,
+                                                T* __restrict__ den_out, const int* __restrict__ active) {
+  __shared__ T dsh;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    T acc = 0;
+    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const T d = sqrt(acc);
+      dsh = d;
+      if (blockIdx.x == 0) den_out[r] = d;
+    }
+  }
+  __syncthreads();
+  const T d = dsh;
+  const T s = (d > 0) ? (T)1 / d : (T)0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT)
+    v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
 }
 
 template <class T>
@@ -359,8 +470,10 @@ __global__ void __launch_bounds__(NT) k_hcol(int j, int m, int nrhs, const cx<T>
 
 // Hessenberg column j (as k_hcol) followed by the Givens update (as
 // k_givens) in one launch; host_flags (pinned host memory, or null) receives
-// every RHS's active flag after the step, so the host can poll it without a
-// copy.
+// every RHS's state after the step, so the host can poll it without a copy:
+// 0 converged (inactive), 2 active with the residual estimate within a factor
+// NEAR of its threshold (the next step will most likely end it), 1 active.
+constexpr double NEAR = 32.0;
 template <class T>
 __global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
                                                     const cx<T>* __restrict__ c2, const T* __restrict__ hn,
@@ -370,6 +483,7 @@ __global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, cons
                                                     int* __restrict__ nit, int* __restrict__ host_flags) {
   const int r = blockIdx.x * NT + threadIdx.x;
   if (r >= nrhs) return;
+  int code = 0;
   if (active[r]) {
     cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
     for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
@@ -407,8 +521,9 @@ __global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, cons
     nit[r] = j + 1;
     const T res = sqrt(abs2(gr[j + 1]));
     if (res <= thr[r] || nb == (T)0 || j + 1 == m) active[r] = 0;
+    code = active[r] ? (res <= (T)NEAR * thr[r] ? 2 : 1) : 0;
   }
-  if (host_flags) host_flags[r] = active[r];
+  if (host_flags) host_flags[r] = code;
 }
 
 // y = R^{-1} g with R the rotated (upper triangular) H of nit[r] steps
@@ -648,6 +763,39 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                        nrhs, norm_out, active);
     KCHK();
   }
+}
+
+template <class T>
+int launch_dot_partial(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w, int64_t n,
+                       int nrhs, const int* active, cx<T>* partial) {
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  if (nv <= 0) return (int)nch;
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_dot_multi<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
+                                       nv, w, n, partial, active));
+  KCHK();
+  return (int)nch;
+}
+
+template <class T>
+void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                           int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                           const int* active, T* norm_partial) {
+  require(nv >= 1 && nv <= 64, "update_multi: 1 to 64 vectors");
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
+                                       nv, dpart, nchd, coef_out, ldc, sign, w, n, norm_partial, active));
+  KCHK();
+}
+
+template <class T>
+void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
+                    const int* active) {
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_scale_r<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, den_out, active);
+  KCHK();
 }
 
 template <class T>
@@ -893,6 +1041,13 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                 const int*);                                                      \
   template void launch_givens<T>(hipStream_t, int, int, int, cx<T>*, T*, cx<T>*, cx<T>*, const T*, \
                                  int*, int*);                                                     \
+  template int launch_dot_partial<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*,  \
+                                     int64_t, int, const int*, cx<T>*);                           \
+  template void launch_update_multi_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
+                                         const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,   \
+                                         const int*, T*);                                        \
+  template void launch_scale_r<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*, T*,    \
+                                  const int*);                                                   \
   template void launch_hcol_givens<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,       \
                                       const T*, cx<T>*, T*, cx<T>*, cx<T>*, const T*, int*, int*,    \
                                       int*);                                                       \

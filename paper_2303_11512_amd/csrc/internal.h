@@ -287,6 +287,22 @@ void launch_convert(hipStream_t s, const cx<TI>* in, cx<TO>* out, int64_t count)
 template <class T>
 void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g,
                    const T* thr, int* active, int* nit);
+// The Gram-Schmidt pieces of an Arnoldi step with the chunk reductions moved
+// into the consumers (bitwise the results of dot_multi + update_multi +
+// norm + scale): the dot partials alone (returns their chunk count); the
+// update w += sign V coef that reduces the partials itself (coefficients also
+// to coef_out, optional norm partials of the new w); v = w / ||w|| that
+// reduces the norm partials itself (||w|| also to den_out).
+template <class T>
+int launch_dot_partial(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w, int64_t n,
+                       int nrhs, const int* active, cx<T>* partial);
+template <class T>
+void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                           int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                           const int* active, T* norm_partial);
+template <class T>
+void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
+                    const int* active);
 // the Hessenberg column of step j and its Givens update in one launch;
 // host_flags (pinned, or null) receives the active flags after the step
 template <class T>
@@ -363,7 +379,7 @@ template <class T>
 struct Work {  // FGMRES + multigrid workspace of one level in one precision
   int cap = 0, mcap = 0;
   int64_t n = 0;
-  DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, coef, coef2;
+  DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, npart, coef, coef2;
   DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
   DevBuf rho;                        // inv_B r_B of the premultiplied SAP
   PinnedFlags flags;                 // active flags read back during FGMRES

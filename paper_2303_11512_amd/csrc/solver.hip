@@ -55,6 +55,7 @@ void ensure_work(Level& L, int slot, int nrhs, int m) {
   W.act.ensure(sizeof(int) * 2 * nrhs);  // active flags, then "done" flags
   W.nit.ensure(sizeof(int) * nrhs);
   W.part.ensure(c * (size_t)nrhs * (m + 1) * reduce_chunks(n));
+  W.npart.ensure(sizeof(T) * (size_t)nrhs * reduce_chunks(n));
   W.coef.ensure(c * (size_t)nrhs * (m + 1));
   W.coef2.ensure(c * (size_t)nrhs * (m + 1));
 }
@@ -160,13 +161,15 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   cx<T>* c1 = W.coef.template as<cx<T>>();
   cx<T>* c2 = W.coef2.template as<cx<T>>();
   T* hn = W.beta.template as<T>() ;  // beta is free after the cycle start: reuse for ||w||
+  T* np = W.npart.template as<T>();
   prec(V + j * vs, Z + j * vs, (const int*)act);
   apply_op<T>(c, g, l, nrhs, Z + j * vs, w, nullptr, act);
-  launch_dot_multi_ld<T>(s, V, vs, n, j + 1, w, n, nrhs, c1, m + 1, 0, act, part);
-  launch_update_multi<T>(s, V, vs, n, j + 1, c1, m + 1, (T)-1, w, n, nrhs, act, nullptr, nullptr);
-  launch_dot_multi_ld<T>(s, V, vs, n, j + 1, w, n, nrhs, c2, m + 1, 0, act, part);
-  launch_update_multi<T>(s, V, vs, n, j + 1, c2, m + 1, (T)-1, w, n, nrhs, act, hn, (T*)part);
-  launch_scale<T>(s, w, hn, n, nrhs, V + (j + 1) * vs, act);
+  // CGS2; each reduction over chunks is done by the kernel that consumes it
+  const int nch = launch_dot_partial<T>(s, V, vs, n, j + 1, w, n, nrhs, act, part);
+  launch_update_multi_r<T>(s, V, vs, n, j + 1, part, nch, c1, m + 1, (T)-1, w, n, nrhs, act, nullptr);
+  launch_dot_partial<T>(s, V, vs, n, j + 1, w, n, nrhs, act, part);
+  launch_update_multi_r<T>(s, V, vs, n, j + 1, part, nch, c2, m + 1, (T)-1, w, n, nrhs, act, np);
+  launch_scale_r<T>(s, w, np, n, nrhs, V + (j + 1) * vs, hn, act);
   launch_hcol_givens<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), W.cs.template as<T>(),
                         W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
                         W.nit.template as<int>(), host_flags);
@@ -380,6 +383,13 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         HIPCHK(hipEventSynchronize(W.flags.ev[prev]));
         const int* f = W.flags.h + prev * nrhs;
         if (std::all_of(f, f + nrhs, [](int a) { return a == 0; })) break;
+        // every RHS still running is within reach of its threshold: wait for
+        // step j itself rather than queue a step that would likely be a no-op
+        if (std::all_of(f, f + nrhs, [](int a) { return a != 1; })) {
+          HIPCHK(hipEventSynchronize(W.flags.ev[slot]));
+          const int* fj = W.flags.h + slot * nrhs;
+          if (std::all_of(fj, fj + nrhs, [](int a) { return a == 0; })) break;
+        }
       }
       launch_backsolve<double>(s, m, nrhs, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(), W.y.as<cd>());
       launch_update_multi<double>(s, Z, (int64_t)nrhs * n, n, m, W.y.as<cd>(), m, 1.0, x, n, nrhs,
