@@ -29,8 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # and the SAP blocks below the fine level (2x1 sites on the first coarse level,
 # single sites deeper): a sweep on the 128^2 workload (fine-level solves
 # concurrent with the coarse-level ones) puts the minimum of time per
-# estimate at 4 / 8 / 3
-SAP_CYCLES = (4, 8, 3, 3, 3, 3)
+# estimate at 4 / 10 / 3 (10 cycles on the first coarse level bring its
+# solves from 6 to 5 iterations; 8: 6 iterations, 12: no further gain)
+SAP_CYCLES = (4, 10, 3, 3, 3, 3)
 COARSE_SAP_BLOCKS = [(2, 1), (1, 1), (1, 1), (1, 1), (1, 1)]
 
 
