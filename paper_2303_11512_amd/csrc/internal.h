@@ -228,9 +228,11 @@ void launch_sap_extract(hipStream_t s, const cd* B, int Nx, int Nt, int M, int s
                         cd* blocks_out);
 void launch_small_inverse(hipStream_t s, cd* mats, int K, int count, int* fail);
 template <class T>
+// x64 (or null, 4x4-site blocks of 2 dofs only): also store the swept
+// blocks' new values widened to FP64 there
 void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, int Nt, int M,
                       int sbx, int sbt, const int* blist, int nb, int nrhs, const cx<T>* r,
-                      cx<T>* x, const int* active);
+                      cx<T>* x, const int* active, cd* x64 = nullptr);
 void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M, cd* A);
 // FP16-block variants for coarse levels with 16 dofs per site (FP32 vectors,
 // FP16 matrix-core products, FP32 accumulation)

@@ -1171,11 +1171,13 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
 // old x_B is not read.  One workgroup per block and 64 RHS (a wave per 16):
 // the halo term on the vector units, the 32 x 32 solve as two 16-row tiles
 // of complex MFMAs over 8 K-chunks.
+// x64 (or null): the block's new values are also stored widened to FP64
+// there (the last sweeps of an FP32 cycle write its FP64 result directly).
 template <class T>
 __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
                                                   int Nx, int Nt, const int* __restrict__ blist, int nrhs,
                                                   const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
-                                                  const int* __restrict__ active) {
+                                                  const int* __restrict__ active, cd* __restrict__ x64) {
   constexpr int SB = 4, NS = SB * SB, K = 2 * NS;
   __shared__ cx<T> Is[K * K];
   __shared__ cx<T> Bs[NS * 5 * 4];
@@ -1262,7 +1264,11 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   for (int p = 0; p < 8; ++p) {
     const int ri = 2 * p + (lane >> 5);
     const int r = r0 + ri;
-    if (r < nrhs && !(active && !active[r])) x[(int64_t)r * n + (int64_t)own * 2 + a] = Hs[wave][ri][k];
+    if (r < nrhs && !(active && !active[r])) {
+      const cx<T> v = Hs[wave][ri][k];
+      x[(int64_t)r * n + (int64_t)own * 2 + a] = v;
+      if (x64) x64[(int64_t)r * n + (int64_t)own * 2 + a] = mk((double)v.re, (double)v.im);
+    }
   }
 }
 
@@ -1912,8 +1918,9 @@ void launch_small_inverse(hipStream_t s, cd* mats, int K, int count, int* fail) 
 template <class T>
 void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, int Nt, int M,
                       int sbx, int sbt, const int* blist, int nb, int nrhs, const cx<T>* r,
-                      cx<T>* x, const int* active) {
+                      cx<T>* x, const int* active, cd* x64) {
   if (nb <= 0) return;
+  require(!x64 || (M == 2 && sbx == 4 && sbt == 4), "SAP: an FP64 copy of the result only with 4x4 blocks");
   const int K = sbx * sbt * M;
   require(K <= 32, "SAP block too large");
   if (M == CM && sbx == 1 && sbt == 1) {
@@ -1930,7 +1937,7 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   }
   if (M == 2 && sbx == 4 && sbt == 4) {
     hipLaunchKernelGGL(k_sap0_mfma<T>, dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
-                       nrhs, r, x, active);
+                       nrhs, r, x, active, x64);
     KCHK();
     return;
   }
@@ -1946,9 +1953,9 @@ void launch_sap_sweep(hipStream_t s, const cx<T>* B, const cx<T>* inv, int Nx, i
   KCHK();
 }
 template void launch_sap_sweep<double>(hipStream_t, const cd*, const cd*, int, int, int, int, int,
-                                       const int*, int, int, const cd*, cd*, const int*);
+                                       const int*, int, int, const cd*, cd*, const int*, cd*);
 template void launch_sap_sweep<float>(hipStream_t, const cf*, const cf*, int, int, int, int, int,
-                                      const int*, int, int, const cf*, cf*, const int*);
+                                      const int*, int, int, const cf*, cf*, const int*, cd*);
 
 void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M, cd* A) {
   const int64_t n = (int64_t)Nx * Nt * M;

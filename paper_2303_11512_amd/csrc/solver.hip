@@ -88,7 +88,8 @@ void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* 
 // M_l r -> x.  Coarsest: x = D^{-1} r.  Else x = P_l C_{l+1}(P_l^H r) (or 0
 // while the hierarchy below l is not built), then SAP cycles on D x = r.
 template <class T>
-void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, const int* act) {
+void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, const int* act,
+             cd* x64 = nullptr) {
   hipStream_t s = c->stream;
   Level& L = *g.levels[l];
   LevelData<T>& D = ldata<T>(L);
@@ -139,9 +140,19 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
           continue;
         }
       }
+      // the last cycle's two colours leave every block final: they also
+      // store the FP64 result when the caller asked for it
       launch_sap_sweep<T>(s, D.B(), D.sapinv.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
-                          L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
+                          L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act,
+                          cyc + 1 == L.sap_cycles ? x64 : nullptr);
     }
+}
+
+// whether precond<float> on level l can hand its result over in FP64 itself
+// (last SAP cycle on 4x4-site blocks of 2 dofs)
+bool precond_writes_fp64(const Gauge& g, const Level& L) {
+  return L.M == 2 && L.sbx == 4 && L.sbt == 4 && L.sap_cycles > 0 && !L.is_coarsest &&
+         !(half_blocks(g, L) && L.sbt == 1);
 }
 
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
@@ -222,8 +233,12 @@ void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, c
     W.cvt_in.ensure(sizeof(cf) * cnt);
     W.cvt_out.ensure(sizeof(cf) * cnt);
     launch_convert<float, double>(c->stream, r, W.cvt_in.as<cf>(), cnt);
-    precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act);
-    launch_convert<double, float>(c->stream, W.cvt_out.as<cf>(), x, cnt);
+    if (precond_writes_fp64(g, L)) {
+      precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act, x);
+    } else {
+      precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act);
+      launch_convert<double, float>(c->stream, W.cvt_out.as<cf>(), x, cnt);
+    }
   } else {
     precond<double>(c, g, l, nrhs, r, x, act);
   }

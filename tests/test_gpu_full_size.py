@@ -73,6 +73,26 @@ def test_full_size_solves_meet_tolerance_with_oracle_operator(full128):
     assert d < 1e-6
 
 
+
+def test_fp16_cycle_sees_unit_vectors_whatever_the_rhs_scale(full128):
+    """Range of the FP16 path: the outer FGMRES hands the low-precision cycle
+    its Arnoldi vectors, which have unit norm whatever the scale of b, so the
+    FP16 operands never see the right-hand side's magnitude.  With b scaled
+    by 2^-480 and 2^+480 (far outside the FP16 and FP32 ranges; squares
+    still within FP64, so ||b|| scales exactly) the
+    solutions are exactly the scaled unscaled solution, bit for bit."""
+    ctx, gid, D = full128
+    b = rhs_vectors(D.shape[0], 8, 129)
+    x0, its0, _ = _solve(ctx, gid, b)
+    for e in (-480, 480):
+        a = 2.0 ** e
+        log(f"schwinger128 fp16: b scaled by 2^{e}")
+        x, its, rel = _solve(ctx, gid, b * a)
+        assert np.array_equal(its, its0)
+        assert np.all(rel <= TOL)
+        assert np.array_equal(x, x0 * a), e
+
+
 @pytest.fixture(scope="module")
 def full512():
     from paper_2303_11512_amd import Context, mg_params
