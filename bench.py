@@ -357,6 +357,13 @@ def run_batch8(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rate = total * args.steps / dt
+    # roofline: the fine-level kernels of the largest field at its RHS count
+    # (HIP events on the library stream, back to back)
+    big = max(range(len(jobs)), key=lambda k: jobs[k][2].shape[0] * jobs[k][2].shape[1])
+    gid_b, nrhs_b = jobs[big][0], jobs[big][2].shape[0]
+    kern = {k: ctx.time_kernel(gid_b, k, 0, nrhs_b) for k in ("stencil", "sap", "copy")}
+    st = kern["stencil"]
+    st_gbs = st["bytes"] / (st["us"] * 1e-6) / 1e9
     print(json.dumps({
         "metric": "RHS solves/s (tol 1e-10)", "value": rate, "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": dt / args.steps * 1e3,
@@ -366,6 +373,13 @@ def run_batch8(args):
                                + ", ".join(str(t) for t in BATCH8) + "; MG 4x4 then 2x2, 8 vectors",
                    "per_field_loop_solves_per_s": loop_rate, "speedup_vs_loop": rate / loop_rate,
                    "rhs_blocks": widths, "mean_iters": float(np.mean(its)), "setup_s": setup_s},
+        "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": st_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"fine stencil, FP64, field {big} ({nrhs_b} RHS)", "launch_us": st["us"],
+                     "alg_bytes": st["bytes"],
+                     "others": {k: {"us": round(v["us"], 2), "GB/s": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1)}
+                                for k, v in kern.items()}},
+        "cpu_baseline": None,
     }))
     ctx.close()
 
