@@ -446,6 +446,8 @@ struct EstWork {
   DevBuf Q2[MGM_MAX_LEVELS];  // second basis: the trial of the adaptive choice of d
   DevBuf Z[MGM_MAX_LEVELS], X[MGM_MAX_LEVELS], C[MGM_MAX_LEVELS];
   DevBuf ppart[MGM_MAX_LEVELS];  // partial coefficients of the projection
+  // per-difference CholQR workspaces (the differences' QRs run concurrently)
+  DevBuf qtmp[MGM_MAX_LEVELS], qG[MGM_MAX_LEVELS], qpart[MGM_MAX_LEVELS], qfail[MGM_MAX_LEVELS];
   // per operator level: the merged right-hand sides of one solve and its solutions
   DevBuf lin[MGM_MAX_LEVELS], lout[MGM_MAX_LEVELS];
 };
@@ -522,6 +524,10 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p);
 void orthonormalize(mgm_ctx* c, int64_t n, int d, const cd* Y, cd* Q);
 void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
                        int* fail);
+// the same passes without the read-back: *fail (device) is set when the
+// Gram matrix is not positive definite
+void orthonormalize_launch(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
+                           int* fail);
 int trace_estimate(mgm_ctx* c, Gauge& g, const mgm_trace_params& p, mgm_trace_result& r);
 // learned initial guess (cnn.hip)
 void cnn_check_lattice(const Gauge& g);

@@ -456,8 +456,8 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
 // product of the three triangular factors has a positive diagonal, so Q is
 // the unique thin-QR factor with positive real diag(R).  Workspace: tmp
 // [d][n], G [d][d], part [gram_partials(n)][d][d], fail (one int).
-void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
-                       int* fail) {
+void orthonormalize_launch(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
+                           int* fail) {
   require(d >= 1 && d <= 64 && n >= d, "orthonormalize: need 1 <= d <= 64 and n >= d");
   require(Y != Q, "orthonormalize: Y and Q must not overlap");
   launch_fill_int(s, fail, 1, 0);
@@ -472,6 +472,11 @@ void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* 
     launch_cholesky_rinv(s, G, d, shifts[pass], fail);
     launch_right_tri(s, src, G, n, d, dst);
   }
+}
+
+void orthonormalize_ws(hipStream_t s, int64_t n, int d, const cd* Y, cd* Q, cd* tmp, cd* G, cd* part,
+                       int* fail) {
+  orthonormalize_launch(s, n, d, Y, Q, tmp, G, part, fail);
   int hfail = 0;
   HIPCHK(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -331,11 +331,7 @@ struct Estimator {
     if (todo.size() < 2 || !p.concurrent) {
       for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt, lits[j]);
     } else {
-      if (!g.stream2) {
-        HIPCHK(hipStreamCreateWithFlags(&g.stream2, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
-      }
+      ensure_stream2();
       HIPCHK(hipEventRecord(g.ev_fork, c->stream));
       HIPCHK(hipStreamWaitEvent(g.stream2, g.ev_fork, 0));
       int wst = MGM_OK;
@@ -394,6 +390,75 @@ struct Estimator {
     for (int r = 0; r < k; ++r) out[r] = zc(h[r].re, h[r].im);
   }
 
+  // Several blocks of x_r^H y_r with one read-back: dots_add launches one
+  // block's dots into its own slice of `dots` (sized for the largest batch up
+  // front in run(), so no slice moves while launches are queued) and returns
+  // the slice index; dots_fetch copies every slice with one synchronisation.
+  std::vector<std::array<int, 2>> dslices;
+  int dtot = 0;
+  int dots_add(const cd* x, const cd* y, int64_t n, int k) {
+    require((size_t)(dtot + k) * sizeof(cd) <= dots.bytes, "trace: dot batch exceeds its workspace");
+    part.ensure(sizeof(cd) * (size_t)k * reduce_chunks(n) * 64);
+    launch_dot_multi_ld<double>(c->stream, x, 0, n, 1, y, n, k, dots.as<cd>() + dtot, 1, 0, nullptr,
+                                part.as<cd>());
+    dslices.push_back({dtot, k});
+    dtot += k;
+    return (int)dslices.size() - 1;
+  }
+  std::vector<std::vector<zc>> dots_fetch() {
+    std::vector<cd> h(std::max(1, dtot));
+    if (dtot > 0) HIPCHK(hipMemcpyAsync(h.data(), dots.p, sizeof(cd) * dtot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<std::vector<zc>> out;
+    for (const auto& sl : dslices) {
+      std::vector<zc> v(sl[1]);
+      for (int r = 0; r < sl[1]; ++r) v[r] = zc(h[sl[0] + r].re, h[sl[0] + r].im);
+      out.push_back(std::move(v));
+    }
+    dslices.clear();
+    dtot = 0;
+    return out;
+  }
+
+  // The field's second stream and its fork / join events (created on first use)
+  void ensure_stream2() {
+    if (g.stream2) return;
+    HIPCHK(hipStreamCreateWithFlags(&g.stream2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
+  }
+
+  // Q = qr+(Y) of every item's block: the differences' QRs are independent,
+  // so they run two at a time (the field's stream and its second stream, each
+  // difference with a workspace of its own), and one read-back checks every
+  // failure flag
+  void orthonormalize_items(const std::vector<StochLevel>& lv, const std::vector<Item>& items,
+                            const std::vector<cd*>& dst) {
+    ensure_stream2();
+    HIPCHK(hipEventRecord(g.ev_fork, c->stream));
+    HIPCHK(hipStreamWaitEvent(g.stream2, g.ev_fork, 0));
+    for (size_t q = 0; q < items.size(); ++q) {
+      const Item& x = items[q];
+      const int64_t n = lv[x.i].n;
+      const int d = x.k;
+      EstWork& E = g.est;
+      E.qtmp[x.i].ensure(sizeof(cd) * (size_t)d * n);
+      E.qG[x.i].ensure(sizeof(cd) * (size_t)d * d);
+      E.qpart[x.i].ensure(sizeof(cd) * (size_t)d * d * gram_partials(n));
+      E.qfail[x.i].ensure(sizeof(int));
+      orthonormalize_launch(q % 2 ? g.stream2 : c->stream, n, d, x.Y, dst[q], E.qtmp[x.i].as<cd>(),
+                            E.qG[x.i].as<cd>(), E.qpart[x.i].as<cd>(), E.qfail[x.i].as<int>());
+    }
+    HIPCHK(hipEventRecord(g.ev_join, g.stream2));
+    HIPCHK(hipStreamWaitEvent(c->stream, g.ev_join, 0));
+    std::vector<int> hf(items.size(), 0);
+    for (size_t q = 0; q < items.size(); ++q)
+      HIPCHK(hipMemcpyAsync(&hf[q], g.est.qfail[items[q].i].p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int f : hf)
+      if (f) throw Error(MGM_ENONFINITE, "CholQR: Gram matrix not positive definite (rank-deficient block)");
+  }
+
   // Hutch++ low-rank parts of all differences (d_i > 0), sweep by sweep:
   // k sweeps of Y = A S, Q = qr(Y), S = Q; then tau_lr = sum_i q_i^H A q_i.
   // The solves of the last round (A Q) go together with those of the first
@@ -429,10 +494,10 @@ struct Estimator {
     for (int it = 0; it < std::max(1, p.k_power); ++it) {
       applyA_levels(lv, items, its);
       add_lr_cost(lv, items, its, items.size());
-      for (Item& x : items) {
-        orthonormalize(c, lv[x.i].n, x.k, x.Y, lv[x.i].Q->as<cd>());
-        x.X = lv[x.i].Q->as<cd>();
-      }
+      std::vector<cd*> dst;
+      for (const Item& x : items) dst.push_back(lv[x.i].Q->as<cd>());
+      orthonormalize_items(lv, items, dst);
+      for (Item& x : items) x.X = lv[x.i].Q->as<cd>();
     }
     }
     const size_t nlr = items.size();
@@ -441,19 +506,23 @@ struct Estimator {
     if (!two_sided) sample_start(lv, first, items);
     applyA_levels(lv, items, its);
     add_lr_cost(lv, items, its, nlr);
+    // tau_lr of every difference and the first samples' dots: one read-back
+    std::vector<int> lr_req(nlr);
+    for (size_t q = 0; q < nlr; ++q) lr_req[q] = dots_add(items[q].X, items[q].Y, lv[items[q].i].n, items[q].k);
+    const std::vector<Item> sitems(items.begin() + nlr, items.end());
+    const std::vector<Its> sits(its.begin() + nlr, its.end());
+    std::vector<int> s_req;
+    if (!two_sided) s_req = sample_finish_launch(lv, sitems);
+    const std::vector<std::vector<zc>> got = dots_fetch();
     for (size_t q = 0; q < nlr; ++q) {
-      const Item& x = items[q];
-      std::vector<zc> v;
-      dots_host(x.X, x.Y, lv[x.i].n, x.k, v);
       zc acc = 0;
-      for (const zc& y : v) acc += y;
-      lv[x.i].tau_lr = acc;
+      for (const zc& y : got[lr_req[q]]) acc += y;
+      lv[items[q].i].tau_lr = acc;
     }
     if (two_sided) {
       sample_batches(lv, first, first_vals);
     } else {
-      sample_finish(lv, std::vector<Item>(items.begin() + nlr, items.end()),
-                    std::vector<Its>(its.begin() + nlr, its.end()), first_vals);
+      sample_finish_collect(lv, sitems, sits, got, s_req, first_vals);
     }
     if (deflated) ritz_triplets(lv[0]);
   }
@@ -762,17 +831,30 @@ struct Estimator {
   // sample_start made (X = zeta, Y = A zeta)
   void sample_finish(std::vector<StochLevel>& lv, const std::vector<Item>& items, const std::vector<Its>& its,
                      std::vector<Batch>& out) {
+    const std::vector<int> req = sample_finish_launch(lv, items);
+    sample_finish_collect(lv, items, its, dots_fetch(), req, out);
+  }
+  // the projections and the dots of the blocks (slice indices of dots_add)
+  std::vector<int> sample_finish_launch(std::vector<StochLevel>& lv, const std::vector<Item>& items) {
+    std::vector<int> req;
+    for (const Item& it : items) {
+      StochLevel& sl = lv[it.i];
+      if (!two_sided) project(sl, it.i, it.k);  // (two-sided: done before the solve)
+      req.push_back(dots_add(g.est.Z[it.i].as<cd>(), it.Y, sl.n, it.k));
+    }
+    return req;
+  }
+  void sample_finish_collect(std::vector<StochLevel>& lv, const std::vector<Item>& items,
+                             const std::vector<Its>& its, const std::vector<std::vector<zc>>& got,
+                             const std::vector<int>& req, std::vector<Batch>& out) {
     for (size_t q = 0; q < items.size(); ++q) {
       const Item& it = items[q];
       StochLevel& sl = lv[it.i];
-      const int64_t n = sl.n;
-      cd* Z = g.est.Z[it.i].as<cd>();
-      if (!two_sided) project(sl, it.i, it.k);  // (two-sided: done before the solve)
       Batch& bt = out[it.i];
-      dots_host(Z, it.Y, n, it.k, bt.vals);
+      bt.vals = got[req[q]];
       bt.its = its[q];
       bt.cost.resize(it.k);
-      for (int v = 0; v < it.k; ++v) bt.cost[v] = apply_cost(sl.level, its[q][v]) + 2.0 * (double)n * sl.d;
+      for (int v = 0; v < it.k; ++v) bt.cost[v] = apply_cost(sl.level, its[q][v]) + 2.0 * (double)sl.n * sl.d;
     }
   }
 
@@ -887,6 +969,8 @@ struct Estimator {
     if (adaptive) kmax = std::max(kmax, std::max(p.d_max, p.pilot));
     // every reduction workspace at its largest size up front (no reallocation later)
     part.ensure(sizeof(cd) * (size_t)kmax * 64 * reduce_chunks(g.levels[0]->n) + 64);
+    // one dot batch holds at most two blocks per difference (tau_lr and samples)
+    dots.ensure(sizeof(cd) * (size_t)2 * nst * kmax);
     const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
     zc tau = 0;
     int s = 0;
