@@ -237,12 +237,18 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
 // them (lane l takes chunks l, l+64, ..., then the same shuffle tree), so the
 // result carries the same bits; the workgroups of chunk 0 also store the
 // coefficients to coef_out (row r at coef_out + r * ldc).
-template <class T, int EPT>
+// DOT: the workgroup then forms the next Gram-Schmidt pass's partials of its
+// chunk, V_i^H w_new, into dpart2 (layout and arithmetic of k_dot_multi on
+// the stored w, so the same bits), while the chunk of V it just read is
+// still in cache.  dpart2 must not overlap dpart (other workgroups are still
+// reducing dpart).
+template <class T, int EPT, bool DOT>
 __global__ void __launch_bounds__(NT) k_update_multi_r(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                        int nv, const cx<T>* __restrict__ dpart, int nchd,
                                                        cx<T>* __restrict__ coef_out, int ldc, T sign,
                                                        cx<T>* __restrict__ w, int64_t n, T* __restrict__ partial,
-                                                       const int* __restrict__ active) {
+                                                       const int* __restrict__ active,
+                                                       cx<T>* __restrict__ dpart2) {
   constexpr int CH = NT * EPT;
   __shared__ cx<T> cs[64];
   __shared__ T sh[8];
@@ -311,6 +317,49 @@ __global__ void __launch_bounds__(NT) k_update_multi_r(const cx<T>* __restrict__
   if (partial) {
     nrm = block_sum_real(nrm, sh);
     if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = nrm;
+  }
+  if constexpr (DOT) {
+    __shared__ cx<T> shd[4][64];
+    cx<T> wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) wv[e] = base + (int64_t)e * NT < n ? acc[e] : mk<T>(0, 0);
+    int j = 0;
+    for (; j + DG <= nv; j += DG) {
+      cx<T> d[DG];
+#pragma unroll
+      for (int g = 0; g < DG; ++g) {
+        const cx<T>* __restrict__ vi = Vr + (int64_t)(j + g) * sI;
+        d[g] = mk<T>(0, 0);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int64_t k = base + (int64_t)e * NT;
+          cjfma(d[g], vi[k < n ? k : n - 1], wv[e]);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < DG; ++g) {
+        d[g].re = wave_sum(d[g].re);
+        d[g].im = wave_sum(d[g].im);
+        if (lane == 0) shd[wave][j + g] = d[g];
+      }
+    }
+    for (; j < nv; ++j) {
+      const cx<T>* __restrict__ vi = Vr + (int64_t)j * sI;
+      cx<T> d = mk<T>(0, 0);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = base + (int64_t)e * NT;
+        cjfma(d, vi[k < n ? k : n - 1], wv[e]);
+      }
+      d.re = wave_sum(d.re);
+      d.im = wave_sum(d.im);
+      if (lane == 0) shd[wave][j] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+      const int t = threadIdx.x;
+      dpart2[((int64_t)r * nv + t) * gridDim.x + blockIdx.x] = (shd[0][t] + shd[1][t]) + (shd[2][t] + shd[3][t]);
+    }
   }
 }
 
@@ -784,8 +833,25 @@ void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR
   require(nv >= 1 && nv <= 64, "update_multi: 1 to 64 vectors");
   const int ept = pick_ept(n, nrhs);
   const unsigned nch = nchunks(n, ept);
-  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
-                                       nv, dpart, nchd, coef_out, ldc, sign, w, n, norm_partial, active));
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E, false>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI,
+                                       sR, nv, dpart, nchd, coef_out, ldc, sign, w, n, norm_partial, active,
+                                       (cx<T>*)nullptr));
+  KCHK();
+}
+
+template <class T>
+void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                         int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                         const int* active, cx<T>* dpart2) {
+  require(nv >= 1 && nv <= 64, "update_multi: 1 to 64 vectors");
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  require((int)nch == nchd, "update_dot: chunking differs from the dot partials'");
+  require(dpart2 + (int64_t)nrhs * nv * nch <= dpart || dpart2 >= dpart + (int64_t)nrhs * nv * nch,
+          "update_dot: the two partial buffers overlap");
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E, true>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI,
+                                       sR, nv, dpart, nchd, coef_out, ldc, sign, w, n, (T*)nullptr, active,
+                                       dpart2));
   KCHK();
 }
 
@@ -1046,6 +1112,9 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
   template void launch_update_multi_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
                                          const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,   \
                                          const int*, T*);                                        \
+  template void launch_update_dot_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,            \
+                                       const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,     \
+                                       const int*, cx<T>*);                                        \
   template void launch_scale_r<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*, T*,    \
                                   const int*);                                                   \
   template void launch_hcol_givens<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,       \

@@ -302,6 +302,13 @@ template <class T>
 void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                            int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                            const int* active, T* norm_partial);
+// launch_update_multi_r (no norm) whose workgroups then form the partials of
+// V_i^H w for the updated w (layout of launch_dot_partial) into dpart2, which
+// must not overlap dpart
+template <class T>
+void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                         int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
+                         const int* active, cx<T>* dpart2);
 template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
                     const int* active);

@@ -54,7 +54,7 @@ void ensure_work(Level& L, int slot, int nrhs, int m) {
   W.bnorm.ensure(sizeof(T) * nrhs);
   W.act.ensure(sizeof(int) * 2 * nrhs);  // active flags, then "done" flags
   W.nit.ensure(sizeof(int) * nrhs);
-  W.part.ensure(c * (size_t)nrhs * (m + 1) * reduce_chunks(n));
+  W.part.ensure(2 * c * (size_t)nrhs * (m + 1) * reduce_chunks(n));  // two Gram-Schmidt passes' partials
   W.npart.ensure(sizeof(T) * (size_t)nrhs * reduce_chunks(n));
   W.coef.ensure(c * (size_t)nrhs * (m + 1));
   W.coef2.ensure(c * (size_t)nrhs * (m + 1));
@@ -175,11 +175,12 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   T* np = W.npart.template as<T>();
   prec(V + j * vs, Z + j * vs, (const int*)act);
   apply_op<T>(c, g, l, nrhs, Z + j * vs, w, nullptr, act);
-  // CGS2; each reduction over chunks is done by the kernel that consumes it
+  // CGS2; each reduction over chunks is done by the kernel that consumes it,
+  // and the first pass's update forms the second pass's partials
   const int nch = launch_dot_partial<T>(s, V, vs, n, j + 1, w, n, nrhs, act, part);
-  launch_update_multi_r<T>(s, V, vs, n, j + 1, part, nch, c1, m + 1, (T)-1, w, n, nrhs, act, nullptr);
-  launch_dot_partial<T>(s, V, vs, n, j + 1, w, n, nrhs, act, part);
-  launch_update_multi_r<T>(s, V, vs, n, j + 1, part, nch, c2, m + 1, (T)-1, w, n, nrhs, act, np);
+  cx<T>* part2 = part + (size_t)nrhs * (j + 1) * nch;
+  launch_update_dot_r<T>(s, V, vs, n, j + 1, part, nch, c1, m + 1, (T)-1, w, n, nrhs, act, part2);
+  launch_update_multi_r<T>(s, V, vs, n, j + 1, part2, nch, c2, m + 1, (T)-1, w, n, nrhs, act, np);
   launch_scale_r<T>(s, w, np, n, nrhs, V + (j + 1) * vs, hn, act);
   launch_hcol_givens<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), W.cs.template as<T>(),
                         W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
