@@ -418,6 +418,10 @@ int mgm_trace_jobs(mgm_ctx *ctx, int njobs, const int *gauge_ids, const mgm_trac
  *                       16-dof levels in FP16 mode)
  *   MGM_KERNEL_CONV_H   the same hidden convolution with FP16 weights and
  *                       activations (FP16 matrix cores, FP32 accumulation)
+ *   MGM_KERNEL_DENSE_LOW the low-precision cycle's coarse solve y = D^{-1} x on
+ *                       the coarsest level at the field's current precision
+ *                       (FP32 vectors; in FP16 mode the FP16 copy of the
+ *                       inverse on the FP16 matrix cores when it exists)
  * ------------------------------------------------------------------------- */
 #define MGM_KERNEL_STENCIL 0
 #define MGM_KERNEL_SAP 1
@@ -427,6 +431,7 @@ int mgm_trace_jobs(mgm_ctx *ctx, int njobs, const int *gauge_ids, const mgm_trac
 #define MGM_KERNEL_CONV 5
 #define MGM_KERNEL_SAP_LOW 6
 #define MGM_KERNEL_CONV_H 7
+#define MGM_KERNEL_DENSE_LOW 8
 
 int mgm_time_kernel(mgm_ctx *ctx, int gauge_id, int kind, int level, int nrhs, int reps,
                     double *us_out, double *bytes_out, double *flops_out);

@@ -175,7 +175,7 @@ class Job(C.Structure):
     _fields_ = [("gauge_id", C.c_int), ("level", C.c_int), ("nrhs", C.c_int),
                 ("b", C.c_void_p), ("x", C.c_void_p)]
 
-KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4, "conv": 5, "sap_low": 6, "conv_h": 7}
+KERNELS = {"stencil": 0, "sap": 1, "dense": 2, "cgs": 3, "copy": 4, "conv": 5, "sap_low": 6, "conv_h": 7, "dense_low": 8}
 
 _lib = None
 

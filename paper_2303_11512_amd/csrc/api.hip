@@ -446,6 +446,27 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
         break;
       }
+      case MGM_KERNEL_DENSE_LOW: {
+        require(g.mg_ready && L.is_coarsest && L.f.dinv.p, "level is not the coarsest of a built hierarchy",
+                MGM_ESTATE);
+        require(g.prm.precision != MGM_PREC_FP64, "the preconditioner runs in FP64 (mgm_set_precision)",
+                MGM_ESTATE);
+        lowbuf.ensure(sizeof(cf) * 2 * (size_t)nrhs * n);
+        cf* xf = lowbuf.as<cf>();
+        cf* yf = xf + (int64_t)nrhs * n;
+        launch_convert<float, double>(s, x, xf, (int64_t)nrhs * n);
+        const bool half = g.prm.precision == MGM_PREC_FP16 && L.f.hdinv.p != nullptr;
+        if (half) {
+          launch = [=, &L] { launch_dense_apply_h(s, L.f.hdinv.as<chalf>(), n, nrhs, xf, yf, nullptr); };
+        } else {
+          launch = [=, &L, &g] {
+            launch_dense_apply<float>(s, L.f.dinv.as<cf>(), n, nrhs, xf, yf, nullptr, &g.scratch[c->wslot]);
+          };
+        }
+        bytes = (half ? 4.0 : 8.0) * n * n + 16.0 * n * b;
+        flops = 8.0 * n * n * b;
+        break;
+      }
       case MGM_KERNEL_SAP_LOW: {
         require(g.mg_ready && L.ncolor[0] > 0, "SAP needs setup_mg on this level", MGM_ESTATE);
         require(g.prm.precision != MGM_PREC_FP64, "the preconditioner runs in FP64 (mgm_set_precision)",

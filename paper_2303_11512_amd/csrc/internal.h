@@ -237,6 +237,11 @@ void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M
 // FP16-block variants for coarse levels with 16 dofs per site (FP32 vectors,
 // FP16 matrix-core products, FP32 accumulation)
 void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count);
+// the same, setting *overflow (device) when a component is not finite in FP16
+void launch_to_half_checked(hipStream_t s, const cd* in, chalf* out, int64_t count, int* overflow);
+// y[r] = A x[r], A n x n in FP16 (x rounded to FP16, FP32 accumulation), n % 256 == 0
+void launch_dense_apply_h(hipStream_t s, const chalf* A, int64_t n, int nrhs, const cf* x, cf* y,
+                          const int* active);
 void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nrhs, const cf* x, cf* y,
                       const cf* b, const int* active);
 void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
@@ -352,6 +357,7 @@ struct LevelData {
   DevBuf dinv;     // coarsest: [n][n]
   DevBuf hblocks, hsapinv;  // FP16 copies of blocks / sapinv (16-dof coarse levels)
   DevBuf hsapM;             // FP16 inv_B D_BH of 2x1 SAP blocks (16-dof coarse levels)
+  DevBuf hdinv;             // FP16 dense inverse of the coarsest level (empty if out of range)
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 

@@ -1272,6 +1272,114 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   }
 }
 
+// y[r] = A x[r] for a dense n x n A held in FP16 (x rounded to FP16, FP32
+// accumulation) on the 16x16x32 matrix cores: the coarse solve of the FP16
+// cycle.  A workgroup owns 16 TR rows x 16 RHS; each of its eight waves takes
+// an eighth of the k range with TR 16 x 16 result tiles (one per 16 rows),
+// loading the next 32-wide k step while the matrix cores work on the current
+// one, and the eighths are summed in LDS in wave order.  The RHS tiles of a
+// row group are consecutive in the XCD-ordered workgroup index, so the rows
+// of A they share are fetched into one L2.  Lane l supplies the K slots
+// 8 (l/16) .. 8 (l/16) + 7 of row l%16 of A and of RHS column l%16 (32 bytes
+// of A per row tile, 64 bytes of x); n is a multiple of 256.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h16 __attribute__((ext_vector_type(16)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+constexpr int DH_W = 8;  // waves per workgroup (k split)
+
+template <int TR>
+__device__ __forceinline__ void dense_h_step(const h16 (&a)[TR], const f16v& xv, CAcc<float> (&acc)[TR]) {
+  h8 xr, xi;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xr[j] = (_Float16)xv[2 * j];
+    xi[j] = (_Float16)xv[2 * j + 1];
+  }
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const h8 ar = __builtin_shufflevector(a[t], a[t], 0, 2, 4, 6, 8, 10, 12, 14);
+    const h8 ai = __builtin_shufflevector(a[t], a[t], 1, 3, 5, 7, 9, 11, 13, 15);
+    acc[t].re = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar, xr, acc[t].re, 0, 0, 0);
+    acc[t].re = __builtin_amdgcn_mfma_f32_16x16x32_f16(-ai, xi, acc[t].re, 0, 0, 0);
+    acc[t].im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar, xi, acc[t].im, 0, 0, 0);
+    acc[t].im = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai, xr, acc[t].im, 0, 0, 0);
+  }
+}
+
+template <int TR>
+__global__ void __launch_bounds__(64 * DH_W) k_dense_h(const chalf* __restrict__ A, int64_t n, int nrhs,
+                                                      const cf* __restrict__ x, cf* __restrict__ y,
+                                                      const int* __restrict__ active) {
+  __shared__ float red[DH_W - 1][TR][8][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int ntile = gridDim.y;
+  const int64_t Lg = xcd_tile(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * ntile);
+  const int64_t i0 = (Lg / ntile) * 16 * TR;
+  const int r0 = (int)(Lg % ntile) * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;  // lanes past the last RHS read row r0; never stored
+  const int64_t kw = n / DH_W, kb = kw * wave;
+  CAcc<float> acc[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) acc[t] = CAcc<float>{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const chalf* Ab = A + (i0 + i) * n + kb + 8 * q;
+  const cf* xb = x + rrow * n + kb + 8 * q;
+  h16 a0[TR], a1[TR];
+  f16v x0, x1;
+  auto load = [&](h16 (&a)[TR], f16v& xv, int64_t k0) {
+    xv = *reinterpret_cast<const f16v*>(xb + k0);
+#pragma unroll
+    for (int t = 0; t < TR; ++t) a[t] = *reinterpret_cast<const h16*>(Ab + 16 * t * n + k0);
+  };
+  load(a0, x0, 0);
+  for (int64_t k0 = 0; k0 < kw; k0 += 64) {
+    const bool second = k0 + 32 < kw;
+    if (second) load(a1, x1, k0 + 32);
+    dense_h_step<TR>(a0, x0, acc);
+    if (second) {
+      if (k0 + 64 < kw) load(a0, x0, k0 + 64);
+      dense_h_step<TR>(a1, x1, acc);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[wave - 1][t][v][lane] = acc[t].re[v];
+        red[wave - 1][t][4 + v][lane] = acc[t].im[v];
+      }
+  }
+  __syncthreads();
+  if (wave != 0 || !ok || (active && !active[r])) return;
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+#pragma unroll
+    for (int w = 0; w < DH_W - 1; ++w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[t].re[v] += red[w][t][v][lane];
+        acc[t].im[v] += red[w][t][4 + v][lane];
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      y[(int64_t)r * n + i0 + 16 * t + 4 * q + v] = mk<float>(acc[t].re[v], acc[t].im[v]);
+  }
+}
+
+// FP16 copy of a matrix; *overflow is set when a component does not fit
+// (|v| above the largest finite FP16 value after rounding)
+__global__ void __launch_bounds__(NT) k_to_half_checked(const cd* __restrict__ in, chalf* __restrict__ out,
+                                                        int64_t count, int* __restrict__ overflow) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= count) return;
+  const _Float16 re = (_Float16)in[e].re, im = (_Float16)in[e].im;
+  out[e] = chalf{re, im};
+  if (!__builtin_isfinite((float)re) || !__builtin_isfinite((float)im)) *overflow = 1;
+}
+
 // y[r] = A x[r] for a dense n x n A (n a multiple of 16): a wave owns 16 rows
 // x 16 RHS over a quarter of the workgroup's k range; the quarters are summed
 // in LDS, and k ranges split over gridDim.z go to part[z] (k_dense_reduce).
@@ -1813,6 +1921,26 @@ template void launch_stencil<double>(hipStream_t, const cd*, int, int, int, int,
                                      const cd*, const int*);
 template void launch_stencil<float>(hipStream_t, const cf*, int, int, int, int, const cf*, cf*,
                                     const cf*, const int*);
+
+void launch_dense_apply_h(hipStream_t s, const chalf* A, int64_t n, int nrhs, const cf* x, cf* y,
+                          const int* active) {
+  require(n % (32 * DH_W) == 0, "FP16 dense apply: n must be a multiple of 256");
+  if (nrhs <= 0) return;
+  // four row tiles per workgroup while that still gives 256 workgroups
+  const unsigned nt = (unsigned)((nrhs + 15) / 16);
+  if ((n / 64) * nt >= 256)
+    hipLaunchKernelGGL(k_dense_h<4>, dim3((unsigned)(n / 64), nt), dim3(64 * DH_W), 0, s, A, n, nrhs, x, y,
+                       active);
+  else
+    hipLaunchKernelGGL(k_dense_h<1>, dim3((unsigned)(n / 16), nt), dim3(64 * DH_W), 0, s, A, n, nrhs, x, y,
+                       active);
+  KCHK();
+}
+
+void launch_to_half_checked(hipStream_t s, const cd* in, chalf* out, int64_t count, int* overflow) {
+  hipLaunchKernelGGL(k_to_half_checked, dim3(grid1(count)), dim3(NT), 0, s, in, out, count, overflow);
+  KCHK();
+}
 
 void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count) {
   hipLaunchKernelGGL(k_to_half, dim3(grid1(count)), dim3(NT), 0, s, in, out, count);

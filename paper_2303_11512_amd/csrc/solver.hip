@@ -85,6 +85,20 @@ template <class T>
 void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* x, int m, T tol,
                   const int* parent);
 
+// x = D^{-1} r on the coarsest level from its dense inverse (in the FP16
+// mode the FP16 copy, when the inverse fits FP16's range)
+template <class T>
+void coarse_solve(mgm_ctx* c, Gauge& g, Level& L, int nrhs, const cx<T>* r, cx<T>* x, const int* act) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (g.prm.precision == MGM_PREC_FP16 && L.f.hdinv.p) {
+      launch_dense_apply_h(c->stream, L.f.hdinv.as<chalf>(), L.n, nrhs, r, x, act);
+      return;
+    }
+  }
+  launch_dense_apply<T>(c->stream, ldata<T>(L).dinv.template as<cx<T>>(), L.n, nrhs, r, x, act,
+                        &g.scratch[c->wslot]);
+}
+
 // M_l r -> x.  Coarsest: x = D^{-1} r.  Else x = P_l C_{l+1}(P_l^H r) (or 0
 // while the hierarchy below l is not built), then SAP cycles on D x = r.
 template <class T>
@@ -94,7 +108,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   Level& L = *g.levels[l];
   LevelData<T>& D = ldata<T>(L);
   if (L.is_coarsest) {
-    launch_dense_apply<T>(s, D.dinv.template as<cx<T>>(), L.n, nrhs, r, x, act, &g.scratch[c->wslot]);
+    coarse_solve<T>(c, g, L, nrhs, r, x, act);
     return;
   }
   if (L.has_coarse) {
@@ -106,7 +120,7 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     cx<T>* ec = W.ec.template as<cx<T>>();
     launch_restrict<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, r, rc, act);
     if (C.is_coarsest) {
-      launch_dense_apply<T>(s, ldata<T>(C).dinv.template as<cx<T>>(), C.n, nrhs, rc, ec, act, &g.scratch[c->wslot]);
+      coarse_solve<T>(c, g, C, nrhs, rc, ec, act);
     } else if (C.inner_iters <= 0) {
       precond<T>(c, g, l + 1, nrhs, rc, ec, act);  // plain V-cycle on the coarse level
     } else {
@@ -638,6 +652,20 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
     copy_convert<float>(c, L.d.P, L.f.P);
     copy_convert<float>(c, L.d.sapinv, L.f.sapinv);
     copy_convert<float>(c, L.d.dinv, L.f.dinv);
+    if (L.is_coarsest && L.d.dinv.p && L.n % 256 == 0) {
+      // FP16 copy of the coarsest inverse: the FP16 cycle's coarse solve (kept
+      // only if every entry is in range)
+      const int64_t cnt = L.n * L.n;
+      DevBuf ovf;
+      ovf.ensure(sizeof(int));
+      launch_fill_int(s, ovf.as<int>(), 1, 0);
+      L.f.hdinv.ensure(sizeof(chalf) * cnt);
+      launch_to_half_checked(s, L.d.dinv.as<cd>(), L.f.hdinv.as<chalf>(), cnt, ovf.as<int>());
+      int h = 0;
+      HIPCHK(hipMemcpyAsync(&h, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h) L.f.hdinv.release();
+    }
     if (L.M == 16 && L.d.sapinv.p) {  // FP16 blocks for the FP16 mode
       const int64_t nbk = (int64_t)(L.d.blocks.bytes / sizeof(cd));
       const int64_t nin = (int64_t)(L.d.sapinv.bytes / sizeof(cd));

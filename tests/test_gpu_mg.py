@@ -190,3 +190,33 @@ def test_two_site_sap_blocks(ctx, precision, tol):
     ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-10, restart=24))
     res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
     assert np.all(res <= 1e-10)
+
+
+@pytest.mark.parametrize("L,nrhs", [(32, 21), (64, 1), (64, 40)])
+def test_fp16_coarsest_solve(ctx, L, nrhs):
+    """FP16 mode: the cycle's coarsest solve applies an FP16 copy of the exact
+    inverse on the 16x16x32 matrix cores (x rounded to FP16, FP32 sums).
+    Against D^{-1} r from the oracle's coarsest operator: FP16 rounding of
+    the inverse and of r bounds the error near 1e-3 (checked at 5e-3); the
+    FP32 mode's dense apply is ~1e-6, so the FP16 error also shows that the
+    FP16 kernel ran.  Coarsest n = 256 (L = 32) and 1024 (L = 64): several
+    64-row workgroups and k quarters, ragged and single RHS counts."""
+    th = metropolis_u1(L, L, 3.0, 100, 960 + L)
+    errs = {}
+    for precision in ("fp32", "fp16"):
+        rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (2, 1), (1, 1)],
+                     sap_cycles=[2, 3, 2], inner_iters=[0, 0, 0], precision=precision)
+        log(f"coarsest solve, L={L}, nrhs={nrhs}, {precision}")
+        gid = rec.gpu(ctx)
+        hier = rec.oracle()
+        coarse = hier.levels[-1]
+        r = rhs_vectors(coarse.n, nrhs, 97)
+        x = empty(nrhs, coarse.n)
+        ctx.precondition(gid, 2, to_dev(r), x)
+        ref = np.linalg.solve(coarse.D.toarray(), r.T).T
+        errs[precision] = max(rel_err(to_host(x)[i], ref[i]) for i in range(nrhs))
+        ctx.free_gauge(gid)
+    log(f"  max rel. error per RHS: {errs}")
+    assert errs["fp32"] < 1e-5
+    assert errs["fp16"] < 5e-3
+    assert errs["fp16"] > 10 * errs["fp32"]
