@@ -425,6 +425,33 @@ __global__ void __launch_bounds__(NT) k_scale_r(const cx<T>* __restrict__ w, con
     v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
 }
 
+// k_scale_r (without den_out) that also stores the FP32 rounding of v in vf:
+// the scaling that ends an Arnoldi step, done by the next step's first launch
+// together with the rounding of the preconditioner's input
+template <class T>
+__global__ void __launch_bounds__(NT) k_scale_convert(const cx<T>* __restrict__ w, const T* __restrict__ npart,
+                                                      int nch, int64_t n, cx<T>* __restrict__ v,
+                                                      cf* __restrict__ vf, const int* __restrict__ active) {
+  __shared__ T dsh;
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    T acc = 0;
+    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
+    acc = wave_sum(acc);
+    if (lane == 0) dsh = sqrt(acc);
+  }
+  __syncthreads();
+  const T d = dsh;
+  const T s = (d > 0) ? (T)1 / d : (T)0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+    const cx<T> vv = s * w[(int64_t)r * n + k];
+    v[(int64_t)r * n + k] = vv;
+    vf[(int64_t)r * n + k] = mk<float>((float)vv.re, (float)vv.im);
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(NT) k_scale(const cx<T>* __restrict__ w, const T* __restrict__ den,
                                               int64_t n, cx<T>* __restrict__ v,
@@ -524,19 +551,17 @@ __global__ void __launch_bounds__(NT) k_hcol(int j, int m, int nrhs, const cx<T>
 // NEAR of its threshold (the next step will most likely end it), 1 active.
 constexpr double NEAR = 32.0;
 template <class T>
-__global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
-                                                    const cx<T>* __restrict__ c2, const T* __restrict__ hn,
-                                                    cx<T>* __restrict__ H, T* __restrict__ cs,
-                                                    cx<T>* __restrict__ sn, cx<T>* __restrict__ g,
-                                                    const T* __restrict__ thr, int* __restrict__ active,
-                                                    int* __restrict__ nit, int* __restrict__ host_flags) {
-  const int r = blockIdx.x * NT + threadIdx.x;
-  if (r >= nrhs) return;
+__device__ __forceinline__ void hcol_givens_rhs(int r, int j, int m, const cx<T>* __restrict__ c1,
+                                                const cx<T>* __restrict__ c2, T hnr, cx<T>* __restrict__ H,
+                                                T* __restrict__ cs, cx<T>* __restrict__ sn,
+                                                cx<T>* __restrict__ g, const T* __restrict__ thr,
+                                                int* __restrict__ active, int* __restrict__ nit,
+                                                int* __restrict__ host_flags) {
   int code = 0;
   if (active[r]) {
     cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
     for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
-    h[j + 1] = mk<T>(hn[r], 0);
+    h[j + 1] = mk<T>(hnr, 0);
     T* c = cs + (int64_t)r * m;
     cx<T>* s = sn + (int64_t)r * m;
     cx<T>* gr = g + (int64_t)r * (m + 1);
@@ -573,6 +598,37 @@ __global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, cons
     code = active[r] ? (res <= (T)NEAR * thr[r] ? 2 : 1) : 0;
   }
   if (host_flags) host_flags[r] = code;
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
+                                                    const cx<T>* __restrict__ c2, const T* __restrict__ hn,
+                                                    cx<T>* __restrict__ H, T* __restrict__ cs,
+                                                    cx<T>* __restrict__ sn, cx<T>* __restrict__ g,
+                                                    const T* __restrict__ thr, int* __restrict__ active,
+                                                    int* __restrict__ nit, int* __restrict__ host_flags) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrhs) return;
+  hcol_givens_rhs<T>(r, j, m, c1, c2, hn[r], H, cs, sn, g, thr, active, nit, host_flags);
+}
+
+// The same with |w| formed here from the chunk partials of |w|^2 (one wave
+// per RHS, added as k_scale_r adds them, so the same bits)
+template <class T>
+__global__ void __launch_bounds__(NT) k_hcol_givens_np(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
+                                                       const cx<T>* __restrict__ c2, const T* __restrict__ npart,
+                                                       int nch, cx<T>* __restrict__ H, T* __restrict__ cs,
+                                                       cx<T>* __restrict__ sn, cx<T>* __restrict__ g,
+                                                       const T* __restrict__ thr, int* __restrict__ active,
+                                                       int* __restrict__ nit, int* __restrict__ host_flags) {
+  const int r = (int)(((int64_t)blockIdx.x * NT + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= nrhs) return;
+  T acc = 0;
+  if (active[r])
+    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
+  acc = wave_sum(acc);
+  if (lane == 0) hcol_givens_rhs<T>(r, j, m, c1, c2, sqrt(acc), H, cs, sn, g, thr, active, nit, host_flags);
 }
 
 // y = R^{-1} g with R the rotated (upper triangular) H of nit[r] steps
@@ -856,6 +912,25 @@ void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
 }
 
 template <class T>
+void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
+                          const int* active) {
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active);
+  KCHK();
+}
+
+template <class T>
+void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,
+                           const T* npart, int64_t n, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr,
+                           int* active, int* nit, int* host_flags) {
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  hipLaunchKernelGGL(k_hcol_givens_np<T>, dim3((unsigned)(((int64_t)nrhs * 64 + NT - 1) / NT)), dim3(NT), 0, s, j,
+                     m, nrhs, c1, c2, npart, (int)nch, H, cs, sn, g, thr, active, nit, host_flags);
+  KCHK();
+}
+
+template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
                     const int* active) {
   const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
@@ -1115,6 +1190,11 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
   template void launch_update_dot_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,            \
                                        const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,     \
                                        const int*, cx<T>*);                                        \
+  template void launch_scale_convert<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,  \
+                                        cf*, const int*);                                          \
+  template void launch_hcol_givens_np<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,     \
+                                         const T*, int64_t, cx<T>*, T*, cx<T>*, cx<T>*, const T*,   \
+                                         int*, int*, int*);                                        \
   template void launch_scale_r<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*, T*,    \
                                   const int*);                                                   \
   template void launch_hcol_givens<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,       \

@@ -314,6 +314,16 @@ template <class T>
 void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                          int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                          const int* active, cx<T>* dpart2);
+// v = w / |w| from the chunk partials of |w|^2 (chunking of
+// launch_update_multi_r), and vf = v rounded to FP32
+template <class T>
+void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
+                          const int* active);
+// launch_hcol_givens with |w| formed from the chunk partials of |w|^2
+template <class T>
+void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,
+                           const T* npart, int64_t n, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr,
+                           int* active, int* nit, int* host_flags);
 template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
                     const int* active);

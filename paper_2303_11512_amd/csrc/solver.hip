@@ -171,9 +171,13 @@ bool precond_writes_fp64(const Gauge& g, const Level& L) {
 
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
 // Hessenberg column, v_{j+1} = w/||w||, Givens update.
+// fused (FP64 steps whose preconditioner rounds its input to FP32): the
+// scaling v_j = w / |w| that ends step j - 1 is done by step j's first launch
+// together with that rounding (into W.cvt_in), and prec is then called with
+// v = null; step j's own |w| goes to the Givens kernel as chunk partials.
 template <class T, class PrecFn>
 void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec,
-                  int* host_flags = nullptr) {
+                  int* host_flags = nullptr, bool fused = false) {
   hipStream_t s = c->stream;
   Level& L = *g.levels[l];
   const int64_t n = L.n;
@@ -187,7 +191,15 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   cx<T>* c2 = W.coef2.template as<cx<T>>();
   T* hn = W.beta.template as<T>() ;  // beta is free after the cycle start: reuse for ||w||
   T* np = W.npart.template as<T>();
-  prec(V + j * vs, Z + j * vs, (const int*)act);
+  if (fused && j > 0) {
+    if constexpr (std::is_same<T, double>::value) {
+      W.cvt_in.ensure(sizeof(cf) * (size_t)vs);
+      launch_scale_convert<T>(s, w, np, n, nrhs, V + j * vs, W.cvt_in.template as<cf>(), act);
+    }
+    prec(nullptr, Z + j * vs, (const int*)act);
+  } else {
+    prec(V + j * vs, Z + j * vs, (const int*)act);
+  }
   apply_op<T>(c, g, l, nrhs, Z + j * vs, w, nullptr, act);
   // CGS2; each reduction over chunks is done by the kernel that consumes it,
   // and the first pass's update forms the second pass's partials
@@ -195,6 +207,12 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   cx<T>* part2 = part + (size_t)nrhs * (j + 1) * nch;
   launch_update_dot_r<T>(s, V, vs, n, j + 1, part, nch, c1, m + 1, (T)-1, w, n, nrhs, act, part2);
   launch_update_multi_r<T>(s, V, vs, n, j + 1, part2, nch, c2, m + 1, (T)-1, w, n, nrhs, act, np);
+  if (fused) {
+    launch_hcol_givens_np<T>(s, j, m, nrhs, c1, c2, np, n, W.H.template as<cx<T>>(), W.cs.template as<T>(),
+                             W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
+                             W.nit.template as<int>(), host_flags);
+    return;
+  }
   launch_scale_r<T>(s, w, np, n, nrhs, V + (j + 1) * vs, hn, act);
   launch_hcol_givens<T>(s, j, m, nrhs, c1, c2, hn, W.H.template as<cx<T>>(), W.cs.template as<T>(),
                         W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
@@ -240,20 +258,30 @@ void apply_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* x, cd* y) {
 
 // FP64 preconditioner entry; in FP32 mode the residual is rounded to FP32, the
 // whole multigrid cycle runs in FP32, and the correction is widened again.
+bool precondition_in_fp32(const Gauge& g) { return g.prm.precision != MGM_PREC_FP64 && g.mg_ready; }
+
+// the FP32 cycle on the residual already rounded into W.cvt_in; x in FP64
+void precondition_f32in(mgm_ctx* c, Gauge& g, int l, int nrhs, cd* x, const int* act) {
+  Level& L = *g.levels[l];
+  Work<double>& W = L.wd[c->wslot];
+  const int64_t cnt = (int64_t)nrhs * L.n;
+  W.cvt_out.ensure(sizeof(cf) * cnt);
+  if (precond_writes_fp64(g, L)) {
+    precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act, x);
+  } else {
+    precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act);
+    launch_convert<double, float>(c->stream, W.cvt_out.as<cf>(), x, cnt);
+  }
+}
+
 void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, const int* act) {
   Level& L = *g.levels[l];
-  if (g.prm.precision != MGM_PREC_FP64 && g.mg_ready) {
+  if (precondition_in_fp32(g)) {
     Work<double>& W = L.wd[c->wslot];
     const int64_t cnt = (int64_t)nrhs * L.n;
     W.cvt_in.ensure(sizeof(cf) * cnt);
-    W.cvt_out.ensure(sizeof(cf) * cnt);
     launch_convert<float, double>(c->stream, r, W.cvt_in.as<cf>(), cnt);
-    if (precond_writes_fp64(g, L)) {
-      precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act, x);
-    } else {
-      precond<float>(c, g, l, nrhs, W.cvt_in.as<cf>(), W.cvt_out.as<cf>(), act);
-      launch_convert<double, float>(c->stream, W.cvt_out.as<cf>(), x, cnt);
-    }
+    precondition_f32in(c, g, l, nrhs, x, act);
   } else {
     precond<double>(c, g, l, nrhs, r, x, act);
   }
@@ -377,6 +405,8 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
     launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
 
   bool final_known = false;  // hr holds the residuals of the returned x
+  // steps that hand the preconditioner an FP32 input scale and round v_j in one launch
+  const bool fused = !stage && precondition_in_fp32(g);
   if (L.has_dense) {
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch[c->wslot]);
   } else {
@@ -403,9 +433,10 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
               c, g, l, nrhs, j, m, W,
               [&](const cd* v, cd* z, const int* a) {
                 if (stage) cnn_precondition(c, g, nrhs, v, z, a);
-                else precondition_d(c, g, l, nrhs, v, z, a);
+                else if (v) precondition_d(c, g, l, nrhs, v, z, a);
+                else precondition_f32in(c, g, l, nrhs, z, a);
               },
-              W.flags.h + slot * nrhs);
+              W.flags.h + slot * nrhs, fused);
         });
         HIPCHK(hipEventRecord(W.flags.ev[slot], s));
         if (j + 1 < PinnedFlags::kDepth) continue;
