@@ -921,6 +921,11 @@ struct Estimator {
         }
         common = (int)std::min<double>(p.batch, std::max(4.0, std::ceil(1.15 * need) + 2));
       }
+      // up to the 16-RHS tile of the matrix-core kernels: no slower, the
+      // replay below takes the same samples whatever the batch holds, and
+      // the level solves see few distinct RHS counts (their captured graphs
+      // are replayed instead of captured again)
+      common = std::min(p.batch, (common + 15) / 16 * 16);
     }
     std::vector<int> nb(nst, 0);
     for (int i = 0; i < nst; ++i) {
