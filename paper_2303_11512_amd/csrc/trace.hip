@@ -501,9 +501,10 @@ struct Estimator {
     }
     }
     const size_t nlr = items.size();
+    const std::vector<int> first_b = equal_work_batch(lv, first);
     // A zeta does not depend on Q, so the first batch of one-sided samples
     // rides with the last round; two-sided samples need the final Q first
-    if (!two_sided) sample_start(lv, first, items);
+    if (!two_sided) sample_start(lv, first_b, items);
     applyA_levels(lv, items, its);
     add_lr_cost(lv, items, its, nlr);
     // tau_lr of every difference and the first samples' dots: one read-back
@@ -520,11 +521,38 @@ struct Estimator {
       lv[items[q].i].tau_lr = acc;
     }
     if (two_sided) {
-      sample_batches(lv, first, first_vals);
+      sample_batches(lv, first_b, first_vals);
     } else {
       sample_finish_collect(lv, sitems, sits, got, s_req, first_vals);
     }
     if (deflated) ritz_triplets(lv[0]);
+  }
+
+  // The first stochastic batch, speculative like every batch (the replay
+  // takes the same samples whatever it holds): each difference is given
+  // about the cost-model work of the costliest one, so the cheaper
+  // differences evaluate proportionally more samples in the same phase.
+  // Per-vector costs are those of the power rounds so far; rounded up to the
+  // 16-RHS tile, at most `batch`.
+  std::vector<int> equal_work_batch(const std::vector<StochLevel>& lv, const std::vector<int>& b) const {
+    if (p.fixed_samples || p.k_power < 1) return b;
+    std::vector<double> cv(lv.size(), 0.0);
+    double cmax = 0;
+    for (size_t i = 0; i < lv.size(); ++i) {
+      if (b[i] <= 0 || lv[i].d <= 0) continue;
+      cv[i] = lv[i].lr_cost / ((double)p.k_power * lv[i].d);
+      if (!(cv[i] > 0) || !std::isfinite(cv[i])) return b;
+      cmax = std::max(cmax, cv[i]);
+    }
+    const int maxS = p.max_samples > 0 ? p.max_samples : (1 << 30);
+    std::vector<int> out = b;
+    for (size_t i = 0; i < lv.size(); ++i) {
+      if (cv[i] <= 0) continue;
+      const double want = std::ceil(std::ceil(b[i] * cmax / cv[i]) / 16.0) * 16.0;
+      const int v = std::max(b[i], (int)std::min<double>(p.batch, want));
+      out[i] = std::min(v, maxS - lv[i].s());
+    }
+    return out;
   }
 
   // ---- adaptive number of Hutch++ vectors per level difference (the
