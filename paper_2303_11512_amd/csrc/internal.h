@@ -423,8 +423,8 @@ struct Level {
   LevelData<float> f;
   // two workspace sets: set 1 serves a solve that runs concurrently with
   // one on set 0 (the estimator's coarse-level solves)
-  Work<double> wd[2];
-  Work<float> wf[2];
+  Work<double> wd[3];
+  Work<float> wf[3];
   int64_t nrow() const { return (int64_t)bx * bt * (M / 2); }
   int64_t nagg() const { return bx ? (int64_t)(Nx / bx) * (Nt / bt) : 0; }
 };
@@ -490,14 +490,14 @@ struct Gauge {
   // caller's stream with ev_in / ev_out at every entry point
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  // second stream of the field (default priority) for the concurrent
-  // solves, with its fork / join events; created on first use
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  DevBuf scratch[2];  // split-k partials of the dense applies, per workspace set
+  // second and third streams of the field (default priority) for the
+  // concurrent solves, with their fork / join events; created on first use
+  hipStream_t stream2 = nullptr, stream3 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join3 = nullptr;
+  DevBuf scratch[3];  // split-k partials of the dense applies, per workspace set
   CnnWork cnn;
   EstWork est;
-  std::map<GraphKey, GraphEntry> graphs[2];  // per workspace set (one host thread each)
+  std::map<GraphKey, GraphEntry> graphs[3];  // per workspace set (one host thread each)
   // the field's own worker context of mgm_trace_jobs, kept so that its
   // workspaces (and the graphs that hold their addresses) are reused
   std::shared_ptr<mgm_ctx> view;
@@ -511,13 +511,16 @@ struct Gauge {
   ~Gauge() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (stream2) (void)hipStreamSynchronize(stream2);
+    if (stream3) (void)hipStreamSynchronize(stream3);
     clear_graphs();
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_join3) (void)hipEventDestroy(ev_join3);
     if (stream) (void)hipStreamDestroy(stream);
     if (stream2) (void)hipStreamDestroy(stream2);
+    if (stream3) (void)hipStreamDestroy(stream3);
   }
 };
 
@@ -526,7 +529,7 @@ struct Gauge {
 struct mgm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int wslot = 0;  // workspace set of the levels this view solves with (0 or 1)
+  int wslot = 0;  // workspace set of the levels this view solves with (0, 1 or 2)
   std::string err;
   std::vector<std::unique_ptr<mgm::Gauge>> gauges;
   mgm::DevBuf scratch, scratch2, scratch3, ibuf;

@@ -318,42 +318,53 @@ struct Estimator {
 
   // Solve level j's total[j] right-hand sides src[j] into g.est.lout[j] for
   // every j.  The solves are independent: the finest runs on this thread and
-  // the field's stream, the others one after the other on the field's second
-  // stream from a worker thread with its own workspace set, so the
-  // latency-bound coarse-level kernels overlap the fine level's.
+  // the field's stream; the other iterative ones one after the other on the
+  // field's second stream from a worker thread with its own workspace set, so
+  // the latency-bound coarse-level kernels overlap the fine level's; the
+  // exact (dense-inverse) solves from a third thread on the third stream.
   void solve_levels(const std::vector<int>& total, const std::vector<const cd*>& src,
                     std::vector<std::vector<int>>& lits) {
     std::vector<int> todo;
     for (int j = 0; j < L; ++j)
       if (total[j] > 0) todo.push_back(j);
-    std::vector<std::array<int64_t, 2>> cnt(MGM_MAX_LEVELS, {0, 0}), wcnt(MGM_MAX_LEVELS, {0, 0});
+    using Counts = std::vector<std::array<int64_t, 2>>;
+    Counts cnt(MGM_MAX_LEVELS, {0, 0});
+    std::vector<Counts> wcnt(2, Counts(MGM_MAX_LEVELS, {0, 0}));
     auto out = [&](int j) { return g.est.lout[j].as<cd>(); };
     if (todo.size() < 2 || !p.concurrent) {
       for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt, lits[j]);
     } else {
+      // worker 0: iterative levels on stream 2; worker 1: exact levels on stream 3
+      std::vector<int> part[2];
+      for (size_t q = 1; q < todo.size(); ++q) part[g.levels[todo[q]]->has_dense ? 1 : 0].push_back(todo[q]);
+      if (part[0].empty()) part[0].swap(part[1]);
       ensure_stream2();
       HIPCHK(hipEventRecord(g.ev_fork, c->stream));
       HIPCHK(hipStreamWaitEvent(g.stream2, g.ev_fork, 0));
-      int wst = MGM_OK;
-      std::string wmsg;
-      std::thread worker([&] {
-        mgm_ctx w;  // worker view: second stream, workspace set 1, private scratch
-        w.device = c->device;
-        w.stream = g.stream2;
-        w.cnn = c->cnn;
-        w.wslot = 1;
-        try {
-          HIPCHK(hipSetDevice(c->device));
-          for (size_t q = 1; q < todo.size(); ++q)
-            solve_on(&w, todo[q], total[todo[q]], src[todo[q]], out(todo[q]), wcnt, lits[todo[q]]);
-        } catch (const Error& e) {
-          wst = e.code;
-          wmsg = e.what();
-        } catch (const std::exception& e) {
-          wst = MGM_EHIP;
-          wmsg = e.what();
-        }
-      });
+      if (!part[1].empty()) HIPCHK(hipStreamWaitEvent(g.stream3, g.ev_fork, 0));
+      int wst[2] = {MGM_OK, MGM_OK};
+      std::string wmsg[2];
+      std::vector<std::thread> workers;
+      for (int k = 0; k < 2; ++k) {
+        if (part[k].empty()) continue;
+        workers.emplace_back([&, k] {
+          mgm_ctx w;  // worker view: its stream, its workspace set, private scratch
+          w.device = c->device;
+          w.stream = k == 0 ? g.stream2 : g.stream3;
+          w.cnn = c->cnn;
+          w.wslot = 1 + k;
+          try {
+            HIPCHK(hipSetDevice(c->device));
+            for (int j : part[k]) solve_on(&w, j, total[j], src[j], out(j), wcnt[k], lits[j]);
+          } catch (const Error& e) {
+            wst[k] = e.code;
+            wmsg[k] = e.what();
+          } catch (const std::exception& e) {
+            wst[k] = MGM_EHIP;
+            wmsg[k] = e.what();
+          }
+        });
+      }
       int st = MGM_OK;
       std::string msg;
       try {
@@ -365,15 +376,20 @@ struct Estimator {
         st = MGM_EHIP;
         msg = e.what();
       }
-      worker.join();
+      for (auto& t : workers) t.join();
       HIPCHK(hipEventRecord(g.ev_join, g.stream2));
       HIPCHK(hipStreamWaitEvent(c->stream, g.ev_join, 0));
+      if (!part[1].empty()) {
+        HIPCHK(hipEventRecord(g.ev_join3, g.stream3));
+        HIPCHK(hipStreamWaitEvent(c->stream, g.ev_join3, 0));
+      }
       if (st != MGM_OK) throw Error(st, msg);
-      if (wst != MGM_OK) throw Error(wst, wmsg);
+      for (int k = 0; k < 2; ++k)
+        if (wst[k] != MGM_OK) throw Error(wst[k], wmsg[k]);
     }
     for (int j = 0; j < L; ++j) {
-      res.lvl_solves[j] += (int)(cnt[j][0] + wcnt[j][0]);
-      res.lvl_iters[j] += (int)(cnt[j][1] + wcnt[j][1]);
+      res.lvl_solves[j] += (int)(cnt[j][0] + wcnt[0][j][0] + wcnt[1][j][0]);
+      res.lvl_iters[j] += (int)(cnt[j][1] + wcnt[0][j][1] + wcnt[1][j][1]);
     }
   }
 
@@ -424,8 +440,10 @@ struct Estimator {
   void ensure_stream2() {
     if (g.stream2) return;
     HIPCHK(hipStreamCreateWithFlags(&g.stream2, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&g.stream3, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&g.ev_join3, hipEventDisableTiming));
   }
 
   // Q = qr+(Y) of every item's block: the differences' QRs are independent,
