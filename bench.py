@@ -26,13 +26,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # red/black SAP cycles per level of the V-cycle (fine, first coarse, deeper)
-# and the SAP blocks below the fine level (2x1 sites on the first coarse level,
-# single sites deeper): a sweep on the 128^2 workload (fine-level solves
-# concurrent with the coarse-level ones) puts the minimum of time per
-# estimate at 4 / 10 / 3 (10 cycles on the first coarse level bring its
-# solves from 6 to 5 iterations; 8: 6 iterations, 12: no further gain)
-SAP_CYCLES = (4, 10, 3, 3, 3, 3)
-COARSE_SAP_BLOCKS = [(2, 1), (1, 1), (1, 1), (1, 1), (1, 1)]
+# and the SAP blocks below the fine level (2x2 sites on the first coarse
+# level, single sites deeper): a sweep on the 128^2 workload (fine-level
+# solves concurrent with the coarse-level ones) puts the minimum of time per
+# estimate at 4 / 6 / 3 with 2x2 blocks (6 cycles: 5 / 6 iterations on levels
+# 0 / 1; 7 or 8: 5 / 5 but no faster; 4: the fine level needs 5-6), ahead of
+# 2x1 blocks (best at 10 cycles, 5 / 5 iterations, 5% slower)
+SAP_CYCLES = (4, 6, 3, 3, 3, 3)
+COARSE_SAP_BLOCKS = [(2, 2), (1, 1), (1, 1), (1, 1), (1, 1)]
 
 
 def mg_setup_kwargs(cfg):
@@ -84,13 +85,13 @@ def trace_kwargs(cfg, step):
 KERNEL_RHS = 64
 # the kernel with the largest share of the step's GPU time (rocprofv3 of the
 # 128^2 step) per preconditioner precision: one colour of the SAP sweep on the
-# first coarse level (16 dofs per site)
+# first coarse level (16 dofs per site, 2x2-site blocks, premultiplied form)
 DOMINANT = {"fp64": "sap_l1", "fp32": "saplow_l1", "fp16": "saplow_l1"}
-KERNEL_NAME = {"fp64": "k_sap2_mfma<double>", "fp32": "k_sap2_mfma<float>", "fp16": "k_sap2p_h<false>"}
+KERNEL_NAME = {"fp64": "k_sap4p<double, false>", "fp32": "k_sap4p<float, false>", "fp16": "k_sap4p_h<false>"}
 # counter summaries of those kernels (FETCH_SIZE / WRITE_SIZE runs, scaled by
 # the copy-kernel calibration), keyed to the source file they were measured from
-TRAFFIC_SUMMARY = {p: os.path.join(ROOT, "profiles", f"{KERNEL_NAME[p].replace('<', '_').replace('>', '')}"
-                                                     f"_l1_schwinger128_traffic.txt") for p in DOMINANT}
+TRAFFIC_SUMMARY = {p: os.path.join(ROOT, "profiles", KERNEL_NAME[p].replace(", ", "_").replace("<", "_")
+                                   .replace(">", "") + "_l1_schwinger128_traffic.txt") for p in DOMINANT}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_11512_amd", "csrc", "ops.hip")
 
 
@@ -824,6 +825,7 @@ def main():
                                f"{cfg['noise']} noise, eps {cfg['eps']}, FGMRES tol 1e-10",
                    "solves_per_s": solves / dt, "setup_s": setup_s,
                    "preconditioner": args.precision, "sap_cycles": list(SAP_CYCLES[:4]),
+                   "sap_blocks": [list(b) for b in mg_setup_kwargs(cfg)["sap_block"][:3]],
                    "min_samples": MIN_SAMPLES, "cost_model": "flops (Sec. 4)", "estimates": spread,
                    "fp64_preconditioner_same_schedule": plain,
                    "plain_fp64_mg_fgmres": unbatched,

@@ -432,18 +432,28 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         break;
       case MGM_KERNEL_SAP: {
         require(g.mg_ready && L.ncolor[0] > 0, "SAP needs setup_mg on this level", MGM_ESTATE);
-        launch = [=, &L] {
-          launch_sap_sweep<double>(s, L.d.B(), L.d.sapinv.as<cd>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
-                                   L.color_list[0].as<int>(), L.ncolor[0], nrhs, r, y, nullptr);
-        };
+        const bool quad = L.d.sapM.p != nullptr;  // premultiplied 2x2 blocks (r stands in for rho)
+        if (quad) {
+          launch = [=, &L] {
+            launch_sap4p<double>(s, L.d.sapM.as<cd>(), L.d.sapinv.as<cd>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
+                                 L.ncolor[0], nrhs, false, nullptr, const_cast<cd*>(r), y, nullptr);
+          };
+        } else {
+          launch = [=, &L] {
+            launch_sap_sweep<double>(s, L.d.B(), L.d.sapinv.as<cd>(), L.Nx, L.Nt, L.M, L.sbx, L.sbt,
+                                     L.color_list[0].as<int>(), L.ncolor[0], nrhs, r, y, nullptr);
+          };
+        }
         // with the exact block inverse a sweep is x_B = inv_B (r_B - D_BH x_H):
         // r_B and the distinct halo values read, x_B written, inv_B and the
-        // outward hops read (each once)
+        // outward hops read (each once); premultiplied: rho_B, the halo and
+        // M_B read, x_B written
         const double nb = L.ncolor[0];
         const double halo = 2.0 * (L.sbx + L.sbt) * L.M;  // outward hop dofs per block
         const double hx = (double)sap_halo_sites(L) * L.M;
-        bytes = 16.0 * b * (2.0 * nb * L.K + hx) + 16.0 * nb * ((double)L.K * L.K + halo * L.M);
-        flops = 8.0 * b * nb * ((double)L.K * L.K + halo * L.M);
+        const double ment = quad ? (double)L.K * halo : (double)L.K * L.K + halo * L.M;
+        bytes = 16.0 * b * (2.0 * nb * L.K + hx) + 16.0 * nb * ment;
+        flops = 8.0 * b * nb * ment;
         break;
       }
       case MGM_KERNEL_DENSE_LOW: {
@@ -476,12 +486,23 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         cf* rf = xf + (int64_t)nrhs * n;
         launch_convert<float, double>(s, x, xf, (int64_t)nrhs * n);
         launch_convert<float, double>(s, r, rf, (int64_t)nrhs * n);
-        const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 && L.sbt == 1 &&
-                          (L.sbx == 1 || L.sbx == 2) && L.f.hblocks.p != nullptr;
+        const bool quad = L.f.sapM.p != nullptr;  // premultiplied 2x2 blocks
+        const bool half = g.prm.precision == MGM_PREC_FP16 && L.M == 16 &&
+                          ((L.sbt == 1 && (L.sbx == 1 || L.sbx == 2)) || quad) && L.f.hblocks.p != nullptr;
         // the premultiplied two-site sweep x_B = rho_B - M_B x_H of the later
         // cycles (rf stands in for rho)
         const bool premul = half && L.sbx == 2 && L.f.hsapM.p != nullptr;
-        if (premul) {
+        if (quad && half) {
+          launch = [=, &L] {
+            launch_sap4p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
+                           L.ncolor[0], nrhs, false, nullptr, rf, xf, nullptr);
+          };
+        } else if (quad) {
+          launch = [=, &L] {
+            launch_sap4p<float>(s, L.f.sapM.as<cf>(), L.f.sapinv.as<cf>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
+                                L.ncolor[0], nrhs, false, nullptr, rf, xf, nullptr);
+          };
+        } else if (premul) {
           launch = [=, &L] {
             launch_sap2p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
                            L.ncolor[0], nrhs, false, nullptr, rf, xf, nullptr);
@@ -503,7 +524,7 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         const double mb = half ? 4.0 : 8.0;  // bytes per complex matrix entry
         // matrix entries per block: inv_B (K^2) and the outward hops (halo M),
         // or M_B (K x halo) in the premultiplied form
-        const double ment = premul ? (double)L.K * halo : (double)L.K * L.K + halo * L.M;
+        const double ment = premul || quad ? (double)L.K * halo : (double)L.K * L.K + halo * L.M;
         bytes = 8.0 * b * (2.0 * nb * L.K + hx) + mb * nb * ment;
         flops = 8.0 * b * nb * ment;
         break;

@@ -251,6 +251,15 @@ void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, 
 // first sweep of each colour in a visit (`first`) forms rho_B = inv_B r_B
 // from r and stores it in rho ([nrhs][n]) for the later ones
 void launch_sap2_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, chalf* M);
+// 2x2-site blocks of 16-dof levels: M_B = inv_B D_BH ([nblk][8 hops][64][16], FP64)
+// and one colour of the premultiplied sweep x_B = rho_B - M_B x_H (first:
+// rho_B = inv_B r_B formed and stored); FP16 operands, or FP32 / FP64
+void launch_sap4_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, cd* M);
+void launch_sap4p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active);
+template <class T>
+void launch_sap4p(hipStream_t s, const cx<T>* M, const cx<T>* inv, int Nx, int Nt, const int* blist, int nb,
+                  int nrhs, bool first, const cx<T>* r, cx<T>* rho, cx<T>* x, const int* active);
 void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
                     int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active);
 // In-place Gauss-Jordan inverse with partial pivoting of the n x n matrix A.
@@ -368,6 +377,7 @@ struct LevelData {
   DevBuf hblocks, hsapinv;  // FP16 copies of blocks / sapinv (16-dof coarse levels)
   DevBuf hsapM;             // FP16 inv_B D_BH of 2x1 SAP blocks (16-dof coarse levels)
   DevBuf hdinv;             // FP16 dense inverse of the coarsest level (empty if out of range)
+  DevBuf sapM;              // inv_B D_BH of 2x2 SAP blocks (16-dof levels; FP16 copy in hsapM)
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 

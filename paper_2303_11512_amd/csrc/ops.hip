@@ -573,12 +573,13 @@ __global__ void __launch_bounds__(NT) k_sap_extract(const cd* __restrict__ B, in
 }
 
 // Gauss-Jordan inverse with partial pivoting of `count` K x K matrices in LDS
-// (one workgroup per matrix, K <= 32).  Sets *fail on a zero pivot.
+// (one workgroup per matrix, K <= KMAX).  Sets *fail on a zero pivot.
+template <int KMAX>
 __global__ void __launch_bounds__(NT) k_small_inverse(cd* __restrict__ mats, int K,
                                                       int* __restrict__ fail) {
-  __shared__ cd A[32 * 32];
-  __shared__ cd fcol[32];
-  __shared__ int perm[32];
+  __shared__ cd A[KMAX * KMAX];
+  __shared__ cd fcol[KMAX];
+  __shared__ int perm[KMAX];
   __shared__ cd pivinv;
   __shared__ int prow;
   const int tid = threadIdx.x;
@@ -1086,6 +1087,222 @@ __global__ void __launch_bounds__(NT) k_sap2p_h(const chalf* __restrict__ M, con
       for (int v = 0; v < 4; ++v)
         x[rrow * n + (u0 + rt) * CM + 4 * q + v] = mk<float>(rv[rt].re[v] - acc.re[v], rv[rt].im[v] - acc.im[v]);
     }
+  }
+}
+
+// ---- 2x2-site SAP blocks (K = 64) in premultiplied form, every precision:
+// x_B = rho_B - M_B x_H with M_B = inv_B D_BH (64 x 128: the eight outward
+// hops, 16 dofs each) formed at setup and rho_B = inv_B r_B formed by each
+// colour's first sweep of a smoothing visit.  Sites s = 2 dt + dx of the
+// block (t-major, the order of the block extraction); hop h = 2 s + e leaves
+// site s along x (e = 0: -x for dx = 0, +x for dx = 1) or t (e = 1: -t for
+// dt = 0, +t for dt = 1).  A wave owns the 32 rows of sites 2 hh, 2 hh + 1
+// (hh its row half) for 16 RHS and sums its 16 hop products itself: no LDS,
+// no barrier.
+__device__ __forceinline__ int sap4_hop_dir(int h) {
+  const int s = h >> 1;
+  return (h & 1) ? ((s >> 1) ? 3 : 4) : ((s & 1) ? 1 : 2);
+}
+__device__ __forceinline__ int64_t sap4_site(int blk, int s, int Nx) {
+  const int NBx = Nx / 2;
+  return (int64_t)((blk / NBx) * 2 + (s >> 1)) * Nx + (blk % NBx) * 2 + (s & 1);
+}
+
+// M[blk][h][row][col] = sum_k inv[blk][row][16 s(h) + k] B[u_s(h)][dir(h)][k][col], in FP64
+__global__ void __launch_bounds__(NT) k_sap4_premul(const cd* __restrict__ B, const cd* __restrict__ inv,
+                                                    int Nx, int nblk, cd* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)nblk * 8 * 64 * CM) return;
+  const int col = (int)(e % CM), row = (int)((e / CM) % 64), h = (int)((e / (CM * 64)) % 8);
+  const int blk = (int)(e / (CM * 64 * 8));
+  const int64_t us = sap4_site(blk, h >> 1, Nx);
+  const cd* ir = inv + ((int64_t)blk * 64 + row) * 64 + 16 * (h >> 1);
+  const cd* bc = B + ((us * 5 + sap4_hop_dir(h)) * CM) * CM + col;
+  cd acc = mk(0.0, 0.0);
+  for (int k = 0; k < CM; ++k) cfma(acc, ir[k], bc[(int64_t)k * CM]);
+  M[e] = acc;
+}
+
+// FP16 operands (FP32 vectors, FP32 accumulation) on the 16x16x16 matrix cores
+template <bool FIRST>
+__global__ void __launch_bounds__(NT) k_sap4p_h(const chalf* __restrict__ M, const chalf* __restrict__ inv,
+                                                int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                const cf* __restrict__ rr, cf* __restrict__ rho,
+                                                cf* __restrict__ x, const int* __restrict__ active) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int hh = wave & 1;
+  const int r0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
+  if (r0 >= nrhs) return;
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;  // lanes past the last RHS read row r0; never stored
+  // every load of the wave is issued before the first product
+  h4 br[8], bi[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const cf* xv = x + rrow * n + nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt) * CM + 4 * q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cf v = xv[j];
+      br[h][j] = (_Float16)v.re;
+      bi[h][j] = (_Float16)v.im;
+    }
+  }
+  h4 ar[2][8], ai[2][8];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const chalf* a = M + (((int64_t)blk * 8 + h) * 64 + (2 * hh + rt) * 16 + i) * CM + 4 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const chalf av = a[j];
+        ar[rt][h][j] = av.re;
+        ai[rt][h][j] = av.im;
+      }
+    }
+  CAcc<float> rv[2];
+  if constexpr (FIRST) {
+    // rho rows of site 2 hh + rt: sum over the block's sites kt of inv_B[.][kt] r_kt
+    h4 sr[4], si[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      const cf* rv_ = rr + rrow * n + sap4_site(blk, kt, Nx) * CM + 4 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cf v = rv_[j];
+        sr[kt][j] = (_Float16)v.re;
+        si[kt][j] = (_Float16)v.im;
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      rv[rt] = CAcc<float>{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        const chalf* a = inv + ((int64_t)blk * 64 + (2 * hh + rt) * 16 + i) * 64 + kt * 16 + 4 * q;
+        h4 ir, ii;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const chalf av = a[j];
+          ir[j] = av.re;
+          ii[j] = av.im;
+        }
+        hmma(ir, ii, sr[kt], si[kt], rv[rt]);
+      }
+      if (ok) {
+        const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rho[rrow * n + u * CM + 4 * q + v] = mk<float>(rv[rt].re[v], rv[rt].im[v]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const cf t = rho[rrow * n + u * CM + 4 * q + v];
+        rv[rt].re[v] = t.re;
+        rv[rt].im[v] = t.im;
+      }
+    }
+  }
+  const bool on = ok && (!active || active[rrow] != 0);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int h = 0; h < 8; ++h) hmma(ar[rt][h], ai[rt][h], br[h], bi[h], acc);
+    if (on) {
+      const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        x[rrow * n + u * CM + 4 * q + v] = mk<float>(rv[rt].re[v] - acc.re[v], rv[rt].im[v] - acc.im[v]);
+    }
+  }
+}
+
+// FP32 / FP64 operands on the 16x16x4 matrix cores (K chunks of 4 per hop;
+// in chunk c lane l takes the K index out_row(l, c), so a product's result
+// layout is the next one's B layout, as for the coarse stencil)
+template <class T, bool FIRST>
+__global__ void __launch_bounds__(NT) k_sap4p(const cx<T>* __restrict__ M, const cx<T>* __restrict__ inv,
+                                              int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                              const cx<T>* __restrict__ rr, cx<T>* __restrict__ rho,
+                                              cx<T>* __restrict__ x, const int* __restrict__ active) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15;
+  const int hh = wave & 1;
+  const int r0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
+  if (r0 >= nrhs) return;
+  const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  CAcc<T> rv[2];
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      rv[rt] = CAcc<T>{{0, 0, 0, 0}, {0, 0, 0, 0}};
+      const cx<T>* ir = inv + ((int64_t)blk * 64 + (2 * hh + rt) * 16 + i) * 64;
+      for (int kt = 0; kt < 4; ++kt) {
+        const cx<T>* rv_ = rr + rrow * n + sap4_site(blk, kt, Nx) * CM;
+        cx<T> a[4], b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int k = MF<T>::out_row(lane, c);
+          a[c] = ir[kt * 16 + k];
+          b[c] = rv_[k];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cmma(a[c], b[c], rv[rt]);
+      }
+      if (ok) {
+        const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          rho[rrow * n + u * CM + MF<T>::out_row(lane, v)] = mk<T>(rv[rt].re[v], rv[rt].im[v]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const cx<T> t = rho[rrow * n + u * CM + MF<T>::out_row(lane, v)];
+        rv[rt].re[v] = t.re;
+        rv[rt].im[v] = t.im;
+      }
+    }
+  }
+  CAcc<T> acc[2] = {CAcc<T>{{0, 0, 0, 0}, {0, 0, 0, 0}}, CAcc<T>{{0, 0, 0, 0}, {0, 0, 0, 0}}};
+#pragma unroll 2
+  for (int h = 0; h < 8; ++h) {
+    const cx<T>* xv = x + rrow * n + nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt) * CM;
+    cx<T> b[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = xv[MF<T>::out_row(lane, c)];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const cx<T>* a = M + (((int64_t)blk * 8 + h) * 64 + (2 * hh + rt) * 16 + i) * CM;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cmma(a[MF<T>::out_row(lane, c)], b[c], acc[rt]);
+    }
+  }
+  if (!ok || (active && !active[rrow])) return;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      x[rrow * n + u * CM + MF<T>::out_row(lane, v)] =
+          mk<T>(rv[rt].re[v] - acc[rt].re[v], rv[rt].im[v] - acc[rt].im[v]);
   }
 }
 
@@ -1960,6 +2177,39 @@ void launch_sap2_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, 
   KCHK();
 }
 
+void launch_sap4_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, cd* M) {
+  const int64_t cnt = (int64_t)nblk * 8 * 64 * CM;
+  hipLaunchKernelGGL(k_sap4_premul, dim3((unsigned)((cnt + NT - 1) / NT)), dim3(NT), 0, s, blocks, inv, Nx, nblk, M);
+  KCHK();
+}
+
+void launch_sap4p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active) {
+  if (nb <= 0 || nrhs <= 0) return;
+  const dim3 g(nb, ((nrhs + 15) / 16 + 1) / 2);
+  if (first)
+    hipLaunchKernelGGL(k_sap4p_h<true>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+  else
+    hipLaunchKernelGGL(k_sap4p_h<false>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+  KCHK();
+}
+
+template <class T>
+void launch_sap4p(hipStream_t s, const cx<T>* M, const cx<T>* inv, int Nx, int Nt, const int* blist, int nb,
+                  int nrhs, bool first, const cx<T>* r, cx<T>* rho, cx<T>* x, const int* active) {
+  if (nb <= 0 || nrhs <= 0) return;
+  const dim3 g(nb, ((nrhs + 15) / 16 + 1) / 2);
+  if (first)
+    hipLaunchKernelGGL((k_sap4p<T, true>), g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+  else
+    hipLaunchKernelGGL((k_sap4p<T, false>), g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+  KCHK();
+}
+template void launch_sap4p<double>(hipStream_t, const cd*, const cd*, int, int, const int*, int, int, bool,
+                                   const cd*, cd*, cd*, const int*);
+template void launch_sap4p<float>(hipStream_t, const cf*, const cf*, int, int, const int*, int, int, bool,
+                                  const cf*, cf*, cf*, const int*);
+
 void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
                     int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active) {
   if (nb <= 0) return;
@@ -2038,8 +2288,11 @@ void launch_sap_extract(hipStream_t s, const cd* B, int Nx, int Nt, int M, int s
 }
 
 void launch_small_inverse(hipStream_t s, cd* mats, int K, int count, int* fail) {
-  require(K >= 1 && K <= 32, "SAP block too large: sbx*sbt*M must be <= 32");
-  hipLaunchKernelGGL(k_small_inverse, dim3(count), dim3(NT), 0, s, mats, K, fail);
+  require(K >= 1 && K <= 64, "SAP block too large: sbx*sbt*M must be <= 64");
+  if (K <= 32)
+    hipLaunchKernelGGL(k_small_inverse<32>, dim3(count), dim3(NT), 0, s, mats, K, fail);
+  else
+    hipLaunchKernelGGL(k_small_inverse<64>, dim3(count), dim3(NT), 0, s, mats, K, fail);
   KCHK();
 }
 

@@ -130,6 +130,27 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   } else {
     launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
   }
+  if (L.M == 16 && L.sbx == 2 && L.sbt == 2 && L.sap_cycles > 0) {
+    // premultiplied 2x2-site sweeps x_B = rho_B - M_B x_H; the first cycle
+    // forms rho_B = inv_B r_B and keeps it for the others
+    require(D.sapM.p && D.sapinv.p, "2x2 SAP blocks: premultiplied operator missing", MGM_ESTATE);
+    Work<T>& W = work<T>(L, c->wslot);
+    W.rho.ensure(sizeof(cx<T>) * (size_t)nrhs * L.n);
+    for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
+      for (int col = 0; col < 2; ++col) {
+        const int* bl = L.color_list[col].as<int>();
+        if constexpr (std::is_same<T, float>::value) {
+          if (half_blocks(g, L)) {
+            launch_sap4p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, bl, L.ncolor[col], nrhs,
+                           cyc == 0, r, W.rho.template as<cf>(), x, act);
+            continue;
+          }
+        }
+        launch_sap4p<T>(s, D.sapM.template as<cx<T>>(), D.sapinv.template as<cx<T>>(), L.Nx, L.Nt, bl,
+                        L.ncolor[col], nrhs, cyc == 0, r, W.rho.template as<cx<T>>(), x, act);
+      }
+    return;
+  }
   bool half = false;
   if constexpr (std::is_same<T, float>::value) {
     half = half_blocks(g, L) && L.sbt == 1 && (L.sbx == 1 || L.sbx == 2);
@@ -552,7 +573,11 @@ void build_sap(mgm_ctx* c, Level& L, int sbx, int sbt) {
   L.sbx = sbx;
   L.sbt = sbt;
   L.K = sbx * sbt * L.M;
-  require(L.K <= 32, "SAP block too large: sbx*sbt*dofs must be <= 32");
+  // 2x2 sites of 16 dofs (K = 64) run in premultiplied form, whose eight
+  // outward hops must leave the block: at least two blocks per direction
+  const bool quad = L.M == 16 && sbx == 2 && sbt == 2;
+  require(L.K <= 32 || quad, "SAP block too large: sbx*sbt*dofs must be <= 32 (or 2x2 sites of 16 dofs)");
+  require(!quad || (NBx >= 2 && NBt >= 2), "2x2 SAP blocks need at least two blocks per direction");
   L.nblk = NBx * NBt;
   L.d.sapinv.ensure(sizeof(cd) * (size_t)L.nblk * L.K * L.K);
   launch_sap_extract(s, L.d.B(), L.Nx, L.Nt, L.M, sbx, sbt, L.d.sapinv.as<cd>());
@@ -573,6 +598,11 @@ void build_sap(mgm_ctx* c, Level& L, int sbx, int sbt) {
   }
   HIPCHK(hipStreamSynchronize(s));
   require(!hf, "singular SAP block", MGM_ENONFINITE);
+  if (quad) {  // M_B = inv_B D_BH of the premultiplied sweeps (the setup's own solves use it)
+    L.d.sapM.ensure(sizeof(cd) * (size_t)L.nblk * 8 * 64 * 16);
+    launch_sap4_premul(s, L.d.blocks.as<cd>(), L.d.sapinv.as<cd>(), L.Nx, L.nblk, L.d.sapM.as<cd>());
+    HIPCHK(hipStreamSynchronize(s));
+  }
 }
 
 template <class TO>
@@ -697,6 +727,7 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
       HIPCHK(hipStreamSynchronize(s));
       if (h) L.f.hdinv.release();
     }
+    copy_convert<float>(c, L.d.sapM, L.f.sapM);
     if (L.M == 16 && L.d.sapinv.p) {  // FP16 blocks for the FP16 mode
       const int64_t nbk = (int64_t)(L.d.blocks.bytes / sizeof(cd));
       const int64_t nin = (int64_t)(L.d.sapinv.bytes / sizeof(cd));
@@ -707,6 +738,11 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
       if (L.sbx == 2 && L.sbt == 1 && L.nblk > 0) {
         L.f.hsapM.ensure(sizeof(chalf) * (size_t)L.nblk * 6 * 32 * 16);  // 16 dofs per site
         launch_sap2_premul(s, L.d.blocks.as<cd>(), L.d.sapinv.as<cd>(), L.Nx, L.nblk, L.f.hsapM.as<chalf>());
+      }
+      if (L.sbx == 2 && L.sbt == 2 && L.d.sapM.p) {
+        const int64_t nm = (int64_t)(L.d.sapM.bytes / sizeof(cd));
+        L.f.hsapM.ensure(sizeof(chalf) * nm);
+        launch_to_half(s, L.d.sapM.as<cd>(), L.f.hsapM.as<chalf>(), nm);
       }
     }
   }

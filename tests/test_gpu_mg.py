@@ -220,3 +220,35 @@ def test_fp16_coarsest_solve(ctx, L, nrhs):
     assert errs["fp32"] < 1e-5
     assert errs["fp16"] < 5e-3
     assert errs["fp16"] > 10 * errs["fp32"]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 1e-4), ("fp16", 3e-2)])
+@pytest.mark.parametrize("L", [32, 64])
+def test_quad_site_sap_blocks(ctx, precision, tol, L):
+    """Coarse SAP with 2x2-site blocks (K = 64, premultiplied sweeps
+    x_B = rho_B - M_B x_H in every precision) inside a V-cycle, against the
+    oracle's cycle (exact block solves, red/black); level 1 holds 4x4 and 8x8
+    blocks, 20 RHS (a ragged second RHS tile); then FP64 FGMRES reaches 1e-10
+    with it."""
+    from paper_2303_11512_amd import solve_params
+    th = metropolis_u1(L, L, 3.0, 100, 975 + L)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (2, 2), (1, 1)],
+                 sap_cycles=[2, 3, 2], inner_iters=[0, 0, 0], precision=precision)
+    log(f"2x2 SAP blocks, L={L}, {precision}")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    kc = rec.kcycle(hier)
+    for l in range(2):
+        lev = hier.levels[l]
+        r = rhs_vectors(lev.n, 20, 180 + l)
+        x = empty(20, lev.n)
+        ctx.precondition(gid, l, to_dev(r), x)
+        assert rel_err(to_host(x), kc.apply(l, r.T).T) < tol, (precision, l)
+    for l in range(2):
+        lev = hier.levels[l]
+        b = rhs_vectors(lev.n, 6, 37 + l)
+        x = empty(6, lev.n)
+        ctx.solve_batch(gid, l, to_dev(b), x, solve_params(tol=1e-10, restart=24))
+        res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
+        assert np.all(res <= 1e-10), (precision, l, res)
+    ctx.free_gauge(gid)
