@@ -334,9 +334,29 @@ struct Estimator {
     if (todo.size() < 2 || !p.concurrent) {
       for (int j : todo) solve_on(c, j, total[j], src[j], out(j), cnt, lits[j]);
     } else {
-      // worker 0: iterative levels on stream 2; worker 1: exact levels on stream 3
-      std::vector<int> part[2];
-      for (size_t q = 1; q < todo.size(); ++q) part[g.levels[todo[q]]->has_dense ? 1 : 0].push_back(todo[q]);
+      // worker 0: iterative levels on stream 2; worker 1: exact levels on
+      // stream 3, then the second half of an iterative level with more than
+      // 64 right-hand sides (its solves are independent per RHS)
+      struct Job {
+        int j, off, k;
+        std::vector<int> its;
+      };
+      std::vector<Job> part[2];
+      for (size_t q = 1; q < todo.size(); ++q) {
+        const int j = todo[q];
+        if (g.levels[j]->has_dense) part[1].push_back({j, 0, total[j], {}});
+      }
+      for (size_t q = 1; q < todo.size(); ++q) {
+        const int j = todo[q];
+        if (g.levels[j]->has_dense) continue;
+        if (total[j] > 64) {
+          const int k0 = (total[j] / 2 + 15) / 16 * 16;
+          part[0].push_back({j, 0, k0, {}});
+          part[1].push_back({j, k0, total[j] - k0, {}});
+        } else {
+          part[0].push_back({j, 0, total[j], {}});
+        }
+      }
       if (part[0].empty()) part[0].swap(part[1]);
       ensure_stream2();
       HIPCHK(hipEventRecord(g.ev_fork, c->stream));
@@ -355,7 +375,11 @@ struct Estimator {
           w.wslot = 1 + k;
           try {
             HIPCHK(hipSetDevice(c->device));
-            for (int j : part[k]) solve_on(&w, j, total[j], src[j], out(j), wcnt[k], lits[j]);
+            for (Job& jb : part[k]) {
+              const int64_t n = g.levels[jb.j]->n;
+              solve_on(&w, jb.j, jb.k, src[jb.j] + (int64_t)jb.off * n, out(jb.j) + (int64_t)jb.off * n, wcnt[k],
+                       jb.its);
+            }
           } catch (const Error& e) {
             wst[k] = e.code;
             wmsg[k] = e.what();
@@ -386,6 +410,11 @@ struct Estimator {
       if (st != MGM_OK) throw Error(st, msg);
       for (int k = 0; k < 2; ++k)
         if (wst[k] != MGM_OK) throw Error(wst[k], wmsg[k]);
+      for (int k = 0; k < 2; ++k)
+        for (const Job& jb : part[k]) {
+          lits[jb.j].resize(total[jb.j]);
+          std::copy(jb.its.begin(), jb.its.end(), lits[jb.j].begin() + jb.off);
+        }
     }
     for (int j = 0; j < L; ++j) {
       res.lvl_solves[j] += (int)(cnt[j][0] + wcnt[0][j][0] + wcnt[1][j][0]);
