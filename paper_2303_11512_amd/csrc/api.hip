@@ -492,7 +492,15 @@ int mgm_time_kernel(mgm_ctx* c, int gauge_id, int kind, int level, int nrhs, int
         // the premultiplied two-site sweep x_B = rho_B - M_B x_H of the later
         // cycles (rf stands in for rho)
         const bool premul = half && L.sbx == 2 && L.f.hsapM.p != nullptr;
-        if (quad && half) {
+        // the fine level's FP32 cycle runs its sweeps in the block-major layout
+        const bool fblk = L.M == 2 && L.sbx == 4 && L.sbt == 4 && L.has_coarse && L.bx == 4 && L.bt == 4 &&
+                          L.ntv == 8;
+        if (fblk) {
+          launch = [=, &L] {
+            launch_sap0_blk(s, L.f.B(), L.f.sapinv.as<cf>(), L.Nx, L.Nt, L.color_list[0].as<int>(), L.ncolor[0],
+                            nrhs, rf, xf, nullptr, nullptr);
+          };
+        } else if (quad && half) {
           launch = [=, &L] {
             launch_sap4p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.color_list[0].as<int>(),
                            L.ncolor[0], nrhs, false, nullptr, rf, xf, nullptr);

@@ -425,13 +425,25 @@ __global__ void __launch_bounds__(NT) k_scale_r(const cx<T>* __restrict__ w, con
     v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
 }
 
-// k_scale_r (without den_out) that also stores the FP32 rounding of v in vf:
-// the scaling that ends an Arnoldi step, done by the next step's first launch
-// together with the rounding of the preconditioner's input
+// Position of fine-level dof k (lattice layout: site-major, 2 dofs) in the
+// block-major layout of the fine FP32 cycle (4x4-site blocks of 32 dofs,
+// sites t-major within a block); Nx = 0: the lattice layout itself
+__device__ __forceinline__ int64_t blk_pos(int64_t k, int Nx) {
+  if (Nx == 0) return k;
+  const int64_t site = k >> 1;
+  const int x = (int)(site % Nx), t = (int)(site / Nx);
+  return ((int64_t)(t >> 2) * (Nx >> 2) + (x >> 2)) * 32 + (((t & 3) << 2) + (x & 3)) * 2 + (k & 1);
+}
+
+// k_scale_r (without den_out) that also stores the FP32 rounding of v in vf
+// (block-major when blk_nx > 0): the scaling that ends an Arnoldi step, done
+// by the next step's first launch together with the rounding of the
+// preconditioner's input
 template <class T>
 __global__ void __launch_bounds__(NT) k_scale_convert(const cx<T>* __restrict__ w, const T* __restrict__ npart,
                                                       int nch, int64_t n, cx<T>* __restrict__ v,
-                                                      cf* __restrict__ vf, const int* __restrict__ active) {
+                                                      cf* __restrict__ vf, const int* __restrict__ active,
+                                                      int blk_nx) {
   __shared__ T dsh;
   const int r = blockIdx.y;
   if (active && !active[r]) return;
@@ -448,7 +460,16 @@ __global__ void __launch_bounds__(NT) k_scale_convert(const cx<T>* __restrict__ 
   for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
     const cx<T> vv = s * w[(int64_t)r * n + k];
     v[(int64_t)r * n + k] = vv;
-    vf[(int64_t)r * n + k] = mk<float>((float)vv.re, (float)vv.im);
+    vf[(int64_t)r * n + blk_pos(k, blk_nx)] = mk<float>((float)vv.re, (float)vv.im);
+  }
+}
+
+// FP32 rounding of a fine-level FP64 block [nrhs][n] into the block-major layout
+__global__ void __launch_bounds__(NT) k_convert_blk(const cd* __restrict__ in, cf* __restrict__ out, int Nx,
+                                                    int64_t n, int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < count; e += (int64_t)gridDim.x * NT) {
+    const int64_t r = e / n, k = e % n;
+    out[r * n + blk_pos(k, Nx)] = mk<float>((float)in[e].re, (float)in[e].im);
   }
 }
 
@@ -913,10 +934,18 @@ void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
 
 template <class T>
 void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
-                          const int* active) {
+                          const int* active, int blk_nx) {
   const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
   unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
-  hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active);
+  hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active,
+                     blk_nx);
+  KCHK();
+}
+
+void launch_convert_blk(hipStream_t s, const cd* in, cf* out, int Nx, int Nt, int nrhs) {
+  const int64_t n = (int64_t)Nx * Nt * 2, cnt = n * nrhs;
+  const unsigned gx = (unsigned)std::min<int64_t>((cnt + NT - 1) / NT, 4096);
+  hipLaunchKernelGGL(k_convert_blk, dim3(gx), dim3(NT), 0, s, in, out, Nx, n, cnt);
   KCHK();
 }
 
@@ -1191,7 +1220,7 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                        const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,     \
                                        const int*, cx<T>*);                                        \
   template void launch_scale_convert<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,  \
-                                        cf*, const int*);                                          \
+                                        cf*, const int*, int);                                     \
   template void launch_hcol_givens_np<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,     \
                                          const T*, int64_t, cx<T>*, T*, cx<T>*, cx<T>*, const T*,   \
                                          int*, int*, int*);                                        \

@@ -237,6 +237,18 @@ void launch_dense_from_stencil(hipStream_t s, const cd* B, int Nx, int Nt, int M
 // FP16-block variants for coarse levels with 16 dofs per site (FP32 vectors,
 // FP16 matrix-core products, FP32 accumulation)
 void launch_to_half(hipStream_t s, const cd* in, chalf* out, int64_t count);
+// The fine level's FP32 cycle in the block-major layout (4x4-site blocks =
+// 4x4 aggregates, 2 dofs, 8 test vectors: a block's 32 dofs contiguous, sites
+// t-major): restriction from it, prolongation into it (overwriting), one SAP
+// colour sweep in it (x64: the result also widened to FP64 in the lattice
+// layout, or null), and the FP64 lattice -> FP32 block-major rounding
+void launch_restrict_blk(hipStream_t s, const cf* P, int Nx, int Nt, int nrhs, const cf* xf, cf* xc,
+                         const int* active);
+void launch_prolong_blk(hipStream_t s, const cf* P, int Nx, int Nt, int nrhs, const cf* xc, cf* yf,
+                        const int* active);
+void launch_sap0_blk(hipStream_t s, const cf* B, const cf* inv, int Nx, int Nt, const int* blist, int nb,
+                     int nrhs, const cf* r, cf* x, const int* active, cd* x64);
+void launch_convert_blk(hipStream_t s, const cd* in, cf* out, int Nx, int Nt, int nrhs);
 // the same, setting *overflow (device) when a component is not finite in FP16
 void launch_to_half_checked(hipStream_t s, const cd* in, chalf* out, int64_t count, int* overflow);
 // y[r] = A x[r], A n x n in FP16 (x rounded to FP16, FP32 accumulation), n % 256 == 0
@@ -324,10 +336,11 @@ void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                          int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                          const int* active, cx<T>* dpart2);
 // v = w / |w| from the chunk partials of |w|^2 (chunking of
-// launch_update_multi_r), and vf = v rounded to FP32
+// launch_update_multi_r), and vf = v rounded to FP32 (in the fine level's
+// block-major layout when blk_nx = Nx > 0)
 template <class T>
 void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
-                          const int* active);
+                          const int* active, int blk_nx = 0);
 // launch_hcol_givens with |w| formed from the chunk partials of |w|^2
 template <class T>
 void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,

@@ -426,7 +426,9 @@ __global__ void __launch_bounds__(NT) k_prolong(const cx<T>* __restrict__ P, int
 // shift or a multiply and the row loop is unrolled, so a thread issues all of
 // its loads at once instead of one dependent round trip per aggregate row;
 // the generic kernels above are latency bound for exactly that reason.
-template <class T, int M, int BX, int BT, int NTV>
+// BLK: xf in the block-major layout of the fine FP32 cycle (the BX x BT
+// aggregate's sites t-major, then dofs, contiguous per aggregate)
+template <class T, int M, int BX, int BT, int NTV, bool BLK = false>
 __global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, int Nx, int Nt,
                                                    const cx<T>* __restrict__ xf, cx<T>* __restrict__ xc,
                                                    const int* __restrict__ active) {
@@ -443,14 +445,15 @@ __global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, 
   const int c = (int)(Ac % 2);
   const int Ax = (int)(A % NAx), At = (int)(A / NAx);
   const cx<T>* __restrict__ xr =
-      xf + (int64_t)r * Nx * Nt * M + ((int64_t)At * BT * Nx + (int64_t)Ax * BX) * M + c * Mh;
+      BLK ? xf + (int64_t)r * Nx * Nt * M + A * (BX * BT * M) + c * Mh
+          : xf + (int64_t)r * Nx * Nt * M + ((int64_t)At * BT * Nx + (int64_t)Ax * BX) * M + c * Mh;
   const cx<T>* __restrict__ Pc = P + Ac * NROW * NTV + k;
   cx<T> pv[NROW], xv[NROW];
 #pragma unroll
   for (int s = 0; s < NROW; ++s) {
     const int sl = s / Mh, a = s % Mh;
     pv[s] = Pc[s * NTV];
-    xv[s] = xr[((int64_t)(sl / BX) * Nx + sl % BX) * M + a];
+    xv[s] = BLK ? xr[sl * M + a] : xr[((int64_t)(sl / BX) * Nx + sl % BX) * M + a];
   }
   cx<T> acc = mk<T>(0, 0);
 #pragma unroll
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, 
   xc[(int64_t)r * nc + idx] = acc;
 }
 
-template <class T, int M, int BX, int BT, int NTV>
+template <class T, int M, int BX, int BT, int NTV, bool BLK = false>
 __global__ void __launch_bounds__(NT) k_prolong_t(const cx<T>* __restrict__ P, int Nx, int Nt,
                                                   const cx<T>* __restrict__ xc, cx<T>* __restrict__ yf,
                                                   int accumulate, const int* __restrict__ active) {
@@ -470,12 +473,21 @@ __global__ void __launch_bounds__(NT) k_prolong_t(const cx<T>* __restrict__ P, i
   if (row >= n) return;
   const int NAx = Nx / BX;
   const int64_t nc = (int64_t)NAx * (Nt / BT) * 2 * NTV;
-  const int64_t site = row / M;
-  const int alpha = (int)(row % M);
-  const int c = alpha / Mh, a = alpha % Mh;
-  const int sx = (int)(site % Nx), st = (int)(site / Nx);
-  const int64_t Ac = ((int64_t)(st / BT) * NAx + sx / BX) * 2 + c;
-  const int s = ((st % BT) * BX + (sx % BX)) * Mh + a;
+  int64_t Ac;
+  int s;
+  if (BLK) {  // row = aggregate * BX BT M + sl M + alpha
+    const int64_t A = row / (BX * BT * M);
+    const int q = (int)(row % (BX * BT * M)), alpha = q % M;
+    Ac = A * 2 + alpha / Mh;
+    s = (q / M) * Mh + alpha % Mh;
+  } else {
+    const int64_t site = row / M;
+    const int alpha = (int)(row % M);
+    const int c = alpha / Mh, a = alpha % Mh;
+    const int sx = (int)(site % Nx), st = (int)(site / Nx);
+    Ac = ((int64_t)(st / BT) * NAx + sx / BX) * 2 + c;
+    s = ((st % BT) * BX + (sx % BX)) * Mh + a;
+  }
   const cx<T>* __restrict__ Pr = P + (Ac * NROW + s) * NTV;
   const cx<T>* __restrict__ xv = xc + (int64_t)r * nc + Ac * NTV;
   cx<T> pv[NTV], cv[NTV];
@@ -1389,8 +1401,12 @@ __global__ void __launch_bounds__(NT) k_sap2_mfma(const cx<T>* __restrict__ B, c
 // the halo term on the vector units, the 32 x 32 solve as two 16-row tiles
 // of complex MFMAs over 8 K-chunks.
 // x64 (or null): the block's new values are also stored widened to FP64
-// there (the last sweeps of an FP32 cycle write its FP64 result directly).
-template <class T>
+// there, in the lattice layout (the last sweeps of an FP32 cycle write its
+// FP64 result directly).  BLK: r and x in the block-major layout (a block's
+// 32 dofs contiguous, sites t-major), so that a colour's sweep fetches only
+// its own r and the other colour's x; unused hop slots then read the row's
+// +x neighbour outside the block, which that row's last site loads anyway.
+template <class T, bool BLK = false>
 __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, const cx<T>* __restrict__ inv,
                                                   int Nx, int Nt, const int* __restrict__ blist, int nrhs,
                                                   const cx<T>* __restrict__ rr, cx<T>* __restrict__ x,
@@ -1421,12 +1437,22 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   const int gx = bx + sx, gt = bt + st;
   const int own = gt * Nx + gx;
   // at most two outward hops per site of a 4x4 block; unused slots point at
-  // the site itself so that every load is unconditional
-  int nbs[2] = {own, own}, dirs[2] = {0, 0}, nh = 0;
+  // the site itself (BLK: at the row's +x neighbour) so that every load is
+  // unconditional
+  const int fill = BLK ? gt * Nx + (bx + SB == Nx ? 0 : bx + SB) : own;
+  int nbs[2] = {fill, fill}, dirs[2] = {0, 0}, nh = 0;
   if (sx == SB - 1) { dirs[nh] = 1; nbs[nh++] = gt * Nx + (gx + 1 == Nx ? 0 : gx + 1); }
   if (sx == 0) { dirs[nh] = 2; nbs[nh++] = gt * Nx + (gx == 0 ? Nx - 1 : gx - 1); }
   if (st == SB - 1) { dirs[nh] = 3; nbs[nh++] = (gt + 1 == Nt ? 0 : gt + 1) * Nx + gx; }
   if (st == 0) { dirs[nh] = 4; nbs[nh++] = (gt == 0 ? Nt - 1 : gt - 1) * Nx + gx; }
+  // offsets of the two dofs of a site in r / x (lattice or block-major)
+  auto vofs = [&](int v) -> int64_t {
+    if (!BLK) return (int64_t)v * 2;
+    const int vx = v % Nx, vt = v / Nx;
+    return (int64_t)((vt / SB) * NBx + vx / SB) * K + ((vt % SB) * SB + vx % SB) * 2;
+  };
+  const int64_t own_o = BLK ? (int64_t)blk * K + k : (int64_t)own * 2 + a;
+  const int64_t nbo[2] = {vofs(nbs[0]), vofs(nbs[1])};
   __syncthreads();
   cx<T> bb[2][2];
 #pragma unroll
@@ -1442,12 +1468,12 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
     const int r = r0 + ri;
     const int64_t rc = r < nrhs ? r : 0;
     const cx<T>* xr = x + rc * n;
-    cx<T> acc = rr[rc * n + (int64_t)own * 2 + a];
+    cx<T> acc = rr[rc * n + own_o];
     cx<T> xh[2][2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      xh[j][0] = xr[(int64_t)nbs[j] * 2];
-      xh[j][1] = xr[(int64_t)nbs[j] * 2 + 1];
+      xh[j][0] = xr[nbo[j]];
+      xh[j][1] = xr[nbo[j] + 1];
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc = acc - bb[j][0] * xh[j][0] - bb[j][1] * xh[j][1];
@@ -1483,7 +1509,7 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
     const int r = r0 + ri;
     if (r < nrhs && !(active && !active[r])) {
       const cx<T> v = Hs[wave][ri][k];
-      x[(int64_t)r * n + (int64_t)own * 2 + a] = v;
+      x[(int64_t)r * n + own_o] = v;
       if (x64) x64[(int64_t)r * n + (int64_t)own * 2 + a] = mk((double)v.re, (double)v.im);
     }
   }
@@ -2271,6 +2297,30 @@ template void launch_prolong<double>(hipStream_t, const cd*, int, int, int, int,
                                      const cd*, cd*, int, const int*);
 template void launch_prolong<float>(hipStream_t, const cf*, int, int, int, int, int, int, int,
                                     const cf*, cf*, int, const int*);
+
+void launch_sap0_blk(hipStream_t s, const cf* B, const cf* inv, int Nx, int Nt, const int* blist, int nb,
+                     int nrhs, const cf* r, cf* x, const int* active, cd* x64) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_sap0_mfma<float, true>), dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
+                     nrhs, r, x, active, x64);
+  KCHK();
+}
+
+void launch_restrict_blk(hipStream_t s, const cf* P, int Nx, int Nt, int nrhs, const cf* xf, cf* xc,
+                         const int* active) {
+  const int64_t nc = (int64_t)(Nx / 4) * (Nt / 4) * 2 * 8;
+  hipLaunchKernelGGL((k_restrict_t<float, 2, 4, 4, 8, true>), dim3(grid1(nc), nrhs), dim3(NT), 0, s, P, Nx, Nt,
+                     xf, xc, active);
+  KCHK();
+}
+
+void launch_prolong_blk(hipStream_t s, const cf* P, int Nx, int Nt, int nrhs, const cf* xc, cf* yf,
+                        const int* active) {
+  const int64_t n = (int64_t)Nx * Nt * 2;
+  hipLaunchKernelGGL((k_prolong_t<float, 2, 4, 4, 8, true>), dim3(grid1(n), nrhs), dim3(NT), 0, s, P, Nx, Nt, xc,
+                     yf, 0, active);
+  KCHK();
+}
 
 void launch_galerkin(hipStream_t s, const cd* Bf, int Nx, int Nt, int Mf, const cd* P, int bx,
                      int bt, int ntv, cd* Bc) {

@@ -85,6 +85,21 @@ template <class T>
 void fgmres_inner(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* b, cx<T>* x, int m, T tol,
                   const int* parent);
 
+// whether precond<float> on level l can hand its result over in FP64 itself
+// (last SAP cycle on 4x4-site blocks of 2 dofs)
+bool precond_writes_fp64(const Gauge& g, const Level& L) {
+  return L.M == 2 && L.sbx == 4 && L.sbt == 4 && L.sap_cycles > 0 && !L.is_coarsest &&
+         !(half_blocks(g, L) && L.sbt == 1);
+}
+
+// whether the FP32 cycle on level l keeps its vectors in the block-major
+// layout (SAP blocks = aggregates = 4x4 sites of 2 dofs, 8 test vectors; its
+// input is rounded into that layout and its FP64 result written back in the
+// lattice layout by the last SAP sweeps)
+bool fine_blocked(const Gauge& g, const Level& L) {
+  return precond_writes_fp64(g, L) && L.has_coarse && L.bx == 4 && L.bt == 4 && L.ntv == 8;
+}
+
 // x = D^{-1} r on the coarsest level from its dense inverse (in the FP16
 // mode the FP16 copy, when the inverse fits FP16's range)
 template <class T>
@@ -110,6 +125,30 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
   if (L.is_coarsest) {
     coarse_solve<T>(c, g, L, nrhs, r, x, act);
     return;
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (x64 && fine_blocked(g, L)) {  // r and x block-major, the result also into x64
+      Level& C = *g.levels[l + 1];
+      Work<float>& W = work<float>(L, c->wslot);
+      W.rc.ensure(sizeof(cf) * (size_t)nrhs * C.n);
+      W.ec.ensure(sizeof(cf) * (size_t)nrhs * C.n);
+      cf* rc = W.rc.as<cf>();
+      cf* ec = W.ec.as<cf>();
+      launch_restrict_blk(s, D.P.template as<cf>(), L.Nx, L.Nt, nrhs, r, rc, act);
+      if (C.is_coarsest) {
+        coarse_solve<float>(c, g, C, nrhs, rc, ec, act);
+      } else if (C.inner_iters <= 0) {
+        precond<float>(c, g, l + 1, nrhs, rc, ec, act);
+      } else {
+        fgmres_inner<float>(c, g, l + 1, nrhs, rc, ec, C.inner_iters, (float)g.prm.inner_tol, act);
+      }
+      launch_prolong_blk(s, D.P.template as<cf>(), L.Nx, L.Nt, nrhs, ec, x, act);
+      for (int cyc = 0; cyc < L.sap_cycles; ++cyc)
+        for (int col = 0; col < 2; ++col)
+          launch_sap0_blk(s, D.B(), D.sapinv.template as<cf>(), L.Nx, L.Nt, L.color_list[col].as<int>(),
+                          L.ncolor[col], nrhs, r, x, act, cyc + 1 == L.sap_cycles ? x64 : nullptr);
+      return;
+    }
   }
   if (L.has_coarse) {
     Level& C = *g.levels[l + 1];
@@ -183,13 +222,6 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     }
 }
 
-// whether precond<float> on level l can hand its result over in FP64 itself
-// (last SAP cycle on 4x4-site blocks of 2 dofs)
-bool precond_writes_fp64(const Gauge& g, const Level& L) {
-  return L.M == 2 && L.sbx == 4 && L.sbt == 4 && L.sap_cycles > 0 && !L.is_coarsest &&
-         !(half_blocks(g, L) && L.sbt == 1);
-}
-
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
 // Hessenberg column, v_{j+1} = w/||w||, Givens update.
 // fused (FP64 steps whose preconditioner rounds its input to FP32): the
@@ -215,7 +247,8 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   if (fused && j > 0) {
     if constexpr (std::is_same<T, double>::value) {
       W.cvt_in.ensure(sizeof(cf) * (size_t)vs);
-      launch_scale_convert<T>(s, w, np, n, nrhs, V + j * vs, W.cvt_in.template as<cf>(), act);
+      launch_scale_convert<T>(s, w, np, n, nrhs, V + j * vs, W.cvt_in.template as<cf>(), act,
+                              fine_blocked(g, L) ? L.Nx : 0);
     }
     prec(nullptr, Z + j * vs, (const int*)act);
   } else {
@@ -301,7 +334,10 @@ void precondition_d(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* r, cd* x, c
     Work<double>& W = L.wd[c->wslot];
     const int64_t cnt = (int64_t)nrhs * L.n;
     W.cvt_in.ensure(sizeof(cf) * cnt);
-    launch_convert<float, double>(c->stream, r, W.cvt_in.as<cf>(), cnt);
+    if (fine_blocked(g, L))
+      launch_convert_blk(c->stream, r, W.cvt_in.as<cf>(), L.Nx, L.Nt, nrhs);
+    else
+      launch_convert<float, double>(c->stream, r, W.cvt_in.as<cf>(), cnt);
     precondition_f32in(c, g, l, nrhs, x, act);
   } else {
     precond<double>(c, g, l, nrhs, r, x, act);
