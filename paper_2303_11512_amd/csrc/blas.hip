@@ -139,6 +139,178 @@ __global__ void __launch_bounds__(NT) k_dot_multi(const cx<T>* __restrict__ V, i
   }
 }
 
+// k_dot_multi against two vectors: partial[(r * 2 nv + i) * nch + chunk] =
+// V_i^H w (i < nv) and V_{i - nv}^H u (i >= nv), one read of the basis for
+// both (u is the newest basis vector in the Gram-corrected Arnoldi step).
+template <class T, int EPT>
+__global__ void __launch_bounds__(NT) k_dot_multi2(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
+                                                   int nv, const cx<T>* __restrict__ w, const cx<T>* __restrict__ u,
+                                                   int64_t n, cx<T>* __restrict__ partial,
+                                                   const int* __restrict__ active) {
+  constexpr int CH = NT * EPT;
+  __shared__ cx<T> sh[4][128];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int nch = gridDim.x;
+  const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  const cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  const cx<T>* __restrict__ ur = u + (int64_t)r * sR;
+  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
+  cx<T> wv[EPT], uv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    wv[e] = ld_or0(wr + (k < n ? k : 0), k < n);
+    uv[e] = ld_or0(ur + (k < n ? k : 0), k < n);
+  }
+  auto put = [&](int slot, cx<T> acc) {
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) sh[wv_id][slot] = acc;
+  };
+  for (int i0 = 0; i0 < nv; i0 += 64) {
+    const int nb = min(64, nv - i0);
+    for (int j = 0; j < nb; j += 2) {
+      const int g2 = min(2, nb - j);
+      cx<T> aw[2], au[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        aw[g] = mk<T>(0, 0);
+        au[g] = mk<T>(0, 0);
+        if (g < g2) {
+          const cx<T>* __restrict__ vi = Vr + (int64_t)(i0 + j + g) * sI;
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int64_t k = base + (int64_t)e * NT;
+            const cx<T> x = vi[k < n ? k : n - 1];
+            cjfma(aw[g], x, wv[e]);
+            cjfma(au[g], x, uv[e]);
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < g2) {
+          put(2 * (j + g), aw[g]);
+          put(2 * (j + g) + 1, au[g]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nb) {
+      const int t = threadIdx.x, i = i0 + (t >> 1);
+      const cx<T> v = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+      partial[((int64_t)r * 2 * nv + (t & 1) * nv + i) * nch + blockIdx.x] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// The Arnoldi step's Gram-Schmidt in one update: from the partials of
+// k_dot_multi2, h1 = V^H w and the newest Gram column g = V^H v_j; with the
+// earlier columns of G = V^H V (gram, [r][ldg][ldg], column-major: G[i][k] at
+// k ldg + i), coef = h1 + (I - G) h1 -- the second classical Gram-Schmidt pass
+// with V^H (w - V h1) = h1 - G h1 -- and w -= V coef.  The workgroups of
+// chunk 0 store g into G and coef to coef_out; every workgroup adds the
+// partials in the order of k_reduce_chunks.  Optional |w|^2 chunk partials.
+template <class T, int EPT>
+__global__ void __launch_bounds__(NT) k_update_gram(const cx<T>* __restrict__ V, int64_t sI, int64_t sR, int nv,
+                                                    const cx<T>* __restrict__ dpart, int nchd,
+                                                    cx<T>* __restrict__ gram, int ldg,
+                                                    cx<T>* __restrict__ coef_out, int ldc,
+                                                    cx<T>* __restrict__ w, int64_t n, T* __restrict__ partial,
+                                                    const int* __restrict__ active) {
+  constexpr int CH = NT * EPT;
+  __shared__ cx<T> h1[64], gc[64], cs[64];
+  __shared__ T sh[8];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < 2 * nv; q += NT / 64) {
+    const cx<T>* p = dpart + ((int64_t)r * 2 * nv + q) * nchd;
+    cx<T> acc = mk<T>(0, 0);
+    for (int c = lane; c < nchd; c += 64) acc = acc + p[c];
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) {
+      if (q < nv) h1[q] = acc;
+      else gc[q - nv] = acc;
+    }
+  }
+  __syncthreads();
+  cx<T>* G = gram + (int64_t)r * ldg * ldg;
+  const int j = nv - 1;  // the new column
+  for (int i = threadIdx.x; i < nv; i += NT) {
+    // (G h1)_i = sum_{k < j} G[i][k] h1[k] + G[i][j] h1[j], G[i][j] = g_i, G[j][k] = conj(g_k)
+    cx<T> gh = mk<T>(0, 0);
+    if (i < j) {
+      for (int k = 0; k < j; ++k) cfma(gh, G[(int64_t)k * ldg + i], h1[k]);
+    } else {
+      for (int k = 0; k < j; ++k) cfma(gh, conj(gc[k]), h1[k]);
+    }
+    cfma(gh, gc[i], h1[j]);
+    const cx<T> c = h1[i] + (h1[i] - gh);
+    cs[i] = (T)-1 * c;
+    if (blockIdx.x == 0) {
+      coef_out[(int64_t)r * ldc + i] = c;
+      G[(int64_t)j * ldg + i] = gc[i];
+      if (i < j) G[(int64_t)i * ldg + j] = conj(gc[i]);
+    }
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  cx<T>* __restrict__ wr = w + (int64_t)r * n;
+  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
+  cx<T> acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    acc[e] = wr[k < n ? k : n - 1];  // past n: computed, never stored
+  }
+  constexpr int G2 = EPT >= 8 ? 2 : DG;
+  int i = 0;
+  for (; i + G2 <= nv; i += G2) {
+    cx<T> vv[G2][EPT];
+#pragma unroll
+    for (int g = 0; g < G2; ++g) {
+      const cx<T>* __restrict__ vi = Vr + (int64_t)(i + g) * sI;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = base + (int64_t)e * NT;
+        vv[g][e] = vi[k < n ? k : n - 1];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G2; ++g) {
+      const cx<T> c = cs[i + g];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) cfma(acc[e], vv[g][e], c);
+    }
+  }
+  for (; i < nv; ++i) {
+    const cx<T>* __restrict__ vi = Vr + (int64_t)i * sI;
+    const cx<T> c = cs[i];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t k = base + (int64_t)e * NT;
+      cfma(acc[e], vi[k < n ? k : n - 1], c);
+    }
+  }
+  T nrm = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t k = base + (int64_t)e * NT;
+    if (k < n) {
+      wr[k] = acc[e];
+      nrm += abs2(acc[e]);
+    }
+  }
+  if (partial) {
+    nrm = block_sum_real(nrm, sh);
+    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = nrm;
+  }
+}
+
 // out[r*ldo + i] (=|+=) sum_chunks partial: one wave per output, lane l adds
 // chunks l, l+64, ... in order, then a fixed shuffle tree.
 template <class T>
@@ -581,7 +753,8 @@ __device__ __forceinline__ void hcol_givens_rhs(int r, int j, int m, const cx<T>
   int code = 0;
   if (active[r]) {
     cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
-    for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
+    for (int i = 0; i <= j; ++i)
+      h[i] = c2 ? c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i] : c1[(int64_t)r * (m + 1) + i];
     h[j + 1] = mk<T>(hnr, 0);
     T* c = cs + (int64_t)r * m;
     cx<T>* s = sn + (int64_t)r * m;
@@ -917,6 +1090,31 @@ void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR
 }
 
 template <class T>
+int launch_dot_partial2(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w,
+                        const cx<T>* u, int64_t n, int nrhs, const int* active, cx<T>* partial) {
+  require(nv >= 1 && nv <= 64, "dot_partial2: 1 to 64 vectors");
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_dot_multi2<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv, w, u,
+                                       n, partial, active));
+  KCHK();
+  return (int)nch;
+}
+
+template <class T>
+void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                        int nchd, cx<T>* gram, int ldg, cx<T>* coef_out, int ldc, cx<T>* w, int64_t n, int nrhs,
+                        const int* active, T* norm_partial) {
+  require(nv >= 1 && nv <= 64 && nv <= ldg, "update_gram: 1 to 64 vectors");
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  require((int)nch == nchd, "update_gram: chunking differs from the dot partials'");
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_gram<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR, nv,
+                                       dpart, nchd, gram, ldg, coef_out, ldc, w, n, norm_partial, active));
+  KCHK();
+}
+
+template <class T>
 void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                          int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                          const int* active, cx<T>* dpart2) {
@@ -1216,6 +1414,11 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
   template void launch_update_multi_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
                                          const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,   \
                                          const int*, T*);                                        \
+  template int launch_dot_partial2<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*, \
+                                      const cx<T>*, int64_t, int, const int*, cx<T>*);              \
+  template void launch_update_gram<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*, \
+                                      int, cx<T>*, int, cx<T>*, int, cx<T>*, int64_t, int,          \
+                                      const int*, T*);                                             \
   template void launch_update_dot_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,            \
                                        const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,     \
                                        const int*, cx<T>*);                                        \

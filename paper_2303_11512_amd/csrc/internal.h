@@ -328,6 +328,19 @@ template <class T>
 void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                            int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                            const int* active, T* norm_partial);
+// V_i^H w and V_i^H u (i < nv) with one read of the basis: partials
+// [r][2 nv][nch] (w's first); returns nch
+template <class T>
+int launch_dot_partial2(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w,
+                        const cx<T>* u, int64_t n, int nrhs, const int* active, cx<T>* partial);
+// w -= V (h1 + (I - G) h1) from those partials (h1 = V^H w, new Gram column
+// g = V^H v_{nv-1}; gram: per RHS ldg x ldg column-major, earlier columns
+// kept from the previous steps, column nv-1 stored here); coefficients to
+// coef_out; optional |w|^2 chunk partials
+template <class T>
+void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
+                        int nchd, cx<T>* gram, int ldg, cx<T>* coef_out, int ldc, cx<T>* w, int64_t n, int nrhs,
+                        const int* active, T* norm_partial);
 // launch_update_multi_r (no norm) whose workgroups then form the partials of
 // V_i^H w for the updated w (layout of launch_dot_partial) into dpart2, which
 // must not overlap dpart
@@ -427,7 +440,7 @@ template <class T>
 struct Work {  // FGMRES + multigrid workspace of one level in one precision
   int cap = 0, mcap = 0;
   int64_t n = 0;
-  DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, npart, coef, coef2;
+  DevBuf V, Z, w, H, cs, sn, g, y, beta, thr, bnorm, act, nit, part, npart, coef, coef2, gram;
   DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
   DevBuf rho;                        // inv_B r_B of the premultiplied SAP
   PinnedFlags flags;                 // active flags read back during FGMRES

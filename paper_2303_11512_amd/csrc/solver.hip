@@ -58,6 +58,7 @@ void ensure_work(Level& L, int slot, int nrhs, int m) {
   W.npart.ensure(sizeof(T) * (size_t)nrhs * reduce_chunks(n));
   W.coef.ensure(c * (size_t)nrhs * (m + 1));
   W.coef2.ensure(c * (size_t)nrhs * (m + 1));
+  W.gram.ensure(c * (size_t)nrhs * (m + 1) * (m + 1));
 }
 
 // FP16 mode: coarse levels with 16 dofs per site apply their blocks in FP16
@@ -255,12 +256,14 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
     prec(V + j * vs, Z + j * vs, (const int*)act);
   }
   apply_op<T>(c, g, l, nrhs, Z + j * vs, w, nullptr, act);
-  // CGS2; each reduction over chunks is done by the kernel that consumes it,
-  // and the first pass's update forms the second pass's partials
-  const int nch = launch_dot_partial<T>(s, V, vs, n, j + 1, w, n, nrhs, act, part);
-  cx<T>* part2 = part + (size_t)nrhs * (j + 1) * nch;
-  launch_update_dot_r<T>(s, V, vs, n, j + 1, part, nch, c1, m + 1, (T)-1, w, n, nrhs, act, part2);
-  launch_update_multi_r<T>(s, V, vs, n, j + 1, part2, nch, c2, m + 1, (T)-1, w, n, nrhs, act, np);
+  // Classical Gram-Schmidt applied twice, the second pass in its Gram form:
+  // one read of the basis gives h1 = V^H w and the Gram column V^H v_j, and
+  // one update applies h1 + (I - G) h1 (= h1 + V^H (w - V h1) with G = V^H V);
+  // each reduction over chunks is done by the kernel that consumes it
+  const int nch = launch_dot_partial2<T>(s, V, vs, n, j + 1, w, V + j * vs, n, nrhs, act, part);
+  launch_update_gram<T>(s, V, vs, n, j + 1, part, nch, W.gram.template as<cx<T>>(), m + 1, c1, m + 1, w, n, nrhs,
+                        act, np);
+  c2 = nullptr;
   if (fused) {
     launch_hcol_givens_np<T>(s, j, m, nrhs, c1, c2, np, n, W.H.template as<cx<T>>(), W.cs.template as<T>(),
                              W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
