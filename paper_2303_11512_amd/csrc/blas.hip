@@ -403,138 +403,6 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
   }
 }
 
-// k_update_multi with the chunk reduction of the coefficients done in the
-// same launch: coef = sum over chunks of the Gram-Schmidt partials (layout
-// of k_dot_multi), added per coefficient exactly as k_reduce_chunks adds
-// them (lane l takes chunks l, l+64, ..., then the same shuffle tree), so the
-// result carries the same bits; the workgroups of chunk 0 also store the
-// coefficients to coef_out (row r at coef_out + r * ldc).
-// DOT: the workgroup then forms the next Gram-Schmidt pass's partials of its
-// chunk, V_i^H w_new, into dpart2 (layout and arithmetic of k_dot_multi on
-// the stored w, so the same bits), while the chunk of V it just read is
-// still in cache.  dpart2 must not overlap dpart (other workgroups are still
-// reducing dpart).
-template <class T, int EPT, bool DOT>
-__global__ void __launch_bounds__(NT) k_update_multi_r(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
-                                                       int nv, const cx<T>* __restrict__ dpart, int nchd,
-                                                       cx<T>* __restrict__ coef_out, int ldc, T sign,
-                                                       cx<T>* __restrict__ w, int64_t n, T* __restrict__ partial,
-                                                       const int* __restrict__ active,
-                                                       cx<T>* __restrict__ dpart2) {
-  constexpr int CH = NT * EPT;
-  __shared__ cx<T> cs[64];
-  __shared__ T sh[8];
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nv; i += NT / 64) {
-    const cx<T>* p = dpart + ((int64_t)r * nv + i) * nchd;
-    cx<T> acc = mk<T>(0, 0);
-    for (int c = lane; c < nchd; c += 64) acc = acc + p[c];
-    acc.re = wave_sum(acc.re);
-    acc.im = wave_sum(acc.im);
-    if (lane == 0) {
-      cs[i] = sign * acc;
-      if (blockIdx.x == 0) coef_out[(int64_t)r * ldc + i] = acc;
-    }
-  }
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
-  cx<T>* __restrict__ wr = w + (int64_t)r * n;
-  const cx<T>* __restrict__ Vr = V + (int64_t)r * sR;
-  cx<T> acc[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t k = base + (int64_t)e * NT;
-    acc[e] = wr[k < n ? k : n - 1];  // past n: computed, never stored
-  }
-  constexpr int G = EPT >= 8 ? 2 : DG;
-  int i = 0;
-  for (; i + G <= nv; i += G) {
-    cx<T> vv[G][EPT];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const cx<T>* __restrict__ vi = Vr + (int64_t)(i + g) * sI;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int64_t k = base + (int64_t)e * NT;
-        vv[g][e] = vi[k < n ? k : n - 1];
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const cx<T> c = cs[i + g];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) cfma(acc[e], vv[g][e], c);
-    }
-  }
-  for (; i < nv; ++i) {
-    const cx<T>* __restrict__ vi = Vr + (int64_t)i * sI;
-    const cx<T> c = cs[i];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int64_t k = base + (int64_t)e * NT;
-      cfma(acc[e], vi[k < n ? k : n - 1], c);
-    }
-  }
-  T nrm = 0;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t k = base + (int64_t)e * NT;
-    if (k < n) {
-      wr[k] = acc[e];
-      nrm += abs2(acc[e]);
-    }
-  }
-  if (partial) {
-    nrm = block_sum_real(nrm, sh);
-    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = nrm;
-  }
-  if constexpr (DOT) {
-    __shared__ cx<T> shd[4][64];
-    cx<T> wv[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) wv[e] = base + (int64_t)e * NT < n ? acc[e] : mk<T>(0, 0);
-    int j = 0;
-    for (; j + DG <= nv; j += DG) {
-      cx<T> d[DG];
-#pragma unroll
-      for (int g = 0; g < DG; ++g) {
-        const cx<T>* __restrict__ vi = Vr + (int64_t)(j + g) * sI;
-        d[g] = mk<T>(0, 0);
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int64_t k = base + (int64_t)e * NT;
-          cjfma(d[g], vi[k < n ? k : n - 1], wv[e]);
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < DG; ++g) {
-        d[g].re = wave_sum(d[g].re);
-        d[g].im = wave_sum(d[g].im);
-        if (lane == 0) shd[wave][j + g] = d[g];
-      }
-    }
-    for (; j < nv; ++j) {
-      const cx<T>* __restrict__ vi = Vr + (int64_t)j * sI;
-      cx<T> d = mk<T>(0, 0);
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int64_t k = base + (int64_t)e * NT;
-        cjfma(d, vi[k < n ? k : n - 1], wv[e]);
-      }
-      d.re = wave_sum(d.re);
-      d.im = wave_sum(d.im);
-      if (lane == 0) shd[wave][j] = d;
-    }
-    __syncthreads();
-    if (threadIdx.x < nv) {
-      const int t = threadIdx.x;
-      dpart2[((int64_t)r * nv + t) * gridDim.x + blockIdx.x] = (shd[0][t] + shd[1][t]) + (shd[2][t] + shd[3][t]);
-    }
-  }
-}
-
 template <class T, int EPT>
 __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w, int64_t n,
                                                      T* __restrict__ partial,
@@ -1065,31 +933,6 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
 }
 
 template <class T>
-int launch_dot_partial(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w, int64_t n,
-                       int nrhs, const int* active, cx<T>* partial) {
-  const int ept = pick_ept(n, nrhs);
-  const unsigned nch = nchunks(n, ept);
-  if (nv <= 0) return (int)nch;
-  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_dot_multi<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
-                                       nv, w, n, partial, active));
-  KCHK();
-  return (int)nch;
-}
-
-template <class T>
-void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
-                           int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
-                           const int* active, T* norm_partial) {
-  require(nv >= 1 && nv <= 64, "update_multi: 1 to 64 vectors");
-  const int ept = pick_ept(n, nrhs);
-  const unsigned nch = nchunks(n, ept);
-  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E, false>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI,
-                                       sR, nv, dpart, nchd, coef_out, ldc, sign, w, n, norm_partial, active,
-                                       (cx<T>*)nullptr));
-  KCHK();
-}
-
-template <class T>
 int launch_dot_partial2(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w,
                         const cx<T>* u, int64_t n, int nrhs, const int* active, cx<T>* partial) {
   require(nv >= 1 && nv <= 64, "dot_partial2: 1 to 64 vectors");
@@ -1115,25 +958,9 @@ void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, i
 }
 
 template <class T>
-void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
-                         int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
-                         const int* active, cx<T>* dpart2) {
-  require(nv >= 1 && nv <= 64, "update_multi: 1 to 64 vectors");
-  const int ept = pick_ept(n, nrhs);
-  const unsigned nch = nchunks(n, ept);
-  require((int)nch == nchd, "update_dot: chunking differs from the dot partials'");
-  require(dpart2 + (int64_t)nrhs * nv * nch <= dpart || dpart2 >= dpart + (int64_t)nrhs * nv * nch,
-          "update_dot: the two partial buffers overlap");
-  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi_r<T, E, true>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI,
-                                       sR, nv, dpart, nchd, coef_out, ldc, sign, w, n, (T*)nullptr, active,
-                                       dpart2));
-  KCHK();
-}
-
-template <class T>
 void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
                           const int* active, int blk_nx) {
-  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
   unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active,
                      blk_nx);
@@ -1151,7 +978,7 @@ template <class T>
 void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,
                            const T* npart, int64_t n, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr,
                            int* active, int* nit, int* host_flags) {
-  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
   hipLaunchKernelGGL(k_hcol_givens_np<T>, dim3((unsigned)(((int64_t)nrhs * 64 + NT - 1) / NT)), dim3(NT), 0, s, j,
                      m, nrhs, c1, c2, npart, (int)nch, H, cs, sn, g, thr, active, nit, host_flags);
   KCHK();
@@ -1160,7 +987,7 @@ void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c
 template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
                     const int* active) {
-  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_multi_r
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
   unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_scale_r<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, den_out, active);
   KCHK();
@@ -1409,19 +1236,11 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                 const int*);                                                      \
   template void launch_givens<T>(hipStream_t, int, int, int, cx<T>*, T*, cx<T>*, cx<T>*, const T*, \
                                  int*, int*);                                                     \
-  template int launch_dot_partial<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*,  \
-                                     int64_t, int, const int*, cx<T>*);                           \
-  template void launch_update_multi_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
-                                         const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,   \
-                                         const int*, T*);                                        \
   template int launch_dot_partial2<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*, \
                                       const cx<T>*, int64_t, int, const int*, cx<T>*);              \
   template void launch_update_gram<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*, \
                                       int, cx<T>*, int, cx<T>*, int, cx<T>*, int64_t, int,          \
                                       const int*, T*);                                             \
-  template void launch_update_dot_r<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,            \
-                                       const cx<T>*, int, cx<T>*, int, T, cx<T>*, int64_t, int,     \
-                                       const int*, cx<T>*);                                        \
   template void launch_scale_convert<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,  \
                                         cf*, const int*, int);                                     \
   template void launch_hcol_givens_np<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,     \

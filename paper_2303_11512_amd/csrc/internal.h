@@ -316,20 +316,10 @@ template <class T>
 void launch_givens(hipStream_t s, int j, int m, int nrhs, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g,
                    const T* thr, int* active, int* nit);
 // The Gram-Schmidt pieces of an Arnoldi step with the chunk reductions moved
-// into the consumers (bitwise the results of dot_multi + update_multi +
-// norm + scale): the dot partials alone (returns their chunk count); the
-// update w += sign V coef that reduces the partials itself (coefficients also
-// to coef_out, optional norm partials of the new w); v = w / ||w|| that
-// reduces the norm partials itself (||w|| also to den_out).
-template <class T>
-int launch_dot_partial(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w, int64_t n,
-                       int nrhs, const int* active, cx<T>* partial);
-template <class T>
-void launch_update_multi_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
-                           int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
-                           const int* active, T* norm_partial);
-// V_i^H w and V_i^H u (i < nv) with one read of the basis: partials
-// [r][2 nv][nch] (w's first); returns nch
+// into the consumers: V_i^H w and V_i^H u (i < nv) with one read of the
+// basis, partials [r][2 nv][nch] (w's first; returns nch); the update that
+// reduces them itself; v = w / ||w|| that reduces the norm partials itself
+// (||w|| also to den_out).
 template <class T>
 int launch_dot_partial2(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* w,
                         const cx<T>* u, int64_t n, int nrhs, const int* active, cx<T>* partial);
@@ -341,15 +331,8 @@ template <class T>
 void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                         int nchd, cx<T>* gram, int ldg, cx<T>* coef_out, int ldc, cx<T>* w, int64_t n, int nrhs,
                         const int* active, T* norm_partial);
-// launch_update_multi_r (no norm) whose workgroups then form the partials of
-// V_i^H w for the updated w (layout of launch_dot_partial) into dpart2, which
-// must not overlap dpart
-template <class T>
-void launch_update_dot_r(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
-                         int nchd, cx<T>* coef_out, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
-                         const int* active, cx<T>* dpart2);
 // v = w / |w| from the chunk partials of |w|^2 (chunking of
-// launch_update_multi_r), and vf = v rounded to FP32 (in the fine level's
+// launch_update_gram), and vf = v rounded to FP32 (in the fine level's
 // block-major layout when blk_nx = Nx > 0)
 template <class T>
 void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
