@@ -267,8 +267,12 @@ void launch_sap2_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, 
 // and one colour of the premultiplied sweep x_B = rho_B - M_B x_H (first:
 // rho_B = inv_B r_B formed and stored); FP16 operands, or FP32 / FP64
 void launch_sap4_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, int nblk, cd* M);
+// ec (with first): the colour's first sweep after the coarse correction,
+// whose halo comes from ec (coarse vector) through hP (FP16 prolongation of
+// 2x2 aggregates with 8 test vectors) instead of from x
 void launch_sap4p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
-                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active);
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active, const chalf* hP = nullptr,
+                    const cf* ec = nullptr);
 template <class T>
 void launch_sap4p(hipStream_t s, const cx<T>* M, const cx<T>* inv, int Nx, int Nt, const int* blist, int nb,
                   int nrhs, bool first, const cx<T>* r, cx<T>* rho, cx<T>* x, const int* active);
@@ -387,6 +391,7 @@ struct LevelData {
   DevBuf hsapM;             // FP16 inv_B D_BH of 2x1 SAP blocks (16-dof coarse levels)
   DevBuf hdinv;             // FP16 dense inverse of the coarsest level (empty if out of range)
   DevBuf sapM;              // inv_B D_BH of 2x2 SAP blocks (16-dof levels; FP16 copy in hsapM)
+  DevBuf hP;                // FP16 copy of P (16-dof levels with 2x2 aggregates, 8 test vectors)
   const cx<T>* B() const { return blocks.as<cx<T>>(); }
 };
 

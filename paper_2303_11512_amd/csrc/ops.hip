@@ -1135,12 +1135,19 @@ __global__ void __launch_bounds__(NT) k_sap4_premul(const cd* __restrict__ B, co
   M[e] = acc;
 }
 
-// FP16 operands (FP32 vectors, FP32 accumulation) on the 16x16x16 matrix cores
-template <bool FIRST>
-__global__ void __launch_bounds__(NT) k_sap4p_h(const chalf* __restrict__ M, const chalf* __restrict__ inv,
-                                                int Nx, int Nt, const int* __restrict__ blist, int nrhs,
-                                                const cf* __restrict__ rr, cf* __restrict__ rho,
-                                                cf* __restrict__ x, const int* __restrict__ active) {
+// FP16 operands (FP32 vectors, FP32 accumulation) on the 16x16x16 matrix cores.
+// FROMC (with FIRST: the first colour's first sweep after the coarse
+// correction): the halo values x_H = P e come from the coarse correction e
+// itself (hP: FP16 copy of the 2x2-aggregate prolongation, [agg][2][32][8]),
+// one 16x16x16 product per hop whose result layout is the B layout of the
+// sweep's own product, so the prolongated x is never stored; x is then only
+// written.
+template <bool FIRST, bool FROMC>
+__device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const chalf* __restrict__ inv, int Nx,
+                                             int Nt, const int* __restrict__ blist, int nrhs,
+                                             const cf* __restrict__ rr, cf* __restrict__ rho, cf* __restrict__ x,
+                                             const int* __restrict__ active, const chalf* __restrict__ hP,
+                                             const cf* __restrict__ ec) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
   const int hh = wave & 1;
@@ -1153,14 +1160,48 @@ __global__ void __launch_bounds__(NT) k_sap4p_h(const chalf* __restrict__ M, con
   const int64_t rrow = ok ? r : r0;  // lanes past the last RHS read row r0; never stored
   // every load of the wave is issued before the first product
   h4 br[8], bi[8];
+  if constexpr (FROMC) {
+    // x_H at hop site v: rows = v's 16 dofs (chirality i / 8, row sl' 8 + i % 8
+    // of its 2x2 aggregate A'), K = the 16 coarse dofs of A' (c' 8 + k; zero
+    // unless c' = chirality), columns = RHS
+    const int64_t ncoarse = (int64_t)(Nx / 2) * (Nt / 2) * CM;
+    const int c = i >> 3, cq = q >> 1;
 #pragma unroll
-  for (int h = 0; h < 8; ++h) {
-    const cf* xv = x + rrow * n + nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt) * CM + 4 * q;
+    for (int h = 0; h < 8; ++h) {
+      const int v = (int)nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt);
+      const int vx = v % Nx, vt = v / Nx;
+      const int64_t A = (int64_t)(vt >> 1) * (Nx >> 1) + (vx >> 1);
+      const int sl = ((vt & 1) << 1) + (vx & 1);
+      const chalf* pa = hP + (((A * 2 + c) * 32 + sl * 8 + (i & 7)) * 8) + 4 * (q & 1);
+      const cf* ev = ec + rrow * ncoarse + A * CM + 4 * q;
+      h4 pr, pi, er, ei;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const cf v = xv[j];
-      br[h][j] = (_Float16)v.re;
-      bi[h][j] = (_Float16)v.im;
+      for (int j = 0; j < 4; ++j) {
+        const chalf pv = pa[j];
+        pr[j] = cq == c ? pv.re : (_Float16)0;
+        pi[j] = cq == c ? pv.im : (_Float16)0;
+        const cf e = ev[j];
+        er[j] = (_Float16)e.re;
+        ei[j] = (_Float16)e.im;
+      }
+      CAcc<float> xh{{0, 0, 0, 0}, {0, 0, 0, 0}};
+      hmma(pr, pi, er, ei, xh);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        br[h][j] = (_Float16)xh.re[j];
+        bi[h][j] = (_Float16)xh.im[j];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const cf* xv = x + rrow * n + nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt) * CM + 4 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cf v = xv[j];
+        br[h][j] = (_Float16)v.re;
+        bi[h][j] = (_Float16)v.im;
+      }
     }
   }
   h4 ar[2][8], ai[2][8];
@@ -1236,6 +1277,21 @@ __global__ void __launch_bounds__(NT) k_sap4p_h(const chalf* __restrict__ M, con
         x[rrow * n + u * CM + 4 * q + v] = mk<float>(rv[rt].re[v] - acc.re[v], rv[rt].im[v] - acc.im[v]);
     }
   }
+}
+
+template <bool FIRST>
+__global__ void __launch_bounds__(NT) k_sap4p_h(const chalf* __restrict__ M, const chalf* __restrict__ inv,
+                                                int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                const cf* __restrict__ rr, cf* __restrict__ rho,
+                                                cf* __restrict__ x, const int* __restrict__ active) {
+  sap4p_h_body<FIRST, false>(M, inv, Nx, Nt, blist, nrhs, rr, rho, x, active, nullptr, nullptr);
+}
+__global__ void __launch_bounds__(NT) k_sap4p_hc(const chalf* __restrict__ M, const chalf* __restrict__ inv,
+                                                 int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                                 const cf* __restrict__ rr, cf* __restrict__ rho,
+                                                 cf* __restrict__ x, const int* __restrict__ active,
+                                                 const chalf* __restrict__ hP, const cf* __restrict__ ec) {
+  sap4p_h_body<true, true>(M, inv, Nx, Nt, blist, nrhs, rr, rho, x, active, hP, ec);
 }
 
 // FP32 / FP64 operands on the 16x16x4 matrix cores (K chunks of 4 per hop;
@@ -2210,10 +2266,14 @@ void launch_sap4_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, 
 }
 
 void launch_sap4p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
-                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active) {
+                    int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active, const chalf* hP,
+                    const cf* ec) {
   if (nb <= 0 || nrhs <= 0) return;
   const dim3 g(nb, ((nrhs + 15) / 16 + 1) / 2);
-  if (first)
+  require(!ec || (first && hP), "FP16 2x2 SAP: the halo from the coarse correction needs the first sweep and P");
+  if (ec)
+    hipLaunchKernelGGL(k_sap4p_hc, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active, hP, ec);
+  else if (first)
     hipLaunchKernelGGL(k_sap4p_h<true>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
   else
     hipLaunchKernelGGL(k_sap4p_h<false>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);

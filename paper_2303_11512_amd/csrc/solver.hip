@@ -151,6 +151,10 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
       return;
     }
   }
+  // FP16 2x2 sweeps after a 2x2-aggregate coarse correction: the first
+  // colour's first sweep forms its halo from the coarse correction itself,
+  // so the prolongation is not stored (it is read nowhere else)
+  const cf* ec_halo = nullptr;
   if (L.has_coarse) {
     Level& C = *g.levels[l + 1];
     Work<T>& W = work<T>(L, c->wslot);
@@ -166,7 +170,13 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     } else {
       fgmres_inner<T>(c, g, l + 1, nrhs, rc, ec, C.inner_iters, (T)g.prm.inner_tol, act);
     }
-    launch_prolong<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, ec, x, 0, act);
+    bool fused = false;
+    if constexpr (std::is_same<T, float>::value)
+      fused = half_blocks(g, L) && L.sbx == 2 && L.sbt == 2 && L.sap_cycles > 0 && L.f.hP.p && L.f.hsapM.p;
+    if (fused)
+      ec_halo = reinterpret_cast<const cf*>(ec);
+    else
+      launch_prolong<T>(s, D.P.template as<cx<T>>(), L.Nx, L.Nt, L.M, L.bx, L.bt, L.ntv, nrhs, ec, x, 0, act);
   } else {
     launch_axpby<T>(s, (T)0, r, (T)0, nullptr, x, L.n, nrhs, act);
   }
@@ -181,8 +191,10 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
         const int* bl = L.color_list[col].as<int>();
         if constexpr (std::is_same<T, float>::value) {
           if (half_blocks(g, L)) {
+            const bool from_coarse = ec_halo && cyc == 0 && col == 0;
             launch_sap4p_h(s, L.f.hsapM.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, bl, L.ncolor[col], nrhs,
-                           cyc == 0, r, W.rho.template as<cf>(), x, act);
+                           cyc == 0, r, W.rho.template as<cf>(), x, act, from_coarse ? L.f.hP.as<chalf>() : nullptr,
+                           from_coarse ? ec_halo : nullptr);
             continue;
           }
         }
@@ -782,6 +794,11 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
         const int64_t nm = (int64_t)(L.d.sapM.bytes / sizeof(cd));
         L.f.hsapM.ensure(sizeof(chalf) * nm);
         launch_to_half(s, L.d.sapM.as<cd>(), L.f.hsapM.as<chalf>(), nm);
+      }
+      if (L.sbx == 2 && L.sbt == 2 && L.has_coarse && L.bx == 2 && L.bt == 2 && L.ntv == 8 && L.d.P.p) {
+        const int64_t np = (int64_t)(L.d.P.bytes / sizeof(cd));  // [nagg][2][32][8]
+        L.f.hP.ensure(sizeof(chalf) * np);
+        launch_to_half(s, L.d.P.as<cd>(), L.f.hP.as<chalf>(), np);
       }
     }
   }
