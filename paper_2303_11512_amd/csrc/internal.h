@@ -256,8 +256,12 @@ void launch_dense_apply_h(hipStream_t s, const chalf* A, int64_t n, int nrhs, co
                           const int* active);
 void launch_stencil_h(hipStream_t s, const chalf* blocks, int Nx, int Nt, int nrhs, const cf* x, cf* y,
                       const cf* b, const int* active);
+// ec (single-site blocks): the first colour's first sweep after the coarse
+// correction, the neighbours' x formed from ec through hP (FP16 prolongation
+// of 2x2 aggregates with 8 test vectors) instead of read from x
 void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
-                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active);
+                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active, const chalf* hP = nullptr,
+                  const cf* ec = nullptr);
 // Two-site (2x1) FP16 SAP in premultiplied form: M_B = inv_B D_BH at setup
 // ([nblk][6 hops][32][16] FP16) and a colour sweep x_B = rho_B - M_B x_H; the
 // first sweep of each colour in a visit (`first`) forms rho_B = inv_B r_B

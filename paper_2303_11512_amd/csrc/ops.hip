@@ -926,6 +926,46 @@ __global__ void __launch_bounds__(NT) k_stencil_h(const chalf* __restrict__ B, i
   }
 }
 
+// coarse_hop_h with x at the neighbour taken from the coarse correction: x_nb
+// = P e for the 2x2 aggregate of the neighbour (hP: FP16 copy of P, [agg][2]
+// [32][8]; ec: coarse vector, ncoarse per RHS), formed on the matrix cores in
+// the B layout of the hop product
+__device__ __forceinline__ void coarse_hop_hc(const chalf* __restrict__ B, const chalf* __restrict__ hP,
+                                              const cf* __restrict__ ec, int64_t ncoarse, int64_t u, int d, int Nx,
+                                              int Nt, int64_t rrow, int lane, CAcc<float>& acc) {
+  const int i = lane & 15, q = lane >> 4;
+  const int v = (int)nb_site(u, d, Nx, Nt);
+  const int vx = v % Nx, vt = v / Nx;
+  const int64_t A = (int64_t)(vt >> 1) * (Nx >> 1) + (vx >> 1);
+  const int sl = ((vt & 1) << 1) + (vx & 1);
+  const int c = i >> 3, cq = q >> 1;
+  const chalf* pa = hP + (((A * 2 + c) * 32 + sl * 8 + (i & 7)) * 8) + 4 * (q & 1);
+  const cf* ev = ec + rrow * ncoarse + A * CM + 4 * q;
+  const chalf* row = B + ((u * 5 + d) * CM + i) * CM + 4 * q;
+  h4 pr, pi, er, ei, ar, ai;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const chalf pv = pa[j];
+    pr[j] = cq == c ? pv.re : (_Float16)0;
+    pi[j] = cq == c ? pv.im : (_Float16)0;
+    const cf e = ev[j];
+    er[j] = (_Float16)e.re;
+    ei[j] = (_Float16)e.im;
+    const chalf a = row[j];
+    ar[j] = a.re;
+    ai[j] = a.im;
+  }
+  CAcc<float> xh{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  hmma(pr, pi, er, ei, xh);
+  h4 br, bi;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    br[j] = (_Float16)xh.re[j];
+    bi[j] = (_Float16)xh.im[j];
+  }
+  hmma(ar, ai, br, bi, acc);
+}
+
 __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const chalf* __restrict__ inv,
                                               int Nx, int Nt, const int* __restrict__ blist, int nrhs,
                                               const cf* __restrict__ rr, cf* __restrict__ x,
@@ -941,6 +981,56 @@ __global__ void __launch_bounds__(NT) k_sap_h(const chalf* __restrict__ B, const
   const int64_t rrow = ok ? r : r0;
   CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
   coarse_hop_h(B, x, n, u, wave + 1, Nx, Nt, rrow, ok, lane, acc);
+  // the block solve's operands are loaded after the hops (measured faster
+  // than loading them first)
+  cf rv[4];
+  chalf iv[4];
+  if (wave == 0) {
+    const chalf* Iu = inv + (u * CM + i) * CM + 4 * q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rv[j] = rr[rrow * n + u * CM + 4 * q + j];
+      iv[j] = Iu[j];
+    }
+  }
+  if (!reduce_waves(acc, red, wave, lane)) return;
+  // t = r_u - hops: element j of this lane is row 4q + j, which is also the
+  // B operand layout of the next product
+  h4 tr, ti, ar, ai;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    tr[j] = (_Float16)(rv[j].re - acc.re[j]);
+    ti[j] = (_Float16)(rv[j].im - acc.im[j]);
+    ar[j] = iv[j].re;
+    ai[j] = iv[j].im;
+  }
+  CAcc<float> cor{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  hmma(ar, ai, tr, ti, cor);
+  if (!ok || (active && !active[r])) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[(int64_t)r * n + u * CM + 4 * q + v] = mk<float>(cor.re[v], cor.im[v]);
+}
+
+// k_sap_h for the first colour's first sweep after the coarse correction:
+// the neighbours' x come from the coarse correction (coarse_hop_hc), so the
+// prolongation is never stored
+__global__ void __launch_bounds__(NT) k_sap_hc(const chalf* __restrict__ B, const chalf* __restrict__ inv,
+                                              int Nx, int Nt, const int* __restrict__ blist, int nrhs,
+                                               const cf* __restrict__ rr, cf* __restrict__ x,
+                                               const int* __restrict__ active, const chalf* __restrict__ hP,
+                                               const cf* __restrict__ ec) {
+  __shared__ float red[3][8][64];
+  const int64_t u = blist[xcd_tile(blockIdx.x, gridDim.x)];
+  const int64_t n = (int64_t)Nx * Nt * CM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int r0 = blockIdx.y * 16;
+  const int r = r0 + i;
+  const bool ok = r < nrhs;
+  const int64_t rrow = ok ? r : r0;
+  CAcc<float> acc{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const int64_t ncoarse = (int64_t)(Nx / 2) * (Nt / 2) * CM;
+  coarse_hop_hc(B, hP, ec, ncoarse, u, wave + 1, Nx, Nt, rrow, lane, acc);
   // the block solve's operands are loaded after the hops (measured faster
   // than loading them first)
   cf rv[4];
@@ -2308,8 +2398,16 @@ void launch_sap2p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int
 }
 
 void launch_sap_h(hipStream_t s, const chalf* blocks, const chalf* inv, int Nx, int Nt, int sbx, int sbt,
-                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active) {
+                  const int* blist, int nb, int nrhs, const cf* r, cf* x, const int* active, const chalf* hP,
+                  const cf* ec) {
   if (nb <= 0) return;
+  if (ec) {
+    require(hP && sbx == 1 && sbt == 1, "FP16 SAP: the halo from the coarse correction needs single sites and P");
+    hipLaunchKernelGGL(k_sap_hc, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs, r, x,
+                       active, hP, ec);
+    KCHK();
+    return;
+  }
   // (2x1 blocks take the premultiplied sweep, launch_sap2p_h)
   if (sbx == 1 && sbt == 1)
     hipLaunchKernelGGL(k_sap_h, dim3(nb, (nrhs + 15) / 16), dim3(NT), 0, s, blocks, inv, Nx, Nt, blist, nrhs,

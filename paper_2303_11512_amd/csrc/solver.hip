@@ -151,9 +151,9 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
       return;
     }
   }
-  // FP16 2x2 sweeps after a 2x2-aggregate coarse correction: the first
-  // colour's first sweep forms its halo from the coarse correction itself,
-  // so the prolongation is not stored (it is read nowhere else)
+  // FP16 2x2 or single-site sweeps after a 2x2-aggregate coarse correction:
+  // the first colour's first sweep forms its halo from the coarse correction
+  // itself, so the prolongation is not stored (it is read nowhere else)
   const cf* ec_halo = nullptr;
   if (L.has_coarse) {
     Level& C = *g.levels[l + 1];
@@ -172,7 +172,8 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     }
     bool fused = false;
     if constexpr (std::is_same<T, float>::value)
-      fused = half_blocks(g, L) && L.sbx == 2 && L.sbt == 2 && L.sap_cycles > 0 && L.f.hP.p && L.f.hsapM.p;
+      fused = half_blocks(g, L) && L.sap_cycles > 0 && L.f.hP.p &&
+              ((L.sbx == 2 && L.sbt == 2 && L.f.hsapM.p) || (L.sbx == 1 && L.sbt == 1));
     if (fused)
       ec_halo = reinterpret_cast<const cf*>(ec);
     else
@@ -222,8 +223,10 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
     for (int col = 0; col < 2; ++col) {
       if constexpr (std::is_same<T, float>::value) {
         if (half) {
+          const bool from_coarse = ec_halo && cyc == 0 && col == 0;
           launch_sap_h(s, L.f.hblocks.as<chalf>(), L.f.hsapinv.as<chalf>(), L.Nx, L.Nt, L.sbx, L.sbt,
-                       L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act);
+                       L.color_list[col].as<int>(), L.ncolor[col], nrhs, r, x, act,
+                       from_coarse ? L.f.hP.as<chalf>() : nullptr, from_coarse ? ec_halo : nullptr);
           continue;
         }
       }
@@ -795,7 +798,7 @@ void setup_hierarchy(mgm_ctx* c, Gauge& g, const mgm_mg_params& p) {
         L.f.hsapM.ensure(sizeof(chalf) * nm);
         launch_to_half(s, L.d.sapM.as<cd>(), L.f.hsapM.as<chalf>(), nm);
       }
-      if (L.sbx == 2 && L.sbt == 2 && L.has_coarse && L.bx == 2 && L.bt == 2 && L.ntv == 8 && L.d.P.p) {
+      if (L.has_coarse && L.bx == 2 && L.bt == 2 && L.ntv == 8 && L.d.P.p) {
         const int64_t np = (int64_t)(L.d.P.bytes / sizeof(cd));  // [nagg][2][32][8]
         L.f.hP.ensure(sizeof(chalf) * np);
         launch_to_half(s, L.d.P.as<cd>(), L.f.hP.as<chalf>(), np);
