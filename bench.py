@@ -671,8 +671,8 @@ def run_scan(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="schwinger128")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default="fp16", choices=["fp64", "fp32", "fp16"],
