@@ -424,9 +424,11 @@ __global__ void __launch_bounds__(NT) k_norm_partial(const cx<T>* __restrict__ w
 }
 
 // out[r] = sqrt(sum_chunks partial): one wave per RHS, as k_reduce_chunks.
+// zero_done (optional): 1 where the norm is 0, else 0.
 template <class T>
 __global__ void __launch_bounds__(NT) k_norm_reduce(const T* __restrict__ partial, int nch, int nrhs,
-                                                    T* __restrict__ out, const int* __restrict__ active) {
+                                                    T* __restrict__ out, const int* __restrict__ active,
+                                                    int* __restrict__ zero_done) {
   const int r = (int)(((int64_t)blockIdx.x * NT + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= nrhs) return;
@@ -434,7 +436,33 @@ __global__ void __launch_bounds__(NT) k_norm_reduce(const T* __restrict__ partia
   T acc = 0;
   for (int c = lane; c < nch; c += 64) acc += partial[(int64_t)r * nch + c];
   acc = wave_sum(acc);
-  if (lane == 0) out[r] = sqrt(acc);
+  if (lane == 0) {
+    const T v = sqrt(acc);
+    out[r] = v;
+    if (zero_done) zero_done[r] = v == (T)0 ? 1 : 0;
+  }
+}
+
+// k_norm_reduce (same sum, same bits) for norms the host reads: lane 0 also
+// stores them, the RHS norms and the iteration counts into pinned host
+// memory (host[r], host[nrhs + r], hnit[r]), so no copies follow.
+__global__ void __launch_bounds__(NT) k_norm_reduce_rb(const double* __restrict__ partial, int nch, int nrhs,
+                                                       double* __restrict__ out, const double* __restrict__ bnorm,
+                                                       const int* __restrict__ nit, double* __restrict__ host,
+                                                       int* __restrict__ hnit) {
+  const int r = (int)(((int64_t)blockIdx.x * NT + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= nrhs) return;
+  double acc = 0;
+  for (int c = lane; c < nch; c += 64) acc += partial[(int64_t)r * nch + c];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const double v = sqrt(acc);
+    out[r] = v;
+    host[r] = v;
+    host[nrhs + r] = bnorm[r];
+    hnit[r] = nit[r];
+  }
 }
 
 // v = w / ||w|| with ||w|| = sqrt(sum over chunks of the norm partials),
@@ -728,12 +756,6 @@ __global__ void __launch_bounds__(NT) k_fgmres_init(int nrhs, const T* __restric
   thr[r] = tol * (bnorm ? bnorm[r] : beta[r]);
 }
 
-template <class T>
-__global__ void __launch_bounds__(NT) k_done_from_norm(const T* __restrict__ bnorm, int nrhs,
-                                                       int* __restrict__ done) {
-  const int r = blockIdx.x * NT + threadIdx.x;
-  if (r < nrhs) done[r] = bnorm[r] == (T)0 ? 1 : 0;
-}
 
 // ------------------------------------------------------------------ CholQR2 pieces
 // Gram partials on the FP64 matrix cores: partial[chunk][i][j] = sum over the
@@ -927,7 +949,7 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
   KCHK();
   if (norm_out) {
     hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch,
-                       nrhs, norm_out, active);
+                       nrhs, norm_out, active, (int*)nullptr);
     KCHK();
   }
 }
@@ -995,14 +1017,26 @@ void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, in
 
 template <class T>
 void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
-                 T* partial) {
+                 T* partial, int* zero_done) {
   const int ept = pick_ept(n, nrhs);
   const unsigned nch = nchunks(n, ept);
   EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, w, n,
                                        partial, active));
   KCHK();
   hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch,
-                     nrhs, out, active);
+                     nrhs, out, active, zero_done);
+  KCHK();
+}
+
+void launch_norm_readback(hipStream_t s, const cd* w, int64_t n, int nrhs, double* out, double* partial,
+                          const double* bnorm, const int* nit, double* host, int* hnit) {
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<double, E>), dim3(nch, nrhs), dim3(NT), 0, s, w, n,
+                                       partial, (const int*)nullptr));
+  KCHK();
+  hipLaunchKernelGGL(k_norm_reduce_rb, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch, nrhs, out, bnorm,
+                     nit, host, hnit);
   KCHK();
 }
 
@@ -1069,12 +1103,6 @@ void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* paren
   KCHK();
 }
 
-template <class T>
-void launch_done_from_norm(hipStream_t s, const T* bnorm, int nrhs, int* done) {
-  hipLaunchKernelGGL(k_done_from_norm<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, bnorm, nrhs, done);
-  KCHK();
-}
-template void launch_done_from_norm<double>(hipStream_t, const double*, int, int*);
 
 void launch_gram(hipStream_t s, const cd* Y, int64_t n, int d, cd* G, cd* partial) {
   require(d >= 1 && d <= 64, "orthonormalize: 1 <= d <= 64");
@@ -1229,7 +1257,7 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                        T*, const int*);                                           \
   template void launch_hcol<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*, const T*,   \
                                cx<T>*, const int*);                                               \
-  template void launch_norm<T>(hipStream_t, const cx<T>*, int64_t, int, T*, const int*, T*);       \
+  template void launch_norm<T>(hipStream_t, const cx<T>*, int64_t, int, T*, const int*, T*, int*);       \
   template void launch_scale<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,         \
                                 const int*);                                                      \
   template void launch_axpby<T>(hipStream_t, T, const cx<T>*, T, const cx<T>*, cx<T>*, int64_t, int, \

@@ -296,8 +296,6 @@ void launch_dot_multi_ld(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
                          const cx<T>* w, int64_t n, int nrhs, cx<T>* out, int ldo, int accumulate,
                          const int* active, cx<T>* partial);
 // done[r] = (bnorm[r] == 0)
-template <class T>
-void launch_done_from_norm(hipStream_t s, const T* bnorm, int nrhs, int* done);
 // number of chunk partials a reduction over n elements produces
 // (upper bound: the shortest chunk is 256 elements)
 inline int64_t reduce_chunks(int64_t n) { return (n + 255) / 256; }
@@ -309,9 +307,15 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
 template <class T>
 void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
                  cx<T>* H, const int* active);
+// zero_done (optional): zero_done[r] = 1 where the norm is 0, else 0
 template <class T>
 void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
-                 T* partial);
+                 T* partial, int* zero_done = nullptr);
+// launch_norm (same bits) whose reduce kernel also hands the host what it
+// reads with the norms, in pinned host memory: host[r] = ||w_r||,
+// host[nrhs + r] = bnorm[r], hnit[r] = nit[r] (no copies)
+void launch_norm_readback(hipStream_t s, const cd* w, int64_t n, int nrhs, double* out, double* partial,
+                          const double* bnorm, const int* nit, double* host, int* hnit);
 template <class T>
 void launch_scale(hipStream_t s, const cx<T>* w, const T* den, int64_t n, int nrhs, cx<T>* v,
                   const int* active);
@@ -428,6 +432,29 @@ struct PinnedFlags {
   }
 };
 
+// Pinned host copies of a cycle's end residuals, RHS norms and iteration
+// counts, written by the norm's reduce kernel (launch_norm_readback).
+struct PinnedReadback {
+  double* h = nullptr;  // [2][cap]: ||r||, ||b||; then cap ints of iterations
+  int cap = 0;
+  PinnedReadback() = default;
+  PinnedReadback(const PinnedReadback&) = delete;
+  PinnedReadback& operator=(const PinnedReadback&) = delete;
+  void ensure(int n) {
+    if (n <= cap) return;
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h), (2 * sizeof(double) + sizeof(int)) * (size_t)n,
+                         hipHostMallocDefault));
+    cap = n;
+  }
+  int* nit() const { return reinterpret_cast<int*>(h + 2 * (size_t)cap); }
+  ~PinnedReadback() {
+    if (h) (void)hipHostFree(h);
+  }
+};
+
 template <class T>
 struct Work {  // FGMRES + multigrid workspace of one level in one precision
   int cap = 0, mcap = 0;
@@ -436,6 +463,7 @@ struct Work {  // FGMRES + multigrid workspace of one level in one precision
   DevBuf rc, ec, cvt_in, cvt_out;  // coarse rhs/solution, precision conversions
   DevBuf rho;                        // inv_B r_B of the premultiplied SAP
   PinnedFlags flags;                 // active flags read back during FGMRES
+  PinnedReadback rb;                 // residuals read back at a cycle's end
 };
 
 struct Level {

@@ -468,16 +468,28 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
     }
   };
 
-  launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p);
-  launch_done_from_norm<double>(s, bnorm, nrhs, done);  // zero right-hand sides are solved
+  W.rb.ensure(nrhs);
+  // ||b||; zero right-hand sides are solved
+  launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p, done);
   require(sp.use_cnn >= 0 && sp.use_cnn <= (MGM_CNN_GUESS | MGM_CNN_STAGE), "use_cnn: unknown flags");
   const bool learned = l == 0 && !L.has_dense;
   const bool stage = learned && (sp.use_cnn & MGM_CNN_STAGE);
   if (stage) require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
-  if (learned && (sp.use_cnn & MGM_CNN_GUESS))
+  const bool guess = learned && (sp.use_cnn & MGM_CNN_GUESS);
+  if (guess)
     cnn_initial_guess(c, g, nrhs, b, x, w);
   else
     launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
+  // read the residual norms, ||b|| and the iteration counts the reduce kernel
+  // stored in pinned memory (the stream is synchronised)
+  auto take_rb = [&] {
+    const double* h = W.rb.h;
+    for (int r = 0; r < nrhs; ++r) {
+      hr[r] = h[r];
+      hb[r] = h[nrhs + r];
+      hnit[r] = W.rb.nit()[r];
+    }
+  };
 
   bool final_known = false;  // hr holds the residuals of the returned x
   // steps that hand the preconditioner an FP32 input scale and round v_j in one launch
@@ -486,12 +498,20 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch[c->wslot]);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
-      // r0 = b - D x ; v0 = r0 / ||r0||
-      apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
-      launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
-      launch_fgmres_init<double>(s, nrhs, beta, nullptr, done, sp.tol, bnorm, m, act,
+      // r0 = b - D x ; v0 = r0 / ||r0||.  From x = 0 that is r0 = b and
+      // ||r0|| = ||b|| exactly, both at hand
+      const cd* r0 = w;
+      const double* b0 = beta;
+      if (cycle == 0 && !guess) {
+        r0 = b;
+        b0 = bnorm;
+      } else {
+        apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
+        launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+      }
+      launch_fgmres_init<double>(s, nrhs, b0, nullptr, done, sp.tol, bnorm, m, act,
                                  W.nit.as<int>(), W.g.as<cd>(), W.thr.as<double>());
-      launch_scale<double>(s, w, beta, n, nrhs, V, act);
+      launch_scale<double>(s, r0, b0, n, nrhs, V, act);
       for (int j = 0; j < m; ++j) {
         // the whole step is one graph: key level field (m + 1) * 1000 + l
         // (+ 500 with the learned stage) tells it from the preconditioner's
@@ -532,12 +552,10 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                                   nullptr, nullptr, nullptr, W.nit.as<int>());
       // true residual
       apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
-      launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
-      HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hnit.data(), W.nit.p, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
-      if (!have_hb)
-        HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      launch_norm_readback(s, w, n, nrhs, beta, (double*)W.part.p, bnorm, W.nit.as<int>(), W.rb.h,
+                           W.rb.nit());
       HIPCHK(hipStreamSynchronize(s));
+      take_rb();
       read_hb();
       bool all = true;
       for (int r = 0; r < nrhs; ++r) {
@@ -556,10 +574,9 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   }
   if (!final_known) {
     apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
-    launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
-    HIPCHK(hipMemcpyAsync(hr.data(), beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-    if (!have_hb) HIPCHK(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    launch_norm_readback(s, w, n, nrhs, beta, (double*)W.part.p, bnorm, W.nit.as<int>(), W.rb.h, W.rb.nit());
     HIPCHK(hipStreamSynchronize(s));
+    take_rb();
     read_hb();
   }
   bool ok = true;
