@@ -816,13 +816,19 @@ __global__ void __launch_bounds__(NT) k_gram_reduce(const cd* __restrict__ parti
 }
 
 // G + shift * tr(G) * I = R^H R (R upper, positive real diagonal); on exit G
-// holds R^{-1} (upper).  One workgroup, the matrix in LDS: right-looking
-// Cholesky with the trailing update spread over the threads, then R^{-1} by
-// backward Gauss-Jordan.  *fail is set on a non-positive pivot.
+// holds R^{-1} (upper).  One workgroup, the matrix in LDS.  The elimination
+// keeps the unscaled upper factor A (row j of A = sqrt(a_jj) times row j of
+// R), so a step needs no square root: A_k. -= conj(a_jk) (a_j. / a_jj) for
+// k > j.  Then A^{-1} by backward Gauss-Jordan on [A | I] with each row's
+// division by its pivot deferred to the end, and R^{-1} = A^{-1} diag(sqrt
+// a_jj).  One barrier per step; square roots and divisions by the pivots
+// are taken for all rows at once outside the dependent chains.  *fail is
+// set on a non-positive pivot.
 __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d, double shift,
                                                       int* __restrict__ fail) {
-  __shared__ cd R[64][65];
+  __shared__ cd A[64][65];
   __shared__ cd X[64][65];
+  __shared__ double inva[64], sqa[64];
   __shared__ double trs;
   const int t = threadIdx.x;
   // thread (row slot, column) = (t / 64, t % 64): rows stride 4, so no loop
@@ -834,56 +840,52 @@ __global__ void __launch_bounds__(NT) k_cholesky_rinv(cd* __restrict__ G, int d,
 #pragma unroll 4
   for (int a = tr; a < d; a += 4) {
     const cd v = G[(col_ok ? a * d + tc : 0)];
-    if (col_ok) R[a][tc] = tc >= a ? v : mk(0.0, 0.0);
+    if (col_ok) A[a][tc] = tc >= a ? v : mk(0.0, 0.0);
   }
   __syncthreads();
   if (t < 64) {  // shift * tr(G), summed by wave 0
-    const double tr_sum = wave_sum(t < d ? R[t][t].re : 0.0);
+    const double tr_sum = wave_sum(t < d ? A[t][t].re : 0.0);
     if (t == 0) trs = shift * tr_sum;
   }
   __syncthreads();
-  if (t < d) R[t][t].re += trs;
+  if (t < d) A[t][t].re += trs;
   __syncthreads();
   bool failed = false;
   for (int j = 0; j < d; ++j) {
-    const double s = R[j][j].re;
-    if (!(s > 0.0)) {  // uniform: every thread reads the same s
+    const double s = A[j][j].re;  // final since the last barrier; same for every thread
+    if (!(s > 0.0)) {
       failed = true;
       break;
     }
-    const double rjj = sqrt(s), inv = 1.0 / rjj;
-    __syncthreads();
-    // row j of R: R[j][i] /= rjj (i > j); R[j][j] = rjj
-    if (tr == 0 && tc > j && col_ok) R[j][tc] = inv * R[j][tc];
-    if (t == 0) R[j][j] = mk(rjj, 0.0);
-    __syncthreads();
-    // trailing update of the upper triangle: R[k][i] -= conj(R[j][k]) R[j][i], i >= k > j
-    for (int k = j + 1 + tr; k < d; k += 4)
-      if (tc >= k && col_ok) R[k][tc] = R[k][tc] - cjmul(R[j][k], R[j][tc]);
+    const double inv = 1.0 / s;
+    if (tc > j && col_ok) {
+      const cd u = inv * A[j][tc];
+      for (int k = j + 1 + tr; k <= tc; k += 4) A[k][tc] = A[k][tc] - cjmul(A[j][k], u);
+    }
     __syncthreads();
   }
   if (failed) {
     if (t == 0) atomicOr(fail, 1);
     return;
   }
-  // X = R^{-1} by backward Gauss-Jordan on [R | I]: for j = d-1 .. 0, row j
-  // of R is R_jj e_j once the columns right of j are eliminated, so row j of X
-  // is divided by R_jj and R_ij X_j is subtracted from every row i < j (R_ij
-  // itself is never changed by the earlier steps).  Every step spreads over
-  // the whole workgroup; a per-column back substitution would walk up to
-  // d^2/2 dependent LDS reads in one thread.
+  if (t < d) {
+    inva[t] = 1.0 / A[t][t].re;
+    sqa[t] = sqrt(A[t][t].re);
+  }
   for (int a = tr; a < d; a += 4)
     if (col_ok) X[a][tc] = mk(a == tc ? 1.0 : 0.0, 0.0);
   __syncthreads();
-  for (int j = d - 1; j >= 0; --j) {
-    if (tr == 0 && tc >= j && col_ok) X[j][tc] = (1.0 / R[j][j].re) * X[j][tc];
-    __syncthreads();
-    for (int i = tr; i < j; i += 4)
-      if (tc >= j && col_ok) X[i][tc] = X[i][tc] - R[i][j] * X[j][tc];
+  // Y = unscaled rows of A^{-1}: for j = d-1 .. 0, row j of Y is final (its
+  // true value is Y_j / a_jj) and is eliminated from every row i < j
+  for (int j = d - 1; j > 0; --j) {
+    if (tc >= j && col_ok) {
+      const cd u = inva[j] * X[j][tc];
+      for (int i = tr; i < j; i += 4) X[i][tc] = X[i][tc] - A[i][j] * u;
+    }
     __syncthreads();
   }
   for (int a = tr; a < d; a += 4)
-    if (col_ok) G[a * d + tc] = X[a][tc];
+    if (col_ok) G[a * d + tc] = tc >= a ? (inva[a] * sqa[tc]) * X[a][tc] : mk(0.0, 0.0);
 }
 
 // Q_j[k] = sum_{i <= j} Y_i[k] Rinv[i][j] on the FP64 matrix cores: a wave
