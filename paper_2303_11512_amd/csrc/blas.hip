@@ -335,20 +335,54 @@ __global__ void __launch_bounds__(NT) k_reduce_chunks(const cx<T>* __restrict__ 
 
 // w[r] += sign * sum_i V_i[r] coef[r*ldc + i]; optional partial |w|^2 per chunk.
 // Vectors are added in index order, a few of them loaded together.
-template <class T, int EPT>
+// BS: the coefficients are y = R^{-1} g of an FGMRES cycle (R: the rotated
+// Hessenberg Hb, [r][m][m + 1] with m = ldc; g: gb, [r][m + 1]; nlim[r]
+// steps), solved by every workgroup for its RHS with k_backsolve's
+// operations in its order: the triangle and g staged in LDS by the whole
+// workgroup, the substitution by one thread.  overwrite: w = sum (w not read).
+template <class T, int EPT, bool BS>
 __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V, int64_t sI, int64_t sR,
                                                      int nv, const cx<T>* __restrict__ coef, int ldc,
                                                      T sign, cx<T>* __restrict__ w, int64_t n,
                                                      T* __restrict__ partial,
                                                      const int* __restrict__ active,
-                                                     const int* __restrict__ nlim) {
+                                                     const int* __restrict__ nlim, const cx<T>* __restrict__ Hb,
+                                                     const cx<T>* __restrict__ gb, int overwrite) {
   constexpr int CH = NT * EPT;
   __shared__ cx<T> cs[64];
   __shared__ T sh[8];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   if (nlim) nv = min(nv, nlim[r]);
-  for (int i = threadIdx.x; i < nv; i += NT) cs[i] = sign * coef[(int64_t)r * ldc + i];
+  if constexpr (BS) {
+    constexpr int KT = 32;  // largest step count staged in LDS
+    __shared__ cx<T> ht[KT * (KT + 1) / 2];
+    __shared__ cx<T> gs[KT];
+    const int m = ldc;
+    const cx<T>* __restrict__ Hr = Hb + (int64_t)r * m * (m + 1);
+    const cx<T>* __restrict__ gr = gb + (int64_t)r * (m + 1);
+    const bool lds = nv <= KT;
+    if (lds) {
+      // ht[l (l + 1) / 2 + i] = R(i, l) = Hr[l (m + 1) + i], i <= l < nv
+      for (int e = threadIdx.x; e < nv * KT; e += NT) {
+        const int l = e / KT, i = e % KT;
+        if (i <= l) ht[l * (l + 1) / 2 + i] = Hr[(int64_t)l * (m + 1) + i];
+      }
+      for (int i = threadIdx.x; i < nv; i += NT) gs[i] = gr[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = nv - 1; i >= 0; --i) {
+        cx<T> acc = lds ? gs[i] : gr[i];
+        for (int l = i + 1; l < nv; ++l)
+          acc = acc - (lds ? ht[l * (l + 1) / 2 + i] : Hr[(int64_t)l * (m + 1) + i]) * cs[l];
+        cs[i] = cdiv(acc, lds ? ht[i * (i + 1) / 2 + i] : Hr[(int64_t)i * (m + 1) + i]);
+      }
+      for (int i = 0; i < nv; ++i) cs[i] = sign * cs[i];
+    }
+  } else {
+    for (int i = threadIdx.x; i < nv; i += NT) cs[i] = sign * coef[(int64_t)r * ldc + i];
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
   cx<T>* __restrict__ wr = w + (int64_t)r * n;
@@ -357,7 +391,7 @@ __global__ void __launch_bounds__(NT) k_update_multi(const cx<T>* __restrict__ V
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int64_t k = base + (int64_t)e * NT;
-    acc[e] = wr[k < n ? k : n - 1];  // past n: computed, never stored
+    acc[e] = overwrite ? cx<T>{0, 0} : wr[k < n ? k : n - 1];  // past n: computed, never stored
   }
   constexpr int G = EPT >= 8 ? 2 : DG;  // G * EPT loads in flight, within the register budget
   int i = 0;
@@ -945,15 +979,27 @@ void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, 
   if (nv <= 0) return;
   const int ept = pick_ept(n, nrhs);
   const unsigned nch = nchunks(n, ept);
-  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi<T, E>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI, sR,
-                                       nv, coef, ldc, sign, w, n, norm_out ? partial : (T*)nullptr,
-                                       active, nlim));
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi<T, E, false>), dim3(nch, nrhs), dim3(NT), 0, s, V, sI,
+                                       sR, nv, coef, ldc, sign, w, n, norm_out ? partial : (T*)nullptr,
+                                       active, nlim, (const cx<T>*)nullptr, (const cx<T>*)nullptr, 0));
   KCHK();
   if (norm_out) {
     hipLaunchKernelGGL(k_norm_reduce<T>, dim3((nrhs + 3) / 4), dim3(NT), 0, s, partial, (int)nch,
                        nrhs, norm_out, active, (int*)nullptr);
     KCHK();
   }
+}
+
+template <class T>
+void launch_update_backsolve(hipStream_t s, const cx<T>* Z, int64_t sI, int64_t n, int m, const cx<T>* H,
+                             const cx<T>* g, const int* nit, cx<T>* x, int nrhs, bool overwrite) {
+  require(m >= 1 && m <= 64, "update_backsolve: 1 <= m <= 64");
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_update_multi<T, E, true>), dim3(nch, nrhs), dim3(NT), 0, s, Z, sI,
+                                       n, m, (const cx<T>*)nullptr, m, (T)1, x, n, (T*)nullptr,
+                                       (const int*)nullptr, nit, H, g, overwrite ? 1 : 0));
+  KCHK();
 }
 
 template <class T>
@@ -1283,6 +1329,8 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                       int*);                                                       \
   template void launch_backsolve<T>(hipStream_t, int, int, const cx<T>*, const cx<T>*, const int*, \
                                     cx<T>*);                                                      \
+  template void launch_update_backsolve<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,         \
+                                           const cx<T>*, const cx<T>*, const int*, cx<T>*, int, bool); \
   template void launch_fgmres_init<T>(hipStream_t, int, const T*, const int*, const int*, T,       \
                                       const T*, int, int*, int*, cx<T>*, T*);
 INST(double)

@@ -366,6 +366,12 @@ void launch_hcol_givens(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, 
 template <class T>
 void launch_backsolve(hipStream_t s, int m, int nrhs, const cx<T>* H, const cx<T>* g,
                       const int* nit, cx<T>* y);
+// x += Z y (overwrite: x = Z y, x not read) with y = R^{-1} g solved inside
+// the update (k_backsolve's arithmetic, same bits): Z [r] at stride sI per
+// basis vector, H/g/nit as launch_backsolve takes them
+template <class T>
+void launch_update_backsolve(hipStream_t s, const cx<T>* Z, int64_t sI, int64_t n, int m, const cx<T>* H,
+                             const cx<T>* g, const int* nit, cx<T>* x, int nrhs, bool overwrite);
 template <class T>
 void launch_fgmres_init(hipStream_t s, int nrhs, const T* beta, const int* parent, const int* done,
                         T tol, const T* bnorm, int m, int* active, int* nit, cx<T>* g, T* thr);

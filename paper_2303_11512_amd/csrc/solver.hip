@@ -478,8 +478,10 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   const bool guess = learned && (sp.use_cnn & MGM_CNN_GUESS);
   if (guess)
     cnn_initial_guess(c, g, nrhs, b, x, w);
-  else
+  else if (!L.has_dense && sp.max_restarts < 0)
     launch_axpby<double>(s, 0.0, b, 0.0, nullptr, x, n, nrhs, nullptr);
+  // otherwise x = 0 is never stored: the dense apply or the first cycle's
+  // update writes x without reading it
   // read the residual norms, ||b|| and the iteration counts the reduce kernel
   // stored in pinned memory (the stream is synchronised)
   auto take_rb = [&] {
@@ -547,9 +549,9 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
           if (std::all_of(fj, fj + nrhs, [](int a) { return a == 0; })) break;
         }
       }
-      launch_backsolve<double>(s, m, nrhs, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(), W.y.as<cd>());
-      launch_update_multi<double>(s, Z, (int64_t)nrhs * n, n, m, W.y.as<cd>(), m, 1.0, x, n, nrhs,
-                                  nullptr, nullptr, nullptr, W.nit.as<int>());
+      // x += Z y (from x = 0: x = Z y), y = R^{-1} g solved by the update's workgroups
+      launch_update_backsolve<double>(s, Z, (int64_t)nrhs * n, n, m, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(),
+                                      x, nrhs, cycle == 0 && !guess);
       // true residual
       apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
       launch_norm_readback(s, w, n, nrhs, beta, (double*)W.part.p, bnorm, W.nit.as<int>(), W.rb.h,
