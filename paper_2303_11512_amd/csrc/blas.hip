@@ -527,6 +527,43 @@ __global__ void __launch_bounds__(NT) k_scale_r(const cx<T>* __restrict__ w, con
     v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
 }
 
+// The first cycle of FGMRES from x = 0, started in one launch per RHS r:
+// ||b_r|| from the norm partials (k_norm_reduce's sum, same bits); the cycle
+// state as k_fgmres_init sets it with beta = ||b_r|| (no parent), a zero
+// right-hand side marked solved; v_0 = b_r / ||b_r|| (k_scale's arithmetic).
+// Workgroup 0 of each RHS stores ||b_r||, the flags and the state.
+__global__ void __launch_bounds__(NT) k_fgmres_start(const cd* __restrict__ b, const double* __restrict__ npart,
+                                                     int nch, int64_t n, int m, double tol,
+                                                     double* __restrict__ bnorm, int* __restrict__ done,
+                                                     int* __restrict__ active, int* __restrict__ nit,
+                                                     cd* __restrict__ g, double* __restrict__ thr,
+                                                     cd* __restrict__ v) {
+  __shared__ double dsh;
+  const int r = blockIdx.y;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double acc = 0;
+    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
+    acc = wave_sum(acc);
+    if (lane == 0) dsh = sqrt(acc);
+  }
+  __syncthreads();
+  const double d = dsh;
+  const bool on = d > 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bnorm[r] = d;
+    done[r] = d == 0.0 ? 1 : 0;
+    active[r] = on ? 1 : 0;
+    nit[r] = 0;
+    g[(int64_t)r * (m + 1)] = mk<double>(on ? d : 0.0, 0);
+    thr[r] = tol * d;
+  }
+  if (!on) return;
+  const double sc = 1.0 / d;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT)
+    v[(int64_t)r * n + k] = sc * b[(int64_t)r * n + k];
+}
+
 // Position of fine-level dof k (lattice layout: site-major, 2 dofs) in the
 // block-major layout of the fine FP32 cycle (4x4-site blocks of 32 dofs,
 // sites t-major within a block); Nx = 0: the lattice layout itself
@@ -1060,6 +1097,19 @@ void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, in
   const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
   unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_scale_r<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, den_out, active);
+  KCHK();
+}
+
+void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double* partial, int m, double tol,
+                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v) {
+  const int ept = pick_ept(n, nrhs);
+  const unsigned nch = nchunks(n, ept);
+  EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<double, E>), dim3(nch, nrhs), dim3(NT), 0, s, b, n,
+                                       partial, (const int*)nullptr));
+  KCHK();
+  const unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_fgmres_start, dim3(gx, nrhs), dim3(NT), 0, s, b, partial, (int)nch, n, m, tol, bnorm,
+                     done, active, nit, g, thr, v);
   KCHK();
 }
 

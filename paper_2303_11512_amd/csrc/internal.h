@@ -311,6 +311,12 @@ void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const c
 template <class T>
 void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
                  T* partial, int* zero_done = nullptr);
+// FGMRES from x = 0: ||b|| (with the zero-RHS flags), the first cycle's
+// state (launch_fgmres_init with beta = ||b||) and v_0 = b / ||b|| in one
+// norm-partial launch and one more (same bits as launch_norm, launch_fgmres_init
+// and launch_scale)
+void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double* partial, int m, double tol,
+                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v);
 // launch_norm (same bits) whose reduce kernel also hands the host what it
 // reads with the norms, in pinned host memory: host[r] = ||w_r||,
 // host[nrhs + r] = bnorm[r], hnit[r] = nit[r] (no copies)

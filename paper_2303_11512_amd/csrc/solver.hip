@@ -469,13 +469,16 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   };
 
   W.rb.ensure(nrhs);
-  // ||b||; zero right-hand sides are solved
-  launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p, done);
   require(sp.use_cnn >= 0 && sp.use_cnn <= (MGM_CNN_GUESS | MGM_CNN_STAGE), "use_cnn: unknown flags");
   const bool learned = l == 0 && !L.has_dense;
   const bool stage = learned && (sp.use_cnn & MGM_CNN_STAGE);
   if (stage) require(c->cnn && c->cnn->ready, "no network parameters set (mgm_cnn_set_params)", MGM_ESTATE);
   const bool guess = learned && (sp.use_cnn & MGM_CNN_GUESS);
+  // from x = 0 the first cycle starts from r0 = b and ||r0|| = ||b||
+  // exactly: ||b|| and that start come from one launch in the loop below
+  const bool zero_start = !L.has_dense && !guess && sp.max_restarts >= 0;
+  // ||b||; zero right-hand sides are solved
+  if (!zero_start) launch_norm<double>(s, b, n, nrhs, bnorm, nullptr, (double*)W.part.p, done);
   if (guess)
     cnn_initial_guess(c, g, nrhs, b, x, w);
   else if (!L.has_dense && sp.max_restarts < 0)
@@ -500,20 +503,17 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch[c->wslot]);
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
-      // r0 = b - D x ; v0 = r0 / ||r0||.  From x = 0 that is r0 = b and
-      // ||r0|| = ||b|| exactly, both at hand
-      const cd* r0 = w;
-      const double* b0 = beta;
-      if (cycle == 0 && !guess) {
-        r0 = b;
-        b0 = bnorm;
+      // r0 = b - D x ; v0 = r0 / ||r0||
+      if (cycle == 0 && zero_start) {
+        launch_fgmres_start(s, b, n, nrhs, (double*)W.part.p, m, sp.tol, bnorm, done, act, W.nit.as<int>(),
+                            W.g.as<cd>(), W.thr.as<double>(), V);
       } else {
         apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
         launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
+        launch_fgmres_init<double>(s, nrhs, beta, nullptr, done, sp.tol, bnorm, m, act,
+                                   W.nit.as<int>(), W.g.as<cd>(), W.thr.as<double>());
+        launch_scale<double>(s, w, beta, n, nrhs, V, act);
       }
-      launch_fgmres_init<double>(s, nrhs, b0, nullptr, done, sp.tol, bnorm, m, act,
-                                 W.nit.as<int>(), W.g.as<cd>(), W.thr.as<double>());
-      launch_scale<double>(s, r0, b0, n, nrhs, V, act);
       for (int j = 0; j < m; ++j) {
         // the whole step is one graph: key level field (m + 1) * 1000 + l
         // (+ 500 with the learned stage) tells it from the preconditioner's
@@ -551,7 +551,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
       }
       // x += Z y (from x = 0: x = Z y), y = R^{-1} g solved by the update's workgroups
       launch_update_backsolve<double>(s, Z, (int64_t)nrhs * n, n, m, W.H.as<cd>(), W.g.as<cd>(), W.nit.as<int>(),
-                                      x, nrhs, cycle == 0 && !guess);
+                                      x, nrhs, cycle == 0 && zero_start);
       // true residual
       apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
       launch_norm_readback(s, w, n, nrhs, beta, (double*)W.part.p, bnorm, W.nit.as<int>(), W.rb.h,
