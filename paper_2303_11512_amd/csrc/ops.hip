@@ -421,20 +421,25 @@ __global__ void __launch_bounds__(NT) k_prolong(const cx<T>* __restrict__ P, int
   *o = accumulate ? (*o + acc) : acc;
 }
 
+// right-hand sides per restriction thread (measured: 4 / 2 beat 2 / 1 and 8 / 2)
+constexpr int RT_RESTRICT_FINE = 4;    // 2-dof sites in 4x4 aggregates
+constexpr int RT_RESTRICT_COARSE = 2;  // 16-dof sites in 2x2 aggregates
+
 // The same two maps for a hierarchy shape fixed at compile time (M dofs per
 // site, BX x BT aggregates, NTV test vectors per chirality).  Every index is a
 // shift or a multiply and the row loop is unrolled, so a thread issues all of
 // its loads at once instead of one dependent round trip per aggregate row;
 // the generic kernels above are latency bound for exactly that reason.
 // BLK: xf in the block-major layout of the fine FP32 cycle (the BX x BT
-// aggregate's sites t-major, then dofs, contiguous per aggregate)
-template <class T, int M, int BX, int BT, int NTV, bool BLK = false>
+// aggregate's sites t-major, then dofs, contiguous per aggregate).
+// RT right-hand sides per thread (blockIdx.y: RHS r0 = RT blockIdx.y ..):
+// the thread's P column is loaded once for all of them.
+template <class T, int M, int BX, int BT, int NTV, bool BLK = false, int RT = 1>
 __global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, int Nx, int Nt,
                                                    const cx<T>* __restrict__ xf, cx<T>* __restrict__ xc,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active, int nrhs) {
   constexpr int Mh = M / 2, NROW = BX * BT * Mh;
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
+  const int r0 = blockIdx.y * RT;
   const int NAx = Nx / BX;
   const int64_t nc = (int64_t)NAx * (Nt / BT) * 2 * NTV;
   const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -444,21 +449,32 @@ __global__ void __launch_bounds__(NT) k_restrict_t(const cx<T>* __restrict__ P, 
   const int64_t A = Ac / 2;
   const int c = (int)(Ac % 2);
   const int Ax = (int)(A % NAx), At = (int)(A / NAx);
-  const cx<T>* __restrict__ xr =
-      BLK ? xf + (int64_t)r * Nx * Nt * M + A * (BX * BT * M) + c * Mh
-          : xf + (int64_t)r * Nx * Nt * M + ((int64_t)At * BT * Nx + (int64_t)Ax * BX) * M + c * Mh;
+  const int64_t nf = (int64_t)Nx * Nt * M;
+  const cx<T>* __restrict__ xa = BLK ? xf + A * (BX * BT * M) + c * Mh
+                                     : xf + ((int64_t)At * BT * Nx + (int64_t)Ax * BX) * M + c * Mh;
   const cx<T>* __restrict__ Pc = P + Ac * NROW * NTV + k;
-  cx<T> pv[NROW], xv[NROW];
+  cx<T> pv[NROW], xv[RT][NROW];
+  bool on[RT];
 #pragma unroll
-  for (int s = 0; s < NROW; ++s) {
-    const int sl = s / Mh, a = s % Mh;
-    pv[s] = Pc[s * NTV];
-    xv[s] = BLK ? xr[sl * M + a] : xr[((int64_t)(sl / BX) * Nx + sl % BX) * M + a];
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = r0 + rt;
+    on[rt] = r < nrhs && (!active || active[r]);
+    const cx<T>* __restrict__ xr = xa + (int64_t)(r < nrhs ? r : r0) * nf;  // lanes past nrhs: never stored
+#pragma unroll
+    for (int s = 0; s < NROW; ++s) {
+      const int sl = s / Mh, a = s % Mh;
+      xv[rt][s] = BLK ? xr[sl * M + a] : xr[((int64_t)(sl / BX) * Nx + sl % BX) * M + a];
+    }
   }
-  cx<T> acc = mk<T>(0, 0);
 #pragma unroll
-  for (int s = 0; s < NROW; ++s) cjfma(acc, pv[s], xv[s]);
-  xc[(int64_t)r * nc + idx] = acc;
+  for (int s = 0; s < NROW; ++s) pv[s] = Pc[s * NTV];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int s = 0; s < NROW; ++s) cjfma(acc, pv[s], xv[rt][s]);
+    if (on[rt]) xc[(int64_t)(r0 + rt) * nc + idx] = acc;
+  }
 }
 
 template <class T, int M, int BX, int BT, int NTV, bool BLK = false>
@@ -2423,9 +2439,13 @@ void launch_restrict(hipStream_t s, const cx<T>* P, int Nx, int Nt, int M, int b
   const int64_t nc = (int64_t)(Nx / bx) * (Nt / bt) * 2 * ntv;
   const dim3 g(grid1(nc), nrhs);
   if (M == 2 && bx == 4 && bt == 4 && ntv == 8)
-    hipLaunchKernelGGL((k_restrict_t<T, 2, 4, 4, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xf, xc, active);
+    hipLaunchKernelGGL((k_restrict_t<T, 2, 4, 4, 8, false, RT_RESTRICT_FINE>),
+                       dim3(grid1(nc), (nrhs + RT_RESTRICT_FINE - 1) / RT_RESTRICT_FINE), dim3(NT), 0, s, P, Nx,
+                       Nt, xf, xc, active, nrhs);
   else if (M == 16 && bx == 2 && bt == 2 && ntv == 8)
-    hipLaunchKernelGGL((k_restrict_t<T, 16, 2, 2, 8>), g, dim3(NT), 0, s, P, Nx, Nt, xf, xc, active);
+    hipLaunchKernelGGL((k_restrict_t<T, 16, 2, 2, 8, false, RT_RESTRICT_COARSE>),
+                       dim3(grid1(nc), (nrhs + RT_RESTRICT_COARSE - 1) / RT_RESTRICT_COARSE), dim3(NT), 0, s, P,
+                       Nx, Nt, xf, xc, active, nrhs);
   else
     hipLaunchKernelGGL(k_restrict<T>, g, dim3(NT), 0, s, P, Nx, Nt, M, bx, bt, ntv, xf, xc, active);
   KCHK();
@@ -2467,8 +2487,9 @@ void launch_sap0_blk(hipStream_t s, const cf* B, const cf* inv, int Nx, int Nt, 
 void launch_restrict_blk(hipStream_t s, const cf* P, int Nx, int Nt, int nrhs, const cf* xf, cf* xc,
                          const int* active) {
   const int64_t nc = (int64_t)(Nx / 4) * (Nt / 4) * 2 * 8;
-  hipLaunchKernelGGL((k_restrict_t<float, 2, 4, 4, 8, true>), dim3(grid1(nc), nrhs), dim3(NT), 0, s, P, Nx, Nt,
-                     xf, xc, active);
+  hipLaunchKernelGGL((k_restrict_t<float, 2, 4, 4, 8, true, RT_RESTRICT_FINE>),
+                     dim3(grid1(nc), (nrhs + RT_RESTRICT_FINE - 1) / RT_RESTRICT_FINE), dim3(NT), 0, s, P, Nx, Nt,
+                     xf, xc, active, nrhs);
   KCHK();
 }
 
