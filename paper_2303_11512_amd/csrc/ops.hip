@@ -1257,7 +1257,7 @@ __device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
   const int hh = wave & 1;
-  const int r0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
+  const int r0 = (blockIdx.y * (int)(blockDim.x >> 7) + (wave >> 1)) * 16;  // 2 waves per 16-RHS tile
   if (r0 >= nrhs) return;
   const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int64_t n = (int64_t)Nx * Nt * CM;
@@ -1411,7 +1411,7 @@ __global__ void __launch_bounds__(NT) k_sap4p(const cx<T>* __restrict__ M, const
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15;
   const int hh = wave & 1;
-  const int r0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
+  const int r0 = (blockIdx.y * (int)(blockDim.x >> 7) + (wave >> 1)) * 16;  // 2 waves per 16-RHS tile
   if (r0 >= nrhs) return;
   const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int64_t n = (int64_t)Nx * Nt * CM;
@@ -2371,18 +2371,25 @@ void launch_sap4_premul(hipStream_t s, const cd* blocks, const cd* inv, int Nx, 
   KCHK();
 }
 
+// 16-RHS tiles per workgroup of the FP16 2x2 sweep: one (two waves) spreads
+// a 32-RHS sweep over 256 workgroups instead of 128; measured inside the
+// step against two: 94.0 vs 93.5 estimates/s (back to back at 64 RHS 5.9 vs
+// 5.8 us)
+constexpr int SAP4_TILES_PER_WG = 1;
 void launch_sap4p_h(hipStream_t s, const chalf* M, const chalf* inv, int Nx, int Nt, const int* blist, int nb,
                     int nrhs, bool first, const cf* r, cf* rho, cf* x, const int* active, const chalf* hP,
                     const cf* ec) {
   if (nb <= 0 || nrhs <= 0) return;
-  const dim3 g(nb, ((nrhs + 15) / 16 + 1) / 2);
+  constexpr int TPW = SAP4_TILES_PER_WG;  // 16-RHS tiles per workgroup (two waves each)
+  const dim3 g(nb, ((nrhs + 15) / 16 + TPW - 1) / TPW);
   require(!ec || (first && hP), "FP16 2x2 SAP: the halo from the coarse correction needs the first sweep and P");
   if (ec)
-    hipLaunchKernelGGL(k_sap4p_hc, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active, hP, ec);
+    hipLaunchKernelGGL(k_sap4p_hc, g, dim3(128 * TPW), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active, hP,
+                       ec);
   else if (first)
-    hipLaunchKernelGGL(k_sap4p_h<true>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+    hipLaunchKernelGGL(k_sap4p_h<true>, g, dim3(128 * TPW), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
   else
-    hipLaunchKernelGGL(k_sap4p_h<false>, g, dim3(NT), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
+    hipLaunchKernelGGL(k_sap4p_h<false>, g, dim3(128 * TPW), 0, s, M, inv, Nx, Nt, blist, nrhs, r, rho, x, active);
   KCHK();
 }
 
