@@ -1580,14 +1580,15 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   const int blk = blist[xcd_tile(blockIdx.x, gridDim.x)];
   const int NBx = Nx / SB;
   const int bx = (blk % NBx) * SB, bt = (blk / NBx) * SB;
-  for (int e = threadIdx.x; e < K * K; e += NT) Is[e] = inv[(int64_t)blk * K * K + e];
-  for (int e = threadIdx.x; e < NS * 20; e += NT) {
+  const int nthr = blockDim.x;  // 64 per 16-RHS tile, at most NT
+  for (int e = threadIdx.x; e < K * K; e += nthr) Is[e] = inv[(int64_t)blk * K * K + e];
+  for (int e = threadIdx.x; e < NS * 20; e += nthr) {
     const int s = e / 20;
     const int64_t us = (int64_t)(bt + s / SB) * Nx + bx + s % SB;
     Bs[e] = B[us * 20 + e % 20];
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.y * 4 + wave) * 16;
+  const int r0 = (blockIdx.y * (nthr >> 6) + wave) * 16;
   const int64_t n = (int64_t)Nx * Nt * 2;
   // Halo term h = r_B - D_BH x_H on the vector units, lanes along the block's
   // dofs (k = lane % 32: a time row of the block is 8 consecutive dofs) and
@@ -2486,8 +2487,10 @@ template void launch_prolong<float>(hipStream_t, const cf*, int, int, int, int, 
 void launch_sap0_blk(hipStream_t s, const cf* B, const cf* inv, int Nx, int Nt, const int* blist, int nb,
                      int nrhs, const cf* r, cf* x, const int* active, cd* x64) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL((k_sap0_mfma<float, true>), dim3(nb, (nrhs + 63) / 64), dim3(NT), 0, s, B, inv, Nx, Nt, blist,
-                     nrhs, r, x, active, x64);
+  // one wave per 16-RHS tile, at most four per workgroup: no idle waves below 64 RHS
+  const int nt = (nrhs + 15) / 16, w = std::min(4, nt);
+  hipLaunchKernelGGL((k_sap0_mfma<float, true>), dim3(nb, (nt + w - 1) / w), dim3(64 * w), 0, s, B, inv, Nx, Nt,
+                     blist, nrhs, r, x, active, x64);
   KCHK();
 }
 
