@@ -527,17 +527,29 @@ __global__ void __launch_bounds__(NT) k_scale_r(const cx<T>* __restrict__ w, con
     v[(int64_t)r * n + k] = s * w[(int64_t)r * n + k];
 }
 
+// Position of fine-level dof k (lattice layout: site-major, 2 dofs) in the
+// block-major layout of the fine FP32 cycle (4x4-site blocks of 32 dofs,
+// sites t-major within a block); Nx = 0: the lattice layout itself
+__device__ __forceinline__ int64_t blk_pos(int64_t k, int Nx) {
+  if (Nx == 0) return k;
+  const int64_t site = k >> 1;
+  const int x = (int)(site % Nx), t = (int)(site / Nx);
+  return ((int64_t)(t >> 2) * (Nx >> 2) + (x >> 2)) * 32 + (((t & 3) << 2) + (x & 3)) * 2 + (k & 1);
+}
+
 // The first cycle of FGMRES from x = 0, started in one launch per RHS r:
 // ||b_r|| from the norm partials (k_norm_reduce's sum, same bits); the cycle
 // state as k_fgmres_init sets it with beta = ||b_r|| (no parent), a zero
-// right-hand side marked solved; v_0 = b_r / ||b_r|| (k_scale's arithmetic).
-// Workgroup 0 of each RHS stores ||b_r||, the flags and the state.
+// right-hand side marked solved; v_0 = b_r / ||b_r|| (k_scale's arithmetic),
+// and, with vf, its FP32 rounding for the preconditioner (block-major when
+// blk_nx > 0, as k_scale_convert stores it).  Workgroup 0 of each RHS stores
+// ||b_r||, the flags and the state.
 __global__ void __launch_bounds__(NT) k_fgmres_start(const cd* __restrict__ b, const double* __restrict__ npart,
                                                      int nch, int64_t n, int m, double tol,
                                                      double* __restrict__ bnorm, int* __restrict__ done,
                                                      int* __restrict__ active, int* __restrict__ nit,
                                                      cd* __restrict__ g, double* __restrict__ thr,
-                                                     cd* __restrict__ v) {
+                                                     cd* __restrict__ v, cf* __restrict__ vf, int blk_nx) {
   __shared__ double dsh;
   const int r = blockIdx.y;
   if (threadIdx.x < 64) {
@@ -560,19 +572,13 @@ __global__ void __launch_bounds__(NT) k_fgmres_start(const cd* __restrict__ b, c
   }
   if (!on) return;
   const double sc = 1.0 / d;
-  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT)
-    v[(int64_t)r * n + k] = sc * b[(int64_t)r * n + k];
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+    const cd vv = sc * b[(int64_t)r * n + k];
+    v[(int64_t)r * n + k] = vv;
+    if (vf) vf[(int64_t)r * n + blk_pos(k, blk_nx)] = mk<float>((float)vv.re, (float)vv.im);
+  }
 }
 
-// Position of fine-level dof k (lattice layout: site-major, 2 dofs) in the
-// block-major layout of the fine FP32 cycle (4x4-site blocks of 32 dofs,
-// sites t-major within a block); Nx = 0: the lattice layout itself
-__device__ __forceinline__ int64_t blk_pos(int64_t k, int Nx) {
-  if (Nx == 0) return k;
-  const int64_t site = k >> 1;
-  const int x = (int)(site % Nx), t = (int)(site / Nx);
-  return ((int64_t)(t >> 2) * (Nx >> 2) + (x >> 2)) * 32 + (((t & 3) << 2) + (x & 3)) * 2 + (k & 1);
-}
 
 // k_scale_r (without den_out) that also stores the FP32 rounding of v in vf
 // (block-major when blk_nx > 0): the scaling that ends an Arnoldi step, done
@@ -1101,7 +1107,8 @@ void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, in
 }
 
 void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double* partial, int m, double tol,
-                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v) {
+                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v, cf* vf,
+                         int blk_nx) {
   const int ept = pick_ept(n, nrhs);
   const unsigned nch = nchunks(n, ept);
   EPT_DISPATCH(ept, hipLaunchKernelGGL((k_norm_partial<double, E>), dim3(nch, nrhs), dim3(NT), 0, s, b, n,
@@ -1109,7 +1116,7 @@ void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double
   KCHK();
   const unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_fgmres_start, dim3(gx, nrhs), dim3(NT), 0, s, b, partial, (int)nch, n, m, tol, bnorm,
-                     done, active, nit, g, thr, v);
+                     done, active, nit, g, thr, v, vf, blk_nx);
   KCHK();
 }
 

@@ -314,9 +314,11 @@ void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, con
 // FGMRES from x = 0: ||b|| (with the zero-RHS flags), the first cycle's
 // state (launch_fgmres_init with beta = ||b||) and v_0 = b / ||b|| in one
 // norm-partial launch and one more (same bits as launch_norm, launch_fgmres_init
-// and launch_scale)
+// and launch_scale); vf (or null): v_0 rounded to FP32 as launch_scale_convert
+// stores it (block-major when blk_nx > 0)
 void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double* partial, int m, double tol,
-                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v);
+                         double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v, cf* vf,
+                         int blk_nx);
 // launch_norm (same bits) whose reduce kernel also hands the host what it
 // reads with the norms, in pinned host memory: host[r] = ||w_r||,
 // host[nrhs + r] = bnorm[r], hnit[r] = nit[r] (no copies)

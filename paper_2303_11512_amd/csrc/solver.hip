@@ -244,9 +244,10 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
 // scaling v_j = w / |w| that ends step j - 1 is done by step j's first launch
 // together with that rounding (into W.cvt_in), and prec is then called with
 // v = null; step j's own |w| goes to the Givens kernel as chunk partials.
+// cvt0 (with fused, step 0): the cycle start has rounded v_0 into W.cvt_in.
 template <class T, class PrecFn>
 void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec,
-                  int* host_flags = nullptr, bool fused = false) {
+                  int* host_flags = nullptr, bool fused = false, bool cvt0 = false) {
   hipStream_t s = c->stream;
   Level& L = *g.levels[l];
   const int64_t n = L.n;
@@ -267,6 +268,8 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
                               fine_blocked(g, L) ? L.Nx : 0);
     }
     prec(nullptr, Z + j * vs, (const int*)act);
+  } else if (fused && cvt0) {
+    prec(nullptr, Z, (const int*)act);
   } else {
     prec(V + j * vs, Z + j * vs, (const int*)act);
   }
@@ -504,9 +507,14 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   } else {
     for (int cycle = 0; cycle <= sp.max_restarts; ++cycle) {
       // r0 = b - D x ; v0 = r0 / ||r0||
+      // from x = 0 with an FP32-input preconditioner the start also rounds v_0
+      // for it, and step 0 hands the preconditioner that copy
+      const bool cvt0 = cycle == 0 && zero_start && fused;
       if (cycle == 0 && zero_start) {
+        if (cvt0) W.cvt_in.ensure(sizeof(cf) * (size_t)nrhs * n);
         launch_fgmres_start(s, b, n, nrhs, (double*)W.part.p, m, sp.tol, bnorm, done, act, W.nit.as<int>(),
-                            W.g.as<cd>(), W.thr.as<double>(), V);
+                            W.g.as<cd>(), W.thr.as<double>(), V, cvt0 ? W.cvt_in.as<cf>() : nullptr,
+                            fine_blocked(g, L) ? L.Nx : 0);
       } else {
         apply_op<double>(c, g, l, nrhs, x, w, b, nullptr);
         launch_norm<double>(s, w, n, nrhs, beta, nullptr, (double*)W.part.p);
@@ -520,7 +528,8 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
         // own graphs, from other restart lengths and from the plain step;
         // the step index is in the V / Z addresses
         const int64_t vs = (int64_t)nrhs * n;
-        const GraphKey key{(m + 1) * 1000 + l + (stage ? 500 : 0), nrhs, (const void*)(V + j * vs),
+        const GraphKey key{(m + 1) * 1000 + l + (stage ? 500 : 0) + (cvt0 && j == 0 ? 250 : 0), nrhs,
+                           (const void*)(V + j * vs),
                            (void*)(Z + j * vs), act, g.prm.precision};
         // the step's last kernel writes the active flags into pinned host
         // slot j % kDepth (no copy); the event marks the step's end
@@ -533,7 +542,7 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
                 else if (v) precondition_d(c, g, l, nrhs, v, z, a);
                 else precondition_f32in(c, g, l, nrhs, z, a);
               },
-              W.flags.h + slot * nrhs, fused);
+              W.flags.h + slot * nrhs, fused, cvt0 && j == 0);
         });
         HIPCHK(hipEventRecord(W.flags.ev[slot], s));
         if (j + 1 < PinnedFlags::kDepth) continue;
