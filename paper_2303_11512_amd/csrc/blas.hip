@@ -798,6 +798,50 @@ __global__ void __launch_bounds__(NT) k_hcol_givens_np(int j, int m, int nrhs, c
   if (lane == 0) hcol_givens_rhs<T>(r, j, m, c1, c2, sqrt(acc), H, cs, sn, g, thr, active, nit, host_flags);
 }
 
+// The end of a fused Arnoldi step j in one launch: workgroup 0 of each RHS
+// forms |w| and the Hessenberg column with its Givens update as
+// k_hcol_givens_np does (same bits; it may end the RHS and writes the host
+// flag); every workgroup forms v_{j+1} = w / |w| and its FP32 rounding for
+// the next step's preconditioner as k_scale_convert does.  The active flag
+// is read once when a workgroup starts: for a RHS that this step ends,
+// v_{j+1} may or may not be written, and it is never read.
+template <class T>
+__global__ void __launch_bounds__(NT) k_hcol_scale(int j, int m, const cx<T>* __restrict__ c1,
+                                                   const T* __restrict__ npart, int nch, cx<T>* __restrict__ H,
+                                                   T* __restrict__ cs, cx<T>* __restrict__ sn,
+                                                   cx<T>* __restrict__ g, const T* __restrict__ thr,
+                                                   int* __restrict__ active, int* __restrict__ nit,
+                                                   int* __restrict__ host_flags, const cx<T>* __restrict__ w,
+                                                   int64_t n, cx<T>* __restrict__ v, cf* __restrict__ vf,
+                                                   int blk_nx) {
+  __shared__ T dsh;
+  const int r = blockIdx.y;
+  const bool was = active[r] != 0;
+  if (!was && blockIdx.x != 0) return;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    T acc = 0;
+    if (was)
+      for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const T d = sqrt(acc);
+      dsh = d;
+      if (blockIdx.x == 0)
+        hcol_givens_rhs<T>(r, j, m, c1, (const cx<T>*)nullptr, d, H, cs, sn, g, thr, active, nit, host_flags);
+    }
+  }
+  __syncthreads();
+  if (!was) return;
+  const T d = dsh;
+  const T sc = (d > 0) ? (T)1 / d : (T)0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+    const cx<T> vv = sc * w[(int64_t)r * n + k];
+    v[(int64_t)r * n + k] = vv;
+    vf[(int64_t)r * n + blk_pos(k, blk_nx)] = mk<float>((float)vv.re, (float)vv.im);
+  }
+}
+
 // y = R^{-1} g with R the rotated (upper triangular) H of nit[r] steps
 template <class T>
 __global__ void __launch_bounds__(NT) k_backsolve(int m, int nrhs, const cx<T>* __restrict__ H,
@@ -1077,6 +1121,17 @@ void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t
   unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
   hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active,
                      blk_nx);
+  KCHK();
+}
+
+template <class T>
+void launch_hcol_scale(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const T* npart, cx<T>* H, T* cs,
+                       cx<T>* sn, cx<T>* g, const T* thr, int* active, int* nit, int* host_flags, const cx<T>* w,
+                       int64_t n, cx<T>* v, cf* vf, int blk_nx) {
+  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
+  const unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(k_hcol_scale<T>, dim3(gx, nrhs), dim3(NT), 0, s, j, m, c1, npart, (int)nch, H, cs, sn, g, thr,
+                     active, nit, host_flags, w, n, v, vf, blk_nx);
   KCHK();
 }
 
@@ -1376,6 +1431,9 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
                                       const int*, T*);                                             \
   template void launch_scale_convert<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,  \
                                         cf*, const int*, int);                                     \
+  template void launch_hcol_scale<T>(hipStream_t, int, int, int, const cx<T>*, const T*, cx<T>*, T*, \
+                                     cx<T>*, cx<T>*, const T*, int*, int*, int*, const cx<T>*,       \
+                                     int64_t, cx<T>*, cf*, int);                                    \
   template void launch_hcol_givens_np<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,     \
                                          const T*, int64_t, cx<T>*, T*, cx<T>*, cx<T>*, const T*,   \
                                          int*, int*, int*);                                        \

@@ -357,6 +357,12 @@ void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, i
 template <class T>
 void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
                           const int* active, int blk_nx = 0);
+// the end of a fused Arnoldi step j: launch_hcol_givens_np (no c2) and
+// launch_scale_convert into v = v_{j+1}, vf, in one launch (same bits)
+template <class T>
+void launch_hcol_scale(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const T* npart, cx<T>* H, T* cs,
+                       cx<T>* sn, cx<T>* g, const T* thr, int* active, int* nit, int* host_flags, const cx<T>* w,
+                       int64_t n, cx<T>* v, cf* vf, int blk_nx);
 // launch_hcol_givens with |w| formed from the chunk partials of |w|^2
 template <class T>
 void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,

@@ -240,10 +240,10 @@ void precond(mgm_ctx* c, Gauge& g, int l, int nrhs, const cx<T>* r, cx<T>* x, co
 
 // One Arnoldi step j of FGMRES: z_j = M v_j, w = D z_j, CGS2 against v_0..v_j,
 // Hessenberg column, v_{j+1} = w/||w||, Givens update.
-// fused (FP64 steps whose preconditioner rounds its input to FP32): the
-// scaling v_j = w / |w| that ends step j - 1 is done by step j's first launch
-// together with that rounding (into W.cvt_in), and prec is then called with
-// v = null; step j's own |w| goes to the Givens kernel as chunk partials.
+// fused (FP64 steps whose preconditioner rounds its input to FP32): step
+// j's last launch forms the Hessenberg column and Givens update together
+// with v_{j+1} = w / |w| and its FP32 rounding (into W.cvt_in), and the next
+// step calls prec with v = null.
 // cvt0 (with fused, step 0): the cycle start has rounded v_0 into W.cvt_in.
 template <class T, class PrecFn>
 void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& W, PrecFn&& prec,
@@ -261,15 +261,10 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
   cx<T>* c2 = W.coef2.template as<cx<T>>();
   T* hn = W.beta.template as<T>() ;  // beta is free after the cycle start: reuse for ||w||
   T* np = W.npart.template as<T>();
-  if (fused && j > 0) {
-    if constexpr (std::is_same<T, double>::value) {
-      W.cvt_in.ensure(sizeof(cf) * (size_t)vs);
-      launch_scale_convert<T>(s, w, np, n, nrhs, V + j * vs, W.cvt_in.template as<cf>(), act,
-                              fine_blocked(g, L) ? L.Nx : 0);
-    }
+  if (fused && (j > 0 || cvt0)) {
+    // v_j was rounded into W.cvt_in by the previous step's last launch (or,
+    // for step 0, by the cycle start)
     prec(nullptr, Z + j * vs, (const int*)act);
-  } else if (fused && cvt0) {
-    prec(nullptr, Z, (const int*)act);
   } else {
     prec(V + j * vs, Z + j * vs, (const int*)act);
   }
@@ -283,9 +278,15 @@ void arnoldi_step(mgm_ctx* c, Gauge& g, int l, int nrhs, int j, int m, Work<T>& 
                         act, np);
   c2 = nullptr;
   if (fused) {
-    launch_hcol_givens_np<T>(s, j, m, nrhs, c1, c2, np, n, W.H.template as<cx<T>>(), W.cs.template as<T>(),
-                             W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
-                             W.nit.template as<int>(), host_flags);
+    // Hessenberg column, Givens update, host flags, and v_{j+1} = w / |w|
+    // with its FP32 rounding for the next step, in one launch
+    if constexpr (std::is_same<T, double>::value) {
+      W.cvt_in.ensure(sizeof(cf) * (size_t)vs);
+      launch_hcol_scale<T>(s, j, m, nrhs, c1, np, W.H.template as<cx<T>>(), W.cs.template as<T>(),
+                           W.sn.template as<cx<T>>(), W.g.template as<cx<T>>(), W.thr.template as<T>(), act,
+                           W.nit.template as<int>(), host_flags, w, n, V + (j + 1) * vs, W.cvt_in.template as<cf>(),
+                           fine_blocked(g, L) ? L.Nx : 0);
+    }
     return;
   }
   launch_scale_r<T>(s, w, np, n, nrhs, V + (j + 1) * vs, hn, act);
