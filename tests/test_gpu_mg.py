@@ -252,3 +252,38 @@ def test_quad_site_sap_blocks(ctx, precision, tol, L):
         res = np.linalg.norm(b - (lev.D @ to_host(x).T).T, axis=1) / np.linalg.norm(b, axis=1)
         assert np.all(res <= 1e-10), (precision, l, res)
     ctx.free_gauge(gid)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_restarted_solves_and_zero_rhs(ctx, precision):
+    """FGMRES(3) with restarts to 1e-10 in every preconditioner precision.
+    The first cycle starts from x = 0 (r_0 = b and ||b|| exactly; in the
+    FP32-input modes the start also rounds v_0 for the preconditioner) and
+    writes x = Z y; later cycles start from the true residual and add to x.
+    A zero right-hand side is solved at once and its x stays exactly 0.  True
+    residuals with the oracle's operator; solutions against its exact
+    solve."""
+    from paper_2303_11512_amd import solve_params
+    th = metropolis_u1(32, 32, 3.0, 100, 1975)
+    rec = Recipe(th, -0.08, [(4, 4), (2, 2)], [8, 8], seed=11, sap_block=[(4, 4), (2, 2), (1, 1)],
+                 sap_cycles=[1, 1, 1], inner_iters=[0, 0, 0], precision=precision)
+    log(f"restarted solves, {precision}")
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    nz = [0, 1, 3, 4]
+    for l in range(2):
+        lev = hier.levels[l]
+        b = rhs_vectors(lev.n, 5, 61 + l)
+        b[2] = 0
+        x = empty(5, lev.n)
+        st, its, rel = ctx.solve_batch(gid, l, to_dev(b), x,
+                                       solve_params(tol=1e-10, restart=3, max_restarts=300))
+        xs = to_host(x)
+        its = np.asarray(its)
+        log(f"  level {l}: iterations {its.tolist()}")
+        assert np.all(xs[2] == 0) and its[2] == 0, (precision, l)
+        assert its[nz].max() > 3, (precision, l, its)  # at least one restart
+        res = np.linalg.norm(b[nz] - (lev.D @ xs[nz].T).T, axis=1) / np.linalg.norm(b[nz], axis=1)
+        assert np.all(res <= 1e-10), (precision, l, res)
+        assert rel_err(xs[nz], lev.solve(b[nz].T).T) < 1e-6, (precision, l)
+    ctx.free_gauge(gid)
