@@ -542,7 +542,7 @@ __device__ __forceinline__ int64_t blk_pos(int64_t k, int Nx) {
 // state as k_fgmres_init sets it with beta = ||b_r|| (no parent), a zero
 // right-hand side marked solved; v_0 = b_r / ||b_r|| (k_scale's arithmetic),
 // and, with vf, its FP32 rounding for the preconditioner (block-major when
-// blk_nx > 0, as k_scale_convert stores it).  Workgroup 0 of each RHS stores
+// blk_nx > 0, as k_hcol_scale stores it).  Workgroup 0 of each RHS stores
 // ||b_r||, the flags and the state.
 __global__ void __launch_bounds__(NT) k_fgmres_start(const cd* __restrict__ b, const double* __restrict__ npart,
                                                      int nch, int64_t n, int m, double tol,
@@ -580,34 +580,6 @@ __global__ void __launch_bounds__(NT) k_fgmres_start(const cd* __restrict__ b, c
 }
 
 
-// k_scale_r (without den_out) that also stores the FP32 rounding of v in vf
-// (block-major when blk_nx > 0): the scaling that ends an Arnoldi step, done
-// by the next step's first launch together with the rounding of the
-// preconditioner's input
-template <class T>
-__global__ void __launch_bounds__(NT) k_scale_convert(const cx<T>* __restrict__ w, const T* __restrict__ npart,
-                                                      int nch, int64_t n, cx<T>* __restrict__ v,
-                                                      cf* __restrict__ vf, const int* __restrict__ active,
-                                                      int blk_nx) {
-  __shared__ T dsh;
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    T acc = 0;
-    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
-    acc = wave_sum(acc);
-    if (lane == 0) dsh = sqrt(acc);
-  }
-  __syncthreads();
-  const T d = dsh;
-  const T s = (d > 0) ? (T)1 / d : (T)0;
-  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
-    const cx<T> vv = s * w[(int64_t)r * n + k];
-    v[(int64_t)r * n + k] = vv;
-    vf[(int64_t)r * n + blk_pos(k, blk_nx)] = mk<float>((float)vv.re, (float)vv.im);
-  }
-}
 
 // FP32 rounding of a fine-level FP64 block [nrhs][n] into the block-major layout
 __global__ void __launch_bounds__(NT) k_convert_blk(const cd* __restrict__ in, cf* __restrict__ out, int Nx,
@@ -697,18 +669,6 @@ __global__ void __launch_bounds__(NT) k_givens(int j, int m, int nrhs, cx<T>* __
   if (res <= thr[r] || nb == (T)0 || j + 1 == m) active[r] = 0;
 }
 
-// Hessenberg column j of RHS r: entries 0..j = c1 + c2 (the two Gram-Schmidt
-// passes), entry j+1 = ||w||.
-template <class T>
-__global__ void __launch_bounds__(NT) k_hcol(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
-                                             const cx<T>* __restrict__ c2, const T* __restrict__ hn,
-                                             cx<T>* __restrict__ H, const int* __restrict__ active) {
-  const int r = blockIdx.x * NT + threadIdx.x;
-  if (r >= nrhs || (active && !active[r])) return;
-  cx<T>* h = H + ((int64_t)r * m + j) * (m + 1);
-  for (int i = 0; i <= j; ++i) h[i] = c1[(int64_t)r * (m + 1) + i] + c2[(int64_t)r * (m + 1) + i];
-  h[j + 1] = mk<T>(hn[r], 0);
-}
 
 // Hessenberg column j (as k_hcol) followed by the Givens update (as
 // k_givens) in one launch; host_flags (pinned host memory, or null) receives
@@ -779,32 +739,15 @@ __global__ void __launch_bounds__(NT) k_hcol_givens(int j, int m, int nrhs, cons
   hcol_givens_rhs<T>(r, j, m, c1, c2, hn[r], H, cs, sn, g, thr, active, nit, host_flags);
 }
 
-// The same with |w| formed here from the chunk partials of |w|^2 (one wave
-// per RHS, added as k_scale_r adds them, so the same bits)
-template <class T>
-__global__ void __launch_bounds__(NT) k_hcol_givens_np(int j, int m, int nrhs, const cx<T>* __restrict__ c1,
-                                                       const cx<T>* __restrict__ c2, const T* __restrict__ npart,
-                                                       int nch, cx<T>* __restrict__ H, T* __restrict__ cs,
-                                                       cx<T>* __restrict__ sn, cx<T>* __restrict__ g,
-                                                       const T* __restrict__ thr, int* __restrict__ active,
-                                                       int* __restrict__ nit, int* __restrict__ host_flags) {
-  const int r = (int)(((int64_t)blockIdx.x * NT + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= nrhs) return;
-  T acc = 0;
-  if (active[r])
-    for (int c = lane; c < nch; c += 64) acc += npart[(int64_t)r * nch + c];
-  acc = wave_sum(acc);
-  if (lane == 0) hcol_givens_rhs<T>(r, j, m, c1, c2, sqrt(acc), H, cs, sn, g, thr, active, nit, host_flags);
-}
 
-// The end of a fused Arnoldi step j in one launch: workgroup 0 of each RHS
-// forms |w| and the Hessenberg column with its Givens update as
-// k_hcol_givens_np does (same bits; it may end the RHS and writes the host
-// flag); every workgroup forms v_{j+1} = w / |w| and its FP32 rounding for
-// the next step's preconditioner as k_scale_convert does.  The active flag
-// is read once when a workgroup starts: for a RHS that this step ends,
-// v_{j+1} may or may not be written, and it is never read.
+// The end of a fused Arnoldi step j in one launch: every workgroup sums |w|
+// from the chunk partials of |w|^2 (k_norm_reduce's order, same bits);
+// workgroup 0 of each RHS forms the Hessenberg column with its Givens update
+// as k_hcol_givens does (it may end the RHS and writes the host flag);
+// every workgroup forms v_{j+1} = w / |w| and its FP32 rounding for the next
+// step's preconditioner (block-major when blk_nx > 0).  The active flag is
+// read once when a workgroup starts: for a RHS that this step ends, v_{j+1}
+// may or may not be written, and it is never read.
 template <class T>
 __global__ void __launch_bounds__(NT) k_hcol_scale(int j, int m, const cx<T>* __restrict__ c1,
                                                    const T* __restrict__ npart, int nch, cx<T>* __restrict__ H,
@@ -1114,15 +1057,6 @@ void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, i
   KCHK();
 }
 
-template <class T>
-void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
-                          const int* active, int blk_nx) {
-  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
-  unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
-  hipLaunchKernelGGL(k_scale_convert<T>, dim3(gx, nrhs), dim3(NT), 0, s, w, npart, (int)nch, n, v, vf, active,
-                     blk_nx);
-  KCHK();
-}
 
 template <class T>
 void launch_hcol_scale(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const T* npart, cx<T>* H, T* cs,
@@ -1142,15 +1076,6 @@ void launch_convert_blk(hipStream_t s, const cd* in, cf* out, int Nx, int Nt, in
   KCHK();
 }
 
-template <class T>
-void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,
-                           const T* npart, int64_t n, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr,
-                           int* active, int* nit, int* host_flags) {
-  const unsigned nch = nchunks(n, pick_ept(n, nrhs));  // the chunks of k_update_gram
-  hipLaunchKernelGGL(k_hcol_givens_np<T>, dim3((unsigned)(((int64_t)nrhs * 64 + NT - 1) / NT)), dim3(NT), 0, s, j,
-                     m, nrhs, c1, c2, npart, (int)nch, H, cs, sn, g, thr, active, nit, host_flags);
-  KCHK();
-}
 
 template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
@@ -1240,13 +1165,6 @@ void launch_hcol_givens(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, 
   KCHK();
 }
 
-template <class T>
-void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
-                 cx<T>* H, const int* active) {
-  hipLaunchKernelGGL(k_hcol<T>, dim3((nrhs + NT - 1) / NT), dim3(NT), 0, s, j, m, nrhs, c1, c2, hn, H,
-                     active);
-  KCHK();
-}
 
 template <class T>
 void launch_backsolve(hipStream_t s, int m, int nrhs, const cx<T>* H, const cx<T>* g, const int* nit,
@@ -1415,8 +1333,6 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
   template void launch_update_multi<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int,          \
                                        const cx<T>*, int, T, cx<T>*, int64_t, int, const int*, T*, \
                                        T*, const int*);                                           \
-  template void launch_hcol<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*, const T*,   \
-                               cx<T>*, const int*);                                               \
   template void launch_norm<T>(hipStream_t, const cx<T>*, int64_t, int, T*, const int*, T*, int*);       \
   template void launch_scale<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,         \
                                 const int*);                                                      \
@@ -1429,14 +1345,9 @@ void launch_right_tri(hipStream_t s, const cd* Y, const cd* Rinv, int64_t n, int
   template void launch_update_gram<T>(hipStream_t, const cx<T>*, int64_t, int64_t, int, const cx<T>*, \
                                       int, cx<T>*, int, cx<T>*, int, cx<T>*, int64_t, int,          \
                                       const int*, T*);                                             \
-  template void launch_scale_convert<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*,  \
-                                        cf*, const int*, int);                                     \
   template void launch_hcol_scale<T>(hipStream_t, int, int, int, const cx<T>*, const T*, cx<T>*, T*, \
                                      cx<T>*, cx<T>*, const T*, int*, int*, int*, const cx<T>*,       \
                                      int64_t, cx<T>*, cf*, int);                                    \
-  template void launch_hcol_givens_np<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,     \
-                                         const T*, int64_t, cx<T>*, T*, cx<T>*, cx<T>*, const T*,   \
-                                         int*, int*, int*);                                        \
   template void launch_scale_r<T>(hipStream_t, const cx<T>*, const T*, int64_t, int, cx<T>*, T*,    \
                                   const int*);                                                   \
   template void launch_hcol_givens<T>(hipStream_t, int, int, int, const cx<T>*, const cx<T>*,       \

@@ -304,9 +304,6 @@ template <class T>
 void launch_update_multi(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv,
                          const cx<T>* coef, int ldc, T sign, cx<T>* w, int64_t n, int nrhs,
                          const int* active, T* norm_out, T* partial, const int* nlim = nullptr);
-template <class T>
-void launch_hcol(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2, const T* hn,
-                 cx<T>* H, const int* active);
 // zero_done (optional): zero_done[r] = 1 where the norm is 0, else 0
 template <class T>
 void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, const int* active,
@@ -314,8 +311,8 @@ void launch_norm(hipStream_t s, const cx<T>* w, int64_t n, int nrhs, T* out, con
 // FGMRES from x = 0: ||b|| (with the zero-RHS flags), the first cycle's
 // state (launch_fgmres_init with beta = ||b||) and v_0 = b / ||b|| in one
 // norm-partial launch and one more (same bits as launch_norm, launch_fgmres_init
-// and launch_scale); vf (or null): v_0 rounded to FP32 as launch_scale_convert
-// stores it (block-major when blk_nx > 0)
+// and launch_scale); vf (or null): v_0 rounded to FP32 as launch_hcol_scale
+// stores v_{j+1} (block-major when blk_nx > 0)
 void launch_fgmres_start(hipStream_t s, const cd* b, int64_t n, int nrhs, double* partial, int m, double tol,
                          double* bnorm, int* done, int* active, int* nit, cd* g, double* thr, cd* v, cf* vf,
                          int blk_nx);
@@ -351,23 +348,13 @@ template <class T>
 void launch_update_gram(hipStream_t s, const cx<T>* V, int64_t sI, int64_t sR, int nv, const cx<T>* dpart,
                         int nchd, cx<T>* gram, int ldg, cx<T>* coef_out, int ldc, cx<T>* w, int64_t n, int nrhs,
                         const int* active, T* norm_partial);
-// v = w / |w| from the chunk partials of |w|^2 (chunking of
-// launch_update_gram), and vf = v rounded to FP32 (in the fine level's
-// block-major layout when blk_nx = Nx > 0)
-template <class T>
-void launch_scale_convert(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, cf* vf,
-                          const int* active, int blk_nx = 0);
-// the end of a fused Arnoldi step j: launch_hcol_givens_np (no c2) and
-// launch_scale_convert into v = v_{j+1}, vf, in one launch (same bits)
+// the end of a fused Arnoldi step j: |w| from the chunk partials of |w|^2,
+// launch_hcol_givens (no c2), and v = v_{j+1} = w / |w| with its FP32
+// rounding vf (block-major when blk_nx > 0), in one launch
 template <class T>
 void launch_hcol_scale(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const T* npart, cx<T>* H, T* cs,
                        cx<T>* sn, cx<T>* g, const T* thr, int* active, int* nit, int* host_flags, const cx<T>* w,
                        int64_t n, cx<T>* v, cf* vf, int blk_nx);
-// launch_hcol_givens with |w| formed from the chunk partials of |w|^2
-template <class T>
-void launch_hcol_givens_np(hipStream_t s, int j, int m, int nrhs, const cx<T>* c1, const cx<T>* c2,
-                           const T* npart, int64_t n, cx<T>* H, T* cs, cx<T>* sn, cx<T>* g, const T* thr,
-                           int* active, int* nit, int* host_flags);
 template <class T>
 void launch_scale_r(hipStream_t s, const cx<T>* w, const T* npart, int64_t n, int nrhs, cx<T>* v, T* den_out,
                     const int* active);
