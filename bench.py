@@ -694,7 +694,7 @@ def main():
                     help="scan128 workload: Wilson masses of the scan")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library drives one GPU per process; --gpus must be 1 (multi-GPU sharding is not built)"}))
         sys.exit(2)
     if args.workload == "batch8":
         run_batch8(args)

@@ -1,7 +1,7 @@
 """Pins for the oracle's cost model (Sec. 4: arithmetic of every
-matrix-vector product) and for the parts of the oracle that round 1 left
-unpinned: the blocked branch of the coarsest exact trace and the telescoping
-sum closed on a level above the hierarchy's coarsest."""
+matrix-vector product) and for two further parts of the oracle: the blocked
+branch of the coarsest exact trace and the telescoping sum closed on a level
+above the hierarchy's coarsest."""
 import numpy as np
 import pytest
 
