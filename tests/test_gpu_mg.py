@@ -287,3 +287,29 @@ def test_restarted_solves_and_zero_rhs(ctx, precision):
         assert np.all(res <= 1e-10), (precision, l, res)
         assert rel_err(xs[nz], lev.solve(b[nz].T).T) < 1e-6, (precision, l)
     ctx.free_gauge(gid)
+
+
+def test_long_cycles_backsolve_beyond_lds(ctx):
+    """FGMRES(48) with a deliberately weak cycle (2x2 SAP blocks, one cycle,
+    two test vectors): cycles run past 32 steps, where the update's own
+    back-substitution reads the rotated Hessenberg matrix from global memory
+    instead of its LDS copy.  True residuals with the oracle's operator and
+    the solution against its exact solve."""
+    from paper_2303_11512_amd import solve_params
+    th = metropolis_u1(32, 32, 3.0, 100, 2011)
+    rec = Recipe(th, -0.12, [(4, 4)], [2], seed=11, sap_block=[(2, 2), (1, 1)], sap_cycles=[1, 1],
+                 inner_iters=[0, 0])
+    gid = rec.gpu(ctx)
+    hier = rec.oracle()
+    lev = hier.levels[0]
+    b = rhs_vectors(lev.n, 3, 71)
+    x = empty(3, lev.n)
+    st, its, rel = ctx.solve_batch(gid, 0, to_dev(b), x, solve_params(tol=1e-12, restart=48, max_restarts=20))
+    its = np.asarray(its)
+    log(f"long cycles: iterations {its.tolist()}")
+    assert its.max() > 32, its  # the case the test is for
+    xs = to_host(x)
+    res = np.linalg.norm(b - (lev.D @ xs.T).T, axis=1) / np.linalg.norm(b, axis=1)
+    assert np.all(res <= 1e-12), res
+    assert rel_err(xs, lev.solve(b.T).T) < 1e-8
+    ctx.free_gauge(gid)
