@@ -1616,6 +1616,22 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
   };
   const int64_t own_o = BLK ? (int64_t)blk * K + k : (int64_t)own * 2 + a;
   const int64_t nbo[2] = {vofs(nbs[0]), vofs(nbs[1])};
+  // the r and halo x of all eight passes are loaded before the barrier that
+  // ends the staging of inv_B and the links, so both sets of loads are in
+  // flight together (one memory round trip, not two)
+  cx<T> rv[8], xh[8][2][2];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int r = r0 + 2 * p + (lane >> 5);
+    const int64_t rc = r < nrhs ? r : 0;
+    const cx<T>* xr = x + rc * n;
+    rv[p] = rr[rc * n + own_o];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      xh[p][j][0] = xr[nbo[j]];
+      xh[p][j][1] = xr[nbo[j] + 1];
+    }
+  }
   __syncthreads();
   cx<T> bb[2][2];
 #pragma unroll
@@ -1628,18 +1644,9 @@ __global__ void __launch_bounds__(NT) k_sap0_mfma(const cx<T>* __restrict__ B, c
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int ri = 2 * p + (lane >> 5);
-    const int r = r0 + ri;
-    const int64_t rc = r < nrhs ? r : 0;
-    const cx<T>* xr = x + rc * n;
-    cx<T> acc = rr[rc * n + own_o];
-    cx<T> xh[2][2];
+    cx<T> acc = rv[p];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      xh[j][0] = xr[nbo[j]];
-      xh[j][1] = xr[nbo[j] + 1];
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc = acc - bb[j][0] * xh[j][0] - bb[j][1] * xh[j][1];
+    for (int j = 0; j < 2; ++j) acc = acc - bb[j][0] * xh[p][j][0] - bb[j][1] * xh[p][j][1];
     Hs[wave][ri][k] = acc;
   }
   __syncthreads();
