@@ -501,7 +501,8 @@ int solve_level(mgm_ctx* c, Gauge& g, int l, int nrhs, const cd* b, cd* x,
   };
 
   bool final_known = false;  // hr holds the residuals of the returned x
-  // steps that hand the preconditioner an FP32 input scale and round v_j in one launch
+  // steps whose preconditioner takes an FP32 input: each step's last launch
+  // also scales and rounds v_{j+1} for the next one
   const bool fused = !stage && precondition_in_fp32(g);
   if (L.has_dense) {
     launch_dense_apply<double>(s, L.d.dinv.as<cd>(), n, nrhs, b, x, nullptr, &g.scratch[c->wslot]);
