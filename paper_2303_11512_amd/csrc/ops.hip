@@ -1266,12 +1266,15 @@ __device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const 
   const int64_t rrow = ok ? r : r0;  // lanes past the last RHS read row r0; never stored
   // every load of the wave is issued before the first product
   h4 br[8], bi[8];
+  // FROMC operands: P and e of every hop, loaded with everything else below
+  chalf pvs[FROMC ? 8 : 1][4];
+  cf evs[FROMC ? 8 : 1][4];
+  const int c = i >> 3, cq = q >> 1;
   if constexpr (FROMC) {
     // x_H at hop site v: rows = v's 16 dofs (chirality i / 8, row sl' 8 + i % 8
     // of its 2x2 aggregate A'), K = the 16 coarse dofs of A' (c' 8 + k; zero
     // unless c' = chirality), columns = RHS
     const int64_t ncoarse = (int64_t)(Nx / 2) * (Nt / 2) * CM;
-    const int c = i >> 3, cq = q >> 1;
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       const int v = (int)nb_site(sap4_site(blk, h >> 1, Nx), sap4_hop_dir(h), Nx, Nt);
@@ -1280,22 +1283,10 @@ __device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const 
       const int sl = ((vt & 1) << 1) + (vx & 1);
       const chalf* pa = hP + (((A * 2 + c) * 32 + sl * 8 + (i & 7)) * 8) + 4 * (q & 1);
       const cf* ev = ec + rrow * ncoarse + A * CM + 4 * q;
-      h4 pr, pi, er, ei;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const chalf pv = pa[j];
-        pr[j] = cq == c ? pv.re : (_Float16)0;
-        pi[j] = cq == c ? pv.im : (_Float16)0;
-        const cf e = ev[j];
-        er[j] = (_Float16)e.re;
-        ei[j] = (_Float16)e.im;
-      }
-      CAcc<float> xh{{0, 0, 0, 0}, {0, 0, 0, 0}};
-      hmma(pr, pi, er, ei, xh);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        br[h][j] = (_Float16)xh.re[j];
-        bi[h][j] = (_Float16)xh.im[j];
+        pvs[h][j] = pa[j];
+        evs[h][j] = ev[j];
       }
     }
   } else {
@@ -1324,31 +1315,79 @@ __device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const 
       }
     }
   CAcc<float> rv[2];
+  // FIRST operands: the block's r and the rows of inv_B, loaded here too
+  cf rs[FIRST ? 4 : 1][4];
+  chalf ivs[FIRST ? 2 : 1][FIRST ? 4 : 1][4];
   if constexpr (FIRST) {
-    // rho rows of site 2 hh + rt: sum over the block's sites kt of inv_B[.][kt] r_kt
-    h4 sr[4], si[4];
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) {
       const cf* rv_ = rr + rrow * n + sap4_site(blk, kt, Nx) * CM + 4 * q;
 #pragma unroll
+      for (int j = 0; j < 4; ++j) rs[kt][j] = rv_[j];
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        const chalf* a = inv + ((int64_t)blk * 64 + (2 * hh + rt) * 16 + i) * 64 + kt * 16 + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ivs[rt][kt][j] = a[j];
+      }
+  }
+  // later cycles: rho_B of the first sweep
+  cf rhos[FIRST ? 1 : 2][4];
+  if constexpr (!FIRST) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rhos[rt][v] = rho[rrow * n + u * CM + 4 * q + v];
+    }
+  }
+  // every load above is issued before the first product below
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (FROMC) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      h4 pr, pi, er, ei;
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const cf v = rv_[j];
-        sr[kt][j] = (_Float16)v.re;
-        si[kt][j] = (_Float16)v.im;
+        const chalf pv = pvs[h][j];
+        pr[j] = cq == c ? pv.re : (_Float16)0;
+        pi[j] = cq == c ? pv.im : (_Float16)0;
+        const cf e = evs[h][j];
+        er[j] = (_Float16)e.re;
+        ei[j] = (_Float16)e.im;
+      }
+      CAcc<float> xh{{0, 0, 0, 0}, {0, 0, 0, 0}};
+      hmma(pr, pi, er, ei, xh);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        br[h][j] = (_Float16)xh.re[j];
+        bi[h][j] = (_Float16)xh.im[j];
       }
     }
+  }
+  if constexpr (FIRST) {
+    // rho rows of site 2 hh + rt: sum over the block's sites kt of inv_B[.][kt] r_kt
+    h4 sr[4], si[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sr[kt][j] = (_Float16)rs[kt][j].re;
+        si[kt][j] = (_Float16)rs[kt][j].im;
+      }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
       rv[rt] = CAcc<float>{{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt) {
-        const chalf* a = inv + ((int64_t)blk * 64 + (2 * hh + rt) * 16 + i) * 64 + kt * 16 + 4 * q;
         h4 ir, ii;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const chalf av = a[j];
-          ir[j] = av.re;
-          ii[j] = av.im;
+          ir[j] = ivs[rt][kt][j].re;
+          ii[j] = ivs[rt][kt][j].im;
         }
         hmma(ir, ii, sr[kt], si[kt], rv[rt]);
       }
@@ -1360,15 +1399,12 @@ __device__ __forceinline__ void sap4p_h_body(const chalf* __restrict__ M, const 
     }
   } else {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const int64_t u = sap4_site(blk, 2 * hh + rt, Nx);
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const cf t = rho[rrow * n + u * CM + 4 * q + v];
-        rv[rt].re[v] = t.re;
-        rv[rt].im[v] = t.im;
+        rv[rt].re[v] = rhos[rt][v].re;
+        rv[rt].im[v] = rhos[rt][v].im;
       }
-    }
   }
   const bool on = ok && (!active || active[rrow] != 0);
 #pragma unroll
